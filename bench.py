@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X state-vector / density-matrix hot path.
+
+One step = one pass of the SV hot path over the deep-circuit workload:
+reset to |0...0>, the depth-40 brickwork random circuit (U3 on every qubit
+then CX on alternating neighbour pairs, seed 0) on n=30 qubits in
+complex128 with one kernel per gate, then <Z_i> for all i in one reduction
+pass.  `value` is the step's algorithmic HBM bytes (each touched amplitude
+read once and written once: 32N per U3, 16N per CX since only the moved half
+is touched, 16N for the reset write and the reduction read) divided by the
+step time, in GB/s, with the state resident in HBM.
+
+Extra legs, reported beside `value` (not part of it): the same circuit
+through fused k-qubit LDS blocks, a per-target-qubit U3/CX sweep, the noisy
+density-matrix gate at n=14, and the oracle on the host CPU.
+
+    python bench.py [--steps K] [--warmup W] [--n 30] [--depth 40]
+    python bench.py --profile-mode {trace,pmc}   (short runs for rocprofv3)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "30q SV gate HBM GB/s (%peak); batched VQE energy+grad evals/s; p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--depth", type=int, default=40)
+    ap.add_argument("--fuse-k", type=int, default=12)
+    ap.add_argument("--no-extras", action="store_true", help="only the timed step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-mode", choices=["trace", "pmc"], default=None)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def step_bytes(n, gates):
+    N = 1 << n
+    b = 16 * N + 16 * N                       # reset write + reduction read
+    for name, q, _ in gates:
+        b += 16 * N if name in ("cx", "swap") else 32 * N
+    return b
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in ("kernels_sv.hip",):
+        h.update(open(os.path.join(ROOT, "paper_2401_06861_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name):
+    """Measured HBM bytes per launch from a committed rocprofv3 --pmc summary,
+    or None when missing or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------- CPU leg
+def cpu_baseline(seconds: float):
+    """The tier-1 oracle (numpy tensor contractions, as written) applying the
+    brickwork circuit's gates in order on n=26 from |0...0>, stopped after
+    `seconds`; GB/s with the same per-gate algorithmic bytes."""
+    import workloads as W
+    from oracle import tensor
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    n = 26
+    gates = W.brickwork_circuit(n, 40, seed=0)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    done, byt = 0, 0
+    t0 = time.perf_counter()
+    for g in gates:
+        psi = tensor.sv_apply(psi, g, n)
+        done += 1
+        byt += (16 if g[0] in ("cx", "swap") else 32) << n
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(byt / dt / 1e9, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"tier-1 numpy oracle, first {done} gates of the depth-40 brickwork at n={n} "
+                      f"(2^{n} complex128 amplitudes, {dt:.1f} s)"}
+
+
+# ---------------------------------------------------------------- GPU legs
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2401_06861_amd import nwq
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    N = 1 << n
+    gates = W.brickwork_circuit(n, args.depth, seed=0)
+    arrays = nwq.circuit_arrays(gates)
+    zterms = W.single_site_terms(n, "Z")
+    stream = torch.cuda.current_stream()
+    log(f"[bench] allocating n={n} state ({16 * N / 1e9:.2f} GB)")
+    psi = torch.empty(N, dtype=torch.complex128, device=dev)
+    st = nwq.SVState(n, tensor=psi, stream=stream)
+
+    if args.profile_mode is not None:
+        # short, fixed work for rocprofv3: a plain copy of known size (counter
+        # calibration), then U3 and CX launches at n
+        src = torch.empty(1 << 27, dtype=torch.complex128, device=dev)   # 2 GiB
+        src.fill_(0.5)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        reps = 3 if args.profile_mode == "pmc" else 10
+        for r in range(reps):
+            for q in (0, 7, n - 1):
+                st.apply("u3", (q,), (0.3, 0.2, 0.1))
+            st.apply("cx", (3, 4), ())
+        torch.cuda.synchronize()
+        log("[bench] profile mode done")
+        print(json.dumps({"profile_mode": args.profile_mode, "n": n}))
+        return
+
+    total_bytes = step_bytes(n, gates)
+
+    def step():
+        st.reset()
+        nwq.nwq_apply_circuit(st.h, *arrays)
+        return st.expvals(zterms)          # synchronises the stream
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        log(f"[bench] warmup {i} {time.perf_counter() - t:.2f}s")
+    nwq.nwq_timing_read(st.h, reset=True)
+    nwq.nwq_timing_enable(st.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"[bench] step {i} done at {time.perf_counter() - t0:.2f}s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nwq.nwq_timing_enable(st.h, False)
+    tim = nwq.nwq_timing_read(st.h, reset=True)
+    ms_per_step = dt * 1e3 / args.steps
+    value = total_bytes / (dt / args.steps) / 1e9
+
+    cnt, ms = tim["sv_1q_dense"]
+    u3_avg_ms = ms / max(cnt, 1)
+    achieved = 32 * N / (u3_avg_ms * 1e-3) / 1e9
+    traffic = load_traffic("sv_1q_dense_n30_pmc.md") if n == 30 else None
+    roofline = {"kernel": "k_sv_1q (U3, one pass of 2^30 pairs)", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_launch_ms": round(u3_avg_ms, 4), "launches": cnt}
+    per_class = {k: {"launches": c, "avg_ms": round(m / c, 4)} for k, (c, m) in tim.items() if c}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"brickwork random circuit depth {args.depth}, n={n} state vector complex128, "
+                                  "one kernel per gate, then <Z_i> for all i", "n": n, "depth": args.depth,
+                      "gates": len(gates), "seed": 0, "parallelism": "single GPU"},
+           "pct_peak": round(value / HBM_PEAK_GBS, 4), "roofline": roofline, "kernels": per_class}
+
+    if not args.no_extras:
+        out["fused"] = fused_leg(nwq, st, arrays, gates, n, args.fuse_k, ms_per_step)
+        out["sweep"] = sweep_leg(nwq, st, n)
+        del st, psi
+        torch.cuda.empty_cache()
+        out["dm_noisy_gate_n14"] = dm_leg(nwq, torch)
+    if not args.no_cpu:
+        log("[bench] cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out))
+
+
+def fused_leg(nwq, st, arrays, gates, n, k, unfused_ms):
+    log(f"[bench] fused leg k={k}")
+    nwq.nwq_set_fusion(st.h, k)
+    st.reset()
+    nwq.nwq_apply_circuit(st.h, *arrays)          # warm-up (and plan)
+    st.flush()
+    import torch
+    torch.cuda.synchronize()
+    reps = 2
+    nwq.nwq_timing_read(st.h, reset=True)
+    nwq.nwq_timing_enable(st.h, True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st.reset()
+        nwq.nwq_apply_circuit(st.h, *arrays)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    nwq.nwq_timing_enable(st.h, False)
+    tim = nwq.nwq_timing_read(st.h, reset=True)
+    blocks, fg = nwq.nwq_fusion_stats(st.h)
+    nwq.nwq_set_fusion(st.h, 0)
+    c, ms = tim["sv_fused"]
+    N = 1 << n
+    avg = ms / max(c, 1)
+    return {"k": k, "blocks": blocks, "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
+            "circuit_ms": round(dt * 1e3, 2), "speedup_vs_one_kernel_per_gate": round(unfused_ms / (dt * 1e3), 2),
+            "avg_block_ms": round(avg, 3), "block_hbm_GBs": round(32 * N / (avg * 1e-3) / 1e9, 1)}
+
+
+def sweep_leg(nwq, st, n):
+    log("[bench] per-qubit sweep")
+    import torch
+    N = 1 << n
+    res = {}
+    for name, qs_list, bytes_per in (("u3", [(q,) for q in (0, 1, 3, 5, 6, 10, 20, n - 1)], 32 * N),
+                                     ("cx", [(0, 1), (5, 6), (14, 15), (n - 2, n - 1)], 16 * N),
+                                     ("rz", [(0,), (n - 1,)], 32 * N), ("rzz", [(0, 1), (n - 2, n - 1)], 32 * N)):
+        for qs in qs_list:
+            p = {"u3": (0.3, 0.2, 0.1), "cx": (), "rz": (0.4,), "rzz": (0.4,)}[name]
+            st.apply(name, qs, p)
+            torch.cuda.synchronize()
+            nwq.nwq_timing_read(st.h, reset=True)
+            nwq.nwq_timing_enable(st.h, True)
+            for _ in range(5):
+                st.apply(name, qs, p)
+            nwq.nwq_timing_enable(st.h, False)
+            tim = nwq.nwq_timing_read(st.h, reset=True)
+            c, ms = max(tim.values(), key=lambda v: v[0])
+            avg = ms / c
+            res[f"{name}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(bytes_per / (avg * 1e-3) / 1e9, 1)}
+    return res
+
+
+def dm_leg(nwq, torch):
+    log("[bench] DM n=14 noisy gate leg")
+    n = 14
+    st = nwq.DMState(n)
+    nbytes = 32 * (1 << (2 * n))
+    out = {}
+    for label, ops, cls in (("1q_u3_dep_ad_pd", [("u3", (3,), (0.3, 0.2, 0.1)), ("depolarize", (3,), (1e-3,)),
+                                                 ("amp_damp", (3,), (1e-3,)), ("phase_damp", (3,), (2e-3,))],
+                             "dm_superop_1q"),
+                            ("2q_rzz_dep2", [("rzz", (3, 4), (0.2,)), ("depolarize2", (3, 4), (1e-2,))], "dm_superop_2q")):
+        st.run(ops)
+        st.flush()
+        torch.cuda.synchronize()
+        nwq.nwq_timing_read(st.h, reset=True)
+        nwq.nwq_timing_enable(st.h, True)
+        for _ in range(5):
+            st.run(ops)
+            st.flush()
+        nwq.nwq_timing_enable(st.h, False)
+        c, ms = nwq.nwq_timing_read(st.h, reset=True)[cls]
+        avg = ms / max(c, 1)
+        out[label] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
+    st.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()

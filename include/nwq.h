@@ -1,0 +1,202 @@
+/*
+ * nwq.h -- C ABI of the MI355X (gfx950) state-vector / density-matrix engine.
+ *
+ * The engine implements the two simulators the paper's Sec. II describes
+ * (a state-vector simulator for ideal circuits and a density-matrix simulator
+ * for noise-aware runs), the noise model of Sec. III (depolarisation and
+ * thermal relaxation, the latter as amplitude + phase damping), and the
+ * observables of Sec. III (magnetisations <Z_i>, Pauli-sum energies, VQE
+ * energies and gradients).  Choosing nwq_sv_create or nwq_dm_create plays
+ * the role of choosing the simulator backend (Sec. II, Fig. 2).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Qubit q is bit q of the basis index (little endian).  A k-qubit matrix
+ *    on qubits (q_0, ..., q_{k-1}) is 2^k x 2^k, complex, row-major, with
+ *    row/column index u = sum_j bit(q_j) 2^j.
+ *  - Complex numbers are interleaved (re, im) FP64 pairs, i.e. the
+ *    torch.complex128 / std::complex<double> layout.
+ *  - SV state: 2^n complex amplitudes.  DM state: 4^n complex entries, the
+ *    row-major vec of rho: entry (r, c) at index r * 2^n + c.
+ *  - Pauli strings are (xmask, zmask) pairs: on qubit q, (x_q, z_q) =
+ *    (0,0) I, (1,0) X, (1,1) Y, (0,1) Z.
+ *  - Every function returns NWQ_OK (0) or a negative nwq_status.  On error
+ *    the state is left unchanged (arguments are validated before any launch)
+ *    and nwq_last_error() holds a message (thread-local).
+ *  - Host arrays passed in are read during the call only; the caller keeps
+ *    ownership.  Device pointers are never freed by the library unless the
+ *    library allocated them.
+ *  - apply_* calls are asynchronous on the handle's HIP stream.  Calls that
+ *    return numbers to the host (expval, trace, purity, get_state)
+ *    synchronise that stream.  A handle is not thread-safe; use one stream
+ *    per handle.
+ */
+#ifndef NWQ_H
+#define NWQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nwq_state* nwq_handle;
+
+enum nwq_status {
+  NWQ_OK = 0,
+  NWQ_EINVAL = -1,    /* bad gate type, parameter count, size or pointer     */
+  NWQ_ERANGE = -2,    /* qubit index >= n, or n outside the supported range  */
+  NWQ_EDUP = -3,      /* the same qubit given twice                          */
+  NWQ_EKIND = -4,     /* operation not valid on this handle kind (SV vs DM)  */
+  NWQ_ENOTCPTP = -5,  /* Kraus set violates sum_k K^dag K = I beyond 1e-12   */
+  NWQ_ENOMEM = -6,    /* device allocation failed                            */
+  NWQ_EDEVICE = -7    /* a HIP runtime call failed (message kept)            */
+};
+
+/* Gate types (Sec. II circuits; Sec. III TFIM and VQE circuits).
+ * Rotations are exp(-i theta P / 2); U3 follows OpenQASM 2:
+ *   U3(t,p,l) = [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]].
+ * Two-qubit gates list the control first (CX, CZ); RZZ = exp(-i t Z Z / 2). */
+enum nwq_gate {
+  NWQ_GATE_I = 0, NWQ_GATE_X, NWQ_GATE_Y, NWQ_GATE_Z, NWQ_GATE_H,
+  NWQ_GATE_S, NWQ_GATE_SDG, NWQ_GATE_T, NWQ_GATE_TDG,
+  NWQ_GATE_RX, NWQ_GATE_RY, NWQ_GATE_RZ, NWQ_GATE_U3,
+  NWQ_GATE_CX, NWQ_GATE_CZ, NWQ_GATE_SWAP, NWQ_GATE_RZZ,
+  NWQ_GATE_COUNT
+};
+
+enum nwq_kind { NWQ_KIND_SV = 0, NWQ_KIND_DM = 1 };
+
+/* ---------------------------------------------------------------------------
+ * Handles (Sec. II: the SV and DM simulators)
+ * ------------------------------------------------------------------------- */
+
+/* Create an SV state of n qubits (1 <= n <= 34) on `hip_stream` (a
+ * hipStream_t, NULL = default stream); the library allocates 16 * 2^n bytes
+ * of device memory and initialises |0...0>.  NWQ_ENOMEM if it does not fit. */
+int nwq_sv_create(int n, void* hip_stream, nwq_handle* out);
+
+/* Create a DM state of n qubits (1 <= n <= 17): 16 * 4^n bytes, rho = |0><0|. */
+int nwq_dm_create(int n, void* hip_stream, nwq_handle* out);
+
+/* Wrap caller-owned device memory (e.g. a torch complex128 tensor) of
+ * 2^n (SV) or 4^n (DM) complex entries, 16-byte aligned.  The contents are
+ * taken as the current state (no reset).  The library never frees it. */
+int nwq_sv_create_from(void* dev_ptr, int n, void* hip_stream, nwq_handle* out);
+int nwq_dm_create_from(void* dev_ptr, int n, void* hip_stream, nwq_handle* out);
+
+/* Synchronise the stream and release everything the library allocated. */
+int nwq_destroy(nwq_handle h);
+
+/* Kind (nwq_kind), qubit count and device pointer of a handle. */
+int nwq_info(nwq_handle h, int* kind, int* n, void** dev_ptr);
+
+/* ---------------------------------------------------------------------------
+ * State operations
+ * ------------------------------------------------------------------------- */
+
+/* Reset to |0...0> (SV) or |0...0><0...0| (DM), the initial state of the
+ * Sec. III experiments, with a fill kernel (no memset node). */
+int nwq_reset(nwq_handle h);
+
+/* Copy the state to / from host memory of n_doubles = 2 * 2^n (SV) or
+ * 2 * 4^n (DM) doubles (interleaved re, im).  get_state synchronises. */
+int nwq_get_state(nwq_handle h, double* host, size_t n_doubles);
+int nwq_set_state(nwq_handle h, const double* host, size_t n_doubles);
+
+/* Launch any deferred work (fused DM superoperator, queued SV gates). */
+int nwq_flush(nwq_handle h);
+
+/* ---------------------------------------------------------------------------
+ * Gates (Sec. II; SV: psi <- U psi, DM: rho <- U rho U^dag)
+ * ------------------------------------------------------------------------- */
+
+/* Apply gate `type` to `qubits` (n_q = 1 or 2, distinct, < n) with n_p
+ * parameters (RX/RY/RZ/RZZ: 1, U3: 3, others: 0).  On a DM handle the
+ * gate's superoperator U (x) conj(U) is held back so that the channels that
+ * follow on the same qubits fuse into the same single pass over rho. */
+int nwq_apply_gate(nwq_handle h, int type, const int* qubits, int n_q,
+                   const double* params, int n_p);
+
+/* Apply an arbitrary k-qubit matrix (k = 1 or 2; 2^k x 2^k complex,
+ * row-major, interleaved) to `qubits`.  Unitarity is not checked on SV; on
+ * DM it is applied as rho <- M rho M^dag. */
+int nwq_apply_matrix(nwq_handle h, const int* qubits, int k, const double* m);
+
+/* Apply the gates of a whole circuit: n_gates entries of types[],
+ * qubits[2*i .. 2*i+1] (second entry ignored for 1-qubit gates) and
+ * params[3*i .. 3*i+2] (unused entries ignored).  With fusion enabled on an
+ * SV handle (nwq_set_fusion) consecutive gates are grouped into k-qubit
+ * blocks, each applied in one pass through LDS. */
+int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types,
+                      const int* qubits, const double* params);
+
+/* Fused-block width for nwq_apply_circuit on SV handles: 0 = off (one
+ * kernel per gate), else the number of qubits a block may touch (6..13).
+ * Returns the value in effect through *k_out when non-NULL. */
+int nwq_set_fusion(nwq_handle h, int k, int* k_out);
+
+/* Statistics of the last nwq_apply_circuit: number of fused blocks and
+ * gates (both 0 when fusion was off). */
+int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates);
+
+/* ---------------------------------------------------------------------------
+ * Noise channels (Sec. III noise model; DM handles only, else NWQ_EKIND)
+ * ------------------------------------------------------------------------- */
+
+/* rho <- sum_k K_k rho K_k^dag for n_kraus operators of size 2^k x 2^k
+ * (k = 1 or 2) given back to back (complex, row-major, interleaved).
+ * NWQ_ENOTCPTP if max |sum K^dag K - I| > 1e-12. */
+int nwq_apply_channel(nwq_handle h, const int* qubits, int k,
+                      const double* kraus, int n_kraus);
+
+/* Depolarising channel on k = 1 or 2 qubits:
+ *   rho <- (1 - p) rho + p I/2^k (x) Tr_qubits(rho),  0 <= p <= 1. */
+int nwq_depolarize(nwq_handle h, const int* qubits, int k, double p);
+/* Amplitude damping: K0 = [[1,0],[0,sqrt(1-g)]], K1 = [[0,sqrt g],[0,0]]. */
+int nwq_amp_damp(nwq_handle h, int q, double gamma);
+/* Phase damping: K0 = [[1,0],[0,sqrt(1-l)]], K1 = [[0,0],[0,sqrt l]]. */
+int nwq_phase_damp(nwq_handle h, int q, double lambda);
+
+/* ---------------------------------------------------------------------------
+ * Observables (Sec. III: magnetisation, energy)
+ * ------------------------------------------------------------------------- */
+
+/* out_real = sum_t coeffs[t] * Re <P_t> (SV: <psi|P|psi>, DM: Tr(rho P)).
+ * Synchronises.  Deterministic: reductions use a fixed order. */
+int nwq_expval_pauli_sum(nwq_handle h, int n_terms, const uint64_t* xmask,
+                         const uint64_t* zmask, const double* coeffs,
+                         double* out_real);
+
+/* out[t] = Re <P_t> for each term (no coefficients).  Synchronises. */
+int nwq_expval_pauli_terms(nwq_handle h, int n_terms, const uint64_t* xmask,
+                           const uint64_t* zmask, double* out);
+
+/* DM only: out = Re Tr(rho) (imaginary part in *imag_out if non-NULL). */
+int nwq_trace(nwq_handle h, double* out, double* imag_out);
+/* DM: sum_jk |rho_jk|^2 (= Tr rho^2 for Hermitian rho); SV: sum |a_j|^2. */
+int nwq_purity(nwq_handle h, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------- */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* nwq_last_error(void);
+
+/* Per-kernel timing with HIP events on the handle's stream: when enabled,
+ * every launch is bracketed by events and nwq_timing_read returns, per
+ * kernel class, the number of launches and the summed milliseconds since
+ * the last reset (it synchronises).  Classes: 0 reset, 1 sv_1q_dense,
+ * 2 sv_diag, 3 sv_perm, 4 sv_2q_dense, 5 sv_fused, 6 dm_superop_1q,
+ * 7 dm_superop_2q, 8 reduce.  count and ms hold NWQ_TIMING_CLASSES entries. */
+#define NWQ_TIMING_CLASSES 9
+int nwq_timing_enable(nwq_handle h, int enable);
+int nwq_timing_read(nwq_handle h, long long* count, double* ms, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NWQ_H */

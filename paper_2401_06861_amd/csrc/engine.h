@@ -1,0 +1,67 @@
+// The handle behind nwq_handle and the engine-internal entry points shared
+// between engine.hip (state, gates, channels, reductions) and circuit.hip
+// (whole-circuit application and the fusion planner).
+#pragma once
+
+#include <vector>
+
+#include "nwq_internal.h"
+
+struct TimedLaunch {
+  int cls;
+  hipEvent_t a, b;
+};
+
+struct nwq_state {
+  int kind = NWQ_KIND_SV;
+  int n = 0;                       // qubits
+  int nbits = 0;                   // bits of the vector index: n (SV) or 2n (DM)
+  unsigned long long len = 0;      // 2^nbits entries
+  double2* data = nullptr;
+  bool owns = false;
+  hipStream_t stream = nullptr;
+
+  // launch shapes per kernel class (autotuned)
+  nwq::LaunchCfg cfg[nwq::KC_COUNT];
+
+  // reduction scratch
+  double* partials = nullptr;
+  size_t partials_cap = 0;
+  double* results_dev = nullptr;
+  double* results_host = nullptr;  // pinned
+  size_t results_cap = 0;
+
+  // upload arena (pinned host ring + device ring)
+  void* arena_dev = nullptr;
+  void* arena_host = nullptr;
+  size_t arena_off = 0;
+
+  // DM: pending superoperator (gate + following channels on the same qubits)
+  bool pend_active = false;
+  int pend_k = 0;
+  int pend_q[2] = {-1, -1};
+  std::vector<nwq::cd> pend_S;
+
+  // SV fusion
+  int fuse_k = 0;                  // 0 = off
+  int last_blocks = 0, last_fused_gates = 0;
+  void* fuse_dev = nullptr;        // device copy of the compiled block program
+  size_t fuse_cap = 0;
+
+  // timing
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  long long t_count[nwq::KC_COUNT] = {0};
+  double t_ms[nwq::KC_COUNT] = {0};
+};
+
+namespace nwq {
+void gate_matrix(int type, const double* p, cd* m);
+int arena_put(nwq_state* h, const void* src, size_t bytes, void** dev_out);
+void timing_begin(nwq_state* h, int cls);
+void timing_end(nwq_state* h);
+int sv_apply_gate_validated(nwq_state* h, int type, const int* q, const double* p);
+int dm_apply_unitary(nwq_state* h, const int* q, int k, const cd* U);
+int flush_all(nwq_state* h);
+}  // namespace nwq

@@ -1,0 +1,281 @@
+// Deterministic reductions: Pauli-term expectation values of a state vector,
+// Tr(rho P) of a density matrix, and sums of squared moduli.
+//
+// Every reduction has a fixed order: per-lane partials, a wave64 xor-shuffle
+// tree, per-wave slots in LDS combined in wave order, per-block partials in
+// global memory, and a second stage that sums each row of block partials in
+// a fixed order.  No atomics, so results are bitwise reproducible for a given
+// input size and launch shape, whatever else runs on the device.
+//
+// Pauli term P = i^{|x&z|} X^x Z^z acts as P|j> = i^y (-1)^{|j&z|} |j^x>, so
+//   <P> = sum_j i^y (-1)^{|j&z|} conj(a_{j^x}) a_j .
+// For x != 0 the contributions of j and j^x are complex conjugates, so the
+// sum over j with bit h(x) clear of 2 Re(...) gives <P> with no imaginary
+// residue; for x = 0 the summand (-1)^{|j&z|} |a_j|^2 is real.
+//
+// Tiling: a workgroup stages a tile of 2^(c+m) amplitudes in LDS -- 2^m
+// contiguous chunks of 2^c amplitudes (c >= 6 gives 1 KiB wave-contiguous
+// loads) whose high bits sit at m chosen positions -- so every term whose
+// flipped bits x lie inside the tile finds its partner in LDS.  The host
+// groups terms into passes of tiles that cover their x bits.
+#include "nwq_internal.h"
+
+namespace nwq {
+namespace {
+
+constexpr int kRedBlock = 256;
+constexpr int kRedWaves = kRedBlock / kWave;
+constexpr int kMaxTermsPerPass = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Tile-local index l -> global index (without the tile base): low c bits
+// pass through; bit c+i of l goes to position hi[i].
+__device__ __forceinline__ unsigned long long scatter_local(unsigned l, int c, int m, const TileShape& t) {
+  unsigned long long g = l & ((1u << c) - 1u);
+#pragma unroll 8
+  for (int i = 0; i < 8; ++i)
+    if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << t.hi[i];
+  return g;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_pauli_tile(const double2* __restrict__ a, int nbits, TileShape t,
+                                                          const TermDev* __restrict__ terms, int count,
+                                                          double* __restrict__ partials, int first_row) {
+  extern __shared__ double2 lds_tile[];
+  __shared__ double acc[kMaxTermsPerPass][kRedWaves];
+  const int k = t.c + t.m;
+  const unsigned tile_len = 1u << k;
+  const unsigned long long ntiles = 1ull << (nbits - k);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < count * kRedWaves; i += kRedBlock) acc[i / kRedWaves][i % kRedWaves] = 0.0;
+
+  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // base: tile index spread over the bits outside the tile (low c bits are inside)
+    unsigned long long base = tile << t.c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < t.m) {
+        const int q = t.hi[i];
+        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
+      }
+    }
+    __syncthreads();   // previous tile's readers are done
+    for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) lds_tile[l] = a[base | scatter_local(l, t.c, t.m, t)];
+    __syncthreads();
+    for (int ti = 0; ti < count; ++ti) {
+      const TermDev T = terms[ti];
+      const int outer = __popcll(base & T.zo) & 1;
+      double s = 0.0;
+      if (T.xl == 0) {
+        for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) {
+          const double2 v = lds_tile[l];
+          const double w = fma(v.x, v.x, v.y * v.y);
+          s += ((__popcll(l & T.zl) + outer) & 1) ? -w : w;
+        }
+      } else {
+        const unsigned long long hbit = T.xl & (~T.xl + 1ull);   // lowest flipped bit
+        for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) {
+          if (l & hbit) continue;
+          const double2 v = lds_tile[l];
+          const double2 p = lds_tile[l ^ (unsigned)T.xl];
+          // w = conj(p) * v
+          const double wr = fma(p.x, v.x, p.y * v.y);
+          const double wi = fma(p.x, v.y, -p.y * v.x);
+          double r;   // Re(i^y w)
+          switch (T.y & 3) {
+            case 0: r = wr; break;
+            case 1: r = -wi; break;
+            case 2: r = -wr; break;
+            default: r = wi; break;
+          }
+          r *= 2.0;
+          s += ((__popcll(l & T.zl) + outer) & 1) ? -r : r;
+        }
+      }
+      s = wave_sum(s);
+      if (lane == 0) acc[ti][wave] += s;
+    }
+  }
+  __syncthreads();
+  for (int ti = threadIdx.x; ti < count; ti += kRedBlock) {
+    double s = 0.0;
+    for (int w = 0; w < kRedWaves; ++w) s += acc[ti][w];
+    partials[(unsigned long long)(first_row + ti) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// One term whose flipped bits do not fit a tile: pairs (j, j^x) over the
+// j with bit h (the lowest bit of x) clear, read straight from global memory.
+__global__ __launch_bounds__(kRedBlock) void k_pauli_pairs(const double2* __restrict__ a, int nbits,
+                                                           unsigned long long x, unsigned long long z, int y,
+                                                           double* __restrict__ partials) {
+  __shared__ double accw[kRedWaves];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int h = __ffsll((long long)x) - 1;
+  const unsigned long long npairs = 1ull << (nbits - 1);
+  double s = 0.0;
+  for (unsigned long long p = (unsigned long long)blockIdx.x * kRedBlock + threadIdx.x; p < npairs;
+       p += (unsigned long long)gridDim.x * kRedBlock) {
+    const unsigned long long j = ((p >> h) << (h + 1)) | (p & ((1ull << h) - 1ull));
+    const double2 v = a[j];
+    const double2 q = a[j ^ x];
+    const double wr = fma(q.x, v.x, q.y * v.y);
+    const double wi = fma(q.x, v.y, -q.y * v.x);
+    double r;
+    switch (y & 3) {
+      case 0: r = wr; break;
+      case 1: r = -wi; break;
+      case 2: r = -wr; break;
+      default: r = wi; break;
+    }
+    r *= 2.0;
+    s += (__popcll(j & z) & 1) ? -r : r;
+  }
+  s = wave_sum(s);
+  if (lane == 0) accw[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kRedWaves; ++w) r += accw[w];
+    partials[blockIdx.x] = r;
+  }
+}
+
+// Tr(rho P) = sum_r rho[r, r^x] i^y (-1)^{|r&z|} over the 2^n rows.
+__global__ __launch_bounds__(kRedBlock) void k_dm_pauli(const double2* __restrict__ rho, int n,
+                                                        const TermDev* __restrict__ terms, int count,
+                                                        double* __restrict__ partials) {
+  __shared__ double accr[kRedWaves], acci[kRedWaves];
+  const unsigned long long dim = 1ull << n;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int ti = 0; ti < count; ++ti) {
+    const TermDev T = terms[ti];    // for DM the masks are global: xl = x, zl = z
+    double sr = 0.0, si = 0.0;
+    for (unsigned long long r = (unsigned long long)blockIdx.x * kRedBlock + threadIdx.x; r < dim;
+         r += (unsigned long long)gridDim.x * kRedBlock) {
+      const double2 v = rho[r * dim + (r ^ T.xl)];
+      double vr = v.x, vi = v.y;
+      switch (T.y & 3) {   // multiply by i^y
+        case 1: { const double t0 = vr; vr = -vi; vi = t0; break; }
+        case 2: vr = -vr; vi = -vi; break;
+        case 3: { const double t0 = vr; vr = vi; vi = -t0; break; }
+        default: break;
+      }
+      if (__popcll(r & T.zl) & 1) { vr = -vr; vi = -vi; }
+      sr += vr;
+      si += vi;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) { accr[wave] = sr; acci[wave] = si; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int w = 0; w < kRedWaves; ++w) { a0 += accr[w]; a1 += acci[w]; }
+      partials[(unsigned long long)(2 * ti) * gridDim.x + blockIdx.x] = a0;
+      partials[(unsigned long long)(2 * ti + 1) * gridDim.x + blockIdx.x] = a1;
+    }
+    __syncthreads();
+  }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kRedBlock) void k_sumsq(const double2* __restrict__ a, unsigned long long len,
+                                                     double* __restrict__ partials) {
+  __shared__ double accw[kRedWaves];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  double s = 0.0;
+  const unsigned long long stride = (unsigned long long)gridDim.x * kRedBlock * EPT;
+  for (unsigned long long i0 = (unsigned long long)blockIdx.x * kRedBlock * EPT + threadIdx.x; i0 < len; i0 += stride) {
+    double2 v[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const unsigned long long i = i0 + (unsigned long long)j * kRedBlock;
+      v[j] = i < len ? a[i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) s += fma(v[j].x, v[j].x, v[j].y * v[j].y);
+  }
+  s = wave_sum(s);
+  if (lane == 0) accw[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kRedWaves; ++w) r += accw[w];
+    partials[blockIdx.x] = r;
+  }
+}
+
+// Second stage: one wave per row, lane-strided partial sums then the xor
+// tree; optional coefficient-weighted total in row order by one lane.
+__global__ __launch_bounds__(kRedBlock) void k_reduce_rows(const double* __restrict__ partials, int rows, int grid,
+                                                           const double* __restrict__ coeffs, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int r = wave; r < rows; r += kRedWaves) {
+    double s = 0.0;
+    for (int b = lane; b < grid; b += kWave) s += partials[(unsigned long long)r * grid + b];
+    s = wave_sum(s);
+    if (lane == 0) out[r] = s;
+  }
+  if (coeffs != nullptr) {
+    __syncthreads();
+    __threadfence_block();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int r = 0; r < rows; ++r) t = fma(coeffs[r], out[r], t);
+      out[rows] = t;
+    }
+  }
+}
+
+}  // namespace
+
+int pauli_tile_grid(int nbits, const TileShape& t) {
+  const unsigned long long ntiles = 1ull << (nbits - t.c - t.m);
+  const unsigned long long cap = 2048;
+  return (int)(ntiles < cap ? ntiles : cap);
+}
+
+void launch_pauli_tile(hipStream_t s, const double2* a, int nbits, const TileShape& t, const TermDev* terms,
+                       int count, double* partials, int first_row, int grid) {
+  const size_t lds = sizeof(double2) << (t.c + t.m);
+  hipLaunchKernelGGL(k_pauli_tile, dim3(grid), dim3(kRedBlock), lds, s, a, nbits, t, terms, count, partials,
+                     first_row);
+}
+
+void launch_pauli_pairs(hipStream_t s, const double2* a, int nbits, unsigned long long x, unsigned long long z,
+                        int y, double* partials, int grid) {
+  hipLaunchKernelGGL(k_pauli_pairs, dim3(grid), dim3(kRedBlock), 0, s, a, nbits, x, z, y, partials);
+}
+
+int dm_pauli_grid(int n) {
+  const unsigned long long dim = 1ull << n;
+  const unsigned long long g = (dim + kRedBlock - 1) / kRedBlock;
+  return (int)(g < 256 ? g : 256);
+}
+
+void launch_dm_pauli(hipStream_t s, const double2* rho, int n, const TermDev* terms, int count, double* partials,
+                     int grid) {
+  hipLaunchKernelGGL(k_dm_pauli, dim3(grid), dim3(kRedBlock), 0, s, rho, n, terms, count, partials);
+}
+
+int sumsq_grid(unsigned long long len) {
+  const unsigned long long g = (len + kRedBlock * 4 - 1) / (kRedBlock * 4);
+  return (int)(g < 2048 ? g : 2048);
+}
+
+void launch_sumsq(hipStream_t s, const double2* a, unsigned long long len, double* partials, int grid) {
+  hipLaunchKernelGGL(k_sumsq<4>, dim3(grid), dim3(kRedBlock), 0, s, a, len, partials);
+}
+
+void launch_reduce_rows(hipStream_t s, const double* partials, int rows, int grid, const double* coeffs,
+                        double* out) {
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kRedBlock), 0, s, partials, rows, grid, coeffs, out);
+}
+
+}  // namespace nwq

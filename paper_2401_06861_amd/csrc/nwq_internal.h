@@ -1,0 +1,106 @@
+// Internal declarations shared by the engine's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nwq.h"
+
+namespace nwq {
+
+using cd = std::complex<double>;
+
+constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront width
+
+// Gate / superoperator matrices passed by value as kernel arguments.
+struct Mat2 { double2 m[4]; };       // 2x2, row-major
+struct Mat4 { double2 m[16]; };      // 4x4, row-major
+struct Diag4 { double2 d[4]; };      // diagonal entries indexed by u = b0 + 2 b1
+
+// Qubit set of a k-qubit dense kernel (k <= 4).
+struct QSet {
+  int sorted[4];                     // ascending positions (zero-insertion order)
+  unsigned long long off[4];         // 2^{q_j} in the operator's own order
+};
+
+// Streaming launch shape chosen by the autotuner (per kernel class).
+struct LaunchCfg {
+  int ppt = 4;                       // pairs / groups / elements per thread
+};
+
+// Kernel classes (also the timing classes of nwq_timing_read).
+enum KClass {
+  KC_RESET = 0, KC_SV1Q = 1, KC_DIAG = 2, KC_PERM = 3, KC_SV2Q = 4,
+  KC_FUSED = 5, KC_DM1 = 6, KC_DM2 = 7, KC_REDUCE = 8, KC_COUNT = 9
+};
+
+// ---- launchers (kernels_sv.hip) -------------------------------------------
+void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len);
+void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, int ppt);
+void launch_sv_diag(hipStream_t s, double2* a, int nbits, int q0, int q1, const Diag4& d, int ppt);
+void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, int ppt);
+void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb,
+                     unsigned long long offA, unsigned long long offB, int ppt);
+void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, int ppt);
+void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits,
+                  const double2* dev_matrix);
+
+// ---- reductions (kernels_reduce.hip) --------------------------------------
+// One pass of the tiled Pauli-term kernel.  `terms` is a device table of
+// `count` TermDev rows; partial sums go to partials[row * grid + block] with
+// row = first_row + term index.
+struct TermDev {
+  unsigned long long xl;    // x mask in tile-local bit positions
+  unsigned long long zl;    // z bits inside the tile, tile-local positions
+  unsigned long long zo;    // z bits outside the tile, global positions
+  int y;                    // popcount(x & z) mod 4
+  int pad;
+};
+struct TileShape {
+  int c;                    // low contiguous bits in the tile
+  int m;                    // number of high bits
+  int hi[8];                // the high bit positions, ascending
+};
+int pauli_tile_grid(int nbits, const TileShape& t);
+void launch_pauli_tile(hipStream_t s, const double2* a, int nbits, const TileShape& t,
+                       const TermDev* terms, int count, double* partials, int first_row, int grid);
+// One term with wide x support, pairs read from global memory; partials[block].
+void launch_pauli_pairs(hipStream_t s, const double2* a, int nbits, unsigned long long x, unsigned long long z,
+                        int y, double* partials, int grid);
+// DM: Tr(rho P_t) for each term, complex partials partials[(2*row + {0,1}) * grid + block].
+int dm_pauli_grid(int n);
+void launch_dm_pauli(hipStream_t s, const double2* rho, int n, const TermDev* terms, int count,
+                     double* partials, int grid);
+// sum |a_j|^2 over len entries into partials[block]
+int sumsq_grid(unsigned long long len);
+void launch_sumsq(hipStream_t s, const double2* a, unsigned long long len, double* partials, int grid);
+// out[r] = sum_b partials[r * grid + b] (fixed order); if coeffs: out[rows] = sum_r coeffs[r] out[r]
+void launch_reduce_rows(hipStream_t s, const double* partials, int rows, int grid,
+                        const double* coeffs, double* out);
+
+// ---- fused LDS blocks (kernels_fuse.hip) ----------------------------------
+struct FusedOp {            // one gate inside a fused block, tile-local bits
+  int kind;                 // 0: 1q dense, 1: 1q diag, 2: 2q dense, 3: 2q member swap, 4: 2q diag
+  int lo, hi;               // sorted tile-local bit positions (hi unused for 1q)
+  int o0, o1;               // kind 2: local offsets of q0, q1; kind 3: offsets swapped; kind 4: local bits of q0, q1
+  int mat;                  // start of its matrix in the block program's matrix table (double2 units)
+  int pad0, pad1;
+};
+struct FusedBlockDev {
+  int c, m;                 // tile = low c bits + m high bits
+  int hi[8];
+  int op_begin, op_count;   // range in the op table
+};
+void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk,
+                        const FusedOp* ops, const double2* mats, int lds_k);
+
+// ---- error handling (engine.hip) ------------------------------------------
+int set_error(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+}  // namespace nwq

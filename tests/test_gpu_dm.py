@@ -1,0 +1,163 @@
+"""GPU parity of the density-matrix path (Sec. II DM simulator, Sec. III
+noise model) against the oracle: gates on every qubit, every channel,
+arbitrary CPTP Kraus sets, the noisy TFIM circuit (n=8, 10 steps) with
+Tr(rho Z_i), purity and trace, and error handling.  Max abs entry error of
+rho <= 1e-12."""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gates as G, tensor
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def nwq():
+    from paper_2401_06861_amd import nwq as mod
+    return mod
+
+
+def maxerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))))
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 6])
+def test_gates_on_every_qubit(nwq, n):
+    rng = np.random.default_rng(n)
+    rho0 = W.random_density_matrix(n, seed=n)
+    st = nwq.DMState(n, reset=False)
+    for name, (nq, npar) in sorted(W.GATE_ARITY.items()):
+        if nq > n:
+            continue
+        qsets = [(q,) for q in range(n)] if nq == 1 else list(itertools.permutations(range(n), 2))
+        for qs in qsets:
+            ps = tuple(float(x) for x in rng.uniform(-math.pi, math.pi, npar))
+            st.load(rho0)
+            st.apply(name, qs, ps)
+            want = tensor.dm_apply(rho0, (name, qs, ps), n)
+            assert maxerr(st.numpy(), want) <= TOL, (name, qs)
+    st.close()
+
+
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_channels_on_every_qubit(nwq, n):
+    rho0 = W.random_density_matrix(n, seed=10 + n)
+    st = nwq.DMState(n, reset=False)
+    ops = []
+    for q in range(n):
+        ops += [("depolarize", (q,), (0.13,)), ("amp_damp", (q,), (0.21,)), ("phase_damp", (q,), (0.37,))]
+    for a, b in itertools.permutations(range(n), 2):
+        ops.append(("depolarize2", (a, b), (0.29,)))
+    for op in ops:
+        st.load(rho0)
+        st.run([op])
+        want = tensor.dm_apply(rho0, op, n)
+        assert maxerr(st.numpy(), want) <= TOL, op
+    st.close()
+
+
+def random_kraus(k, count, rng):
+    """CPTP set from a random isometry V (count*d x d): K_i = rows block i."""
+    d = 1 << k
+    A = rng.standard_normal((count * d, d)) + 1j * rng.standard_normal((count * d, d))
+    Q, _ = np.linalg.qr(A)
+    return [Q[i * d:(i + 1) * d, :] for i in range(count)]
+
+
+def test_generic_kraus_and_fused_gate_channel_runs(nwq):
+    n = 4
+    rng = np.random.default_rng(3)
+    rho0 = W.random_density_matrix(n, seed=3)
+    st = nwq.DMState(n, reset=False)
+    for qs, count in (([2], 3), ([0, 3], 5), ([3, 1], 2), ([1], 1)):
+        ks = random_kraus(len(qs), count, rng)
+        st.load(rho0)
+        st.channel(qs, ks)
+        want = tensor.dm_kraus(rho0, ks, qs, n)
+        assert maxerr(st.numpy(), want) <= TOL, qs
+    # gate followed by several channels on the same qubits (one fused pass),
+    # then a gate on other qubits (flush), compared op by op
+    ops = [("u3", (1,), (0.3, 1.2, -0.4)), ("depolarize", (1,), (0.1,)), ("amp_damp", (1,), (0.2,)),
+           ("phase_damp", (1,), (0.3,)), ("rzz", (0, 2), (0.7,)), ("depolarize2", (0, 2), (0.05,)),
+           ("cx", (3, 0), ()), ("amp_damp", (2,), (0.5,))]
+    st.load(rho0)
+    st.run(ops)
+    assert maxerr(st.numpy(), tensor.dm_run(ops, n, rho0)) <= TOL
+    st.close()
+
+
+def test_noisy_tfim_n8(nwq):
+    n = 8
+    ops = W.noisy_tfim_circuit(n, 10)
+    want = tensor.dm_run(ops, n)
+    gold = json.load(open(os.path.join(HERE, "golden", "tfim_dm_n8.json")))
+    st = nwq.DMState(n)
+    st.run(ops)
+    rho = st.numpy()
+    assert maxerr(rho, want) <= TOL
+    assert maxerr(rho, rho.conj().T) <= TOL
+    Z = st.expvals(W.single_site_terms(n, "Z"))
+    assert maxerr(Z, gold["Z"]) <= TOL
+    tr, tri = st.trace()
+    assert abs(tr - 1) <= TOL and abs(tri) <= 1e-13
+    assert abs(st.purity() - gold["purity"]) <= TOL
+    st.close()
+
+
+def test_dm_pauli_terms(nwq):
+    n = 5
+    rho = W.random_density_matrix(n, seed=21)
+    terms = W.random_pauli_sum(n, 30, seed=22)
+    st = nwq.DMState(n, reset=False)
+    st.load(rho)
+    got = st.expvals(terms)
+    want = np.array([tensor.dm_expval(rho, x, z, n).real for x, z, _ in terms])
+    assert maxerr(got, want) <= TOL
+    assert abs(st.pauli_sum(terms) - sum(c * w for (_, _, c), w in zip(terms, want))) <= TOL
+    st.close()
+
+
+def test_noise_free_dm_equals_sv_outer_product(nwq):
+    n = 6
+    gates = W.random_gate_list(n, 60, seed=5)
+    sv = nwq.SVState(n)
+    sv.run(gates)
+    psi = sv.numpy()
+    dm = nwq.DMState(n)
+    dm.run(gates)
+    assert maxerr(dm.numpy(), np.outer(psi, psi.conj())) <= TOL
+    sv.close()
+    dm.close()
+
+
+def test_dm_errors(nwq):
+    n = 3
+    rho0 = W.random_density_matrix(n, seed=2)
+    st = nwq.DMState(n, reset=False)
+    st.load(rho0)
+    bad = [np.eye(2) * 0.9]                    # not trace preserving
+    with pytest.raises(nwq.NwqError) as e:
+        st.channel([0], bad)
+    assert e.value.code == nwq.NWQ_ENOTCPTP
+    with pytest.raises(nwq.NwqError) as e:
+        st.channel([0, 0], [np.eye(4)])
+    assert e.value.code == nwq.NWQ_EDUP
+    with pytest.raises(nwq.NwqError) as e:
+        st.channel([3], [np.eye(2)])
+    assert e.value.code == nwq.NWQ_ERANGE
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_depolarize(st.h, [0], 1.5)
+    assert e.value.code == nwq.NWQ_EINVAL
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_set_fusion(st.h, 8)
+    assert e.value.code == nwq.NWQ_EKIND
+    assert maxerr(st.numpy(), rho0) == 0.0
+    st.close()
