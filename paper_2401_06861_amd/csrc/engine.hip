@@ -617,7 +617,7 @@ static std::vector<PassPlan> plan_pauli_passes(int n, int T, const uint64_t* xm)
       if ((hx >> b) & 1ull) bits.push_back(b);
     int chosen = -1;
     for (size_t p = 0; p < passes.size() && chosen < 0; ++p) {
-      if ((int)passes[p].terms.size() >= 64 || passes[p].shape.m < 0) continue;
+      if ((int)passes[p].terms.size() >= 16 || passes[p].shape.m < 0) continue;
       std::vector<int> u(passes[p].shape.hi, passes[p].shape.hi + passes[p].shape.m);
       for (int b : bits)
         if (std::find(u.begin(), u.end(), b) == u.end()) u.push_back(b);
@@ -645,6 +645,15 @@ static std::vector<PassPlan> plan_pauli_passes(int n, int T, const uint64_t* xm)
       pp.terms.push_back(t);
       passes.push_back(pp);
     }
+  }
+  // widen every tile to the full 2^(c + mmax) amplitudes with unused high bits
+  for (auto& pp : passes) {
+    if (pp.shape.m < 0) continue;
+    for (int b = c; b < n && pp.shape.m < mmax; ++b) {
+      if (std::find(pp.shape.hi, pp.shape.hi + pp.shape.m, b) == pp.shape.hi + pp.shape.m)
+        pp.shape.hi[pp.shape.m++] = b;
+    }
+    std::sort(pp.shape.hi, pp.shape.hi + pp.shape.m);
   }
   return passes;
 }

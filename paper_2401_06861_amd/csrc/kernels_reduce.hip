@@ -25,7 +25,7 @@ namespace {
 
 constexpr int kRedBlock = 256;
 constexpr int kRedWaves = kRedBlock / kWave;
-constexpr int kMaxTermsPerPass = 64;
+constexpr int kMaxTermsPerPass = 16;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -43,16 +43,33 @@ __device__ __forceinline__ unsigned long long scatter_local(unsigned l, int c, i
   return g;
 }
 
+// Per-term sums over tiles: each thread keeps one register accumulator per
+// term (up to TPL terms per launch) across all tiles it visits, so the wave
+// and workgroup reductions happen once per launch, not once per tile.
+template <int TPL>
 __global__ __launch_bounds__(kRedBlock) void k_pauli_tile(const double2* __restrict__ a, int nbits, TileShape t,
                                                           const TermDev* __restrict__ terms, int count,
                                                           double* __restrict__ partials, int first_row) {
   extern __shared__ double2 lds_tile[];
-  __shared__ double acc[kMaxTermsPerPass][kRedWaves];
+  __shared__ unsigned s_xl[TPL], s_zl[TPL], s_hb[TPL];
+  __shared__ int s_y[TPL];
+  __shared__ unsigned long long s_zo[TPL];
+  __shared__ double s_acc[TPL][kRedWaves];
   const int k = t.c + t.m;
   const unsigned tile_len = 1u << k;
   const unsigned long long ntiles = 1ull << (nbits - k);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < count * kRedWaves; i += kRedBlock) acc[i / kRedWaves][i % kRedWaves] = 0.0;
+  if ((int)threadIdx.x < count) {
+    const TermDev T = terms[threadIdx.x];
+    s_xl[threadIdx.x] = (unsigned)T.xl;
+    s_zl[threadIdx.x] = (unsigned)T.zl;
+    s_hb[threadIdx.x] = (unsigned)(T.xl & (~T.xl + 1ull));   // lowest flipped bit
+    s_y[threadIdx.x] = T.y & 3;
+    s_zo[threadIdx.x] = T.zo;
+  }
+  double acc[TPL];
+#pragma unroll
+  for (int i = 0; i < TPL; ++i) acc[i] = 0.0;
 
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     // base: tile index spread over the bits outside the tile (low c bits are inside)
@@ -64,48 +81,49 @@ __global__ __launch_bounds__(kRedBlock) void k_pauli_tile(const double2* __restr
         base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
       }
     }
-    __syncthreads();   // previous tile's readers are done
+    __syncthreads();   // previous tile's readers are done (and the term table is written)
     for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) lds_tile[l] = a[base | scatter_local(l, t.c, t.m, t)];
     __syncthreads();
-    for (int ti = 0; ti < count; ++ti) {
-      const TermDev T = terms[ti];
-      const int outer = __popcll(base & T.zo) & 1;
-      double s = 0.0;
-      if (T.xl == 0) {
-        for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) {
-          const double2 v = lds_tile[l];
-          const double w = fma(v.x, v.x, v.y * v.y);
-          s += ((__popcll(l & T.zl) + outer) & 1) ? -w : w;
-        }
-      } else {
-        const unsigned long long hbit = T.xl & (~T.xl + 1ull);   // lowest flipped bit
-        for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) {
-          if (l & hbit) continue;
-          const double2 v = lds_tile[l];
-          const double2 p = lds_tile[l ^ (unsigned)T.xl];
-          // w = conj(p) * v
-          const double wr = fma(p.x, v.x, p.y * v.y);
-          const double wi = fma(p.x, v.y, -p.y * v.x);
-          double r;   // Re(i^y w)
-          switch (T.y & 3) {
-            case 0: r = wr; break;
-            case 1: r = -wi; break;
-            case 2: r = -wr; break;
-            default: r = wi; break;
+    unsigned outer = 0;
+#pragma unroll
+    for (int ti = 0; ti < TPL; ++ti)
+      if (ti < count) outer |= (unsigned)(__popcll(base & s_zo[ti]) & 1) << ti;
+    for (unsigned l = threadIdx.x; l < tile_len; l += kRedBlock) {
+      const double2 v = lds_tile[l];
+      const double nv = fma(v.x, v.x, v.y * v.y);
+#pragma unroll
+      for (int ti = 0; ti < TPL; ++ti) {
+        if (ti < count) {
+          const unsigned xl = s_xl[ti];
+          double r = 0.0;
+          if (xl == 0u) {
+            r = nv;
+          } else if ((l & s_hb[ti]) == 0u) {
+            const double2 p = lds_tile[l ^ xl];
+            const double wr = fma(p.x, v.x, p.y * v.y);    // w = conj(p) v
+            const double wi = fma(p.x, v.y, -p.y * v.x);
+            const int y = s_y[ti];                           // Re(i^y w)
+            r = (y == 0) ? wr : (y == 1) ? -wi : (y == 2) ? -wr : wi;
+            r *= 2.0;
           }
-          r *= 2.0;
-          s += ((__popcll(l & T.zl) + outer) & 1) ? -r : r;
+          const unsigned sg = ((unsigned)__popc(l & s_zl[ti]) ^ (outer >> ti)) & 1u;
+          acc[ti] += sg ? -r : r;
         }
       }
-      s = wave_sum(s);
-      if (lane == 0) acc[ti][wave] += s;
+    }
+  }
+#pragma unroll
+  for (int ti = 0; ti < TPL; ++ti) {
+    if (ti < count) {
+      const double w = wave_sum(acc[ti]);
+      if (lane == 0) s_acc[ti][wave] = w;
     }
   }
   __syncthreads();
-  for (int ti = threadIdx.x; ti < count; ti += kRedBlock) {
+  if ((int)threadIdx.x < count) {
     double s = 0.0;
-    for (int w = 0; w < kRedWaves; ++w) s += acc[ti][w];
-    partials[(unsigned long long)(first_row + ti) * gridDim.x + blockIdx.x] = s;
+    for (int w = 0; w < kRedWaves; ++w) s += s_acc[threadIdx.x][w];
+    partials[(unsigned long long)(first_row + threadIdx.x) * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -244,7 +262,7 @@ int pauli_tile_grid(int nbits, const TileShape& t) {
 void launch_pauli_tile(hipStream_t s, const double2* a, int nbits, const TileShape& t, const TermDev* terms,
                        int count, double* partials, int first_row, int grid) {
   const size_t lds = sizeof(double2) << (t.c + t.m);
-  hipLaunchKernelGGL(k_pauli_tile, dim3(grid), dim3(kRedBlock), lds, s, a, nbits, t, terms, count, partials,
+  hipLaunchKernelGGL(k_pauli_tile<kMaxTermsPerPass>, dim3(grid), dim3(kRedBlock), lds, s, a, nbits, t, terms, count, partials,
                      first_row);
 }
 

@@ -13,6 +13,11 @@
 namespace nwq {
 namespace {
 
+// Clang vector of two doubles: a first-class 16-byte value that stays in
+// registers (HIP's double2 struct can take a round trip through scratch
+// when only copied).
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ unsigned long long insert0(unsigned long long p, int q) {
   const unsigned long long lo = p & ((1ull << q) - 1ull);
   return ((p >> q) << (q + 1)) | lo;
@@ -114,12 +119,13 @@ __global__ __launch_bounds__(kBlock) void k_sv_swap1(double2* __restrict__ a, un
 // control=1 pair; SWAP: |01> <-> |10>).  Only the moved half of the vector
 // is read and written.
 template <int PPT>
-__global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, unsigned long long nquads,
+__global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a2, unsigned long long nquads,
                                                      int qlo, int qhi, unsigned long long offA,
                                                      unsigned long long offB) {
+  vd2* __restrict__ a = reinterpret_cast<vd2*>(a2);
   const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
   if (start + (unsigned long long)(PPT - 1) * kBlock < nquads) {
-    double2 va[PPT], vb[PPT];
+    vd2 va[PPT], vb[PPT];
     unsigned long long b[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -137,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, un
       const unsigned long long p = start + (unsigned long long)j * kBlock;
       if (p >= nquads) break;
       const unsigned long long base = insert0(insert0(p, qlo), qhi);
-      const double2 x = a[base + offA], y = a[base + offB];
+      const vd2 x = a[base + offA], y = a[base + offB];
       a[base + offA] = y;
       a[base + offB] = x;
     }

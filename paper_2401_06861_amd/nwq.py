@@ -17,6 +17,11 @@ from typing import Iterable, Sequence, Tuple
 
 import numpy as np
 
+# torch ships its own HIP runtime with the same soname as the system one; it
+# must be loaded first so that libnwq.so binds to that single runtime instead
+# of pulling a second copy into the process.
+import torch  # noqa: F401
+
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnwq.so")
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"HIP engine not built ({_LIB_PATH} missing); run `python -m paper_2401_06861_amd.build`")
