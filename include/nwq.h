@@ -141,6 +141,15 @@ int nwq_set_fusion(nwq_handle h, int k, int* k_out);
  * gates (both 0 when fusion was off). */
 int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates);
 
+/* Host-only: the block plan nwq_apply_circuit would use for a circuit on n
+ * qubits at fusion width k (parameters are not needed).  Writes the number
+ * of blocks to *n_blocks, the block index of each gate to block_of_gate[]
+ * (n_gates entries), and, if block_qubits is non-NULL, each block's tile
+ * qubit mask as two 32-bit halves (2 * n_gates ints of room).  Touches no
+ * device. */
+int nwq_fusion_plan(int n, int k, int n_gates, const int* types, const int* qubits,
+                    int* n_blocks, int* block_of_gate, int* block_qubits);
+
 /* ---------------------------------------------------------------------------
  * Noise channels (Sec. III noise model; DM handles only, else NWQ_EKIND)
  * ------------------------------------------------------------------------- */

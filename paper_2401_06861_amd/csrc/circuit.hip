@@ -29,8 +29,10 @@ struct Block {
   std::vector<int> gates;    // indices into the circuit
 };
 
+// Every block has at least two high slots (c <= k - 2), so the first
+// remaining gate always fits and each round absorbs at least one gate.
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k) {
-  const int c = n <= k ? n : std::min(6, k);
+  const int c = n <= k ? n : std::min(6, k - 2);
   const int mmax = n <= k ? 0 : k - c;
   std::vector<int> rem(g.size());
   for (size_t i = 0; i < g.size(); ++i) rem[i] = (int)i;
@@ -68,6 +70,7 @@ std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k) {
           }
       }
     }
+    if (b.gates.empty()) return {};   // cannot happen with two high slots; caller reports it
     std::sort(H.begin(), H.end());
     b.m = (int)H.size();
     for (int i = 0; i < b.m; ++i) b.hi[i] = H[i];
@@ -88,6 +91,7 @@ int local_bit(const Block& b, int q) {
 
 static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   const std::vector<Block> blocks = plan_blocks(gates, h->n, h->fuse_k);
+  if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
   // Program: FusedOp table then double2 matrix table, in one upload.
   std::vector<FusedOp> ops;
   std::vector<double2> mats;
@@ -191,11 +195,10 @@ using namespace nwq;
 
 extern "C" {
 
-int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params) {
-  if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
-  if (n_gates < 0 || (n_gates > 0 && (!types || !qubits || !params))) return set_error(NWQ_EINVAL, "bad circuit arrays");
-  std::vector<PGate> gates(n_gates);
-  // validate everything before launching anything
+static int parse_circuit(int n, int n_gates, const int* types, const int* qubits, const double* params,
+                         bool need_params, std::vector<PGate>& gates) {
+  if (n_gates < 0 || (n_gates > 0 && (!types || !qubits))) return set_error(NWQ_EINVAL, "bad circuit arrays");
+  gates.assign(n_gates, PGate{});
   for (int i = 0; i < n_gates; ++i) {
     PGate& g = gates[i];
     g.type = types[i];
@@ -212,13 +215,23 @@ int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qu
     g.nq = nq;
     g.q[0] = qubits[2 * i];
     g.q[1] = nq == 2 ? qubits[2 * i + 1] : -1;
-    for (int j = 0; j < 3; ++j) g.p[j] = params[3 * i + j];
+    for (int j = 0; j < 3; ++j) g.p[j] = params ? params[3 * i + j] : 0.0;
+    if (np > 0 && need_params && params == nullptr) return set_error(NWQ_EINVAL, "params pointer is NULL");
     for (int j = 0; j < np; ++j)
       if (!std::isfinite(g.p[j])) return set_error(NWQ_EINVAL, "gate " + std::to_string(i) + ": non-finite parameter");
     for (int j = 0; j < nq; ++j)
-      if (g.q[j] < 0 || g.q[j] >= h->n) return set_error(NWQ_ERANGE, "gate " + std::to_string(i) + ": qubit out of range");
+      if (g.q[j] < 0 || g.q[j] >= n) return set_error(NWQ_ERANGE, "gate " + std::to_string(i) + ": qubit out of range");
     if (nq == 2 && g.q[0] == g.q[1]) return set_error(NWQ_EDUP, "gate " + std::to_string(i) + ": repeated qubit");
   }
+  return NWQ_OK;
+}
+
+int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params) {
+  if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
+  std::vector<PGate> gates;
+  // validate everything before launching anything
+  int rc0 = parse_circuit(h->n, n_gates, types, qubits, params, true, gates);
+  if (rc0) return rc0;
   h->last_blocks = 0;
   h->last_fused_gates = 0;
   if (h->kind == NWQ_KIND_SV && h->fuse_k > 0 && n_gates > 0) return apply_fused(h, gates);
@@ -242,6 +255,29 @@ int nwq_set_fusion(nwq_handle h, int k, int* k_out) {
   if (h->kind != NWQ_KIND_SV && k != 0) return set_error(NWQ_EKIND, "fusion applies to state-vector handles");
   h->fuse_k = k;
   if (k_out) *k_out = k;
+  return NWQ_OK;
+}
+
+int nwq_fusion_plan(int n, int k, int n_gates, const int* types, const int* qubits, int* n_blocks,
+                    int* block_of_gate, int* block_qubits) {
+  if (n < 1 || n > 34) return set_error(NWQ_ERANGE, "n outside [1, 34]");
+  if (k < 6 || k > 13) return set_error(NWQ_EINVAL, "fusion width must be in [6, 13]");
+  if (!n_blocks || (n_gates > 0 && !block_of_gate)) return set_error(NWQ_EINVAL, "NULL output pointer");
+  std::vector<PGate> gates;
+  int rc = parse_circuit(n, n_gates, types, qubits, nullptr, false, gates);
+  if (rc) return rc;
+  const std::vector<Block> blocks = plan_blocks(gates, n, k);
+  if (n_gates > 0 && blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
+  *n_blocks = (int)blocks.size();
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    for (int gi : blocks[b].gates) block_of_gate[gi] = (int)b;
+    if (block_qubits) {
+      unsigned long long mask = (1ull << blocks[b].c) - 1ull;
+      for (int i = 0; i < blocks[b].m; ++i) mask |= 1ull << blocks[b].hi[i];
+      block_qubits[2 * b] = (int)(mask & 0xffffffffull);
+      block_qubits[2 * b + 1] = (int)(mask >> 32);
+    }
+  }
   return NWQ_OK;
 }
 

@@ -64,6 +64,7 @@ _SIG = {
     "nwq_apply_circuit": [_h, C.c_int, _ip, _ip, _dp],
     "nwq_set_fusion": [_h, C.c_int, _ip],
     "nwq_fusion_stats": [_h, _ip, _ip],
+    "nwq_fusion_plan": [C.c_int, C.c_int, C.c_int, _ip, _ip, _ip, _ip, _ip],
     "nwq_apply_channel": [_h, _ip, C.c_int, _dp, C.c_int],
     "nwq_depolarize": [_h, _ip, C.c_int, C.c_double],
     "nwq_amp_damp": [_h, C.c_int, C.c_double],
@@ -201,6 +202,20 @@ def nwq_fusion_stats(h: int) -> Tuple[int, int]:
     b, g = C.c_int(), C.c_int()
     _check(lib.nwq_fusion_stats(h, C.byref(b), C.byref(g)))
     return b.value, g.value
+
+
+def nwq_fusion_plan(n: int, k: int, types: np.ndarray, qubits: np.ndarray):
+    """(n_blocks, block_of_gate[], tile qubit mask per block) without a device."""
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    qubits = np.ascontiguousarray(qubits, dtype=np.int32)
+    g = len(types)
+    nb = C.c_int()
+    bog = np.zeros(max(g, 1), dtype=np.int32)
+    bq = np.zeros(2 * max(g, 1), dtype=np.int32)
+    _check(lib.nwq_fusion_plan(n, k, g, types.ctypes.data_as(_ip), qubits.ctypes.data_as(_ip), C.byref(nb),
+                               bog.ctypes.data_as(_ip), bq.ctypes.data_as(_ip)))
+    masks = [(int(bq[2 * b]) & 0xffffffff) | ((int(bq[2 * b + 1]) & 0xffffffff) << 32) for b in range(nb.value)]
+    return nb.value, bog[:g], masks
 
 
 def nwq_apply_channel(h: int, qubits: Sequence[int], kraus: Sequence[np.ndarray]) -> None:
