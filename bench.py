@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--fuse-k", type=int, default=12)
     ap.add_argument("--no-extras", action="store_true", help="only the timed step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-vqe", action="store_true", help="skip the batched VQE leg")
+    ap.add_argument("--vqe-sizes", default="8:4,12:8,16:8,20:8", help="n:L pairs for the VQE leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-mode", choices=["trace", "pmc"], default=None)
     return ap.parse_args()
@@ -210,6 +212,8 @@ def main():
         del st, psi
         torch.cuda.empty_cache()
         out["dm_noisy_gate_n14"] = dm_leg(nwq, torch)
+    if not args.no_extras and not args.no_vqe:
+        out["vqe"] = vqe_leg(torch)
     if not args.no_cpu:
         log("[bench] cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
@@ -293,6 +297,54 @@ def dm_leg(nwq, torch):
         out[label] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
     st.close()
     return out
+
+
+def vqe_leg(torch, sizes=None, B=256):
+    """Energy + full adjoint gradient for B parameter vectors on the batched
+    path (autotuned) against the plain per-circuit path (one vector at a time,
+    one kernel per gate, no graph)."""
+    import workloads as W
+    from paper_2401_06861_amd import vqe as V
+    sizes = sizes or [tuple(int(x) for x in p.split(":")) for p in parse().vqe_sizes.split(",")]
+    res = {}
+    for n, L in sizes:
+        log(f"[bench] vqe n={n} L={L}")
+        prog = W.hea_ansatz(n, L)
+        theta, h = W.vqe_batch(n, L, B=B)
+        ctx = V.VQE(n, prog, W.tfim_hamiltonian(n, 1.0, h))
+        t = torch.from_numpy(theta).cuda()
+        tune_B = B if n <= 16 else 32
+        ctx.autotune(tune_B)
+        cfg = ctx.get_config()
+        E, G = ctx.eval(t)
+        torch.cuda.synchronize()
+        reps = 3 if n <= 16 else 1
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E, G = ctx.eval(t)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        k = 16 if n <= 12 else 4
+        Es = []
+        ctx.eval_single(t[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(k):
+            e1, g1 = ctx.eval_single(t[b])
+            Es.append(e1)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / k
+        dE = max(abs(Es[b].item() - E[b].item()) for b in range(k))
+        dG = float(torch.max(torch.abs(g1[0] - G[k - 1])).item())
+        res[f"n{n}_L{L}"] = {"B": B, "batched_evals_per_s": round(B / tb, 1), "batched_ms": round(tb * 1e3, 3),
+                             "single_evals_per_s": round(1.0 / ts, 1), "speedup": round(ts * B / tb, 2),
+                             "config": {"mode": ["auto", "lds", "per_gate_graph"][cfg[0]], "threads": cfg[1],
+                                        "blocks_per_state": cfg[2]},
+                             "max_abs_dE_batched_vs_single": dE, "max_abs_dgrad": dG}
+        ctx.close()
+        del t, E, G
+        torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -188,6 +188,53 @@ int nwq_trace(nwq_handle h, double* out, double* imag_out);
 int nwq_purity(nwq_handle h, double* out);
 
 /* ---------------------------------------------------------------------------
+ * VQE energies and adjoint gradients (Sec. III, Fig. 4: VQE for the Ising
+ * model).  Gradients follow adjoint differentiation (Jones & Gacon,
+ * arXiv:2009.02823): one backward sweep of U_k^dag over (phi, H phi).
+ * ------------------------------------------------------------------------- */
+
+typedef struct nwq_vqe* nwq_vqe_handle;
+
+/* Build a VQE context for an n-qubit register (1 <= n <= 30) starting from
+ * |0...0>.  The program has n_ops gates: types[i] (nwq_gate), qubits[2i],
+ * qubits[2i+1] (second entry ignored for 1-qubit gates) and params[i], the
+ * index into theta (0 <= params[i] < n_params) for the parametrised types RX,
+ * RY, RZ, RZZ (each exp(-i theta P / 2)); params[i] is ignored for the fixed
+ * types I X Y Z H S SDG T TDG CX CZ SWAP (U3 is not allowed).  The
+ * Hamiltonian is sum_t coeffs[t] P_t over n_terms Pauli strings (xmask,
+ * zmask).  Host arrays are copied.  The context owns a HIP stream of its own;
+ * evaluations are ordered after prior work on `hip_stream` and later work on
+ * `hip_stream` is ordered after them. */
+int nwq_vqe_create(int n, int n_ops, const int* types, const int* qubits, const int* params,
+                   int n_params, int n_terms, const uint64_t* xmask, const uint64_t* zmask,
+                   const double* coeffs, void* hip_stream, nwq_vqe_handle* out);
+int nwq_vqe_destroy(nwq_vqe_handle h);
+int nwq_vqe_info(nwq_vqe_handle h, int* n_params, int* n_ops, int* n_slots);
+
+/* Batched path: B parameter vectors theta_dev[B][n_params] (device, FP64)
+ * -> energy_dev[B] and, if grad_dev is non-NULL, grad_dev[B][n_params]
+ * (device).  n <= 12 runs one persistent LDS-resident kernel (one workgroup
+ * per vector); larger n run the per-gate schedule over all B states,
+ * captured once per (B, with/without gradient) into a hipGraph and replayed.
+ * Results for a vector do not depend on B or on the other vectors. */
+int nwq_vqe_eval(nwq_vqe_handle h, int B, const double* theta_dev, double* energy_dev, double* grad_dev);
+
+/* Plain per-circuit path (the reference point for the batched path): one
+ * vector, one kernel per gate, no graph, no LDS residency. */
+int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energy_dev, double* grad_dev);
+
+/* Launch configuration: mode 0 = automatic, 1 = LDS-resident (n <= 12),
+ * 2 = per-gate graph; threads per workgroup of the LDS kernel (64..1024,
+ * power of two); blocks per state of the per-gate kernels (0 = default). */
+int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_state);
+int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_per_state);
+
+/* Autotuner: times every valid (mode, threads, blocks_per_state) candidate on
+ * B zero parameter vectors with HIP events, keeps the fastest and returns
+ * its time per batch in *best_ms.  Synchronises. */
+int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 

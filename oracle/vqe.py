@@ -9,8 +9,8 @@ independent ways:
   applied per gate occurrence so shared parameters are summed;
 * central finite differences with step h.
 
-The circuit is simulated with tier 0 (dense) for n <= 12 and tier 1 (tensor
-contractions) above.
+The circuit is simulated with tier 0 (dense) for n <= 6 and tier 1 (tensor
+contractions, pinned to tier 0) above.
 """
 from __future__ import annotations
 
@@ -22,14 +22,17 @@ import numpy as np
 from . import dense, tensor
 
 
+DENSE_MAX_N = 6   # tier 0 up to here, tier 1 (pinned to tier 0) above
+
+
 def _run(gates, n):
-    if n <= dense.SV_MAX_N and n <= 10:
+    if n <= DENSE_MAX_N:
         return dense.sv_run(gates, n)
     return tensor.sv_run(gates, n)
 
 
 def _pauli_sum(psi, terms, n):
-    if n <= 10:
+    if n <= DENSE_MAX_N:
         return dense.sv_pauli_sum(psi, terms, n)
     return tensor.sv_pauli_sum(psi, terms, n)
 

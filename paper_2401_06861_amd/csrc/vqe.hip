@@ -1,0 +1,841 @@
+// VQE energies and adjoint gradients for batches of parameter vectors.
+//
+// The VQE experiment of the paper (Sec. III, Fig. 4) evaluates
+// E(theta) = <psi(theta)|H|psi(theta)> for a parametrised circuit.  Here the
+// gradient is computed by adjoint differentiation (Jones & Gacon,
+// arXiv:2009.02823): with phi = U_G...U_1|0>, lambda = H phi, E = Re<phi|lambda>,
+// then for k = G..1:  g_k = Im<lambda|P_k|phi>  (for U_k = exp(-i theta P_k/2)),
+// phi <- U_k^dag phi,  lambda <- U_k^dag lambda.
+//
+// Two execution paths share the op encoding:
+//  * LDS-resident (n <= 12): one workgroup owns one theta vector and keeps
+//    phi and lambda in LDS for the whole forward pass, H application and
+//    backward sweep; a persistent grid walks the batch.  One launch per batch.
+//  * Global (any n): one launch per gate over all B states (blockIdx.y = batch
+//    element), phi and lambda in HBM, gradient partials per (state, gate, block)
+//    reduced in a fixed order; the whole schedule is captured once per batch
+//    size in a hipGraph and replayed.  With B = 1 and no graph this is the
+//    plain per-circuit path.
+// Every reduction has a fixed order that does not depend on B, so a theta
+// vector gives bit-identical results alone or inside any batch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "engine.h"
+
+namespace nwq {
+
+enum VqeKind { OP_ROT = 0, OP_RZZ = 1, OP_FIX1 = 2, OP_CX = 3, OP_CZ = 4, OP_SWAP = 5 };
+
+struct VqeOp {
+  int kind;
+  int q0, q1;
+  int param;   // theta index (OP_ROT, OP_RZZ), else -1
+  int axis;    // OP_ROT: 0 X, 1 Y, 2 Z
+  int slot;    // gradient slot (ordinal among parametrised ops), else -1
+  int mat;     // OP_FIX1: index into the fixed-matrix table (8 double2: U then U^dag)
+  int pad;
+};
+
+struct VqeTerm {
+  unsigned long long x, z;
+  double c;
+  int y;       // popcount(x & z) mod 4
+  int pad;
+};
+
+namespace {
+
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned ins0(unsigned p, int q) { return ((p >> q) << (q + 1)) | (p & ((1u << q) - 1u)); }
+__device__ __forceinline__ unsigned long long ins0l(unsigned long long p, int q) {
+  return ((p >> q) << (q + 1)) | (p & ((1ull << q) - 1ull));
+}
+__device__ __forceinline__ vd2 mk(double a, double b) { vd2 r; r.x = a; r.y = b; return r; }
+__device__ __forceinline__ vd2 cmul(vd2 a, vd2 b) { return mk(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)); }
+__device__ __forceinline__ vd2 cfma(vd2 a, vd2 b, vd2 c) {
+  return mk(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ vd2 ld(const double2* p) { return *reinterpret_cast<const vd2*>(p); }
+__device__ __forceinline__ void st(double2* p, vd2 v) { *reinterpret_cast<vd2*>(p) = v; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// 2x2 matrix of an op for the current theta (dag: adjoint).  For rotations
+// exp(-i t P/2) the adjoint is the rotation by -t.
+struct M2 { vd2 m0, m1, m2, m3; };
+
+__device__ __forceinline__ M2 op_matrix(const VqeOp& op, const double* th, const double2* fixed, bool dag) {
+  M2 r;
+  if (op.kind == OP_ROT) {
+    double s, c;
+    sincos(0.5 * th[op.param], &s, &c);
+    if (dag) s = -s;
+    if (op.axis == 0) { r.m0 = mk(c, 0); r.m1 = mk(0, -s); r.m2 = mk(0, -s); r.m3 = mk(c, 0); }
+    else if (op.axis == 1) { r.m0 = mk(c, 0); r.m1 = mk(-s, 0); r.m2 = mk(s, 0); r.m3 = mk(c, 0); }
+    else { r.m0 = mk(c, -s); r.m1 = mk(0, 0); r.m2 = mk(0, 0); r.m3 = mk(c, s); }
+  } else {
+    const double2* f = fixed + 8 * op.mat + (dag ? 4 : 0);
+    r.m0 = ld(f); r.m1 = ld(f + 1); r.m2 = ld(f + 2); r.m3 = ld(f + 3);
+  }
+  return r;
+}
+
+// RZZ: diagonal e^{-i t/2} (even parity), e^{+i t/2} (odd parity)
+__device__ __forceinline__ void rzz_phases(const VqeOp& op, const double* th, bool dag, vd2& even, vd2& odd) {
+  double s, c;
+  sincos(0.5 * th[op.param], &s, &c);
+  if (dag) s = -s;
+  even = mk(c, -s);
+  odd = mk(c, s);
+}
+
+// Contribution Im( conj(l0) (P phi)_0 + conj(l1) (P phi)_1 ) of one pair for a
+// single-qubit Pauli generator on the pair's qubit.
+__device__ __forceinline__ double pair_grad(int axis, vd2 p0, vd2 p1, vd2 l0, vd2 l1) {
+  vd2 a, b;                      // (P phi)_0, (P phi)_1
+  if (axis == 0) { a = p1; b = p0; }
+  else if (axis == 1) { a = mk(p1.y, -p1.x); b = mk(-p0.y, p0.x); }   // -i p1, i p0
+  else { a = p0; b = mk(-p1.x, -p1.y); }
+  // Im(conj(l) * a) = l.x a.y - l.y a.x
+  return (l0.x * a.y - l0.y * a.x) + (l1.x * b.y - l1.y * b.x);
+}
+
+// ---------------------------------------------------------------------------
+// Gate application on one state held in LDS (or in global memory for the
+// per-gate path: same code, different pointer).  Threads tid..nt stride.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void apply_op_state(double2* v, int n, const VqeOp& op, const double* th, const double2* fixed, bool dag,
+                               unsigned tid, unsigned nt) {
+  const unsigned N = 1u << n;
+  switch (op.kind) {
+    case OP_ROT:
+    case OP_FIX1: {
+      const M2 m = op_matrix(op, th, fixed, dag);
+      const unsigned off = 1u << op.q0;
+      for (unsigned p = tid; p < (N >> 1); p += nt) {
+        const unsigned i0 = ins0(p, op.q0);
+        const vd2 a = ld(v + i0), b = ld(v + i0 + off);
+        st(v + i0, cfma(m.m0, a, cmul(m.m1, b)));
+        st(v + i0 + off, cfma(m.m2, a, cmul(m.m3, b)));
+      }
+      break;
+    }
+    case OP_RZZ: {
+      vd2 e, o;
+      rzz_phases(op, th, dag, e, o);
+      for (unsigned j = tid; j < N; j += nt) {
+        const unsigned par = ((j >> op.q0) ^ (j >> op.q1)) & 1u;
+        st(v + j, cmul(par ? o : e, ld(v + j)));
+      }
+      break;
+    }
+    case OP_CZ: {
+      for (unsigned j = tid; j < N; j += nt)
+        if (((j >> op.q0) & (j >> op.q1)) & 1u) { const vd2 x = ld(v + j); st(v + j, mk(-x.x, -x.y)); }
+      break;
+    }
+    default: {   // OP_CX (control q0, target q1) or OP_SWAP: exchange two members of each quad
+      const int lo = min(op.q0, op.q1), hi = max(op.q0, op.q1);
+      const unsigned oa = op.kind == OP_CX ? (1u << op.q0) : (1u << op.q0);
+      const unsigned ob = op.kind == OP_CX ? (1u << op.q0) + (1u << op.q1) : (1u << op.q1);
+      for (unsigned p = tid; p < (N >> 2); p += nt) {
+        const unsigned b = ins0(ins0(p, lo), hi);
+        const vd2 x = ld(v + b + oa), y = ld(v + b + ob);
+        st(v + b + oa, y);
+        st(v + b + ob, x);
+      }
+      break;
+    }
+  }
+}
+
+// One backward step on (phi, lam): returns this thread's gradient partial
+// (0 for unparametrised ops) and applies U^dag to both states.
+__device__ __forceinline__ double adjoint_step(double2* phi, double2* lam, int n, const VqeOp& op, const double* th,
+                               const double2* fixed, unsigned tid, unsigned nt) {
+  const unsigned N = 1u << n;
+  double g = 0.0;
+  if (op.kind == OP_ROT) {
+    const M2 m = op_matrix(op, th, fixed, true);
+    const unsigned off = 1u << op.q0;
+    for (unsigned p = tid; p < (N >> 1); p += nt) {
+      const unsigned i0 = ins0(p, op.q0);
+      const vd2 p0 = ld(phi + i0), p1 = ld(phi + i0 + off);
+      const vd2 l0 = ld(lam + i0), l1 = ld(lam + i0 + off);
+      g += pair_grad(op.axis, p0, p1, l0, l1);
+      st(phi + i0, cfma(m.m0, p0, cmul(m.m1, p1)));
+      st(phi + i0 + off, cfma(m.m2, p0, cmul(m.m3, p1)));
+      st(lam + i0, cfma(m.m0, l0, cmul(m.m1, l1)));
+      st(lam + i0 + off, cfma(m.m2, l0, cmul(m.m3, l1)));
+    }
+  } else if (op.kind == OP_RZZ) {
+    vd2 e, o;
+    rzz_phases(op, th, true, e, o);
+    for (unsigned j = tid; j < N; j += nt) {
+      const unsigned par = ((j >> op.q0) ^ (j >> op.q1)) & 1u;
+      const vd2 p = ld(phi + j), l = ld(lam + j);
+      const double t = l.x * p.y - l.y * p.x;   // Im(conj(l) p), generator Z Z = +-1
+      g += par ? -t : t;
+      st(phi + j, cmul(par ? o : e, p));
+      st(lam + j, cmul(par ? o : e, l));
+    }
+  } else {
+    apply_op_state(phi, n, op, th, fixed, true, tid, nt);
+    apply_op_state(lam, n, op, th, fixed, true, tid, nt);
+  }
+  return g;
+}
+
+// (H phi)_j = sum_t c_t i^y (-1)^{|(j^x)&z|} phi_{j^x}
+__device__ __forceinline__ vd2 h_apply_at(const double2* phi, unsigned long long j, const VqeTerm* terms, int nterms) {
+  vd2 acc = mk(0.0, 0.0);
+  for (int t = 0; t < nterms; ++t) {
+    const VqeTerm T = terms[t];
+    const unsigned long long k = j ^ T.x;
+    vd2 v = ld(phi + k);
+    switch (T.y & 3) {
+      case 1: v = mk(-v.y, v.x); break;
+      case 2: v = mk(-v.x, -v.y); break;
+      case 3: v = mk(v.y, -v.x); break;
+      default: break;
+    }
+    const double c = (__popcll(k & T.z) & 1) ? -T.c : T.c;
+    acc.x = fma(c, v.x, acc.x);
+    acc.y = fma(c, v.y, acc.y);
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident persistent kernel (n <= 12)
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_vqe_lds(int n, const VqeOp* __restrict__ ops, int nops,
+                                                const double2* __restrict__ fixed, const VqeTerm* __restrict__ terms,
+                                                int nterms, int nslots, const int* __restrict__ slot_param,
+                                                const double* __restrict__ theta, int P, int B,
+                                                double* __restrict__ E, double* __restrict__ grad) {
+  extern __shared__ double2 lds[];
+  constexpr int NW = NT / kWave;
+  const unsigned N = 1u << n;
+  double2* phi = lds;
+  double2* lam = lds + N;
+  double* red = reinterpret_cast<double*>(grad ? lds + 2 * N : lds + N);   // [NW] scratch
+  double* gpart = red + NW;                                              // [nslots][NW]
+  const unsigned tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const double* th = theta + (size_t)b * P;
+    __syncthreads();
+    for (unsigned j = tid; j < N; j += NT) phi[j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    for (int i = 0; i < nops; ++i) {
+      apply_op_state(phi, n, ops[i], th, fixed, false, tid, NT);
+      __syncthreads();
+    }
+    // lambda = H phi and E = Re <phi|lambda>
+    double e = 0.0;
+    for (unsigned j = tid; j < N; j += NT) {
+      const vd2 l = h_apply_at(phi, j, terms, nterms);
+      const vd2 p = ld(phi + j);
+      e += p.x * l.x + p.y * l.y;
+      if (grad) st(lam + j, l);
+    }
+    e = wave_sum(e);
+    if (lane == 0) red[wave] = e;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[w];
+      E[b] = s;
+    }
+    if (!grad) continue;
+    for (int i = nops - 1; i >= 0; --i) {
+      const VqeOp op = ops[i];
+      const double g = adjoint_step(phi, lam, n, op, th, fixed, tid, NT);
+      if (op.slot >= 0) {
+        const double w = wave_sum(g);
+        if (lane == 0) gpart[op.slot * NW + wave] = w;
+      }
+      __syncthreads();
+    }
+    // grad[b][p] = sum over the slots of p (slot order) of the wave partials (wave order)
+    if (tid == 0) {
+      for (int p = 0; p < P; ++p) grad[(size_t)b * P + p] = 0.0;
+      for (int s = 0; s < nslots; ++s) {
+        double v = 0.0;
+        for (int w = 0; w < NW; ++w) v += gpart[s * NW + w];
+        grad[(size_t)b * P + slot_param[s]] += v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Global per-gate kernels: grid (blocks per state, B)
+// ---------------------------------------------------------------------------
+constexpr int kVqeBlock = 256;
+
+__global__ __launch_bounds__(kVqeBlock) void k_vqe_init(double2* __restrict__ phi, int n) {
+  const unsigned long long N = 1ull << n;
+  double2* v = phi + (size_t)blockIdx.y * N;
+  for (unsigned long long j = (unsigned long long)blockIdx.x * kVqeBlock + threadIdx.x; j < N;
+       j += (unsigned long long)gridDim.x * kVqeBlock)
+    v[j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(kVqeBlock) void k_vqe_gate(double2* __restrict__ states, int n, VqeOp op,
+                                                        const double2* __restrict__ fixed,
+                                                        const double* __restrict__ theta, int P, int dag) {
+  const unsigned long long N = 1ull << n;
+  double2* v = states + (size_t)blockIdx.y * N;
+  const double* th = theta + (size_t)blockIdx.y * P;
+  const unsigned long long tid = (unsigned long long)blockIdx.x * kVqeBlock + threadIdx.x;
+  const unsigned long long nt = (unsigned long long)gridDim.x * kVqeBlock;
+  switch (op.kind) {
+    case OP_ROT:
+    case OP_FIX1: {
+      const M2 m = op_matrix(op, th, fixed, dag != 0);
+      const unsigned long long off = 1ull << op.q0;
+      for (unsigned long long p = tid; p < (N >> 1); p += nt) {
+        const unsigned long long i0 = ins0l(p, op.q0);
+        const vd2 a = ld(v + i0), b = ld(v + i0 + off);
+        st(v + i0, cfma(m.m0, a, cmul(m.m1, b)));
+        st(v + i0 + off, cfma(m.m2, a, cmul(m.m3, b)));
+      }
+      break;
+    }
+    case OP_RZZ: {
+      vd2 e, o;
+      rzz_phases(op, th, dag != 0, e, o);
+      for (unsigned long long j = tid; j < N; j += nt) {
+        const unsigned par = (unsigned)(((j >> op.q0) ^ (j >> op.q1)) & 1ull);
+        st(v + j, cmul(par ? o : e, ld(v + j)));
+      }
+      break;
+    }
+    case OP_CZ:
+      for (unsigned long long j = tid; j < N; j += nt)
+        if (((j >> op.q0) & (j >> op.q1)) & 1ull) { const vd2 x = ld(v + j); st(v + j, mk(-x.x, -x.y)); }
+      break;
+    default: {
+      const int lo = min(op.q0, op.q1), hi = max(op.q0, op.q1);
+      const unsigned long long oa = 1ull << op.q0;
+      const unsigned long long ob = op.kind == OP_CX ? (1ull << op.q0) + (1ull << op.q1) : (1ull << op.q1);
+      for (unsigned long long p = tid; p < (N >> 2); p += nt) {
+        const unsigned long long b = ins0l(ins0l(p, lo), hi);
+        const vd2 x = ld(v + b + oa), y = ld(v + b + ob);
+        st(v + b + oa, y);
+        st(v + b + ob, x);
+      }
+      break;
+    }
+  }
+}
+
+// lambda = H phi, energy partials epart[b * G + block]
+__global__ __launch_bounds__(kVqeBlock) void k_vqe_hphi(const double2* __restrict__ phi, double2* __restrict__ lam,
+                                                        int n, const VqeTerm* __restrict__ terms, int nterms,
+                                                        double* __restrict__ epart, int store_lam) {
+  __shared__ double red[kVqeBlock / kWave];
+  const unsigned long long N = 1ull << n;
+  const double2* p = phi + (size_t)blockIdx.y * N;
+  double2* l = lam + (size_t)blockIdx.y * N;
+  double e = 0.0;
+  for (unsigned long long j = (unsigned long long)blockIdx.x * kVqeBlock + threadIdx.x; j < N;
+       j += (unsigned long long)gridDim.x * kVqeBlock) {
+    const vd2 h = h_apply_at(p, j, terms, nterms);
+    const vd2 v = ld(p + j);
+    e += v.x * h.x + v.y * h.y;
+    if (store_lam) st(l + j, h);
+  }
+  e = wave_sum(e);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kVqeBlock / kWave; ++w) s += red[w];
+    epart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Backward step over all states; gradient partials gpart[(b * nslots + slot) * G + block]
+__global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__ phi, double2* __restrict__ lam,
+                                                           int n, VqeOp op, const double2* __restrict__ fixed,
+                                                           const double* __restrict__ theta, int P, int nslots,
+                                                           double* __restrict__ gpart) {
+  __shared__ double red[kVqeBlock / kWave];
+  const unsigned long long N = 1ull << n;
+  double2* pv = phi + (size_t)blockIdx.y * N;
+  double2* lv = lam + (size_t)blockIdx.y * N;
+  const double* th = theta + (size_t)blockIdx.y * P;
+  const unsigned long long tid = (unsigned long long)blockIdx.x * kVqeBlock + threadIdx.x;
+  const unsigned long long nt = (unsigned long long)gridDim.x * kVqeBlock;
+  double g = 0.0;
+  if (op.kind == OP_ROT) {
+    const M2 m = op_matrix(op, th, fixed, true);
+    const unsigned long long off = 1ull << op.q0;
+    for (unsigned long long p = tid; p < (N >> 1); p += nt) {
+      const unsigned long long i0 = ins0l(p, op.q0);
+      const vd2 p0 = ld(pv + i0), p1 = ld(pv + i0 + off);
+      const vd2 l0 = ld(lv + i0), l1 = ld(lv + i0 + off);
+      g += pair_grad(op.axis, p0, p1, l0, l1);
+      st(pv + i0, cfma(m.m0, p0, cmul(m.m1, p1)));
+      st(pv + i0 + off, cfma(m.m2, p0, cmul(m.m3, p1)));
+      st(lv + i0, cfma(m.m0, l0, cmul(m.m1, l1)));
+      st(lv + i0 + off, cfma(m.m2, l0, cmul(m.m3, l1)));
+    }
+  } else {   // OP_RZZ
+    vd2 e, o;
+    rzz_phases(op, th, true, e, o);
+    for (unsigned long long j = tid; j < N; j += nt) {
+      const unsigned par = (unsigned)(((j >> op.q0) ^ (j >> op.q1)) & 1ull);
+      const vd2 p = ld(pv + j), l = ld(lv + j);
+      const double t = l.x * p.y - l.y * p.x;
+      g += par ? -t : t;
+      st(pv + j, cmul(par ? o : e, p));
+      st(lv + j, cmul(par ? o : e, l));
+    }
+  }
+  g = wave_sum(g);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = g;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kVqeBlock / kWave; ++w) s += red[w];
+    gpart[((size_t)blockIdx.y * nslots + op.slot) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// E[b] = sum_blocks epart; grad[b][p] = sum over slots of p (slot order) of
+// the block partials (block order).  One thread per batch element.
+__global__ __launch_bounds__(64) void k_vqe_finish(const double* __restrict__ epart, const double* __restrict__ gpart,
+                                                   int G, int nslots, const int* __restrict__ slot_param, int P,
+                                                   int B, double* __restrict__ E, double* __restrict__ grad) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= B) return;
+  double e = 0.0;
+  for (int k = 0; k < G; ++k) e += epart[(size_t)b * G + k];
+  E[b] = e;
+  if (!grad) return;
+  for (int p = 0; p < P; ++p) grad[(size_t)b * P + p] = 0.0;
+  for (int s = 0; s < nslots; ++s) {
+    double v = 0.0;
+    for (int k = 0; k < G; ++k) v += gpart[((size_t)b * nslots + s) * G + k];
+    grad[(size_t)b * P + slot_param[s]] += v;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host: context
+// ===========================================================================
+struct VqeConfig {
+  int mode = 0;        // 0 auto, 1 LDS-resident, 2 global per-gate (graph)
+  int threads = 256;   // LDS kernel block size
+  int blocks_per_state = 0;   // global path: 0 = derived from n
+};
+
+}  // namespace nwq
+
+struct nwq_vqe {
+  int n = 0, P = 0, nops = 0, nterms = 0, nslots = 0;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;       // own stream (graph capture needs a non-null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<nwq::VqeOp> ops;
+  std::vector<int> slot_param;
+  nwq::VqeOp* d_ops = nullptr;
+  double2* d_fixed = nullptr;
+  nwq::VqeTerm* d_terms = nullptr;
+  int* d_slot_param = nullptr;
+  // global path buffers
+  int Bcap = 0;
+  double2* d_phi = nullptr;
+  double2* d_lam = nullptr;
+  double* d_epart = nullptr;
+  double* d_gpart = nullptr;
+  double* d_theta = nullptr;   // staging copies for graph replays
+  double* d_E = nullptr;
+  double* d_grad = nullptr;
+  nwq::VqeConfig cfg;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (B, want_grad) -> exec
+};
+
+namespace nwq {
+
+static int vqe_fail(int code, const std::string& m) { return set_error(code, m); }
+
+static int blocks_per_state(const nwq_vqe* h) {
+  if (h->cfg.blocks_per_state > 0) return h->cfg.blocks_per_state;
+  const unsigned long long pairs = 1ull << (h->n - 1);
+  const unsigned long long b = (pairs + kVqeBlock * 4 - 1) / (kVqeBlock * 4);
+  return (int)std::max<unsigned long long>(1, std::min<unsigned long long>(b, 64));
+}
+
+static size_t lds_bytes(const nwq_vqe* h, int threads, bool want_grad) {
+  const size_t N = 1ull << h->n;
+  const int NW = threads / kWave;
+  return (want_grad ? 2 : 1) * N * sizeof(double2) + (size_t)NW * sizeof(double) +
+         (want_grad ? (size_t)h->nslots * NW * sizeof(double) : 0);
+}
+
+static bool lds_fits(const nwq_vqe* h, int threads, bool want_grad) {
+  return h->n <= 12 && lds_bytes(h, threads, want_grad) <= 160 * 1024;
+}
+
+static int launch_lds(nwq_vqe* h, int B, const double* theta, double* E, double* grad, hipStream_t s) {
+  const int T = h->cfg.threads;
+  const size_t lds = lds_bytes(h, T, grad != nullptr);
+  const int grid = std::min(B, 4096);
+#define NWQ_VQE_LDS(NTV)                                                                                     \
+  do {                                                                                                       \
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_vqe_lds<NTV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    hipLaunchKernelGGL(k_vqe_lds<NTV>, dim3(grid), dim3(NTV), lds, s, h->n, h->d_ops, h->nops, h->d_fixed,   \
+                       h->d_terms, h->nterms, h->nslots, h->d_slot_param, theta, h->P, B, E, grad);          \
+  } while (0)
+  switch (T) {
+    case 64: NWQ_VQE_LDS(64); break;
+    case 128: NWQ_VQE_LDS(128); break;
+    case 512: NWQ_VQE_LDS(512); break;
+    case 1024: NWQ_VQE_LDS(1024); break;
+    default: NWQ_VQE_LDS(256); break;
+  }
+#undef NWQ_VQE_LDS
+  return check_hip(hipGetLastError(), "k_vqe_lds");
+}
+
+static int ensure_global(nwq_vqe* h, int B) {
+  if (B <= h->Bcap) return NWQ_OK;
+  int rc = check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  for (void* p : {(void*)h->d_phi, (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta,
+                  (void*)h->d_E, (void*)h->d_grad})
+    if (p) (void)hipFree(p);
+  h->d_phi = h->d_lam = nullptr;
+  h->d_epart = h->d_gpart = h->d_theta = h->d_E = h->d_grad = nullptr;
+  h->Bcap = 0;
+  const size_t N = 1ull << h->n;
+  const int G = blocks_per_state(h);
+  rc = check_hip(hipMalloc(&h->d_phi, (size_t)B * N * sizeof(double2)), "hipMalloc(vqe phi)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_lam, (size_t)B * N * sizeof(double2)), "hipMalloc(vqe lambda)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_epart, (size_t)B * G * sizeof(double)), "hipMalloc(vqe epart)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_gpart, (size_t)B * std::max(1, h->nslots) * G * sizeof(double)), "hipMalloc(vqe gpart)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_theta, (size_t)B * std::max(1, h->P) * sizeof(double)), "hipMalloc(vqe theta)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_E, (size_t)B * sizeof(double)), "hipMalloc(vqe E)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_grad, (size_t)B * std::max(1, h->P) * sizeof(double)), "hipMalloc(vqe grad)");
+  if (rc) return rc;
+  h->Bcap = B;
+  return NWQ_OK;
+}
+
+// The per-gate schedule for B states on stream s (captured into a graph by
+// the batched path, launched directly by the per-circuit path).
+static int launch_global(nwq_vqe* h, int B, const double* theta, double* E, double* grad, hipStream_t s) {
+  const int G = blocks_per_state(h);
+  const dim3 grid(G, B);
+  hipLaunchKernelGGL(k_vqe_init, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n);
+  for (int i = 0; i < h->nops; ++i)
+    hipLaunchKernelGGL(k_vqe_gate, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n, h->ops[i], h->d_fixed, theta, h->P, 0);
+  hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
+                     h->d_epart, grad != nullptr ? 1 : 0);
+  if (grad != nullptr) {
+    for (int i = h->nops - 1; i >= 0; --i) {
+      const VqeOp& op = h->ops[i];
+      if (op.slot >= 0) {
+        hipLaunchKernelGGL(k_vqe_adjoint, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, op, h->d_fixed,
+                           theta, h->P, h->nslots, h->d_gpart);
+      } else {
+        hipLaunchKernelGGL(k_vqe_gate, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n, op, h->d_fixed, theta, h->P, 1);
+        hipLaunchKernelGGL(k_vqe_gate, grid, dim3(kVqeBlock), 0, s, h->d_lam, h->n, op, h->d_fixed, theta, h->P, 1);
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_vqe_finish, dim3((B + 63) / 64), dim3(64), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
+                     h->d_slot_param, h->P, B, E, grad);
+  return check_hip(hipGetLastError(), "vqe per-gate schedule");
+}
+
+static int run_graph(nwq_vqe* h, int B, bool want_grad) {
+  const auto key = std::make_pair(B, want_grad ? 1 : 0);
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    int rc = check_hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (rc) return rc;
+    rc = launch_global(h, B, h->d_theta, h->d_E, want_grad ? h->d_grad : nullptr, h->stream);
+    hipGraph_t g = nullptr;
+    const int rc2 = check_hip(hipStreamEndCapture(h->stream, &g), "hipStreamEndCapture");
+    if (rc) return rc;
+    if (rc2) return rc2;
+    hipGraphExec_t ex = nullptr;
+    rc = check_hip(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(g);
+    if (rc) return rc;
+    it = h->graphs.emplace(key, ex).first;
+  }
+  return check_hip(hipGraphLaunch(it->second, h->stream), "hipGraphLaunch");
+}
+
+}  // namespace nwq
+
+using namespace nwq;
+
+extern "C" {
+
+int nwq_vqe_create(int n, int n_ops, const int* types, const int* qubits, const int* params, int n_params,
+                   int n_terms, const uint64_t* xmask, const uint64_t* zmask, const double* coeffs, void* stream,
+                   nwq_vqe_handle* out) {
+  if (!out) return vqe_fail(NWQ_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 30) return vqe_fail(NWQ_ERANGE, "VQE register must have 1..30 qubits");
+  if (n_ops < 0 || (n_ops > 0 && (!types || !qubits || !params))) return vqe_fail(NWQ_EINVAL, "bad op arrays");
+  if (n_terms < 0 || (n_terms > 0 && (!xmask || !zmask || !coeffs))) return vqe_fail(NWQ_EINVAL, "bad term arrays");
+  if (n_params < 0) return vqe_fail(NWQ_EINVAL, "negative parameter count");
+  std::unique_ptr<nwq_vqe> h(new nwq_vqe());
+  h->n = n;
+  h->P = n_params;
+  h->user_stream = static_cast<hipStream_t>(stream);
+  std::vector<double2> fixed;
+  for (int i = 0; i < n_ops; ++i) {
+    const int t = types[i], a = qubits[2 * i], b = qubits[2 * i + 1], p = params[i];
+    VqeOp op{};
+    op.q0 = a;
+    op.q1 = b;
+    op.param = -1;
+    op.slot = -1;
+    op.mat = -1;
+    const bool two = t == NWQ_GATE_CX || t == NWQ_GATE_CZ || t == NWQ_GATE_SWAP || t == NWQ_GATE_RZZ;
+    if (a < 0 || a >= n || (two && (b < 0 || b >= n))) return vqe_fail(NWQ_ERANGE, "op " + std::to_string(i) + ": qubit out of range");
+    if (two && a == b) return vqe_fail(NWQ_EDUP, "op " + std::to_string(i) + ": repeated qubit");
+    const bool param = t == NWQ_GATE_RX || t == NWQ_GATE_RY || t == NWQ_GATE_RZ || t == NWQ_GATE_RZZ;
+    if (param) {
+      if (p < 0 || p >= n_params) return vqe_fail(NWQ_EINVAL, "op " + std::to_string(i) + ": parameter index out of range");
+      op.param = p;
+      op.slot = h->nslots++;
+      h->slot_param.push_back(p);
+      if (t == NWQ_GATE_RZZ) {
+        op.kind = OP_RZZ;
+      } else {
+        op.kind = OP_ROT;
+        op.axis = t == NWQ_GATE_RX ? 0 : (t == NWQ_GATE_RY ? 1 : 2);
+      }
+    } else if (t == NWQ_GATE_CX) {
+      op.kind = OP_CX;
+    } else if (t == NWQ_GATE_CZ) {
+      op.kind = OP_CZ;
+    } else if (t == NWQ_GATE_SWAP) {
+      op.kind = OP_SWAP;
+    } else if (t >= NWQ_GATE_I && t <= NWQ_GATE_TDG) {
+      if (t == NWQ_GATE_I) continue;
+      cd m[16];
+      gate_matrix(t, nullptr, m);
+      op.kind = OP_FIX1;
+      op.mat = (int)(fixed.size() / 8);
+      for (int k = 0; k < 4; ++k) fixed.push_back(make_double2(m[k].real(), m[k].imag()));
+      const int tr[4] = {0, 2, 1, 3};   // U^dag = conj(U^T)
+      for (int k = 0; k < 4; ++k) fixed.push_back(make_double2(m[tr[k]].real(), -m[tr[k]].imag()));
+    } else {
+      return vqe_fail(NWQ_EINVAL, "op " + std::to_string(i) + ": gate type not supported in a VQE program");
+    }
+    h->ops.push_back(op);
+  }
+  h->nops = (int)h->ops.size();
+  std::vector<VqeTerm> terms(n_terms);
+  const unsigned long long all = (1ull << n) - 1ull;
+  for (int t = 0; t < n_terms; ++t) {
+    if ((xmask[t] & ~all) || (zmask[t] & ~all)) return vqe_fail(NWQ_ERANGE, "Pauli mask has bits beyond n");
+    if (!std::isfinite(coeffs[t])) return vqe_fail(NWQ_EINVAL, "non-finite coefficient");
+    terms[t] = VqeTerm{xmask[t], zmask[t], coeffs[t], __builtin_popcountll(xmask[t] & zmask[t]) & 3, 0};
+  }
+  h->nterms = n_terms;
+  int rc = check_hip(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "hipStreamCreate");
+  if (!rc) rc = check_hip(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming), "hipEventCreate");
+  if (!rc) rc = check_hip(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming), "hipEventCreate");
+  auto up = [&](void** dst, const void* src, size_t bytes) -> int {
+    const size_t b = std::max<size_t>(bytes, 16);
+    int r = check_hip(hipMalloc(dst, b), "hipMalloc(vqe program)");
+    if (r) return r;
+    if (bytes) r = check_hip(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(vqe program)");
+    return r;
+  };
+  if (!rc) rc = up((void**)&h->d_ops, h->ops.data(), h->ops.size() * sizeof(VqeOp));
+  if (!rc) rc = up((void**)&h->d_fixed, fixed.data(), fixed.size() * sizeof(double2));
+  if (!rc) rc = up((void**)&h->d_terms, terms.data(), terms.size() * sizeof(VqeTerm));
+  if (!rc) rc = up((void**)&h->d_slot_param, h->slot_param.data(), h->slot_param.size() * sizeof(int));
+  if (rc) {
+    nwq_vqe_destroy(h.release());
+    return rc;
+  }
+  h->cfg.threads = n <= 8 ? 128 : 256;
+  *out = h.release();
+  return NWQ_OK;
+}
+
+int nwq_vqe_destroy(nwq_vqe_handle h) {
+  if (!h) return NWQ_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (void* p : {(void*)h->d_ops, (void*)h->d_fixed, (void*)h->d_terms, (void*)h->d_slot_param, (void*)h->d_phi,
+                  (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta, (void*)h->d_E,
+                  (void*)h->d_grad})
+    if (p) (void)hipFree(p);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return NWQ_OK;
+}
+
+int nwq_vqe_info(nwq_vqe_handle h, int* n_params, int* n_ops, int* n_slots) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (n_params) *n_params = h->P;
+  if (n_ops) *n_ops = h->nops;
+  if (n_slots) *n_slots = h->nslots;
+  return NWQ_OK;
+}
+
+int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_state_) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (mode < 0 || mode > 2) return vqe_fail(NWQ_EINVAL, "mode must be 0 (auto), 1 (LDS) or 2 (per-gate)");
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+    return vqe_fail(NWQ_EINVAL, "threads must be 64, 128, 256, 512 or 1024");
+  if (blocks_per_state_ < 0 || blocks_per_state_ > 4096) return vqe_fail(NWQ_EINVAL, "blocks per state in [0, 4096]");
+  if (mode == 1 && h->n > 12) return vqe_fail(NWQ_EINVAL, "the LDS-resident path holds n <= 12");
+  if (blocks_per_state_ != h->cfg.blocks_per_state) {   // partial buffers and graphs depend on it
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->cfg.blocks_per_state = blocks_per_state_;
+    const int B = h->Bcap;
+    h->Bcap = 0;
+    if (B > 0) {
+      const int rc = ensure_global(h, B);
+      if (rc) return rc;
+    }
+  }
+  h->cfg.mode = mode;
+  h->cfg.threads = threads;
+  return NWQ_OK;
+}
+
+int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_per_state_) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (mode) *mode = h->cfg.mode;
+  if (threads) *threads = h->cfg.threads;
+  if (blocks_per_state_) *blocks_per_state_ = blocks_per_state(h);
+  return NWQ_OK;
+}
+
+static int eval_common(nwq_vqe_handle h, int B, const double* theta, double* E, double* grad, bool single) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (B < 1 || B > 65535) return vqe_fail(NWQ_EINVAL, "batch size must be in [1, 65535]");
+  if ((!theta && h->P > 0) || !E) return vqe_fail(NWQ_EINVAL, "NULL theta or energy pointer");
+  int rc = check_hip(hipEventRecord(h->ev_in, h->user_stream), "hipEventRecord");
+  if (!rc) rc = check_hip(hipStreamWaitEvent(h->stream, h->ev_in, 0), "hipStreamWaitEvent");
+  if (rc) return rc;
+  const bool want_grad = grad != nullptr;
+  const int mode = single ? 2 : h->cfg.mode;
+  const bool use_lds = !single && (mode == 1 || (mode == 0 && lds_fits(h, h->cfg.threads, want_grad)));
+  if (use_lds) {
+    if (!lds_fits(h, h->cfg.threads, want_grad)) return vqe_fail(NWQ_EINVAL, "program does not fit the LDS-resident path");
+    rc = launch_lds(h, B, theta, E, grad, h->stream);
+  } else if (single) {
+    rc = ensure_global(h, B);
+    if (!rc) rc = launch_global(h, B, theta, E, grad, h->stream);
+  } else {
+    rc = ensure_global(h, B);
+    if (!rc && h->P > 0)
+      rc = check_hip(hipMemcpyAsync(h->d_theta, theta, (size_t)B * h->P * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+                     "hipMemcpyAsync(theta)");
+    if (!rc) rc = run_graph(h, B, want_grad);
+    if (!rc) rc = check_hip(hipMemcpyAsync(E, h->d_E, (size_t)B * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+                            "hipMemcpyAsync(E)");
+    if (!rc && want_grad && h->P > 0)
+      rc = check_hip(hipMemcpyAsync(grad, h->d_grad, (size_t)B * h->P * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+                     "hipMemcpyAsync(grad)");
+  }
+  if (rc) return rc;
+  rc = check_hip(hipEventRecord(h->ev_out, h->stream), "hipEventRecord");
+  if (!rc) rc = check_hip(hipStreamWaitEvent(h->user_stream, h->ev_out, 0), "hipStreamWaitEvent");
+  return rc;
+}
+
+int nwq_vqe_eval(nwq_vqe_handle h, int B, const double* theta_dev, double* energy_dev, double* grad_dev) {
+  return eval_common(h, B, theta_dev, energy_dev, grad_dev, false);
+}
+
+int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energy_dev, double* grad_dev) {
+  return eval_common(h, 1, theta_dev, energy_dev, grad_dev, true);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (B < 1 || B > 65535) return vqe_fail(NWQ_EINVAL, "batch size must be in [1, 65535]");
+  double *theta = nullptr, *E = nullptr, *grad = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  const size_t P = std::max(1, h->P);
+  int rc = check_hip(hipMalloc(&theta, (size_t)B * P * sizeof(double)), "hipMalloc(autotune theta)");
+  if (!rc) rc = check_hip(hipMalloc(&E, (size_t)B * sizeof(double)), "hipMalloc(autotune E)");
+  if (!rc) rc = check_hip(hipMalloc(&grad, (size_t)B * P * sizeof(double)), "hipMalloc(autotune grad)");
+  if (!rc) rc = check_hip(hipMemsetAsync(theta, 0, (size_t)B * P * sizeof(double), h->stream), "hipMemsetAsync");
+  if (!rc) rc = check_hip(hipEventCreate(&t0), "hipEventCreate");
+  if (!rc) rc = check_hip(hipEventCreate(&t1), "hipEventCreate");
+  struct Cand { int mode, threads, bps; };
+  std::vector<Cand> cands;
+  if (h->n <= 12)
+    for (int t : {64, 128, 256, 512, 1024})
+      if (lds_fits(h, t, with_grad != 0)) cands.push_back({1, t, 0});
+  const unsigned long long pairs = 1ull << (h->n - 1);
+  for (int bps : {0, 8, 16, 32, 64, 128, 256})
+    if (bps == 0 || (unsigned long long)bps * 256 <= pairs) cands.push_back({2, h->cfg.threads, bps});
+  const VqeConfig saved = h->cfg;
+  double best = 1e300;
+  VqeConfig best_cfg = saved;
+  hipStream_t user = h->user_stream;
+  h->user_stream = h->stream;
+  for (const Cand& c : cands) {
+    if (rc) break;
+    rc = nwq_vqe_set_config(h, c.mode, c.threads, c.bps);
+    if (rc) break;
+    rc = eval_common(h, B, theta, E, with_grad ? grad : nullptr, false);   // warm-up (and graph capture)
+    if (rc) break;
+    rc = check_hip(hipEventRecord(t0, h->stream), "hipEventRecord");
+    for (int r = 0; r < 3 && !rc; ++r) rc = eval_common(h, B, theta, E, with_grad ? grad : nullptr, false);
+    if (!rc) rc = check_hip(hipEventRecord(t1, h->stream), "hipEventRecord");
+    if (!rc) rc = check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
+    float ms = 0.f;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+    if (!rc && ms / 3.0 < best) {
+      best = ms / 3.0;
+      best_cfg = h->cfg;
+    }
+  }
+  h->user_stream = user;
+  if (!rc) rc = nwq_vqe_set_config(h, best_cfg.mode, best_cfg.threads, best_cfg.blocks_per_state);
+  else (void)nwq_vqe_set_config(h, saved.mode, saved.threads, saved.blocks_per_state);
+  (void)hipStreamSynchronize(h->stream);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  for (void* p : {(void*)theta, (void*)E, (void*)grad})
+    if (p) (void)hipFree(p);
+  if (!rc && best_ms) *best_ms = best;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+"""GPU parity of the VQE path (Sec. III, Fig. 4): energies against the
+oracle (<= 1e-10), adjoint gradients against the oracle's parameter-shift
+rule (<= 1e-10) and finite differences (<= 1e-6), on the LDS-resident
+batched path, the per-gate graph path and the plain per-circuit path;
+bit-identical results alone and inside a batch; the autograd wrapper."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import vqe as OV
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2401_06861_amd import vqe as mod
+    return mod
+
+
+def run_all_paths(V, torch, n, prog, terms, theta):
+    ctx = V.VQE(n, prog, terms, n_params=theta.shape[1])
+    t = torch.from_numpy(theta).cuda()
+    out = {}
+    modes = [("lds", 1), ("graph", 2)] if n <= 12 else [("graph", 2)]
+    for name, mode in modes:
+        ctx.set_config(mode, 256, 0)
+        E, G = ctx.eval(t, grad=True)
+        out[name] = (E.cpu().numpy(), G.cpu().numpy())
+    Es, Gs = [], []
+    for b in range(theta.shape[0]):
+        E, G = ctx.eval_single(t[b])
+        Es.append(E.cpu().numpy()[0])
+        Gs.append(G.cpu().numpy()[0])
+    out["single"] = (np.array(Es), np.array(Gs))
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("n,L", [(2, 1), (4, 2), (6, 3), (9, 2)])
+def test_hea_energy_and_gradient(V, torch, n, L):
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=3)
+    terms = W.tfim_hamiltonian(n, 1.0, h)
+    outs = run_all_paths(V, torch, n, prog, terms, theta)
+    for b in range(theta.shape[0]):
+        e_ref = OV.energy(prog, theta[b], terms, n)
+        g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n)
+        for name, (E, G) in outs.items():
+            assert abs(E[b] - e_ref) <= 1e-10, (name, b)
+            assert np.max(np.abs(G[b] - g_ps)) <= 1e-10, (name, b)
+    g_fd = OV.grad_finite_difference(prog, theta[0], terms, n)
+    assert np.max(np.abs(outs["single"][1][0] - g_fd)) <= 1e-6
+
+
+def test_generic_program_with_fixed_gates_and_rzz(V, torch):
+    n = 5
+    A = W.AnsatzGate
+    prog = [A("h", (0,), -1), A("rx", (1,), 0), A("cz", (0, 2), -1), A("rzz", (1, 3), 1), A("s", (4,), -1),
+            A("ry", (4,), 2), A("swap", (2, 4), -1), A("t", (3,), -1), A("rz", (0,), 0), A("cx", (4, 1), -1),
+            A("y", (2,), -1), A("rzz", (4, 0), 3), A("sdg", (1,), -1), A("rx", (3,), 1)]
+    terms = W.random_pauli_sum(n, 12, seed=4)
+    theta = np.random.default_rng(2).uniform(-math.pi, math.pi, (4, 4))
+    outs = run_all_paths(V, torch, n, prog, terms, theta)
+    for b in range(4):
+        e_ref = OV.energy(prog, theta[b], terms, n)
+        g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n)   # shared parameters: summed per occurrence
+        for name, (E, G) in outs.items():
+            assert abs(E[b] - e_ref) <= 1e-10, name
+            assert np.max(np.abs(G[b] - g_ps)) <= 1e-10, name
+
+
+def test_theta_zero_special_cases(V, torch):
+    n, L = 6, 3
+    prog = W.hea_ansatz(n, L)
+    terms = W.tfim_hamiltonian(n, 1.0, 0.8)
+    ctx = V.VQE(n, prog, terms)
+    E, G = ctx.eval(torch.zeros(2, 2 * n * L, dtype=torch.float64, device="cuda"))
+    assert np.max(np.abs(E.cpu().numpy() + (n - 1))) <= 1e-12
+    last_rz = [(L - 1) * 2 * n + n + q for q in range(n)]
+    assert np.max(np.abs(G.cpu().numpy()[:, last_rz])) <= 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,mode", [(7, 1), (7, 2), (13, 2)])
+def test_alone_equals_in_the_mix_bitwise(V, torch, n, mode):
+    L = 2
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=16)
+    ctx = V.VQE(n, prog, W.tfim_hamiltonian(n, 1.0, h))
+    ctx.set_config(mode, 256, 0)
+    t = torch.from_numpy(theta).cuda()
+    E, G = ctx.eval(t)
+    for b in (0, 5, 15):
+        E1, G1 = ctx.eval(t[b:b + 1])
+        assert E1.item() == E[b].item()
+        assert torch.equal(G1[0], G[b])
+    ctx.close()
+
+
+def test_energy_only_matches(V, torch):
+    n, L = 8, 2
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=5)
+    ctx = V.VQE(n, prog, W.tfim_hamiltonian(n, 1.0, h))
+    t = torch.from_numpy(theta).cuda()
+    for mode in (1, 2):
+        ctx.set_config(mode, 128, 0)
+        E1, _ = ctx.eval(t, grad=False)
+        E2, _ = ctx.eval(t, grad=True)
+        assert torch.max(torch.abs(E1 - E2)).item() <= 1e-13
+    ctx.close()
+
+
+def test_larger_register_global_path(V, torch):
+    n, L = 14, 2
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=2)
+    terms = W.tfim_hamiltonian(n, 1.0, h)
+    ctx = V.VQE(n, prog, terms)
+    t = torch.from_numpy(theta).cuda()
+    E, G = ctx.eval(t)
+    E = E.cpu().numpy()
+    G = G.cpu().numpy()
+    pick = [0, 7, 13, 20, 41, 55]
+    for b in range(2):
+        assert abs(E[b] - OV.energy(prog, theta[b], terms, n)) <= 1e-10
+        g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n, params=pick)
+        assert np.max(np.abs(G[b][pick] - g_ps[pick])) <= 1e-10
+    ctx.close()
+
+
+def test_autograd_wrapper(V, torch):
+    n, L = 5, 2
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=4)
+    ctx = V.VQE(n, prog, W.tfim_hamiltonian(n, 1.0, h))
+    t = torch.from_numpy(theta).cuda().requires_grad_(True)
+    w = torch.arange(1, 5, dtype=torch.float64, device="cuda")
+    loss = (V.AdjointEnergy.apply(t, ctx) * w).sum()
+    loss.backward()
+    _, G = ctx.eval(t.detach())
+    assert torch.max(torch.abs(t.grad - w[:, None] * G)).item() <= 1e-14
+    t1 = torch.from_numpy(theta[0]).cuda().requires_grad_(True)
+    e = V.AdjointEnergy.apply(t1, ctx)
+    e.backward()
+    assert torch.max(torch.abs(t1.grad - G[0])).item() <= 1e-14
+    ctx.close()
+
+
+def test_autotune_picks_a_valid_config(V, torch):
+    n, L = 10, 2
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=32)
+    terms = W.tfim_hamiltonian(n, 1.0, h)
+    ctx = V.VQE(n, prog, terms)
+    ms = ctx.autotune(32)
+    assert ms > 0
+    mode, threads, bps = ctx.get_config()
+    assert mode in (1, 2)
+    E, G = ctx.eval(torch.from_numpy(theta).cuda())
+    assert abs(E[0].item() - OV.energy(prog, theta[0], terms, n)) <= 1e-10
+    ctx.close()
+
+
+def test_vqe_create_errors(V, torch):
+    from paper_2401_06861_amd import nwq
+    A = W.AnsatzGate
+    with pytest.raises(nwq.NwqError) as e:
+        V.VQE(3, [A("rx", (3,), 0)], [(1, 0, 1.0)], n_params=1)
+    assert e.value.code == nwq.NWQ_ERANGE
+    with pytest.raises(nwq.NwqError) as e:
+        V.VQE(3, [A("rx", (1,), 2)], [(1, 0, 1.0)], n_params=1)
+    assert e.value.code == nwq.NWQ_EINVAL
+    with pytest.raises(nwq.NwqError) as e:
+        V.VQE(3, [A("u3", (1,), -1)], [(1, 0, 1.0)], n_params=1)
+    assert e.value.code == nwq.NWQ_EINVAL
+    with pytest.raises(nwq.NwqError) as e:
+        V.VQE(3, [A("cx", (1, 1), -1)], [(1, 0, 1.0)], n_params=1)
+    assert e.value.code == nwq.NWQ_EDUP
