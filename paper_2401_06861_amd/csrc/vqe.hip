@@ -69,44 +69,70 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// 2x2 matrix of an op for the current theta (dag: adjoint).  For rotations
-// exp(-i t P/2) the adjoint is the rotation by -t.
+// 2x2 matrices.  Rotations exp(-i t P/2) are built branch-free (the axis
+// picks entries with selects) and fixed gates are loaded from the table in
+// separate code paths: with this toolchain a branchy construction of the
+// rotation matrix whose results merged with the table load was compiled to
+// code that dropped the imaginary part of the RZ diagonal, so the two cases
+// are never merged into one value.  The adjoint of a rotation is the
+// rotation by -t.
 struct M2 { vd2 m0, m1, m2, m3; };
 
-__device__ __forceinline__ M2 op_matrix(const VqeOp& op, const double* th, const double2* fixed, bool dag) {
+__device__ __forceinline__ M2 rot_matrix(int axis, double theta, bool dag) {
+  double s, c;
+  sincos(0.5 * theta, &s, &c);
+  s = dag ? -s : s;
+  const double z = 0.0;
   M2 r;
-  if (op.kind == OP_ROT) {
-    double s, c;
-    sincos(0.5 * th[op.param], &s, &c);
-    if (dag) s = -s;
-    if (op.axis == 0) { r.m0 = mk(c, 0); r.m1 = mk(0, -s); r.m2 = mk(0, -s); r.m3 = mk(c, 0); }
-    else if (op.axis == 1) { r.m0 = mk(c, 0); r.m1 = mk(-s, 0); r.m2 = mk(s, 0); r.m3 = mk(c, 0); }
-    else { r.m0 = mk(c, -s); r.m1 = mk(0, 0); r.m2 = mk(0, 0); r.m3 = mk(c, s); }
-  } else {
-    const double2* f = fixed + 8 * op.mat + (dag ? 4 : 0);
-    r.m0 = ld(f); r.m1 = ld(f + 1); r.m2 = ld(f + 2); r.m3 = ld(f + 3);
-  }
+  r.m0 = mk(c, axis == 2 ? -s : z);
+  r.m1 = mk(axis == 1 ? -s : z, axis == 0 ? -s : z);
+  r.m2 = mk(axis == 1 ? s : z, axis == 0 ? -s : z);
+  r.m3 = mk(c, axis == 2 ? s : z);
+  return r;
+}
+
+__device__ __forceinline__ M2 fixed_matrix(int mat, const double2* fixed, bool dag) {
+  const double2* f = fixed + 8 * mat + (dag ? 4 : 0);
+  M2 r;
+  r.m0 = ld(f); r.m1 = ld(f + 1); r.m2 = ld(f + 2); r.m3 = ld(f + 3);
   return r;
 }
 
 // RZZ: diagonal e^{-i t/2} (even parity), e^{+i t/2} (odd parity)
-__device__ __forceinline__ void rzz_phases(const VqeOp& op, const double* th, bool dag, vd2& even, vd2& odd) {
+__device__ __forceinline__ void rzz_phases(double theta, bool dag, vd2& even, vd2& odd) {
   double s, c;
-  sincos(0.5 * th[op.param], &s, &c);
-  if (dag) s = -s;
+  sincos(0.5 * theta, &s, &c);
+  s = dag ? -s : s;
   even = mk(c, -s);
   odd = mk(c, s);
 }
 
+template <typename Idx>
+__device__ __forceinline__ void pairs_apply(double2* v, Idx N, int q, const M2& m, Idx tid, Idx nt) {
+  const Idx off = Idx(1) << q;
+  for (Idx p = tid; p < (N >> 1); p += nt) {
+    const Idx i0 = ((p >> q) << (q + 1)) | (p & (off - 1));
+    const vd2 a = ld(v + i0), b = ld(v + i0 + off);
+    st(v + i0, cfma(m.m0, a, cmul(m.m1, b)));
+    st(v + i0 + off, cfma(m.m2, a, cmul(m.m3, b)));
+  }
+}
+
 // Contribution Im( conj(l0) (P phi)_0 + conj(l1) (P phi)_1 ) of one pair for a
-// single-qubit Pauli generator on the pair's qubit.
+// single-qubit Pauli generator on the pair's qubit, written with scalar
+// selects only (no per-axis branches building vectors; see rot_matrix):
+//   X: Im(conj(l0) p1) + Im(conj(l1) p0)
+//   Y: Re(conj(l1) p0) - Re(conj(l0) p1)        ((Y phi)_0 = -i p1, (Y phi)_1 = i p0)
+//   Z: Im(conj(l0) p0) - Im(conj(l1) p1)
 __device__ __forceinline__ double pair_grad(int axis, vd2 p0, vd2 p1, vd2 l0, vd2 l1) {
-  vd2 a, b;                      // (P phi)_0, (P phi)_1
-  if (axis == 0) { a = p1; b = p0; }
-  else if (axis == 1) { a = mk(p1.y, -p1.x); b = mk(-p0.y, p0.x); }   // -i p1, i p0
-  else { a = p0; b = mk(-p1.x, -p1.y); }
-  // Im(conj(l) * a) = l.x a.y - l.y a.x
-  return (l0.x * a.y - l0.y * a.x) + (l1.x * b.y - l1.y * b.x);
+  const double im01 = l0.x * p1.y - l0.y * p1.x;
+  const double im10 = l1.x * p0.y - l1.y * p0.x;
+  const double re01 = l0.x * p1.x + l0.y * p1.y;
+  const double re10 = l1.x * p0.x + l1.y * p0.y;
+  const double im00 = l0.x * p0.y - l0.y * p0.x;
+  const double im11 = l1.x * p1.y - l1.y * p1.x;
+  const double gx = im01 + im10, gy = re10 - re01, gz = im00 - im11;
+  return axis == 0 ? gx : (axis == 1 ? gy : gz);
 }
 
 // ---------------------------------------------------------------------------
@@ -118,20 +144,14 @@ __device__ __forceinline__ void apply_op_state(double2* v, int n, const VqeOp& o
   const unsigned N = 1u << n;
   switch (op.kind) {
     case OP_ROT:
-    case OP_FIX1: {
-      const M2 m = op_matrix(op, th, fixed, dag);
-      const unsigned off = 1u << op.q0;
-      for (unsigned p = tid; p < (N >> 1); p += nt) {
-        const unsigned i0 = ins0(p, op.q0);
-        const vd2 a = ld(v + i0), b = ld(v + i0 + off);
-        st(v + i0, cfma(m.m0, a, cmul(m.m1, b)));
-        st(v + i0 + off, cfma(m.m2, a, cmul(m.m3, b)));
-      }
+      pairs_apply<unsigned>(v, N, op.q0, rot_matrix(op.axis, th[op.param], dag), tid, nt);
       break;
-    }
+    case OP_FIX1:
+      pairs_apply<unsigned>(v, N, op.q0, fixed_matrix(op.mat, fixed, dag), tid, nt);
+      break;
     case OP_RZZ: {
       vd2 e, o;
-      rzz_phases(op, th, dag, e, o);
+      rzz_phases(th[op.param], dag, e, o);
       for (unsigned j = tid; j < N; j += nt) {
         const unsigned par = ((j >> op.q0) ^ (j >> op.q1)) & 1u;
         st(v + j, cmul(par ? o : e, ld(v + j)));
@@ -165,7 +185,7 @@ __device__ __forceinline__ double adjoint_step(double2* phi, double2* lam, int n
   const unsigned N = 1u << n;
   double g = 0.0;
   if (op.kind == OP_ROT) {
-    const M2 m = op_matrix(op, th, fixed, true);
+    const M2 m = rot_matrix(op.axis, th[op.param], true);
     const unsigned off = 1u << op.q0;
     for (unsigned p = tid; p < (N >> 1); p += nt) {
       const unsigned i0 = ins0(p, op.q0);
@@ -179,7 +199,7 @@ __device__ __forceinline__ double adjoint_step(double2* phi, double2* lam, int n
     }
   } else if (op.kind == OP_RZZ) {
     vd2 e, o;
-    rzz_phases(op, th, true, e, o);
+    rzz_phases(th[op.param], true, e, o);
     for (unsigned j = tid; j < N; j += nt) {
       const unsigned par = ((j >> op.q0) ^ (j >> op.q1)) & 1u;
       const vd2 p = ld(phi + j), l = ld(lam + j);
@@ -303,20 +323,14 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_gate(double2* __restrict__ st
   const unsigned long long nt = (unsigned long long)gridDim.x * kVqeBlock;
   switch (op.kind) {
     case OP_ROT:
-    case OP_FIX1: {
-      const M2 m = op_matrix(op, th, fixed, dag != 0);
-      const unsigned long long off = 1ull << op.q0;
-      for (unsigned long long p = tid; p < (N >> 1); p += nt) {
-        const unsigned long long i0 = ins0l(p, op.q0);
-        const vd2 a = ld(v + i0), b = ld(v + i0 + off);
-        st(v + i0, cfma(m.m0, a, cmul(m.m1, b)));
-        st(v + i0 + off, cfma(m.m2, a, cmul(m.m3, b)));
-      }
+      pairs_apply<unsigned long long>(v, N, op.q0, rot_matrix(op.axis, th[op.param], dag != 0), tid, nt);
       break;
-    }
+    case OP_FIX1:
+      pairs_apply<unsigned long long>(v, N, op.q0, fixed_matrix(op.mat, fixed, dag != 0), tid, nt);
+      break;
     case OP_RZZ: {
       vd2 e, o;
-      rzz_phases(op, th, dag != 0, e, o);
+      rzz_phases(th[op.param], dag != 0, e, o);
       for (unsigned long long j = tid; j < N; j += nt) {
         const unsigned par = (unsigned)(((j >> op.q0) ^ (j >> op.q1)) & 1ull);
         st(v + j, cmul(par ? o : e, ld(v + j)));
@@ -382,7 +396,7 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__
   const unsigned long long nt = (unsigned long long)gridDim.x * kVqeBlock;
   double g = 0.0;
   if (op.kind == OP_ROT) {
-    const M2 m = op_matrix(op, th, fixed, true);
+    const M2 m = rot_matrix(op.axis, th[op.param], true);
     const unsigned long long off = 1ull << op.q0;
     for (unsigned long long p = tid; p < (N >> 1); p += nt) {
       const unsigned long long i0 = ins0l(p, op.q0);
@@ -396,7 +410,7 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__
     }
   } else {   // OP_RZZ
     vd2 e, o;
-    rzz_phases(op, th, true, e, o);
+    rzz_phases(th[op.param], true, e, o);
     for (unsigned long long j = tid; j < N; j += nt) {
       const unsigned par = (unsigned)(((j >> op.q0) ^ (j >> op.q1)) & 1ull);
       const vd2 p = ld(pv + j), l = ld(lv + j);
