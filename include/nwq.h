@@ -219,6 +219,13 @@ int nwq_vqe_info(nwq_vqe_handle h, int* n_params, int* n_ops, int* n_slots);
  * Results for a vector do not depend on B or on the other vectors. */
 int nwq_vqe_eval(nwq_vqe_handle h, int B, const double* theta_dev, double* energy_dev, double* grad_dev);
 
+/* As nwq_vqe_eval, with per-vector Hamiltonian coefficients:
+ * coeffs_dev[B][n_terms] (device) replaces the context's coefficients for
+ * each vector (same Pauli strings).  Used by the serving loop to batch
+ * requests whose fields differ. */
+int nwq_vqe_eval_coeffs(nwq_vqe_handle h, int B, const double* theta_dev, const double* coeffs_dev,
+                        double* energy_dev, double* grad_dev);
+
 /* Plain per-circuit path (the reference point for the batched path): one
  * vector, one kernel per gate, no graph, no LDS residency. */
 int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energy_dev, double* grad_dev);

@@ -216,10 +216,12 @@ __device__ __forceinline__ double adjoint_step(double2* phi, double2* lam, int n
 }
 
 // (H phi)_j = sum_t c_t i^y (-1)^{|(j^x)&z|} phi_{j^x}
-__device__ __forceinline__ vd2 h_apply_at(const double2* phi, unsigned long long j, const VqeTerm* terms, int nterms) {
+__device__ __forceinline__ vd2 h_apply_at(const double2* phi, unsigned long long j, const VqeTerm* terms, int nterms,
+                                          const double* cb) {
   vd2 acc = mk(0.0, 0.0);
   for (int t = 0; t < nterms; ++t) {
     const VqeTerm T = terms[t];
+    const double tc = cb ? cb[t] : T.c;
     const unsigned long long k = j ^ T.x;
     vd2 v = ld(phi + k);
     switch (T.y & 3) {
@@ -228,7 +230,7 @@ __device__ __forceinline__ vd2 h_apply_at(const double2* phi, unsigned long long
       case 3: v = mk(v.y, -v.x); break;
       default: break;
     }
-    const double c = (__popcll(k & T.z) & 1) ? -T.c : T.c;
+    const double c = (__popcll(k & T.z) & 1) ? -tc : tc;
     acc.x = fma(c, v.x, acc.x);
     acc.y = fma(c, v.y, acc.y);
   }
@@ -243,6 +245,7 @@ __global__ __launch_bounds__(NT) void k_vqe_lds(int n, const VqeOp* __restrict__
                                                 const double2* __restrict__ fixed, const VqeTerm* __restrict__ terms,
                                                 int nterms, int nslots, const int* __restrict__ slot_param,
                                                 const double* __restrict__ theta, int P, int B,
+                                                const double* __restrict__ coeffs,
                                                 double* __restrict__ E, double* __restrict__ grad) {
   extern __shared__ double2 lds[];
   constexpr int NW = NT / kWave;
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(NT) void k_vqe_lds(int n, const VqeOp* __restrict__
     // lambda = H phi and E = Re <phi|lambda>
     double e = 0.0;
     for (unsigned j = tid; j < N; j += NT) {
-      const vd2 l = h_apply_at(phi, j, terms, nterms);
+      const vd2 l = h_apply_at(phi, j, terms, nterms, coeffs ? coeffs + (size_t)b * nterms : nullptr);
       const vd2 p = ld(phi + j);
       e += p.x * l.x + p.y * l.y;
       if (grad) st(lam + j, l);
@@ -359,6 +362,7 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_gate(double2* __restrict__ st
 // lambda = H phi, energy partials epart[b * G + block]
 __global__ __launch_bounds__(kVqeBlock) void k_vqe_hphi(const double2* __restrict__ phi, double2* __restrict__ lam,
                                                         int n, const VqeTerm* __restrict__ terms, int nterms,
+                                                        const double* __restrict__ coeffs,
                                                         double* __restrict__ epart, int store_lam) {
   __shared__ double red[kVqeBlock / kWave];
   const unsigned long long N = 1ull << n;
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_hphi(const double2* __restric
   double e = 0.0;
   for (unsigned long long j = (unsigned long long)blockIdx.x * kVqeBlock + threadIdx.x; j < N;
        j += (unsigned long long)gridDim.x * kVqeBlock) {
-    const vd2 h = h_apply_at(p, j, terms, nterms);
+    const vd2 h = h_apply_at(p, j, terms, nterms, coeffs ? coeffs + (size_t)blockIdx.y * nterms : nullptr);
     const vd2 v = ld(p + j);
     e += v.x * h.x + v.y * h.y;
     if (store_lam) st(l + j, h);
@@ -482,6 +486,7 @@ struct nwq_vqe {
   double* d_theta = nullptr;   // staging copies for graph replays
   double* d_E = nullptr;
   double* d_grad = nullptr;
+  double* d_coeffs = nullptr;  // staging copy of per-vector coefficients
   nwq::VqeConfig cfg;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (B, want_grad) -> exec
 };
@@ -508,7 +513,8 @@ static bool lds_fits(const nwq_vqe* h, int threads, bool want_grad) {
   return h->n <= 12 && lds_bytes(h, threads, want_grad) <= 160 * 1024;
 }
 
-static int launch_lds(nwq_vqe* h, int B, const double* theta, double* E, double* grad, hipStream_t s) {
+static int launch_lds(nwq_vqe* h, int B, const double* theta, const double* coeffs, double* E, double* grad,
+                      hipStream_t s) {
   const int T = h->cfg.threads;
   const size_t lds = lds_bytes(h, T, grad != nullptr);
   const int grid = std::min(B, 4096);
@@ -516,7 +522,7 @@ static int launch_lds(nwq_vqe* h, int B, const double* theta, double* E, double*
   do {                                                                                                       \
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_vqe_lds<NTV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     hipLaunchKernelGGL(k_vqe_lds<NTV>, dim3(grid), dim3(NTV), lds, s, h->n, h->d_ops, h->nops, h->d_fixed,   \
-                       h->d_terms, h->nterms, h->nslots, h->d_slot_param, theta, h->P, B, E, grad);          \
+                       h->d_terms, h->nterms, h->nslots, h->d_slot_param, theta, h->P, B, coeffs, E, grad);  \
   } while (0)
   switch (T) {
     case 64: NWQ_VQE_LDS(64); break;
@@ -536,10 +542,10 @@ static int ensure_global(nwq_vqe* h, int B) {
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   h->graphs.clear();
   for (void* p : {(void*)h->d_phi, (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta,
-                  (void*)h->d_E, (void*)h->d_grad})
+                  (void*)h->d_E, (void*)h->d_grad, (void*)h->d_coeffs})
     if (p) (void)hipFree(p);
   h->d_phi = h->d_lam = nullptr;
-  h->d_epart = h->d_gpart = h->d_theta = h->d_E = h->d_grad = nullptr;
+  h->d_epart = h->d_gpart = h->d_theta = h->d_E = h->d_grad = h->d_coeffs = nullptr;
   h->Bcap = 0;
   const size_t N = 1ull << h->n;
   const int G = blocks_per_state(h);
@@ -550,6 +556,7 @@ static int ensure_global(nwq_vqe* h, int B) {
   if (!rc) rc = check_hip(hipMalloc(&h->d_theta, (size_t)B * std::max(1, h->P) * sizeof(double)), "hipMalloc(vqe theta)");
   if (!rc) rc = check_hip(hipMalloc(&h->d_E, (size_t)B * sizeof(double)), "hipMalloc(vqe E)");
   if (!rc) rc = check_hip(hipMalloc(&h->d_grad, (size_t)B * std::max(1, h->P) * sizeof(double)), "hipMalloc(vqe grad)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_coeffs, (size_t)B * std::max(1, h->nterms) * sizeof(double)), "hipMalloc(vqe coeffs)");
   if (rc) return rc;
   h->Bcap = B;
   return NWQ_OK;
@@ -557,14 +564,15 @@ static int ensure_global(nwq_vqe* h, int B) {
 
 // The per-gate schedule for B states on stream s (captured into a graph by
 // the batched path, launched directly by the per-circuit path).
-static int launch_global(nwq_vqe* h, int B, const double* theta, double* E, double* grad, hipStream_t s) {
+static int launch_global(nwq_vqe* h, int B, const double* theta, const double* coeffs, double* E, double* grad,
+                         hipStream_t s) {
   const int G = blocks_per_state(h);
   const dim3 grid(G, B);
   hipLaunchKernelGGL(k_vqe_init, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n);
   for (int i = 0; i < h->nops; ++i)
     hipLaunchKernelGGL(k_vqe_gate, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n, h->ops[i], h->d_fixed, theta, h->P, 0);
   hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
-                     h->d_epart, grad != nullptr ? 1 : 0);
+                     coeffs, h->d_epart, grad != nullptr ? 1 : 0);
   if (grad != nullptr) {
     for (int i = h->nops - 1; i >= 0; --i) {
       const VqeOp& op = h->ops[i];
@@ -582,13 +590,14 @@ static int launch_global(nwq_vqe* h, int B, const double* theta, double* E, doub
   return check_hip(hipGetLastError(), "vqe per-gate schedule");
 }
 
-static int run_graph(nwq_vqe* h, int B, bool want_grad) {
-  const auto key = std::make_pair(B, want_grad ? 1 : 0);
+static int run_graph(nwq_vqe* h, int B, bool want_grad, bool with_coeffs) {
+  const auto key = std::make_pair(B, (want_grad ? 1 : 0) | (with_coeffs ? 2 : 0));
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
     int rc = check_hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (rc) return rc;
-    rc = launch_global(h, B, h->d_theta, h->d_E, want_grad ? h->d_grad : nullptr, h->stream);
+    rc = launch_global(h, B, h->d_theta, with_coeffs ? h->d_coeffs : nullptr, h->d_E, want_grad ? h->d_grad : nullptr,
+                       h->stream);
     hipGraph_t g = nullptr;
     const int rc2 = check_hip(hipStreamEndCapture(h->stream, &g), "hipStreamEndCapture");
     if (rc) return rc;
@@ -703,7 +712,7 @@ int nwq_vqe_destroy(nwq_vqe_handle h) {
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   for (void* p : {(void*)h->d_ops, (void*)h->d_fixed, (void*)h->d_terms, (void*)h->d_slot_param, (void*)h->d_phi,
                   (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta, (void*)h->d_E,
-                  (void*)h->d_grad})
+                  (void*)h->d_grad, (void*)h->d_coeffs})
     if (p) (void)hipFree(p);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
@@ -752,7 +761,8 @@ int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_pe
   return NWQ_OK;
 }
 
-static int eval_common(nwq_vqe_handle h, int B, const double* theta, double* E, double* grad, bool single) {
+static int eval_common(nwq_vqe_handle h, int B, const double* theta, const double* coeffs, double* E, double* grad,
+                       bool single) {
   if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
   if (B < 1 || B > 65535) return vqe_fail(NWQ_EINVAL, "batch size must be in [1, 65535]");
   if ((!theta && h->P > 0) || !E) return vqe_fail(NWQ_EINVAL, "NULL theta or energy pointer");
@@ -764,16 +774,19 @@ static int eval_common(nwq_vqe_handle h, int B, const double* theta, double* E, 
   const bool use_lds = !single && (mode == 1 || (mode == 0 && lds_fits(h, h->cfg.threads, want_grad)));
   if (use_lds) {
     if (!lds_fits(h, h->cfg.threads, want_grad)) return vqe_fail(NWQ_EINVAL, "program does not fit the LDS-resident path");
-    rc = launch_lds(h, B, theta, E, grad, h->stream);
+    rc = launch_lds(h, B, theta, coeffs, E, grad, h->stream);
   } else if (single) {
     rc = ensure_global(h, B);
-    if (!rc) rc = launch_global(h, B, theta, E, grad, h->stream);
+    if (!rc) rc = launch_global(h, B, theta, coeffs, E, grad, h->stream);
   } else {
     rc = ensure_global(h, B);
     if (!rc && h->P > 0)
       rc = check_hip(hipMemcpyAsync(h->d_theta, theta, (size_t)B * h->P * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
                      "hipMemcpyAsync(theta)");
-    if (!rc) rc = run_graph(h, B, want_grad);
+    if (!rc && coeffs && h->nterms > 0)
+      rc = check_hip(hipMemcpyAsync(h->d_coeffs, coeffs, (size_t)B * h->nterms * sizeof(double), hipMemcpyDeviceToDevice,
+                                    h->stream), "hipMemcpyAsync(coeffs)");
+    if (!rc) rc = run_graph(h, B, want_grad, coeffs != nullptr);
     if (!rc) rc = check_hip(hipMemcpyAsync(E, h->d_E, (size_t)B * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
                             "hipMemcpyAsync(E)");
     if (!rc && want_grad && h->P > 0)
@@ -787,11 +800,16 @@ static int eval_common(nwq_vqe_handle h, int B, const double* theta, double* E, 
 }
 
 int nwq_vqe_eval(nwq_vqe_handle h, int B, const double* theta_dev, double* energy_dev, double* grad_dev) {
-  return eval_common(h, B, theta_dev, energy_dev, grad_dev, false);
+  return eval_common(h, B, theta_dev, nullptr, energy_dev, grad_dev, false);
+}
+
+int nwq_vqe_eval_coeffs(nwq_vqe_handle h, int B, const double* theta_dev, const double* coeffs_dev,
+                        double* energy_dev, double* grad_dev) {
+  return eval_common(h, B, theta_dev, coeffs_dev, energy_dev, grad_dev, false);
 }
 
 int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energy_dev, double* grad_dev) {
-  return eval_common(h, 1, theta_dev, energy_dev, grad_dev, true);
+  return eval_common(h, 1, theta_dev, nullptr, energy_dev, grad_dev, true);
 }
 
 }  // extern "C"
@@ -827,10 +845,10 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms) {
     if (rc) break;
     rc = nwq_vqe_set_config(h, c.mode, c.threads, c.bps);
     if (rc) break;
-    rc = eval_common(h, B, theta, E, with_grad ? grad : nullptr, false);   // warm-up (and graph capture)
+    rc = eval_common(h, B, theta, nullptr, E, with_grad ? grad : nullptr, false);   // warm-up (and graph capture)
     if (rc) break;
     rc = check_hip(hipEventRecord(t0, h->stream), "hipEventRecord");
-    for (int r = 0; r < 3 && !rc; ++r) rc = eval_common(h, B, theta, E, with_grad ? grad : nullptr, false);
+    for (int r = 0; r < 3 && !rc; ++r) rc = eval_common(h, B, theta, nullptr, E, with_grad ? grad : nullptr, false);
     if (!rc) rc = check_hip(hipEventRecord(t1, h->stream), "hipEventRecord");
     if (!rc) rc = check_hip(hipEventSynchronize(t1), "hipEventSynchronize");
     float ms = 0.f;

@@ -22,6 +22,7 @@ for _name, _args in {
     "nwq_vqe_destroy": [_vh],
     "nwq_vqe_info": [_vh, _ip, _ip, _ip],
     "nwq_vqe_eval": [_vh, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+    "nwq_vqe_eval_coeffs": [_vh, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "nwq_vqe_eval_single": [_vh, C.c_void_p, C.c_void_p, C.c_void_p],
     "nwq_vqe_set_config": [_vh, C.c_int, C.c_int, C.c_int],
     "nwq_vqe_get_config": [_vh, _ip, _ip, _ip],
@@ -31,7 +32,8 @@ for _name, _args in {
     _f.argtypes = _args
     _f.restype = C.c_int
 
-EXPORTED = ("nwq_vqe_create", "nwq_vqe_destroy", "nwq_vqe_info", "nwq_vqe_eval", "nwq_vqe_eval_single",
+EXPORTED = ("nwq_vqe_create", "nwq_vqe_destroy", "nwq_vqe_info", "nwq_vqe_eval", "nwq_vqe_eval_coeffs",
+            "nwq_vqe_eval_single",
             "nwq_vqe_set_config", "nwq_vqe_get_config", "nwq_vqe_autotune")
 
 
@@ -92,6 +94,18 @@ class VQE:
         E = torch.empty(B, dtype=torch.float64, device=t.device)
         G = torch.empty(B, self.P, dtype=torch.float64, device=t.device) if grad else None
         _check(lib.nwq_vqe_eval(self.h, B, t.data_ptr(), E.data_ptr(), G.data_ptr() if grad else None))
+        return E, G
+
+    def eval_coeffs(self, theta: torch.Tensor, coeffs: torch.Tensor, grad: bool = True):
+        """As eval, with per-vector Hamiltonian coefficients coeffs [B, n_terms] (device)."""
+        t = self._theta2d(theta)
+        B = t.shape[0]
+        c = coeffs.detach().to(torch.float64).contiguous()
+        assert c.is_cuda and c.shape[0] == B
+        E = torch.empty(B, dtype=torch.float64, device=t.device)
+        G = torch.empty(B, self.P, dtype=torch.float64, device=t.device) if grad else None
+        _check(lib.nwq_vqe_eval_coeffs(self.h, B, t.data_ptr(), c.data_ptr(), E.data_ptr(),
+                                       G.data_ptr() if grad else None))
         return E, G
 
     def eval_single(self, theta: torch.Tensor, grad: bool = True):

@@ -258,7 +258,7 @@ class Request:
     n: int
     L: int = 0
     want_grad: bool = False
-    steps: int = 1            # optimiser steps (sv_vqe) resubmitting new theta
+    steps: int = 1            # sv_vqe: optimiser steps (new theta each); dm_tfim: Trotter steps
     seed: int = 0
     h: float = 1.0
     extra: dict = field(default_factory=dict)
@@ -266,8 +266,10 @@ class Request:
 
 def serving_trace(num: int = 2000, rate: float = 100.0, seed: int = 7,
                   sv_frac: float = 0.7, sv_n=(10, 24), dm_n=(6, 12),
-                  L_range=(4, 8), opt_steps=(1, 20)) -> List[Request]:
-    """Poisson arrivals at `rate` per second of a request mix."""
+                  L_range=(4, 8), opt_steps=(1, 20), dm_steps: int = 10) -> List[Request]:
+    """Poisson arrivals at `rate` per second of a request mix.  `steps` is the
+    number of optimiser steps of an SV request and the number of Trotter
+    steps of a DM request."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out: List[Request] = []
@@ -281,7 +283,7 @@ def serving_trace(num: int = 2000, rate: float = 100.0, seed: int = 7,
                         seed=int(rng.integers(1 << 31)),
                         h=float(rng.uniform(0.5, 1.5)))
         else:
-            r = Request(i, t, "dm_tfim", int(rng.integers(dm_n[0], dm_n[1] + 1)),
+            r = Request(i, t, "dm_tfim", int(rng.integers(dm_n[0], dm_n[1] + 1)), steps=dm_steps,
                         seed=int(rng.integers(1 << 31)))
         out.append(r)
     return out
