@@ -167,6 +167,9 @@ def main():
         return
 
     total_bytes = step_bytes(n, gates)
+    from paper_2401_06861_amd import autotune
+    tuned = autotune.tune(st.h, reps=2, cache_path=None)     # launch shapes for this state size
+    log(f"[bench] autotuned launch shapes: {tuned}")
 
     def step():
         st.reset()
@@ -206,7 +209,8 @@ def main():
            "config": {"workload": f"brickwork random circuit depth {args.depth}, n={n} state vector complex128, "
                                   "one kernel per gate, then <Z_i> for all i", "n": n, "depth": args.depth,
                       "gates": len(gates), "seed": 0, "parallelism": "single GPU"},
-           "pct_peak": round(value / HBM_PEAK_GBS, 4), "roofline": roofline, "kernels": per_class}
+           "pct_peak": round(value / HBM_PEAK_GBS, 4), "roofline": roofline, "kernels": per_class,
+           "launch_shapes": {k: {"ppt": v[0], "nontemporal": v[1]} for k, v in tuned.items()}}
 
     if not args.no_extras:
         out["fused"] = fused_leg(nwq, st, arrays, gates, n, args.fuse_k, ms_per_step)

@@ -242,6 +242,26 @@ int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_pe
 int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
 
 /* ---------------------------------------------------------------------------
+ * Launch shapes and their autotuner
+ * ------------------------------------------------------------------------- */
+
+/* Kernel class ids are the timing classes below (1 sv_1q_dense, 2 sv_diag,
+ * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q).  A launch shape is the number
+ * of pairs / groups per thread (1, 2, 4 or 8) and a non-temporal hint on the
+ * loads and stores (0 or 1). */
+int nwq_set_launch(nwq_handle h, int cls, int ppt, int nontemporal);
+int nwq_get_launch(nwq_handle h, int cls, int* ppt, int* nontemporal);
+
+/* Autotuner: for each class that applies to the handle (SV: 1, 2, 3, 4;
+ * DM: 6) time every launch shape with HIP events on the handle's stream and
+ * state (self-inverse operations applied in pairs on low, middle and high
+ * qubits, so the state is unchanged up to the rounding of H H), keep the
+ * fastest, and write its time per launch in ms to best_ms[class]
+ * (NWQ_TIMING_CLASSES entries, -1 where not tuned; best_ms may be NULL).
+ * Flushes deferred work first; synchronises. */
+int nwq_autotune(nwq_handle h, int reps, double* best_ms);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 

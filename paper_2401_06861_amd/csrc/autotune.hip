@@ -1,0 +1,138 @@
+// Launch-shape autotuner for the streaming gate kernels of a handle.
+//
+// For each kernel class it times every candidate (groups per thread in
+// {1, 2, 4, 8} x non-temporal hint off/on) with HIP events on the handle's
+// own stream and state, and keeps the fastest.  Candidates apply
+// self-inverse operations in pairs on low, middle and high qubits (H H for
+// the dense 1-qubit kernel, Z Z for the diagonal kernel, CX CX for the
+// permutation kernel, CZ as a dense 4x4 twice for the 2-qubit kernel, and on a
+// density matrix Z (x) conj(Z) twice for the 1-qubit superoperator kernel),
+// so the state is unchanged except for the rounding of H H.
+#include <algorithm>
+#include <cmath>
+
+#include "engine.h"
+
+namespace nwq {
+namespace {
+
+struct Cand { int ppt, nt; };
+const Cand kCands[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {1, 1}, {2, 1}, {4, 1}, {8, 1}};
+
+using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
+
+void run_1q(nwq_state* h, const LaunchCfg& c, int q) {
+  const double r = 1.0 / std::sqrt(2.0);
+  Mat2 m;
+  m.m[0] = make_double2(r, 0); m.m[1] = make_double2(r, 0); m.m[2] = make_double2(r, 0); m.m[3] = make_double2(-r, 0);
+  launch_sv_1q(h->stream, h->data, h->nbits, q, m, c);
+  launch_sv_1q(h->stream, h->data, h->nbits, q, m, c);
+}
+void run_diag(nwq_state* h, const LaunchCfg& c, int q) {
+  Diag4 d{};
+  d.d[0] = make_double2(1, 0); d.d[1] = make_double2(-1, 0); d.d[2] = d.d[0]; d.d[3] = d.d[1];
+  launch_sv_diag(h->stream, h->data, h->nbits, q, -1, d, c);
+  launch_sv_diag(h->stream, h->data, h->nbits, q, -1, d, c);
+}
+void run_perm(nwq_state* h, const LaunchCfg& c, int q) {
+  const int t = q + 1 < h->nbits ? q + 1 : q - 1;
+  launch_sv_swap2(h->stream, h->data, h->nbits, q, t, 1ull << q, (1ull << q) + (1ull << t), c);
+  launch_sv_swap2(h->stream, h->data, h->nbits, q, t, 1ull << q, (1ull << q) + (1ull << t), c);
+}
+void run_2q(nwq_state* h, const LaunchCfg& c, int q) {
+  const int t = q + 1 < h->nbits ? q + 1 : q - 1;
+  Mat4 m{};
+  for (int i = 0; i < 4; ++i) m.m[5 * i] = make_double2(i == 3 ? -1.0 : 1.0, 0);
+  launch_sv_2q(h->stream, h->data, h->nbits, q, t, m, c);
+  launch_sv_2q(h->stream, h->data, h->nbits, q, t, m, c);
+}
+void run_dm1(nwq_state* h, const LaunchCfg& c, int q) {
+  Mat4 m{};   // Z (x) conj(Z) on (column q, row q + n): diag(1, -1, -1, 1)
+  const double dz[4] = {1, -1, -1, 1};
+  for (int i = 0; i < 4; ++i) m.m[5 * i] = make_double2(dz[i], 0);
+  launch_sv_2q(h->stream, h->data, h->nbits, q, q + h->n, m, c);
+  launch_sv_2q(h->stream, h->data, h->nbits, q, q + h->n, m, c);
+}
+
+}  // namespace
+}  // namespace nwq
+
+using namespace nwq;
+
+extern "C" {
+
+int nwq_set_launch(nwq_handle h, int cls, int ppt, int nontemporal) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
+  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8");
+  h->cfg[cls].ppt = ppt;
+  h->cfg[cls].nt = nontemporal ? 1 : 0;
+  return NWQ_OK;
+}
+
+int nwq_get_launch(nwq_handle h, int cls, int* ppt, int* nontemporal) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
+  if (ppt) *ppt = h->cfg[cls].ppt;
+  if (nontemporal) *nontemporal = h->cfg[cls].nt;
+  return NWQ_OK;
+}
+
+int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (reps < 1 || reps > 100) return set_error(NWQ_EINVAL, "reps must be in [1, 100]");
+  int rc = flush_all(h);
+  if (rc) return rc;
+  if (best_ms)
+    for (int i = 0; i < KC_COUNT; ++i) best_ms[i] = -1.0;
+  struct Job { int cls; Runner run; int span; };
+  std::vector<Job> jobs;
+  if (h->kind == NWQ_KIND_SV) {
+    jobs.push_back({KC_SV1Q, run_1q, h->n});
+    jobs.push_back({KC_DIAG, run_diag, h->n});
+    if (h->n >= 2) {
+      jobs.push_back({KC_PERM, run_perm, h->n});
+      jobs.push_back({KC_SV2Q, run_2q, h->n});
+    }
+  } else {
+    jobs.push_back({KC_DM1, run_dm1, h->n});
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+  if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+  for (const Job& j : jobs) {
+    if (rc) break;
+    const int qs[3] = {0, j.span / 2, std::max(0, j.span - 1)};
+    double best = 1e300;
+    LaunchCfg best_c = h->cfg[j.cls];
+    for (const Cand& c : kCands) {
+      LaunchCfg cfg;
+      cfg.ppt = c.ppt;
+      cfg.nt = c.nt;
+      for (int q : qs) j.run(h, cfg, q);   // warm-up
+      rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+      for (int r = 0; r < reps && !rc; ++r)
+        for (int q : qs) j.run(h, cfg, q);
+      if (!rc) rc = check_hip(hipGetLastError(), "autotune launch");
+      if (!rc) rc = check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
+      if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (rc) break;
+      const double per = ms / (2.0 * reps * 3.0);   // per launch
+      if (per < best) {
+        best = per;
+        best_c = cfg;
+      }
+    }
+    if (!rc) {
+      h->cfg[j.cls] = best_c;
+      if (best_ms) best_ms[j.cls] = best;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // extern "C"

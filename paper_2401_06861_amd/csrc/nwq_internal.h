@@ -30,7 +30,8 @@ struct QSet {
 
 // Streaming launch shape chosen by the autotuner (per kernel class).
 struct LaunchCfg {
-  int ppt = 4;                       // pairs / groups / elements per thread
+  int ppt = 4;                       // pairs / groups / elements per thread (1, 2, 4, 8)
+  int nt = 0;                        // 1: non-temporal loads and stores
 };
 
 // Kernel classes (also the timing classes of nwq_timing_read).
@@ -41,12 +42,12 @@ enum KClass {
 
 // ---- launchers (kernels_sv.hip) -------------------------------------------
 void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len);
-void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, int ppt);
-void launch_sv_diag(hipStream_t s, double2* a, int nbits, int q0, int q1, const Diag4& d, int ppt);
-void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, int ppt);
+void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, const LaunchCfg& cfg);
+void launch_sv_diag(hipStream_t s, double2* a, int nbits, int q0, int q1, const Diag4& d, const LaunchCfg& cfg);
+void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, const LaunchCfg& cfg);
 void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb,
-                     unsigned long long offA, unsigned long long offB, int ppt);
-void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, int ppt);
+                     unsigned long long offA, unsigned long long offB, const LaunchCfg& cfg);
+void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, const LaunchCfg& cfg);
 void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits,
                   const double2* dev_matrix);
 

@@ -74,6 +74,9 @@ _SIG = {
     "nwq_trace": [_h, _dp, _dp],
     "nwq_purity": [_h, _dp],
     "nwq_timing_enable": [_h, C.c_int],
+    "nwq_set_launch": [_h, C.c_int, C.c_int, C.c_int],
+    "nwq_get_launch": [_h, C.c_int, _ip, _ip],
+    "nwq_autotune": [_h, C.c_int, _dp],
     "nwq_timing_read": [_h, C.POINTER(C.c_longlong), _dp, C.c_int],
 }
 for _name, _args in _SIG.items():
@@ -261,6 +264,22 @@ def nwq_purity(h: int) -> float:
     out = C.c_double()
     _check(lib.nwq_purity(h, C.byref(out)))
     return out.value
+
+
+def nwq_set_launch(h: int, cls: int, ppt: int, nontemporal: int) -> None:
+    _check(lib.nwq_set_launch(h, cls, ppt, nontemporal))
+
+
+def nwq_get_launch(h: int, cls: int) -> Tuple[int, int]:
+    p, t = C.c_int(), C.c_int()
+    _check(lib.nwq_get_launch(h, cls, C.byref(p), C.byref(t)))
+    return p.value, t.value
+
+
+def nwq_autotune(h: int, reps: int = 3) -> dict:
+    ms = (C.c_double * len(TIMING_CLASSES))()
+    _check(lib.nwq_autotune(h, reps, ms))
+    return {name: float(ms[i]) for i, name in enumerate(TIMING_CLASSES) if ms[i] >= 0}
 
 
 def nwq_timing_enable(h: int, enable: bool = True) -> None:

@@ -197,3 +197,54 @@ def test_owned_allocation_and_reset(nwq):
     nwq.nwq_get_state(h, out)
     assert out[0] == 1 and np.count_nonzero(out) == 1
     nwq.nwq_destroy(h)
+
+
+@pytest.mark.parametrize("n", [3, 10, 13])
+def test_every_launch_shape_matches_oracle(nwq, n):
+    """Each kernel class under every (groups per thread, non-temporal) shape,
+    including blocks that are only partly filled (small n)."""
+    psi0 = W.random_state(n, seed=70 + n)
+    st = nwq.SVState(n, reset=False)
+    gates = {1: ("u3", (n - 1,), (0.3, 1.1, -0.7)), 2: ("rz", (n // 2,), (0.9,)),
+             3: ("cx", (0, n - 1), ()), 4: None}
+    m2 = np.array([[0.6, 0.8j, 0, 0.1], [0.2, -0.3, 0.5j, 0], [0, 0.4, 0.1 - 0.2j, 0.7], [0.3j, 0, 0.2, -0.5]])
+    for cls in (1, 2, 3, 4):
+        for ppt in (1, 2, 4, 8):
+            for nt in (0, 1):
+                nwq.nwq_set_launch(st.h, cls, ppt, nt)
+                st.load(psi0)
+                if cls == 4:
+                    st.apply_matrix([1, n - 1], m2)
+                    want = tensor.apply_op(psi0, m2, [1, n - 1], n)
+                else:
+                    st.apply(*gates[cls])
+                    want = tensor.sv_apply(psi0, gates[cls], n)
+                assert maxerr(st.numpy(), want) <= TOL, (cls, ppt, nt)
+    st.close()
+
+
+def test_autotune_keeps_state_and_parity(nwq):
+    from paper_2401_06861_amd import autotune
+    import tempfile, os
+    n = 16
+    psi0 = W.random_state(n, seed=5)
+    st = nwq.SVState(n, reset=False)
+    st.load(psi0)
+    cache = os.path.join(tempfile.mkdtemp(), "tune.json")
+    chosen = autotune.tune(st.h, reps=2, cache_path=cache)
+    assert set(chosen) == {"sv_1q_dense", "sv_diag", "sv_perm", "sv_2q_dense"}
+    assert maxerr(st.numpy(), psi0) <= 1e-13          # H H rounding only
+    again = autotune.tune(st.h, reps=2, cache_path=cache)   # from the cache
+    assert {k: v[:2] for k, v in again.items()} == {k: v[:2] for k, v in chosen.items()}
+    gates = W.random_gate_list(n, 120, seed=3)
+    st.load(psi0)
+    st.run_circuit(gates)
+    assert maxerr(st.numpy(), tensor.sv_run(gates, n, psi0)) <= TOL
+    st.close()
+    dm = nwq.DMState(4, reset=False)
+    rho0 = W.random_density_matrix(4, seed=1)
+    dm.load(rho0)
+    ms = nwq.nwq_autotune(dm.h, 2)
+    assert set(ms) == {"dm_superop_1q"}
+    assert maxerr(dm.numpy(), rho0) == 0.0
+    dm.close()
