@@ -248,11 +248,13 @@ def fused_leg(nwq, st, arrays, gates, n, k, unfused_ms):
     nwq.nwq_timing_enable(st.h, False)
     tim = nwq.nwq_timing_read(st.h, reset=True)
     blocks, fg = nwq.nwq_fusion_stats(st.h)
+    phases = nwq.nwq_fusion_phases(st.h)
     nwq.nwq_set_fusion(st.h, 0)
     c, ms = tim["sv_fused"]
     N = 1 << n
     avg = ms / max(c, 1)
-    return {"k": k, "blocks": blocks, "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
+    return {"k": k, "kernel": "register-blocked (4 register bits per phase)", "blocks": blocks, "phases": phases,
+            "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
             "circuit_ms": round(dt * 1e3, 2), "speedup_vs_one_kernel_per_gate": round(unfused_ms / (dt * 1e3), 2),
             "avg_block_ms": round(avg, 3), "block_hbm_GBs": round(32 * N / (avg * 1e-3) / 1e9, 1)}
 

@@ -141,6 +141,16 @@ int nwq_set_fusion(nwq_handle h, int k, int* k_out);
  * gates (both 0 when fusion was off). */
 int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates);
 
+/* Kernel for fused blocks of at least 2^8 amplitudes: 1 (default) =
+ * register-blocked (each thread holds 16 amplitudes over 4 tile bits and
+ * applies runs of gates on those bits in registers, one LDS exchange per
+ * run), 0 = one LDS pass per gate.  Smaller tiles always use the latter. */
+int nwq_set_fusion_kernel(nwq_handle h, int register_blocked);
+
+/* Number of register phases (LDS exchanges) of the last fused
+ * nwq_apply_circuit (0 when no register-blocked block ran). */
+int nwq_fusion_phases(nwq_handle h, int* phases);
+
 /* Host-only: the block plan nwq_apply_circuit would use for a circuit on n
  * qubits at fusion width k (parameters are not needed).  Writes the number
  * of blocks to *n_blocks, the block index of each gate to block_of_gate[]

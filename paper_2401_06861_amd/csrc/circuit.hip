@@ -8,6 +8,7 @@
 // qubits it needs.  Left-out gates start the next block.  Each block is one
 // read and one write of the state through LDS.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -89,68 +90,156 @@ int local_bit(const Block& b, int q) {
 
 }  // namespace
 
+// Encode one gate as a FusedOp (bits are tile-local for the per-gate LDS
+// kernel, register-bit indices for the register-blocked kernel) and append
+// its matrix entries.  Returns false for the identity (nothing to do).
+static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats, FusedOp& op, bool reg) {
+  cd m[16];
+  gate_matrix(g.type, g.p, m);
+  op = FusedOp{};
+  op.mat = (int)mats.size();
+  op.lo = g.nq == 2 ? std::min(b0, b1) : b0;
+  op.hi = g.nq == 2 ? std::max(b0, b1) : 0;
+  switch (g.type) {
+    case NWQ_GATE_I:
+      return false;
+    case NWQ_GATE_Z: case NWQ_GATE_S: case NWQ_GATE_SDG: case NWQ_GATE_T: case NWQ_GATE_TDG: case NWQ_GATE_RZ:
+      op.kind = 1;
+      mats.push_back(make_double2(m[0].real(), m[0].imag()));
+      mats.push_back(make_double2(m[3].real(), m[3].imag()));
+      return true;
+    case NWQ_GATE_CX:
+      op.kind = 3;
+      op.o0 = reg ? b0 : (1 << b0);
+      op.o1 = reg ? b1 : (1 << b0) + (1 << b1);
+      return true;
+    case NWQ_GATE_SWAP:
+      op.kind = reg ? 5 : 3;
+      op.o0 = reg ? b0 : (1 << b0);
+      op.o1 = reg ? b1 : (1 << b1);
+      return true;
+    case NWQ_GATE_CZ: case NWQ_GATE_RZZ:
+      op.kind = 4;
+      op.o0 = b0;
+      op.o1 = b1;
+      for (int u = 0; u < 4; ++u) mats.push_back(make_double2(m[5 * u].real(), m[5 * u].imag()));
+      return true;
+    default:
+      op.kind = 0;
+      for (int i = 0; i < 4; ++i) mats.push_back(make_double2(m[i].real(), m[i].imag()));
+      return true;
+  }
+}
+
+// Split a block's gates (tile-local bits) into register phases: greedily
+// take, in order, every gate whose bits fit the phase's 4 register bits and
+// that no earlier left-out gate shares a bit with; pad the set to 4 bits.
+struct Phase {
+  int reg[4];
+  std::vector<int> gates;
+};
+
+static std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
+                                      const std::vector<int>& nq, int k) {
+  std::vector<Phase> out;
+  std::vector<int> rem = order;
+  while (!rem.empty()) {
+    unsigned S = 0, blocked = 0;
+    Phase ph;
+    std::vector<int> keep;
+    for (int gi : rem) {
+      unsigned B = 1u << lb[gi][0];
+      if (nq[gi] == 2) B |= 1u << lb[gi][1];
+      if (B & blocked) {
+        blocked |= B;
+        keep.push_back(gi);
+        continue;
+      }
+      if (__builtin_popcount(S | B) <= 4) {
+        S |= B;
+        ph.gates.push_back(gi);
+      } else {
+        blocked |= B;
+        keep.push_back(gi);
+      }
+    }
+    for (int b = 0; b < k && __builtin_popcount(S) < 4; ++b) S |= 1u << b;
+    int r = 0;
+    for (int b = 0; b < k; ++b)
+      if ((S >> b) & 1u) ph.reg[r++] = b;
+    out.push_back(std::move(ph));
+    rem.swap(keep);
+  }
+  return out;
+}
+
 static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   const std::vector<Block> blocks = plan_blocks(gates, h->n, h->fuse_k);
   if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
-  // Program: FusedOp table then double2 matrix table, in one upload.
+  // Program: [phase table][op table][matrix table] in one upload.
+  std::vector<FusedPhase> phases;
   std::vector<FusedOp> ops;
   std::vector<double2> mats;
-  std::vector<FusedBlockDev> bdev;
+  struct Launch { FusedBlockDev d; bool rb; };
+  std::vector<Launch> launches;
   for (const Block& b : blocks) {
     FusedBlockDev d{};
     d.c = b.c;
     d.m = b.m;
     for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
-    d.op_begin = (int)ops.size();
-    for (int gi : b.gates) {
-      const PGate& g = gates[gi];
-      cd m[16];
-      gate_matrix(g.type, g.p, m);
-      FusedOp op{};
-      op.mat = (int)mats.size();
-      const int l0 = local_bit(b, g.q[0]);
-      const int l1 = g.nq == 2 ? local_bit(b, g.q[1]) : -1;
-      op.lo = g.nq == 2 ? std::min(l0, l1) : l0;
-      op.hi = g.nq == 2 ? std::max(l0, l1) : 0;
-      switch (g.type) {
-        case NWQ_GATE_I:
-          continue;
-        case NWQ_GATE_Z: case NWQ_GATE_S: case NWQ_GATE_SDG: case NWQ_GATE_T: case NWQ_GATE_TDG: case NWQ_GATE_RZ:
-          op.kind = 1;
-          mats.push_back(make_double2(m[0].real(), m[0].imag()));
-          mats.push_back(make_double2(m[3].real(), m[3].imag()));
-          break;
-        case NWQ_GATE_CX:
-          op.kind = 3;
-          op.o0 = 1 << l0;
-          op.o1 = (1 << l0) + (1 << l1);
-          break;
-        case NWQ_GATE_SWAP:
-          op.kind = 3;
-          op.o0 = 1 << l0;
-          op.o1 = 1 << l1;
-          break;
-        case NWQ_GATE_CZ: case NWQ_GATE_RZZ:
-          op.kind = 4;
-          op.o0 = l0;
-          op.o1 = l1;
-          for (int u = 0; u < 4; ++u) mats.push_back(make_double2(m[5 * u].real(), m[5 * u].imag()));
-          break;
-        default:
-          op.kind = 0;
-          for (int i = 0; i < 4; ++i) mats.push_back(make_double2(m[i].real(), m[i].imag()));
-          break;
+    const int k = b.c + b.m;
+    const bool rb = h->fuse_rb && k >= 8;
+    if (!rb) {
+      d.op_begin = (int)ops.size();
+      for (int gi : b.gates) {
+        const PGate& g = gates[gi];
+        FusedOp op;
+        if (encode_op(g, local_bit(b, g.q[0]), g.nq == 2 ? local_bit(b, g.q[1]) : 0, mats, op, false))
+          ops.push_back(op);
       }
-      ops.push_back(op);
+      d.op_count = (int)ops.size() - d.op_begin;
+      if (d.op_count > 0) launches.push_back({d, false});
+      continue;
     }
-    d.op_count = (int)ops.size() - d.op_begin;
-    if (d.op_count > 0) bdev.push_back(d);
+    std::vector<std::array<int, 2>> lb(gates.size());
+    std::vector<int> nq(gates.size(), 1);
+    std::vector<int> order;
+    for (int gi : b.gates) {
+      if (gates[gi].type == NWQ_GATE_I) continue;
+      lb[gi] = {local_bit(b, gates[gi].q[0]), gates[gi].nq == 2 ? local_bit(b, gates[gi].q[1]) : 0};
+      nq[gi] = gates[gi].nq;
+      order.push_back(gi);
+    }
+    if (order.empty()) continue;
+    d.op_begin = (int)phases.size();
+    for (const Phase& ph : plan_phases(order, lb, nq, k)) {
+      FusedPhase fp{};
+      for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i];
+      fp.op_begin = (int)ops.size();
+      auto ridx = [&](int bit) {
+        for (int i = 0; i < 4; ++i)
+          if (ph.reg[i] == bit) return i;
+        return -1;
+      };
+      for (int gi : ph.gates) {
+        FusedOp op;
+        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true))
+          ops.push_back(op);
+      }
+      fp.op_count = (int)ops.size() - fp.op_begin;
+      phases.push_back(fp);
+    }
+    d.op_count = (int)phases.size() - d.op_begin;
+    launches.push_back({d, true});
   }
+  const size_t ph_bytes = phases.size() * sizeof(FusedPhase);
+  const size_t ops_off = (ph_bytes + 255) & ~size_t(255);
   const size_t ops_bytes = ops.size() * sizeof(FusedOp);
-  const size_t mats_off = (ops_bytes + 255) & ~size_t(255);
+  const size_t mats_off = (ops_off + ops_bytes + 255) & ~size_t(255);
   const size_t total = mats_off + mats.size() * sizeof(double2) + 16;
   std::vector<char> prog(total, 0);
-  if (!ops.empty()) std::memcpy(prog.data(), ops.data(), ops_bytes);
+  if (!phases.empty()) std::memcpy(prog.data(), phases.data(), ph_bytes);
+  if (!ops.empty()) std::memcpy(prog.data() + ops_off, ops.data(), ops_bytes);
   if (!mats.empty()) std::memcpy(prog.data() + mats_off, mats.data(), mats.size() * sizeof(double2));
   void* dev = nullptr;
   if (total <= (2u << 20)) {
@@ -175,17 +264,22 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
     if (rc) return rc;
     dev = h->fuse_dev;
   }
-  const FusedOp* dops = static_cast<const FusedOp*>(dev);
+  const FusedPhase* dph = static_cast<const FusedPhase*>(dev);
+  const FusedOp* dops = reinterpret_cast<const FusedOp*>(static_cast<char*>(dev) + ops_off);
   const double2* dmats = reinterpret_cast<const double2*>(static_cast<char*>(dev) + mats_off);
-  for (const FusedBlockDev& d : bdev) {
+  for (const Launch& L : launches) {
     timing_begin(h, KC_FUSED);
-    launch_fused_block(h->stream, h->data, h->nbits, d, dops, dmats, h->fuse_k);
+    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats);
+    else launch_fused_block(h->stream, h->data, h->nbits, L.d, dops, dmats, h->fuse_k);
     timing_end(h);
     const int rc = check_hip(hipGetLastError(), "fused_block");
     if (rc) return rc;
   }
-  h->last_blocks = (int)bdev.size();
-  h->last_fused_gates = (int)ops.size();
+  h->last_blocks = (int)launches.size();
+  h->last_fused_gates = 0;
+  for (const Block& b : blocks)
+    for (int gi : b.gates) h->last_fused_gates += gates[gi].type != NWQ_GATE_I;
+  h->last_phases = (int)phases.size();
   return NWQ_OK;
 }
 
@@ -234,6 +328,7 @@ int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qu
   if (rc0) return rc0;
   h->last_blocks = 0;
   h->last_fused_gates = 0;
+  h->last_phases = 0;
   if (h->kind == NWQ_KIND_SV && h->fuse_k > 0 && n_gates > 0) return apply_fused(h, gates);
   for (const PGate& g : gates) {
     int rc;
@@ -246,6 +341,12 @@ int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qu
     }
     if (rc) return rc;
   }
+  return NWQ_OK;
+}
+
+int nwq_set_fusion_kernel(nwq_handle h, int register_blocked) {
+  if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
+  h->fuse_rb = register_blocked != 0;
   return NWQ_OK;
 }
 
@@ -285,6 +386,12 @@ int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
   if (blocks) *blocks = h->last_blocks;
   if (gates) *gates = h->last_fused_gates;
+  return NWQ_OK;
+}
+
+int nwq_fusion_phases(nwq_handle h, int* phases) {
+  if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
+  if (phases) *phases = h->last_phases;
   return NWQ_OK;
 }
 

@@ -44,7 +44,8 @@ struct nwq_state {
 
   // SV fusion
   int fuse_k = 0;                  // 0 = off
-  int last_blocks = 0, last_fused_gates = 0;
+  int last_blocks = 0, last_fused_gates = 0, last_phases = 0;
+  bool fuse_rb = true;             // register-blocked fused kernel for tiles of >= 2^8
   void* fuse_dev = nullptr;        // device copy of the compiled block program
   size_t fuse_cap = 0;
 

@@ -99,6 +99,18 @@ struct FusedBlockDev {
 };
 void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk,
                         const FusedOp* ops, const double2* mats, int lds_k);
+// Register-blocked blocks: blk.op_begin / op_count index a phase table; each
+// phase holds 4 register bits (tile-local, ascending) and a range of ops whose
+// lo / o0 / o1 fields are register-bit indices 0..3.  Tiles of 2^k amplitudes,
+// 8 <= k <= 13, 2^(k-4) threads.  Op kinds as FusedOp plus 5 = SWAP (o0, o1).
+struct FusedPhase {
+  int reg[4];
+  int op_begin, op_count;
+  int pad0, pad1;
+};
+size_t fused_rb_lds_bytes(int k);
+void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
+                     const FusedOp* ops, const double2* mats);
 
 // ---- error handling (engine.hip) ------------------------------------------
 int set_error(int code, const std::string& msg);

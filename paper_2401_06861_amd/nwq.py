@@ -64,6 +64,8 @@ _SIG = {
     "nwq_apply_circuit": [_h, C.c_int, _ip, _ip, _dp],
     "nwq_set_fusion": [_h, C.c_int, _ip],
     "nwq_fusion_stats": [_h, _ip, _ip],
+    "nwq_set_fusion_kernel": [_h, C.c_int],
+    "nwq_fusion_phases": [_h, _ip],
     "nwq_fusion_plan": [C.c_int, C.c_int, C.c_int, _ip, _ip, _ip, _ip, _ip],
     "nwq_apply_channel": [_h, _ip, C.c_int, _dp, C.c_int],
     "nwq_depolarize": [_h, _ip, C.c_int, C.c_double],
@@ -205,6 +207,16 @@ def nwq_fusion_stats(h: int) -> Tuple[int, int]:
     b, g = C.c_int(), C.c_int()
     _check(lib.nwq_fusion_stats(h, C.byref(b), C.byref(g)))
     return b.value, g.value
+
+
+def nwq_set_fusion_kernel(h: int, register_blocked: bool) -> None:
+    _check(lib.nwq_set_fusion_kernel(h, int(bool(register_blocked))))
+
+
+def nwq_fusion_phases(h: int) -> int:
+    p = C.c_int()
+    _check(lib.nwq_fusion_phases(h, C.byref(p)))
+    return p.value
 
 
 def nwq_fusion_plan(n: int, k: int, types: np.ndarray, qubits: np.ndarray):

@@ -248,3 +248,22 @@ def test_autotune_keeps_state_and_parity(nwq):
     assert set(ms) == {"dm_superop_1q"}
     assert maxerr(dm.numpy(), rho0) == 0.0
     dm.close()
+
+
+@pytest.mark.parametrize("n,k", [(8, 8), (12, 8), (14, 12), (17, 13), (20, 12)])
+def test_register_blocked_fused_kernel(nwq, n, k):
+    """Both fused-block kernels (register-blocked phases and one LDS pass per
+    gate) against the oracle on a random circuit with every gate kind."""
+    gates = W.random_gate_list(n, 300, seed=7 * n + k) + W.brickwork_circuit(n, 6, seed=n)
+    psi0 = W.random_state(n, seed=n)
+    want = tensor.sv_run(gates, n, psi0)
+    for rb in (1, 0):
+        st = nwq.SVState(n, reset=False)
+        st.load(psi0)
+        st.set_fusion(k)
+        nwq.nwq_set_fusion_kernel(st.h, rb)
+        st.run_circuit(gates)
+        assert maxerr(st.numpy(), want) <= TOL, (n, k, rb)
+        if rb:
+            assert nwq.nwq_fusion_phases(st.h) > 0
+        st.close()
