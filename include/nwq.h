@@ -224,9 +224,10 @@ int nwq_vqe_info(nwq_vqe_handle h, int* n_params, int* n_ops, int* n_slots);
 /* Batched path: B parameter vectors theta_dev[B][n_params] (device, FP64)
  * -> energy_dev[B] and, if grad_dev is non-NULL, grad_dev[B][n_params]
  * (device).  n <= 12 runs one persistent LDS-resident kernel (one workgroup
- * per vector); larger n run the per-gate schedule over all B states,
- * captured once per (B, with/without gradient) into a hipGraph and replayed.
- * Results for a vector do not depend on B or on the other vectors. */
+ * per vector); larger n run the fused-block schedule over all B states
+ * (see nwq_vqe_set_config), captured once per (B, with/without gradient)
+ * into a hipGraph and replayed.  Results for a vector do not depend on B or
+ * on the other vectors. */
 int nwq_vqe_eval(nwq_vqe_handle h, int B, const double* theta_dev, double* energy_dev, double* grad_dev);
 
 /* As nwq_vqe_eval, with per-vector Hamiltonian coefficients:
@@ -240,9 +241,13 @@ int nwq_vqe_eval_coeffs(nwq_vqe_handle h, int B, const double* theta_dev, const 
  * vector, one kernel per gate, no graph, no LDS residency. */
 int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energy_dev, double* grad_dev);
 
-/* Launch configuration: mode 0 = automatic, 1 = LDS-resident (n <= 12),
- * 2 = per-gate graph; threads per workgroup of the LDS kernel (64..1024,
- * power of two); blocks per state of the per-gate kernels (0 = default). */
+/* Launch configuration: mode 0 = automatic (LDS-resident for n <= 12, fused
+ * for larger n), 1 = LDS-resident (n <= 12), 2 = one kernel per gate over the
+ * batch, 3 = fused blocks (n >= 8: 2^11-amplitude tiles; forward through the
+ * register-blocked block kernel over all B states, backward with tiles of phi
+ * and lambda in LDS); all but the LDS-resident path run as one hipGraph per
+ * batch size.  threads: workgroup size of the LDS kernel (64..1024, power of
+ * two); blocks_per_state: workgroups per state of modes 2 and 3 (0 = default). */
 int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_state);
 int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_per_state);
 

@@ -15,20 +15,6 @@
 #include "engine.h"
 
 namespace nwq {
-namespace {
-
-struct PGate {
-  int type;
-  int q[2];
-  int nq;
-  double p[3];
-};
-
-struct Block {
-  int c = 0, m = 0;
-  int hi[8] = {0};
-  std::vector<int> gates;    // indices into the circuit
-};
 
 // Every block has at least two high slots (c <= k - 2), so the first
 // remaining gate always fits and each round absorbs at least one gate.
@@ -81,14 +67,24 @@ std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k) {
   return out;
 }
 
+// Widen a block's tile with unused high qubits (ascending) up to width
+// k_target (or n): more amplitudes per tile, same gates, same result.
+void pad_block(Block& b, int n, int k_target) {
+  const int want = std::min(k_target, n);
+  for (int q = b.c; q < n && b.c + b.m < want && b.m < 8; ++q) {
+    bool used = false;
+    for (int i = 0; i < b.m; ++i) used |= b.hi[i] == q;
+    if (!used) b.hi[b.m++] = q;
+  }
+  std::sort(b.hi, b.hi + b.m);
+}
+
 int local_bit(const Block& b, int q) {
   if (q < b.c) return q;
   for (int i = 0; i < b.m; ++i)
     if (b.hi[i] == q) return b.c + i;
   return -1;
 }
-
-}  // namespace
 
 // Encode one gate as a FusedOp (bits are tile-local for the per-gate LDS
 // kernel, register-bit indices for the register-blocked kernel) and append
@@ -134,12 +130,7 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
 // Split a block's gates (tile-local bits) into register phases: greedily
 // take, in order, every gate whose bits fit the phase's 4 register bits and
 // that no earlier left-out gate shares a bit with; pad the set to 4 bits.
-struct Phase {
-  int reg[4];
-  std::vector<int> gates;
-};
-
-static std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
+std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
                                       const std::vector<int>& nq, int k) {
   std::vector<Phase> out;
   std::vector<int> rem = order;
@@ -182,7 +173,8 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   std::vector<double2> mats;
   struct Launch { FusedBlockDev d; bool rb; };
   std::vector<Launch> launches;
-  for (const Block& b : blocks) {
+  for (Block b : blocks) {
+    if (h->fuse_rb && b.c + b.m < 8 && h->n >= 8) pad_block(b, h->n, 8);
     FusedBlockDev d{};
     d.c = b.c;
     d.m = b.m;

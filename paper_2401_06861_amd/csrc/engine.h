@@ -3,6 +3,7 @@
 // (whole-circuit application and the fusion planner).
 #pragma once
 
+#include <array>
 #include <vector>
 
 #include "nwq_internal.h"
@@ -58,6 +59,30 @@ struct nwq_state {
 };
 
 namespace nwq {
+// A gate of a circuit (type nwq_gate, qubits, up to 3 parameters).
+struct PGate {
+  int type;
+  int q[2];
+  int nq;
+  double p[3];
+};
+// A fused block: tile qubits {0..c-1} u hi[0..m), and its gates in order.
+struct Block {
+  int c = 0, m = 0;
+  int hi[8] = {0};
+  std::vector<int> gates;
+};
+// A register phase of a block: 4 tile-local register bits and its gates.
+struct Phase {
+  int reg[4];
+  std::vector<int> gates;
+};
+std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
+int local_bit(const Block& b, int q);
+void pad_block(Block& b, int n, int k_target);
+std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
+                               const std::vector<int>& nq, int k);
+
 void gate_matrix(int type, const double* p, cd* m);
 int arena_put(nwq_state* h, const void* src, size_t bytes, void** dev_out);
 void timing_begin(nwq_state* h, int cls);

@@ -251,11 +251,15 @@ __device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[16], const 
   }
 }
 
-__global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a, int nbits, FusedBlockDev blk,
+__global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a0, int nbits, FusedBlockDev blk,
                                                   const FusedPhase* __restrict__ phases,
                                                   const FusedOp* __restrict__ ops,
-                                                  const double2* __restrict__ mats) {
+                                                  const double2* __restrict__ mats0,
+                                                  unsigned long long state_stride, int mat_stride) {
   extern __shared__ double2 t[];
+  // batch element blockIdx.y: its own state and its own matrix table
+  double2* __restrict__ a = a0 + (size_t)blockIdx.y * state_stride;
+  const double2* __restrict__ mats = mats0 + (size_t)blockIdx.y * mat_stride;
   const int c = blk.c, m = blk.m, k = c + m;
   const unsigned len = 1u << k;
   const unsigned nt = len >> 4;
@@ -318,14 +322,15 @@ __global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a, int n
 size_t fused_rb_lds_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << k) / 16); }
 
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
-                     const FusedOp* ops, const double2* mats) {
+                     const FusedOp* ops, const double2* mats, int batch, int mat_stride, int max_grid) {
   const int k = blk.c + blk.m;
   const unsigned long long ntiles = 1ull << (nbits - k);
-  const unsigned long long cap = 1ull << 20;
+  const unsigned long long cap = max_grid > 0 ? (unsigned long long)max_grid : (1ull << 20);
   const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
   const size_t lds = fused_rb_lds_bytes(k);
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused_rb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_fused_rb, dim3(grid), dim3(1u << (k - 4)), lds, s, a, nbits, blk, phases, ops, mats);
+  hipLaunchKernelGGL(k_fused_rb, dim3(grid, batch), dim3(1u << (k - 4)), lds, s, a, nbits, blk, phases, ops, mats,
+                     batch > 1 ? (1ull << nbits) : 0ull, mat_stride);
 }
 
 }  // namespace nwq

@@ -109,8 +109,10 @@ struct FusedPhase {
   int pad0, pad1;
 };
 size_t fused_rb_lds_bytes(int k);
+// batch > 1: blockIdx.y = batch element b works on a + b * 2^nbits with the
+// matrix table mats + b * mat_stride; max_grid caps the tiles' grid (0 = 2^20).
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
-                     const FusedOp* ops, const double2* mats);
+                     const FusedOp* ops, const double2* mats, int batch = 1, int mat_stride = 0, int max_grid = 0);
 
 // ---- error handling (engine.hip) ------------------------------------------
 int set_error(int code, const std::string& msg);

@@ -455,6 +455,169 @@ __global__ __launch_bounds__(64) void k_vqe_finish(const double* __restrict__ ep
 
 }  // namespace
 
+namespace {
+// ---------------------------------------------------------------------------
+// Fused path (any n > tile): gates grouped into k-qubit blocks as for state
+// vectors; the forward pass runs the register-blocked fused kernel over all
+// B states with a per-vector matrix table, the backward pass holds tiles of
+// phi and lambda in LDS and sweeps each block's gates in reverse.
+// ---------------------------------------------------------------------------
+struct VqeBwdOp {
+  int kind;    // 0 rotation, 1 RZZ, 2 fixed 2x2, 3 CX, 4 CZ, 5 SWAP
+  int lo, hi;  // sorted tile-local bits
+  int b0, b1;  // tile-local bits in operator order
+  int axis;    // rotation axis
+  int slot;    // gradient slot or -1
+  int mat;     // index of the adjoint matrix in the per-vector table (double2 units)
+};
+
+constexpr int kBwdBlock = 256;
+constexpr int kBwdMaxOps = 128;
+
+// Per-vector matrix table: for op i, entries [8i, 8i+4) hold the forward
+// matrix (2x2 row-major, or the 4 diagonal entries of RZZ / CZ indexed by
+// u = bit q0 + 2 bit q1) and [8i+4, 8i+8) the adjoint.  Every case stores
+// inside its own branch.
+__global__ __launch_bounds__(256) void k_vqe_mats(const VqeOp* __restrict__ ops, int nops,
+                                                  const double2* __restrict__ fixed,
+                                                  const double* __restrict__ theta, int P,
+                                                  double2* __restrict__ table) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nops) return;
+  const int b = blockIdx.y;
+  const VqeOp op = ops[i];
+  const double* th = theta + (size_t)b * P;
+  double2* t = table + ((size_t)b * nops + i) * 8;
+  if (op.kind == OP_ROT) {
+    const M2 f = rot_matrix(op.axis, th[op.param], false);
+    st(t + 0, f.m0); st(t + 1, f.m1); st(t + 2, f.m2); st(t + 3, f.m3);
+    const M2 a = rot_matrix(op.axis, th[op.param], true);
+    st(t + 4, a.m0); st(t + 5, a.m1); st(t + 6, a.m2); st(t + 7, a.m3);
+  } else if (op.kind == OP_RZZ) {
+    vd2 e, o;
+    rzz_phases(th[op.param], false, e, o);
+    st(t + 0, e); st(t + 1, o); st(t + 2, o); st(t + 3, e);
+    rzz_phases(th[op.param], true, e, o);
+    st(t + 4, e); st(t + 5, o); st(t + 6, o); st(t + 7, e);
+  } else if (op.kind == OP_FIX1) {
+    for (int k = 0; k < 8; ++k) t[k] = fixed[8 * op.mat + k];
+  } else if (op.kind == OP_CZ) {
+    for (int k = 0; k < 8; ++k) st(t + k, mk((k & 3) == 3 ? -1.0 : 1.0, 0.0));
+  } else {
+    for (int k = 0; k < 8; ++k) st(t + k, mk(0.0, 0.0));
+  }
+}
+
+__global__ __launch_bounds__(kBwdBlock) void k_vqe_bwd_tile(double2* __restrict__ phi0, double2* __restrict__ lam0,
+                                                            int n, FusedBlockDev blk,
+                                                            const VqeBwdOp* __restrict__ ops,
+                                                            const double2* __restrict__ table0, int mat_stride,
+                                                            int nslots, double* __restrict__ gpart) {
+  extern __shared__ double2 sh[];
+  __shared__ double acc[kBwdMaxOps][kBwdBlock / kWave];
+  constexpr int NW = kBwdBlock / kWave;
+  const int c = blk.c, m = blk.m, k = c + m;
+  const unsigned len = 1u << k;
+  double2* tp = sh;
+  double2* tl = sh + len;
+  const unsigned long long N = 1ull << n;
+  double2* __restrict__ phi = phi0 + (size_t)blockIdx.y * N;
+  double2* __restrict__ lam = lam0 + (size_t)blockIdx.y * N;
+  const double2* __restrict__ table = table0 + (size_t)blockIdx.y * mat_stride;
+  const unsigned long long ntiles = 1ull << (n - k);
+  const unsigned cmask = (1u << c) - 1u;
+  const unsigned tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  for (int i = tid; i < blk.op_count * NW; i += kBwdBlock) acc[i / NW][i % NW] = 0.0;
+  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    unsigned long long base = tile << c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < m) {
+        const int q = blk.hi[i];
+        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
+      }
+    }
+    __syncthreads();
+    for (unsigned l = tid; l < len; l += kBwdBlock) {
+      unsigned long long g = base | (l & cmask);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
+      tp[l] = phi[g];
+      tl[l] = lam[g];
+    }
+    for (int oi = 0; oi < blk.op_count; ++oi) {
+      const VqeBwdOp op = ops[blk.op_begin + oi];
+      const double2* M = table + op.mat;
+      __syncthreads();
+      double g = 0.0;
+      if (op.kind == 0 || op.kind == 2) {
+        const vd2 m0 = ld(M), m1 = ld(M + 1), m2 = ld(M + 2), m3 = ld(M + 3);
+        const unsigned off = 1u << op.lo;
+        for (unsigned p = tid; p < (len >> 1); p += kBwdBlock) {
+          const unsigned i0 = ins0(p, op.lo);
+          const vd2 p0 = ld(tp + i0), p1 = ld(tp + i0 + off);
+          const vd2 l0 = ld(tl + i0), l1 = ld(tl + i0 + off);
+          if (op.kind == 0) g += pair_grad(op.axis, p0, p1, l0, l1);
+          st(tp + i0, cfma(m0, p0, cmul(m1, p1)));
+          st(tp + i0 + off, cfma(m2, p0, cmul(m3, p1)));
+          st(tl + i0, cfma(m0, l0, cmul(m1, l1)));
+          st(tl + i0 + off, cfma(m2, l0, cmul(m3, l1)));
+        }
+      } else if (op.kind == 1 || op.kind == 4) {
+        const vd2 d0 = ld(M), d1 = ld(M + 1), d2 = ld(M + 2), d3 = ld(M + 3);
+        for (unsigned l = tid; l < len; l += kBwdBlock) {
+          const bool a = (l >> op.b0) & 1u, b = (l >> op.b1) & 1u;
+          const vd2 f = b ? (a ? d3 : d2) : (a ? d1 : d0);
+          const vd2 pv = ld(tp + l), lv = ld(tl + l);
+          if (op.kind == 1) {
+            const double t = lv.x * pv.y - lv.y * pv.x;   // Im(conj(l) p) times the ZZ eigenvalue
+            g += (a != b) ? -t : t;
+          }
+          st(tp + l, cmul(f, pv));
+          st(tl + l, cmul(f, lv));
+        }
+      } else {   // 3 CX (control b0, target b1), 5 SWAP
+        const unsigned oa = 1u << op.b0;
+        const unsigned ob = op.kind == 3 ? (1u << op.b0) + (1u << op.b1) : (1u << op.b1);
+        for (unsigned p = tid; p < (len >> 2); p += kBwdBlock) {
+          const unsigned b = ins0(ins0(p, op.lo), op.hi);
+          const vd2 x = ld(tp + b + oa), y = ld(tp + b + ob);
+          st(tp + b + oa, y);
+          st(tp + b + ob, x);
+          const vd2 u = ld(tl + b + oa), w = ld(tl + b + ob);
+          st(tl + b + oa, w);
+          st(tl + b + ob, u);
+        }
+      }
+      if (op.slot >= 0) {
+        const double w = wave_sum(g);
+        if (lane == 0) acc[oi][wave] += w;
+      }
+    }
+    __syncthreads();
+    for (unsigned l = tid; l < len; l += kBwdBlock) {
+      unsigned long long g = base | (l & cmask);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
+      phi[g] = tp[l];
+      lam[g] = tl[l];
+    }
+  }
+  __syncthreads();
+  for (int oi = tid; oi < blk.op_count; oi += kBwdBlock) {
+    const int slot = ops[blk.op_begin + oi].slot;
+    if (slot < 0) continue;
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += acc[oi][w];
+    gpart[((size_t)blockIdx.y * nslots + slot) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+}  // namespace
+
 // ===========================================================================
 // Host: context
 // ===========================================================================
@@ -487,6 +650,13 @@ struct nwq_vqe {
   double* d_E = nullptr;
   double* d_grad = nullptr;
   double* d_coeffs = nullptr;  // staging copy of per-vector coefficients
+  double2* d_table = nullptr;  // fused path: per-vector matrix table [B][nops][8]
+  // fused path program (built on first use)
+  bool fused_built = false;
+  int fused_k = 11;
+  std::vector<nwq::FusedBlockDev> fwd_blocks, bwd_blocks;
+  void* d_fused = nullptr;     // [forward phases][forward ops][backward ops]
+  size_t fused_ops_off = 0, fused_bwd_off = 0;
   nwq::VqeConfig cfg;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (B, want_grad) -> exec
 };
@@ -542,9 +712,9 @@ static int ensure_global(nwq_vqe* h, int B) {
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   h->graphs.clear();
   for (void* p : {(void*)h->d_phi, (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta,
-                  (void*)h->d_E, (void*)h->d_grad, (void*)h->d_coeffs})
+                  (void*)h->d_E, (void*)h->d_grad, (void*)h->d_coeffs, (void*)h->d_table})
     if (p) (void)hipFree(p);
-  h->d_phi = h->d_lam = nullptr;
+  h->d_phi = h->d_lam = h->d_table = nullptr;
   h->d_epart = h->d_gpart = h->d_theta = h->d_E = h->d_grad = h->d_coeffs = nullptr;
   h->Bcap = 0;
   const size_t N = 1ull << h->n;
@@ -557,6 +727,7 @@ static int ensure_global(nwq_vqe* h, int B) {
   if (!rc) rc = check_hip(hipMalloc(&h->d_E, (size_t)B * sizeof(double)), "hipMalloc(vqe E)");
   if (!rc) rc = check_hip(hipMalloc(&h->d_grad, (size_t)B * std::max(1, h->P) * sizeof(double)), "hipMalloc(vqe grad)");
   if (!rc) rc = check_hip(hipMalloc(&h->d_coeffs, (size_t)B * std::max(1, h->nterms) * sizeof(double)), "hipMalloc(vqe coeffs)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_table, (size_t)B * std::max(1, h->nops) * 8 * sizeof(double2)), "hipMalloc(vqe table)");
   if (rc) return rc;
   h->Bcap = B;
   return NWQ_OK;
@@ -590,14 +761,175 @@ static int launch_global(nwq_vqe* h, int B, const double* theta, const double* c
   return check_hip(hipGetLastError(), "vqe per-gate schedule");
 }
 
+// Fused program: blocks over the ops at tile width fused_k, forward phases for
+// the register-blocked kernel, backward ops in reverse per block (chunks of
+// at most kBwdMaxOps).
+static int build_fused(nwq_vqe* h) {
+  if (h->fused_built) return NWQ_OK;
+  const int n = h->n;
+  std::vector<PGate> g(h->nops);
+  for (int i = 0; i < h->nops; ++i) {
+    const VqeOp& op = h->ops[i];
+    const bool two = op.kind == OP_RZZ || op.kind == OP_CX || op.kind == OP_CZ || op.kind == OP_SWAP;
+    g[i] = PGate{0, {op.q0, two ? op.q1 : -1}, two ? 2 : 1, {0, 0, 0}};
+  }
+  const int k = std::min(h->fused_k, n);
+  const std::vector<Block> blocks = plan_blocks(g, n, std::max(k, 6));
+  if (blocks.empty() && h->nops > 0) return set_error(NWQ_EINVAL, "fusion planner made no progress");
+  std::vector<FusedPhase> phases;
+  std::vector<FusedOp> fops;
+  std::vector<VqeBwdOp> bops;
+  h->fwd_blocks.clear();
+  h->bwd_blocks.clear();
+  std::vector<Block> padded(blocks);
+  for (Block& b : padded) pad_block(b, n, std::max(k, 8));
+  size_t max_bwd_lds = 0;
+  for (const Block& b : padded) {
+    const int kb = b.c + b.m;
+    if (kb < 8) return set_error(NWQ_EINVAL, "fused VQE path needs tiles of at least 2^8 amplitudes");
+    max_bwd_lds = std::max(max_bwd_lds, (size_t)2 * sizeof(double2) << kb);
+    std::vector<std::array<int, 2>> lb(g.size());
+    std::vector<int> nq(g.size(), 1);
+    for (int gi : b.gates) {
+      lb[gi] = {local_bit(b, g[gi].q[0]), g[gi].nq == 2 ? local_bit(b, g[gi].q[1]) : 0};
+      nq[gi] = g[gi].nq;
+    }
+    FusedBlockDev d{};
+    d.c = b.c;
+    d.m = b.m;
+    for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
+    d.op_begin = (int)phases.size();
+    for (const Phase& ph : plan_phases(b.gates, lb, nq, kb)) {
+      FusedPhase fp{};
+      for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i];
+      fp.op_begin = (int)fops.size();
+      auto ridx = [&](int bit) {
+        for (int i = 0; i < 4; ++i)
+          if (ph.reg[i] == bit) return i;
+        return -1;
+      };
+      for (int gi : ph.gates) {
+        const VqeOp& op = h->ops[gi];
+        FusedOp f{};
+        f.mat = 8 * gi;
+        const int r0 = ridx(lb[gi][0]), r1 = nq[gi] == 2 ? ridx(lb[gi][1]) : 0;
+        f.lo = r0;
+        if (op.kind == OP_ROT || op.kind == OP_FIX1) {
+          f.kind = 0;
+        } else if (op.kind == OP_RZZ || op.kind == OP_CZ) {
+          f.kind = 4; f.o0 = r0; f.o1 = r1;
+        } else if (op.kind == OP_CX) {
+          f.kind = 3; f.o0 = r0; f.o1 = r1;
+        } else {
+          f.kind = 5; f.o0 = r0; f.o1 = r1;
+        }
+        fops.push_back(f);
+      }
+      fp.op_count = (int)fops.size() - fp.op_begin;
+      phases.push_back(fp);
+    }
+    d.op_count = (int)phases.size() - d.op_begin;
+    h->fwd_blocks.push_back(d);
+  }
+  for (auto bit = padded.rbegin(); bit != padded.rend(); ++bit) {
+    const Block& b = *bit;
+    std::vector<VqeBwdOp> rev;
+    for (auto it = b.gates.rbegin(); it != b.gates.rend(); ++it) {
+      const int gi = *it;
+      const VqeOp& op = h->ops[gi];
+      VqeBwdOp o{};
+      o.b0 = local_bit(b, op.q0);
+      o.b1 = g[gi].nq == 2 ? local_bit(b, op.q1) : 0;
+      o.lo = g[gi].nq == 2 ? std::min(o.b0, o.b1) : o.b0;
+      o.hi = g[gi].nq == 2 ? std::max(o.b0, o.b1) : 0;
+      o.axis = op.axis;
+      o.slot = op.slot;
+      o.mat = 8 * gi + 4;
+      o.kind = op.kind == OP_ROT ? 0 : op.kind == OP_RZZ ? 1 : op.kind == OP_FIX1 ? 2 : op.kind == OP_CX ? 3
+             : op.kind == OP_CZ ? 4 : 5;
+      rev.push_back(o);
+    }
+    for (size_t s0 = 0; s0 < rev.size(); s0 += kBwdMaxOps) {
+      FusedBlockDev d{};
+      d.c = b.c;
+      d.m = b.m;
+      for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
+      d.op_begin = (int)bops.size();
+      const size_t e = std::min(rev.size(), s0 + kBwdMaxOps);
+      for (size_t i = s0; i < e; ++i) bops.push_back(rev[i]);
+      d.op_count = (int)(e - s0);
+      h->bwd_blocks.push_back(d);
+    }
+  }
+  const size_t ph_bytes = phases.size() * sizeof(FusedPhase);
+  h->fused_ops_off = (ph_bytes + 255) & ~size_t(255);
+  h->fused_bwd_off = (h->fused_ops_off + fops.size() * sizeof(FusedOp) + 255) & ~size_t(255);
+  const size_t total = h->fused_bwd_off + bops.size() * sizeof(VqeBwdOp) + 16;
+  std::vector<char> prog(total, 0);
+  if (!phases.empty()) std::memcpy(prog.data(), phases.data(), ph_bytes);
+  if (!fops.empty()) std::memcpy(prog.data() + h->fused_ops_off, fops.data(), fops.size() * sizeof(FusedOp));
+  if (!bops.empty()) std::memcpy(prog.data() + h->fused_bwd_off, bops.data(), bops.size() * sizeof(VqeBwdOp));
+  int rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)max_bwd_lds), "hipFuncSetAttribute");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_fused, total), "hipMalloc(vqe fused program)");
+  if (!rc) rc = check_hip(hipMemcpy(h->d_fused, prog.data(), total, hipMemcpyHostToDevice), "hipMemcpy(vqe fused program)");
+  if (rc) return rc;
+  h->fused_built = true;
+  return NWQ_OK;
+}
+
+static int fused_grid(const nwq_vqe* h) {
+  const int k = std::min(std::max(h->fused_k, 8), h->n);
+  const unsigned long long ntiles = 1ull << (h->n - k);
+  return (int)std::max<unsigned long long>(1, std::min<unsigned long long>(ntiles, blocks_per_state(h)));
+}
+
+static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* coeffs, double* E, double* grad,
+                        hipStream_t s) {
+  int rc = build_fused(h);
+  if (rc) return rc;
+  const int G = fused_grid(h);
+  const dim3 grid(G, B);
+  const FusedPhase* dph = static_cast<const FusedPhase*>(h->d_fused);
+  const FusedOp* dfo = reinterpret_cast<const FusedOp*>(static_cast<char*>(h->d_fused) + h->fused_ops_off);
+  const VqeBwdOp* dbo = reinterpret_cast<const VqeBwdOp*>(static_cast<char*>(h->d_fused) + h->fused_bwd_off);
+  const int stride = 8 * h->nops;
+  hipLaunchKernelGGL(k_vqe_init, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n);
+  hipLaunchKernelGGL(k_vqe_mats, dim3((h->nops + 255) / 256, B), dim3(256), 0, s, h->d_ops, h->nops, h->d_fixed,
+                     theta, h->P, h->d_table);
+  for (const FusedBlockDev& d : h->fwd_blocks)
+    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, B, stride, G);
+  hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
+                     coeffs, h->d_epart, grad != nullptr ? 1 : 0);
+  if (grad != nullptr) {
+    for (const FusedBlockDev& d : h->bwd_blocks) {
+      const size_t lds = 2 * sizeof(double2) << (d.c + d.m);
+      hipLaunchKernelGGL(k_vqe_bwd_tile, grid, dim3(kBwdBlock), lds, s, h->d_phi, h->d_lam, h->n, d, dbo,
+                         h->d_table, stride, h->nslots, h->d_gpart);
+    }
+  }
+  hipLaunchKernelGGL(k_vqe_finish, dim3((B + 63) / 64), dim3(64), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
+                     h->d_slot_param, h->P, B, E, grad);
+  return check_hip(hipGetLastError(), "vqe fused schedule");
+}
+
 static int run_graph(nwq_vqe* h, int B, bool want_grad, bool with_coeffs) {
-  const auto key = std::make_pair(B, (want_grad ? 1 : 0) | (with_coeffs ? 2 : 0));
+  const bool fused = h->cfg.mode == 3 || (h->cfg.mode == 0 && h->n > 12);
+  const auto key = std::make_pair(B, (want_grad ? 1 : 0) | (with_coeffs ? 2 : 0) | (fused ? 4 : 0));
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
+    if (fused) {
+      const int rcb = build_fused(h);   // host planning and program upload stay outside the capture
+      if (rcb) return rcb;
+    }
     int rc = check_hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (rc) return rc;
-    rc = launch_global(h, B, h->d_theta, with_coeffs ? h->d_coeffs : nullptr, h->d_E, want_grad ? h->d_grad : nullptr,
-                       h->stream);
+    if (fused)
+      rc = launch_fused(h, B, h->d_theta, with_coeffs ? h->d_coeffs : nullptr, h->d_E, want_grad ? h->d_grad : nullptr,
+                        h->stream);
+    else
+      rc = launch_global(h, B, h->d_theta, with_coeffs ? h->d_coeffs : nullptr, h->d_E, want_grad ? h->d_grad : nullptr,
+                         h->stream);
     hipGraph_t g = nullptr;
     const int rc2 = check_hip(hipStreamEndCapture(h->stream, &g), "hipStreamEndCapture");
     if (rc) return rc;
@@ -712,7 +1044,7 @@ int nwq_vqe_destroy(nwq_vqe_handle h) {
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   for (void* p : {(void*)h->d_ops, (void*)h->d_fixed, (void*)h->d_terms, (void*)h->d_slot_param, (void*)h->d_phi,
                   (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta, (void*)h->d_E,
-                  (void*)h->d_grad, (void*)h->d_coeffs})
+                  (void*)h->d_grad, (void*)h->d_coeffs, (void*)h->d_table, h->d_fused})
     if (p) (void)hipFree(p);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
@@ -731,7 +1063,8 @@ int nwq_vqe_info(nwq_vqe_handle h, int* n_params, int* n_ops, int* n_slots) {
 
 int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_state_) {
   if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
-  if (mode < 0 || mode > 2) return vqe_fail(NWQ_EINVAL, "mode must be 0 (auto), 1 (LDS) or 2 (per-gate)");
+  if (mode < 0 || mode > 3) return vqe_fail(NWQ_EINVAL, "mode must be 0 (auto), 1 (LDS), 2 (per-gate) or 3 (fused)");
+  if (mode == 3 && h->n < 8) return vqe_fail(NWQ_EINVAL, "the fused path needs n >= 8");
   if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
     return vqe_fail(NWQ_EINVAL, "threads must be 64, 128, 256, 512 or 1024");
   if (blocks_per_state_ < 0 || blocks_per_state_ > 4096) return vqe_fail(NWQ_EINVAL, "blocks per state in [0, 4096]");
@@ -771,7 +1104,7 @@ static int eval_common(nwq_vqe_handle h, int B, const double* theta, const doubl
   if (rc) return rc;
   const bool want_grad = grad != nullptr;
   const int mode = single ? 2 : h->cfg.mode;
-  const bool use_lds = !single && (mode == 1 || (mode == 0 && lds_fits(h, h->cfg.threads, want_grad)));
+  const bool use_lds = !single && (mode == 1 || (mode == 0 && h->n <= 12 && lds_fits(h, h->cfg.threads, want_grad)));
   if (use_lds) {
     if (!lds_fits(h, h->cfg.threads, want_grad)) return vqe_fail(NWQ_EINVAL, "program does not fit the LDS-resident path");
     rc = launch_lds(h, B, theta, coeffs, E, grad, h->stream);
@@ -836,6 +1169,9 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms) {
   const unsigned long long pairs = 1ull << (h->n - 1);
   for (int bps : {0, 8, 16, 32, 64, 128, 256})
     if (bps == 0 || (unsigned long long)bps * 256 <= pairs) cands.push_back({2, h->cfg.threads, bps});
+  if (h->n >= 13)
+    for (int bps : {0, 16, 32, 64, 128})
+      if (bps == 0 || (unsigned long long)bps * 256 <= pairs) cands.push_back({3, h->cfg.threads, bps});
   const VqeConfig saved = h->cfg;
   double best = 1e300;
   VqeConfig best_cfg = saved;

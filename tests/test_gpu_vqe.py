@@ -31,6 +31,8 @@ def run_all_paths(V, torch, n, prog, terms, theta):
     t = torch.from_numpy(theta).cuda()
     out = {}
     modes = [("lds", 1), ("graph", 2)] if n <= 12 else [("graph", 2)]
+    if n >= 8:
+        modes.append(("fused", 3))
     for name, mode in modes:
         ctx.set_config(mode, 256, 0)
         E, G = ctx.eval(t, grad=True)
@@ -90,7 +92,7 @@ def test_theta_zero_special_cases(V, torch):
     ctx.close()
 
 
-@pytest.mark.parametrize("n,mode", [(7, 1), (7, 2), (13, 2)])
+@pytest.mark.parametrize("n,mode", [(7, 1), (7, 2), (13, 2), (13, 3), (9, 3)])
 def test_alone_equals_in_the_mix_bitwise(V, torch, n, mode):
     L = 2
     prog = W.hea_ansatz(n, L)
@@ -112,7 +114,7 @@ def test_energy_only_matches(V, torch):
     theta, h = W.vqe_batch(n, L, B=5)
     ctx = V.VQE(n, prog, W.tfim_hamiltonian(n, 1.0, h))
     t = torch.from_numpy(theta).cuda()
-    for mode in (1, 2):
+    for mode in (1, 2, 3):
         ctx.set_config(mode, 128, 0)
         E1, _ = ctx.eval(t, grad=False)
         E2, _ = ctx.eval(t, grad=True)
@@ -186,3 +188,52 @@ def test_vqe_create_errors(V, torch):
     with pytest.raises(nwq.NwqError) as e:
         V.VQE(3, [A("cx", (1, 1), -1)], [(1, 0, 1.0)], n_params=1)
     assert e.value.code == nwq.NWQ_EDUP
+
+
+@pytest.mark.parametrize("n,L,bps", [(13, 2, 0), (15, 2, 4), (16, 3, 0)])
+def test_fused_path_matches_oracle(V, torch, n, L, bps):
+    """Fused-block schedule (register-blocked forward over the batch, LDS
+    backward tiles) at sizes with several tiles per state; gradients checked
+    against parameter shift on a sample of parameters, energies exactly."""
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=3)
+    terms = W.tfim_hamiltonian(n, 1.0, h)
+    ctx = V.VQE(n, prog, terms)
+    ctx.set_config(3, 256, bps)
+    t = torch.from_numpy(theta).cuda()
+    E, G = ctx.eval(t)
+    E2, G2 = ctx.eval_single(t[1])
+    E = E.cpu().numpy()
+    G = G.cpu().numpy()
+    pick = [0, 1, n - 1, n, 2 * n - 1, 2 * n * L - 1, n * L]
+    for b in range(3):
+        assert abs(E[b] - OV.energy(prog, theta[b], terms, n)) <= 1e-10
+        g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n, params=pick)
+        assert np.max(np.abs(G[b][pick] - g_ps[pick])) <= 1e-10
+    assert abs(E2.item() - E[1]) <= 1e-12
+    assert np.max(np.abs(G2.cpu().numpy()[0] - G[1])) <= 1e-12
+    ctx.close()
+
+
+def test_fused_generic_program(V, torch):
+    """Fused path with fixed gates, CZ, SWAP and RZZ on a 10-qubit register
+    (one tile) and with several tiles at 13 qubits."""
+    A = W.AnsatzGate
+    for n in (10, 13):
+        prog = []
+        for l in range(2):
+            prog += [A("h", (q,), -1) for q in range(0, n, 3)]
+            prog += [A("rx", (q,), l * 4 + (q % 4)) for q in range(n)]
+            prog += [A("rzz", (q, (q + 5) % n), 8 + l) for q in range(0, n, 2)]
+            prog += [A("cz", (n - 1, 0), -1), A("swap", (1, n - 2), -1), A("s", (3,), -1), A("cx", (n - 1, 2), -1)]
+            prog += [A("ry", (q,), 10 + l) for q in range(1, n, 2)]
+        terms = W.random_pauli_sum(n, 10, seed=n)
+        theta = np.random.default_rng(n).uniform(-math.pi, math.pi, (2, 12))
+        ctx = V.VQE(n, prog, terms, n_params=12)
+        ctx.set_config(3, 256, 0)
+        E, G = ctx.eval(torch.from_numpy(theta).cuda())
+        for b in range(2):
+            assert abs(E[b].item() - OV.energy(prog, theta[b], terms, n)) <= 1e-10
+            g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n)
+            assert np.max(np.abs(G[b].cpu().numpy() - g_ps)) <= 1e-10
+        ctx.close()
