@@ -346,10 +346,21 @@ def vqe_leg(torch, sizes=None, B=256):
         ts = (time.perf_counter() - t0) / k
         dE = max(abs(Es[b].item() - E[b].item()) for b in range(k))
         dG = float(torch.max(torch.abs(g1[0] - G[k - 1])).item())
+        per_gate = None
+        if n > 12:     # the unfused batched schedule, for comparison with the chosen one
+            ctx.set_config(2, cfg[1], 0)
+            ctx.eval(t)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.eval(t)
+            torch.cuda.synchronize()
+            per_gate = round(B / (time.perf_counter() - t0), 1)
+            ctx.set_config(*cfg)
         res[f"n{n}_L{L}"] = {"B": B, "batched_evals_per_s": round(B / tb, 1), "batched_ms": round(tb * 1e3, 3),
                              "single_evals_per_s": round(1.0 / ts, 1), "speedup": round(ts * B / tb, 2),
-                             "config": {"mode": ["auto", "lds", "per_gate_graph"][cfg[0]], "threads": cfg[1],
-                                        "blocks_per_state": cfg[2]},
+                             "config": {"mode": ["auto", "lds", "per_gate_graph", "fused_graph"][cfg[0]],
+                                        "threads": cfg[1], "blocks_per_state": cfg[2]},
+                             "per_gate_graph_evals_per_s": per_gate,
                              "max_abs_dE_batched_vs_single": dE, "max_abs_dgrad": dG}
         ctx.close()
         del t, E, G
