@@ -43,7 +43,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--depth", type=int, default=40)
-    ap.add_argument("--fuse-k", type=int, default=12)
+    ap.add_argument("--fuse-k", type=int, default=None,
+                    help="fusion width for the fused leg (default: picked by the fusion autotuner)")
+    ap.add_argument("--tune-depth", type=int, default=10, help="brickwork depth the fusion autotuner times")
+    ap.add_argument("--no-n32", action="store_true", help="skip the n=32 sweep")
     ap.add_argument("--no-extras", action="store_true", help="only the timed step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-vqe", action="store_true", help="skip the batched VQE leg")
@@ -210,13 +213,16 @@ def main():
                                   "one kernel per gate, then <Z_i> for all i", "n": n, "depth": args.depth,
                       "gates": len(gates), "seed": 0, "parallelism": "single GPU"},
            "pct_peak": round(value / HBM_PEAK_GBS, 4), "roofline": roofline, "kernels": per_class,
-           "launch_shapes": {k: {"ppt": v[0], "nontemporal": v[1]} for k, v in tuned.items()}}
+           "launch_shapes": {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
+                             for k, per in tuned.items()}}
 
     if not args.no_extras:
-        out["fused"] = fused_leg(nwq, st, arrays, gates, n, args.fuse_k, ms_per_step)
+        out["fused"] = fused_leg(nwq, st, arrays, n, args, ms_per_step)
         out["sweep"] = sweep_leg(nwq, st, n)
         del st, psi
         torch.cuda.empty_cache()
+        if n == 30 and not args.no_n32:
+            out["sweep_n32"] = sweep_n32_leg(nwq, torch, tuned)
         out["dm_noisy_gate_n14"] = dm_leg(nwq, torch)
     if not args.no_extras and not args.no_vqe:
         out["vqe"] = vqe_leg(torch)
@@ -228,13 +234,26 @@ def main():
     print(json.dumps(out))
 
 
-def fused_leg(nwq, st, arrays, gates, n, k, unfused_ms):
-    log(f"[bench] fused leg k={k}")
-    nwq.nwq_set_fusion(st.h, k)
+def fused_leg(nwq, st, arrays, n, args, unfused_ms):
+    """The same circuit through fused k-qubit blocks.  The fusion width and
+    kernel are picked by the library's fusion autotuner timing the first
+    --tune-depth layers under every candidate (or fixed by --fuse-k)."""
+    import torch
+    import workloads as W
+    table = None
+    if args.fuse_k is None:
+        log(f"[bench] fusion autotuner on depth {args.tune_depth}")
+        t0 = time.perf_counter()
+        k, rb, table = nwq.nwq_autotune_fusion(st.h, *nwq.circuit_arrays(W.brickwork_circuit(n, args.tune_depth, seed=0)))
+        log(f"[bench] fusion autotuner picked k={k} rb={rb} in {time.perf_counter() - t0:.1f}s")
+    else:
+        k, rb = args.fuse_k, 1
+        nwq.nwq_set_fusion(st.h, k)
+        nwq.nwq_set_fusion_kernel(st.h, rb)
+    log(f"[bench] fused leg k={k} rb={rb}")
     st.reset()
     nwq.nwq_apply_circuit(st.h, *arrays)          # warm-up (and plan)
     st.flush()
-    import torch
     torch.cuda.synchronize()
     reps = 2
     nwq.nwq_timing_read(st.h, reset=True)
@@ -253,10 +272,15 @@ def fused_leg(nwq, st, arrays, gates, n, k, unfused_ms):
     c, ms = tim["sv_fused"]
     N = 1 << n
     avg = ms / max(c, 1)
-    return {"k": k, "kernel": "register-blocked (4 register bits per phase)", "blocks": blocks, "phases": phases,
-            "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
-            "circuit_ms": round(dt * 1e3, 2), "speedup_vs_one_kernel_per_gate": round(unfused_ms / (dt * 1e3), 2),
-            "avg_block_ms": round(avg, 3), "block_hbm_GBs": round(32 * N / (avg * 1e-3) / 1e9, 1)}
+    res = {"k": k, "kernel": "register-blocked (4 register bits per phase)" if rb else "one LDS pass per gate",
+           "blocks": blocks, "phases": phases, "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
+           "circuit_ms": round(dt * 1e3, 2), "speedup_vs_one_kernel_per_gate": round(unfused_ms / (dt * 1e3), 2),
+           "avg_block_ms": round(avg, 3), "block_hbm_GBs": round(32 * N / (avg * 1e-3) / 1e9, 1)}
+    if table is not None:
+        res["autotuner"] = {"depth": args.tune_depth,
+                            "ms_per_circuit": {("unfused" if kk == 0 else f"k{kk}_{'rb' if r else 'lds'}"): round(v, 1)
+                                               for (kk, r), v in sorted(table.items())}}
+    return res
 
 
 def sweep_leg(nwq, st, n):
@@ -280,6 +304,37 @@ def sweep_leg(nwq, st, n):
             c, ms = max(tim.values(), key=lambda v: v[0])
             avg = ms / c
             res[f"{name}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(bytes_per / (avg * 1e-3) / 1e9, 1)}
+    return res
+
+
+def sweep_n32_leg(nwq, torch, tuned):
+    """Per-target U3 and CX launches on a 32-qubit state (68.7 GB), with the
+    launch shapes tuned at 30 qubits."""
+    log("[bench] n=32 sweep")
+    from paper_2401_06861_amd import autotune
+    n = 32
+    N = 1 << n
+    st = nwq.SVState(n)
+    for name, per in tuned.items():
+        for bname, v in per.items():
+            nwq.nwq_set_launch(st.h, autotune.CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(bname), v[0], v[1])
+    res = {}
+    for name, qs_list, bytes_per in (("u3", [(q,) for q in (0, 5, 6, 16, n - 1)], 32 * N),
+                                     ("cx", [(0, 1), (n - 2, n - 1)], 16 * N)):
+        for qs in qs_list:
+            p = (0.3, 0.2, 0.1) if name == "u3" else ()
+            st.apply(name, qs, p)
+            torch.cuda.synchronize()
+            nwq.nwq_timing_read(st.h, reset=True)
+            nwq.nwq_timing_enable(st.h, True)
+            for _ in range(3):
+                st.apply(name, qs, p)
+            nwq.nwq_timing_enable(st.h, False)
+            c, ms = max(nwq.nwq_timing_read(st.h, reset=True).values(), key=lambda v: v[0])
+            avg = ms / c
+            res[f"{name}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(bytes_per / (avg * 1e-3) / 1e9, 1)}
+    st.close()
+    torch.cuda.empty_cache()
     return res
 
 
@@ -369,14 +424,14 @@ def vqe_leg(torch, sizes=None, B=256):
 
 
 def serving_leg(torch, num):
-    """Continuous-batching server on a Poisson stream: 70% SV VQE (n 10..20,
+    """Continuous-batching server on a Poisson stream: 70% SV VQE (n 10..24,
     L 4..8, half with gradient, 1..4 optimiser steps), 30% noisy DM TFIM
     (n 6..12, 10 Trotter steps).  First all requests arrive at once
     (saturation throughput), then at 0.8 x that rate (latency)."""
     import workloads as W
     from paper_2401_06861_amd.serving import GpuExecutor, Server, summarize
     log(f"[bench] serving leg, {num} requests")
-    kw = dict(num=num, seed=7, sv_n=(10, 20), dm_n=(6, 12), L_range=(4, 8), opt_steps=(1, 4), dm_steps=10)
+    kw = dict(num=num, seed=7, sv_n=(10, 24), dm_n=(6, 12), L_range=(4, 8), opt_steps=(1, 4), dm_steps=10)
     ex = GpuExecutor()
     budget = 64 << 30
     warm = W.serving_trace(rate=1e9, **{**kw, "num": 40, "seed": 8})
@@ -391,7 +446,7 @@ def serving_leg(torch, num):
     lat = summarize(res)
     ex.close()
     torch.cuda.empty_cache()
-    return {"requests": num, "mix": "70% SV VQE n10-20 L4-8 (half +grad, 1-4 steps), 30% DM TFIM n6-12",
+    return {"requests": num, "mix": "70% SV VQE n10-24 L4-8 (half +grad, 1-4 steps), 30% DM TFIM n6-12",
             "budget_GB": budget / 1e9, "saturation_req_per_s": round(sat["throughput_req_per_s"], 2),
             "offered_req_per_s": round(rate, 2), "throughput_req_per_s": round(lat["throughput_req_per_s"], 2),
             "p50_ms": round(lat["p50_ms"], 2), "p99_ms": round(lat["p99_ms"], 2),

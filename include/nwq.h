@@ -263,18 +263,36 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
 /* Kernel class ids are the timing classes below (1 sv_1q_dense, 2 sv_diag,
  * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q).  A launch shape is the number
  * of pairs / groups per thread (1, 2, 4 or 8) and a non-temporal hint on the
- * loads and stores (0 or 1). */
-int nwq_set_launch(nwq_handle h, int cls, int ppt, int nontemporal);
-int nwq_get_launch(nwq_handle h, int cls, int* ppt, int* nontemporal);
+ * loads and stores (0 or 1).  Each class keeps one shape per bucket of the
+ * launch's lowest target bit: bucket 0 for bits 0..5 (partner amplitudes
+ * within 1 KiB), bucket 1 for bits 6 and up.  nwq_set_launch with bucket -1
+ * sets both. */
+#define NWQ_LAUNCH_BUCKETS 2
+int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal);
+int nwq_get_launch(nwq_handle h, int cls, int bucket, int* ppt, int* nontemporal);
 
 /* Autotuner: for each class that applies to the handle (SV: 1, 2, 3, 4;
- * DM: 6) time every launch shape with HIP events on the handle's stream and
- * state (self-inverse operations applied in pairs on low, middle and high
- * qubits, so the state is unchanged up to the rounding of H H), keep the
- * fastest, and write its time per launch in ms to best_ms[class]
- * (NWQ_TIMING_CLASSES entries, -1 where not tuned; best_ms may be NULL).
+ * DM: 6) and each bucket, time every launch shape with HIP events on the
+ * handle's stream and state (self-inverse operations applied in pairs on up
+ * to three target bits of the bucket, so the state is unchanged up to the
+ * rounding of H H), keep the fastest, and write its time per launch in ms to
+ * best_ms[class * NWQ_LAUNCH_BUCKETS + bucket] (NWQ_TIMING_CLASSES *
+ * NWQ_LAUNCH_BUCKETS entries, -1 where not tuned; best_ms may be NULL).
  * Flushes deferred work first; synchronises. */
 int nwq_autotune(nwq_handle h, int reps, double* best_ms);
+
+/* Fusion autotuner (SV handles): runs the given circuit (arrays as for
+ * nwq_apply_circuit) from |0...0> once untimed and reps times timed under
+ * each candidate: unfused, and every fusion width from 6 to min(13, n) with
+ * the per-gate LDS kernel and, for widths of 8 and up, the register-blocked
+ * kernel.  Keeps the fastest on the handle and returns it in *best_k
+ * (0 = unfused) and *best_rb (the nwq_set_fusion_kernel value).  If ms_out
+ * is non-NULL it receives NWQ_FUSION_CANDIDATES times in ms per circuit
+ * (-1 for candidates not run): index 0 unfused, 1 + 2 * (k - 6) + rb for
+ * width k.  Overwrites the state and leaves it at |0...0>; synchronises. */
+#define NWQ_FUSION_CANDIDATES 17
+int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* qubits,
+                        const double* params, int reps, int* best_k, int* best_rb, double* ms_out);
 
 /* ---------------------------------------------------------------------------
  * Diagnostics

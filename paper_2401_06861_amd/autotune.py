@@ -2,7 +2,7 @@
 
 `tune(handle)` runs the library's autotuner (nwq_autotune) once per
 (device, state kind, qubit count) and stores the chosen launch shape of each
-kernel class in a JSON file; later calls apply the cached shapes with
+kernel class and target bucket in a JSON file; later calls apply the cached shapes with
 nwq_set_launch without timing again.
 """
 from __future__ import annotations
@@ -32,19 +32,22 @@ def _load(path: str) -> dict:
 
 
 def tune(h: int, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, force: bool = False) -> dict:
-    """Launch shapes for handle h: {class name: [ppt, nontemporal, ms or None]}."""
+    """Launch shapes for handle h: {class name: {bucket: [ppt, nontemporal, ms or None]}}
+    (buckets "low" and "high" of the lowest target bit, below or from 6)."""
     kind, n, _ = nwq.nwq_info(h)
-    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}"
+    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|buckets"
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
-        for name, (ppt, nt, _) in cache[key].items():
-            nwq.nwq_set_launch(h, CLASS_IDS[name], int(ppt), int(nt))
+        for name, per_bucket in cache[key].items():
+            for bname, (ppt, nt, _) in per_bucket.items():
+                nwq.nwq_set_launch(h, CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(bname), int(ppt), int(nt))
         return cache[key]
     ms = nwq.nwq_autotune(h, reps)
     entry = {}
-    for name, t in ms.items():
-        ppt, nt = nwq.nwq_get_launch(h, CLASS_IDS[name])
-        entry[name] = [ppt, nt, t]
+    for name, per_bucket in ms.items():
+        for bname, t in per_bucket.items():
+            ppt, nt = nwq.nwq_get_launch(h, CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(bname))
+            entry.setdefault(name, {})[bname] = [ppt, nt, t]
     if cache_path:
         cache = _load(cache_path)
         cache[key] = entry

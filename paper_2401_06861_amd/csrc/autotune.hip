@@ -1,13 +1,17 @@
 // Launch-shape autotuner for the streaming gate kernels of a handle.
 //
-// For each kernel class it times every candidate (groups per thread in
-// {1, 2, 4, 8} x non-temporal hint off/on) with HIP events on the handle's
-// own stream and state, and keeps the fastest.  Candidates apply
-// self-inverse operations in pairs on low, middle and high qubits (H H for
-// the dense 1-qubit kernel, Z Z for the diagonal kernel, CX CX for the
-// permutation kernel, CZ as a dense 4x4 twice for the 2-qubit kernel, and on a
-// density matrix Z (x) conj(Z) twice for the 1-qubit superoperator kernel),
-// so the state is unchanged except for the rounding of H H.
+// For each kernel class and target bucket (lowest target bit below 6, or at
+// or above it) it times every candidate (groups per thread in {1, 2, 4, 8} x
+// non-temporal hint off/on) with HIP events on the handle's own stream and
+// state, and keeps the fastest.  Candidates apply self-inverse operations in
+// pairs on up to three target bits of the bucket (H H for the dense 1-qubit
+// kernel, Z Z for the diagonal kernel, CX CX for the permutation kernel, CZ
+// as a dense 4x4 twice for the 2-qubit kernel, and on a density matrix
+// Z (x) conj(Z) twice for the 1-qubit superoperator kernel), so the state is
+// unchanged except for the rounding of H H.
+//
+// The fusion autotuner times a caller's circuit under every fusion width and
+// fused-kernel choice and keeps the fastest.
 #include <algorithm>
 #include <cmath>
 
@@ -61,20 +65,25 @@ using namespace nwq;
 
 extern "C" {
 
-int nwq_set_launch(nwq_handle h, int cls, int ppt, int nontemporal) {
+int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) {
   if (!h) return set_error(NWQ_EINVAL, "NULL handle");
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
+  if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0 or 1");
   if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8");
-  h->cfg[cls].ppt = ppt;
-  h->cfg[cls].nt = nontemporal ? 1 : 0;
+  for (int b = 0; b < kBuckets; ++b) {
+    if (bucket >= 0 && b != bucket) continue;
+    h->cfg[cls][b].ppt = ppt;
+    h->cfg[cls][b].nt = nontemporal ? 1 : 0;
+  }
   return NWQ_OK;
 }
 
-int nwq_get_launch(nwq_handle h, int cls, int* ppt, int* nontemporal) {
+int nwq_get_launch(nwq_handle h, int cls, int bucket, int* ppt, int* nontemporal) {
   if (!h) return set_error(NWQ_EINVAL, "NULL handle");
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
-  if (ppt) *ppt = h->cfg[cls].ppt;
-  if (nontemporal) *nontemporal = h->cfg[cls].nt;
+  if (bucket < 0 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be 0 or 1");
+  if (ppt) *ppt = h->cfg[cls][bucket].ppt;
+  if (nontemporal) *nontemporal = h->cfg[cls][bucket].nt;
   return NWQ_OK;
 }
 
@@ -84,51 +93,59 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
   int rc = flush_all(h);
   if (rc) return rc;
   if (best_ms)
-    for (int i = 0; i < KC_COUNT; ++i) best_ms[i] = -1.0;
-  struct Job { int cls; Runner run; int span; };
+    for (int i = 0; i < KC_COUNT * kBuckets; ++i) best_ms[i] = -1.0;
+  struct Job { int cls; Runner run; int lo_max; };   // lo_max: largest lowest-target bit the runner allows
   std::vector<Job> jobs;
   if (h->kind == NWQ_KIND_SV) {
-    jobs.push_back({KC_SV1Q, run_1q, h->n});
-    jobs.push_back({KC_DIAG, run_diag, h->n});
+    jobs.push_back({KC_SV1Q, run_1q, h->n - 1});
+    jobs.push_back({KC_DIAG, run_diag, h->n - 1});
     if (h->n >= 2) {
-      jobs.push_back({KC_PERM, run_perm, h->n});
-      jobs.push_back({KC_SV2Q, run_2q, h->n});
+      jobs.push_back({KC_PERM, run_perm, h->n - 2});
+      jobs.push_back({KC_SV2Q, run_2q, h->n - 2});
     }
   } else {
-    jobs.push_back({KC_DM1, run_dm1, h->n});
+    jobs.push_back({KC_DM1, run_dm1, h->n - 1});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
   for (const Job& j : jobs) {
-    if (rc) break;
-    const int qs[3] = {0, j.span / 2, std::max(0, j.span - 1)};
-    double best = 1e300;
-    LaunchCfg best_c = h->cfg[j.cls];
-    for (const Cand& c : kCands) {
-      LaunchCfg cfg;
-      cfg.ppt = c.ppt;
-      cfg.nt = c.nt;
-      for (int q : qs) j.run(h, cfg, q);   // warm-up
-      rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
-      for (int r = 0; r < reps && !rc; ++r)
-        for (int q : qs) j.run(h, cfg, q);
-      if (!rc) rc = check_hip(hipGetLastError(), "autotune launch");
-      if (!rc) rc = check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
-      if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
-      float ms = 0.f;
-      if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-      if (rc) break;
-      const double per = ms / (2.0 * reps * 3.0);   // per launch
-      if (per < best) {
-        best = per;
-        best_c = cfg;
+    for (int b = 0; b < kBuckets && !rc; ++b) {
+      // target bits of this bucket: low bucket 0, 2, 5; high bucket 6, middle, top
+      std::vector<int> qs;
+      const int cand_q[2][3] = {{0, 2, kLowBits - 1}, {kLowBits, (kLowBits + j.lo_max) / 2, j.lo_max}};
+      for (int q : cand_q[b])
+        if (q >= 0 && q <= j.lo_max && bucket_of(q) == b && std::find(qs.begin(), qs.end(), q) == qs.end())
+          qs.push_back(q);
+      if (qs.empty()) continue;
+      double best = 1e300;
+      LaunchCfg best_c = h->cfg[j.cls][b];
+      for (const Cand& c : kCands) {
+        LaunchCfg cfg;
+        cfg.ppt = c.ppt;
+        cfg.nt = c.nt;
+        for (int q : qs) j.run(h, cfg, q);   // warm-up
+        rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+        for (int r = 0; r < reps && !rc; ++r)
+          for (int q : qs) j.run(h, cfg, q);
+        if (!rc) rc = check_hip(hipGetLastError(), "autotune launch");
+        if (!rc) rc = check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
+        if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (rc) break;
+        const double per = ms / (2.0 * reps * (double)qs.size());   // per launch
+        if (per < best) {
+          best = per;
+          best_c = cfg;
+        }
+      }
+      if (!rc) {
+        h->cfg[j.cls][b] = best_c;
+        if (best_ms) best_ms[j.cls * kBuckets + b] = best;
       }
     }
-    if (!rc) {
-      h->cfg[j.cls] = best_c;
-      if (best_ms) best_ms[j.cls] = best;
-    }
+    if (rc) break;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

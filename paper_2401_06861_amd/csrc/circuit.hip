@@ -351,6 +351,68 @@ int nwq_set_fusion(nwq_handle h, int k, int* k_out) {
   return NWQ_OK;
 }
 
+int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params,
+                        int reps, int* best_k, int* best_rb, double* ms_out) {
+  if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
+  if (h->kind != NWQ_KIND_SV) return set_error(NWQ_EKIND, "fusion applies to state-vector handles");
+  if (reps < 1 || reps > 100) return set_error(NWQ_EINVAL, "reps must be in [1, 100]");
+  if (!best_k || !best_rb) return set_error(NWQ_EINVAL, "NULL output pointer");
+  std::vector<PGate> gates;
+  int rc = parse_circuit(h->n, n_gates, types, qubits, params, true, gates);
+  if (rc) return rc;
+  if (ms_out)
+    for (int i = 0; i < NWQ_FUSION_CANDIDATES; ++i) ms_out[i] = -1.0;
+  struct Cand { int k, rb; };
+  std::vector<Cand> cands = {{0, 0}};
+  for (int k = 6; k <= std::min(13, h->n); ++k) {
+    cands.push_back({k, 0});
+    if (h->n >= 8) cands.push_back({k, 1});
+  }
+  const int saved_k = h->fuse_k;
+  const bool saved_rb = h->fuse_rb;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+  if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+  double best = 1e300;
+  Cand pick{saved_k, saved_rb ? 1 : 0};
+  for (const Cand& c : cands) {
+    if (rc) break;
+    h->fuse_k = c.k;
+    h->fuse_rb = c.rb != 0;
+    double total = 0.0;
+    for (int r = 0; r <= reps && !rc; ++r) {   // r == 0 is the untimed run
+      rc = nwq_reset(h);
+      if (!rc) rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+      if (!rc) rc = nwq_apply_circuit(h, n_gates, types, qubits, params);
+      if (!rc) rc = flush_all(h);
+      if (!rc) rc = check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
+      if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (r > 0) total += ms;
+    }
+    if (rc) break;
+    const double per = total / reps;
+    if (ms_out) ms_out[c.k == 0 ? 0 : 1 + 2 * (c.k - 6) + c.rb] = per;
+    if (per < best) {
+      best = per;
+      pick = c;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) {
+    h->fuse_k = saved_k;
+    h->fuse_rb = saved_rb;
+    return rc;
+  }
+  h->fuse_k = pick.k;
+  h->fuse_rb = pick.rb != 0;
+  *best_k = pick.k;
+  *best_rb = pick.rb;
+  return nwq_reset(h);
+}
+
 int nwq_fusion_plan(int n, int k, int n_gates, const int* types, const int* qubits, int* n_blocks,
                     int* block_of_gate, int* block_qubits) {
   if (n < 1 || n > 34) return set_error(NWQ_ERANGE, "n outside [1, 34]");

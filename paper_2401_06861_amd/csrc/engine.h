@@ -22,8 +22,9 @@ struct nwq_state {
   bool owns = false;
   hipStream_t stream = nullptr;
 
-  // launch shapes per kernel class (autotuned)
-  nwq::LaunchCfg cfg[nwq::KC_COUNT];
+  // launch shapes per kernel class and target bucket (autotuned)
+  nwq::LaunchCfg cfg[nwq::KC_COUNT][nwq::kBuckets];
+  const nwq::LaunchCfg& shape(int cls, int lowest_bit) const { return cfg[cls][nwq::bucket_of(lowest_bit)]; }
 
   // reduction scratch
   double* partials = nullptr;

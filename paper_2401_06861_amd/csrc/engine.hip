@@ -227,7 +227,7 @@ int sv_apply_gate_validated(nwq_state* h, int type, const int* q, const double* 
       return NWQ_OK;
     case NWQ_GATE_X:
       timing_begin(h, KC_PERM);
-      launch_sv_swap1(h->stream, h->data, nb, q[0], h->cfg[KC_PERM]);
+      launch_sv_swap1(h->stream, h->data, nb, q[0], h->shape(KC_PERM, q[0]));
       timing_end(h);
       return last_launch("sv_swap1");
     case NWQ_GATE_Z: case NWQ_GATE_S: case NWQ_GATE_SDG: case NWQ_GATE_T: case NWQ_GATE_TDG:
@@ -235,7 +235,7 @@ int sv_apply_gate_validated(nwq_state* h, int type, const int* q, const double* 
       Diag4 d{};
       d.d[0] = d2(m[0]); d.d[1] = d2(m[3]); d.d[2] = d.d[0]; d.d[3] = d.d[1];
       timing_begin(h, KC_DIAG);
-      launch_sv_diag(h->stream, h->data, nb, q[0], -1, d, h->cfg[KC_DIAG]);
+      launch_sv_diag(h->stream, h->data, nb, q[0], -1, d, h->shape(KC_DIAG, q[0]));
       timing_end(h);
       return last_launch("sv_diag");
     }
@@ -243,26 +243,27 @@ int sv_apply_gate_validated(nwq_state* h, int type, const int* q, const double* 
       Mat2 M;
       for (int i = 0; i < 4; ++i) M.m[i] = d2(m[i]);
       timing_begin(h, KC_SV1Q);
-      launch_sv_1q(h->stream, h->data, nb, q[0], M, h->cfg[KC_SV1Q]);
+      launch_sv_1q(h->stream, h->data, nb, q[0], M, h->shape(KC_SV1Q, q[0]));
       timing_end(h);
       return last_launch("sv_1q");
     }
     case NWQ_GATE_CX:
       timing_begin(h, KC_PERM);
       launch_sv_swap2(h->stream, h->data, nb, q[0], q[1], 1ull << q[0], (1ull << q[0]) + (1ull << q[1]),
-                      h->cfg[KC_PERM]);
+                      h->shape(KC_PERM, std::min(q[0], q[1])));
       timing_end(h);
       return last_launch("sv_swap2(cx)");
     case NWQ_GATE_SWAP:
       timing_begin(h, KC_PERM);
-      launch_sv_swap2(h->stream, h->data, nb, q[0], q[1], 1ull << q[0], 1ull << q[1], h->cfg[KC_PERM]);
+      launch_sv_swap2(h->stream, h->data, nb, q[0], q[1], 1ull << q[0], 1ull << q[1],
+                      h->shape(KC_PERM, std::min(q[0], q[1])));
       timing_end(h);
       return last_launch("sv_swap2(swap)");
     case NWQ_GATE_CZ: case NWQ_GATE_RZZ: {
       Diag4 d{};
       for (int u = 0; u < 4; ++u) d.d[u] = d2(m[5 * u]);
       timing_begin(h, KC_DIAG);
-      launch_sv_diag(h->stream, h->data, nb, q[0], q[1], d, h->cfg[KC_DIAG]);
+      launch_sv_diag(h->stream, h->data, nb, q[0], q[1], d, h->shape(KC_DIAG, std::min(q[0], q[1])));
       timing_end(h);
       return last_launch("sv_diag2");
     }
@@ -276,14 +277,14 @@ int sv_apply_matrix_validated(nwq_state* h, const int* q, int k, const cd* m) {
     Mat2 M;
     for (int i = 0; i < 4; ++i) M.m[i] = d2(m[i]);
     timing_begin(h, KC_SV1Q);
-    launch_sv_1q(h->stream, h->data, h->nbits, q[0], M, h->cfg[KC_SV1Q]);
+    launch_sv_1q(h->stream, h->data, h->nbits, q[0], M, h->shape(KC_SV1Q, q[0]));
     timing_end(h);
     return last_launch("sv_1q");
   }
   Mat4 M;
   for (int i = 0; i < 16; ++i) M.m[i] = d2(m[i]);
   timing_begin(h, KC_SV2Q);
-  launch_sv_2q(h->stream, h->data, h->nbits, q[0], q[1], M, h->cfg[KC_SV2Q]);
+  launch_sv_2q(h->stream, h->data, h->nbits, q[0], q[1], M, h->shape(KC_SV2Q, std::min(q[0], q[1])));
   timing_end(h);
   return last_launch("sv_2q");
 }
@@ -313,7 +314,7 @@ int dm_flush(nwq_state* h) {
     for (int i = 0; i < 16; ++i) M.m[i] = d2(h->pend_S[i]);
     timing_begin(h, KC_DM1);
     // vec bits (column q, row q + n): u = c + 2 r
-    launch_sv_2q(h->stream, h->data, h->nbits, h->pend_q[0], h->pend_q[0] + n, M, h->cfg[KC_DM1]);
+    launch_sv_2q(h->stream, h->data, h->nbits, h->pend_q[0], h->pend_q[0] + n, M, h->shape(KC_DM1, h->pend_q[0]));
     timing_end(h);
     h->pend_active = false;
     return last_launch("dm_superop_1q");

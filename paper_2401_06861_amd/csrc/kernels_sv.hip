@@ -10,7 +10,8 @@
 // targets q >= 6 and cache-line-local addressing below, 64-bit byte offsets
 // only in address arithmetic, and an optional non-temporal hint (the data is
 // touched once per pass).  The launch shape (groups per thread PPT and the
-// hint) is a template choice picked per kernel class by the autotuner.
+// hint) is a template choice picked per kernel class and target bucket by
+// the autotuner.
 #include "nwq_internal.h"
 
 namespace nwq {
@@ -48,8 +49,8 @@ __device__ __forceinline__ void gst(double2* p, vd2 v) {
 // |0...0> (entry 0 = 1, rest 0) written with plain stores (no memset node,
 // so the kernel is safe inside captured graphs).
 template <int EPT>
-__global__ __launch_bounds__(kBlock) void k_fill_basis0(double2* __restrict__ a, unsigned long long len) {
-  const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_fill_basis0(double2* __restrict__ a, unsigned long long u0, unsigned long long len) {
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const unsigned long long i = start + (unsigned long long)j * kBlock;
@@ -60,9 +61,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_basis0(double2* __restrict__ a,
 // 1-qubit dense gate: for each pair p, i0 = insert0(p, q), i1 = i0 | 2^q,
 // (a_i0, a_i1) <- M (a_i0, a_i1).
 template <int PPT, bool NTM>
-__global__ __launch_bounds__(kBlock) void k_sv_1q(double2* __restrict__ a, unsigned long long npairs,
+__global__ __launch_bounds__(kBlock) void k_sv_1q(double2* __restrict__ a, unsigned long long u0, unsigned long long npairs,
                                                   int q, Mat2 m) {
-  const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
   const unsigned long long off = 1ull << q;
   const vd2 m0 = tov(m.m[0]), m1 = tov(m.m[1]), m2 = tov(m.m[2]), m3 = tov(m.m[3]);
   if (start + (unsigned long long)(PPT - 1) * kBlock < npairs) {
@@ -94,9 +95,9 @@ __global__ __launch_bounds__(kBlock) void k_sv_1q(double2* __restrict__ a, unsig
 // Diagonal gate on one or two qubits: a_i <- d[u(i)] a_i, u = bit q0 + 2 bit q1
 // (q1 < 0: one qubit).  Entries are chosen with selects, not an indexed load.
 template <int EPT, bool NTM>
-__global__ __launch_bounds__(kBlock) void k_sv_diag(double2* __restrict__ a, unsigned long long len,
+__global__ __launch_bounds__(kBlock) void k_sv_diag(double2* __restrict__ a, unsigned long long u0, unsigned long long len,
                                                     int q0, int q1, Diag4 d) {
-  const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
   const vd2 d0 = tov(d.d[0]), d1 = tov(d.d[1]), d2 = tov(d.d[2]), d3 = tov(d.d[3]);
   const bool two = q1 >= 0;
   const int qq = two ? q1 : q0;
@@ -124,8 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_sv_diag(double2* __restrict__ a, uns
 
 // X gate: swap the two members of each pair (no arithmetic).
 template <int PPT, bool NTM>
-__global__ __launch_bounds__(kBlock) void k_sv_swap1(double2* __restrict__ a, unsigned long long npairs, int q) {
-  const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_sv_swap1(double2* __restrict__ a, unsigned long long u0, unsigned long long npairs,
+                                                     int q) {
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
   const unsigned long long off = 1ull << q;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
@@ -143,10 +145,10 @@ __global__ __launch_bounds__(kBlock) void k_sv_swap1(double2* __restrict__ a, un
 // control=1 pair; SWAP: |01> <-> |10>).  Only the moved half of the vector
 // is read and written.
 template <int PPT, bool NTM>
-__global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, unsigned long long nquads,
+__global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, unsigned long long u0, unsigned long long nquads,
                                                      int qlo, int qhi, unsigned long long offA,
                                                      unsigned long long offB) {
-  const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
   if (start + (unsigned long long)(PPT - 1) * kBlock < nquads) {
     vd2 va[PPT], vb[PPT];
     unsigned long long b[PPT];
@@ -176,10 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, un
 // Two-qubit dense gate: quads over the sorted bit pair; member u sits at
 // base + bit0(u) 2^{q0} + bit1(u) 2^{q1} (operator order); out = M v.
 template <int PPT, bool NTM>
-__global__ __launch_bounds__(kBlock) void k_sv_2q(double2* __restrict__ a, unsigned long long nquads,
+__global__ __launch_bounds__(kBlock) void k_sv_2q(double2* __restrict__ a, unsigned long long u0, unsigned long long nquads,
                                                   int qlo, int qhi, unsigned long long o0,
                                                   unsigned long long o1, Mat4 m) {
-  const unsigned long long start = (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
   vd2 M[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) M[i] = tov(m.m[i]);
@@ -263,16 +265,32 @@ inline unsigned grid_for(unsigned long long units, int per_block) {
 
 }  // namespace
 
+// A dispatch packet holds the grid size in work-items as a 32-bit value, so
+// a launch covers at most kMaxItems work-items; larger passes (states above
+// 30 qubits at one group per thread) are split into launches that each take
+// their first unit u0.  Every launch but the last covers whole blocks.
+constexpr unsigned long long kMaxItems = 1ull << 30;
+
 void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len) {
-  hipLaunchKernelGGL(k_fill_basis0<4>, dim3(grid_for(len, kBlock * 4)), dim3(kBlock), 0, s, a, len);
+  const unsigned long long per = kMaxItems * 4;
+  for (unsigned long long u0 = 0; u0 < len; u0 += per) {
+    const unsigned long long cnt = len - u0 < per ? len - u0 : per;
+    hipLaunchKernelGGL(k_fill_basis0<4>, dim3(grid_for(cnt, kBlock * 4)), dim3(kBlock), 0, s, a, u0, len);
+  }
 }
 
-#define NWQ_LAUNCH_NT(KERNEL, P, units, ...)                                                          \
-  do {                                                                                                \
-    if (cfg.nt)                                                                                       \
-      hipLaunchKernelGGL((KERNEL<P, true>), dim3(grid_for(units, kBlock * P)), dim3(kBlock), 0, __VA_ARGS__); \
-    else                                                                                              \
-      hipLaunchKernelGGL((KERNEL<P, false>), dim3(grid_for(units, kBlock * P)), dim3(kBlock), 0, __VA_ARGS__); \
+#define NWQ_LAUNCH_NT(KERNEL, P, units, s, a, ...)                                                          \
+  do {                                                                                                      \
+    const unsigned long long per_ = kMaxItems * P;                                                          \
+    for (unsigned long long u0_ = 0; u0_ < (units); u0_ += per_) {                                          \
+      const unsigned long long cnt_ = (units) - u0_ < per_ ? (units) - u0_ : per_;                          \
+      if (cfg.nt)                                                                                           \
+        hipLaunchKernelGGL((KERNEL<P, true>), dim3(grid_for(cnt_, kBlock * P)), dim3(kBlock), 0, s, a, u0_, \
+                           __VA_ARGS__);                                                                    \
+      else                                                                                                  \
+        hipLaunchKernelGGL((KERNEL<P, false>), dim3(grid_for(cnt_, kBlock * P)), dim3(kBlock), 0, s, a, u0_, \
+                           __VA_ARGS__);                                                                    \
+    }                                                                                                       \
   } while (0)
 
 #define NWQ_PPT_SWITCH(KERNEL, units, ...)                               \

@@ -28,11 +28,20 @@ struct QSet {
   unsigned long long off[4];         // 2^{q_j} in the operator's own order
 };
 
-// Streaming launch shape chosen by the autotuner (per kernel class).
+// Streaming launch shape chosen by the autotuner (per kernel class and
+// target bucket).
 struct LaunchCfg {
   int ppt = 4;                       // pairs / groups / elements per thread (1, 2, 4, 8)
   int nt = 0;                        // 1: non-temporal loads and stores
 };
+
+// Launch shapes are kept in two buckets per class, by the lowest target bit
+// of the launch: below kLowBits the partner amplitudes of a group share
+// 1 KiB spans (a few cache lines read by one wave), at or above it each
+// group reads 2 or 4 separate streams; the best shape differs between them.
+constexpr int kLowBits = 6;
+constexpr int kBuckets = 2;
+inline int bucket_of(int lowest_bit) { return lowest_bit < kLowBits ? 0 : 1; }
 
 // Kernel classes (also the timing classes of nwq_timing_read).
 enum KClass {

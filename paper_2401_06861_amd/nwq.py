@@ -76,9 +76,10 @@ _SIG = {
     "nwq_trace": [_h, _dp, _dp],
     "nwq_purity": [_h, _dp],
     "nwq_timing_enable": [_h, C.c_int],
-    "nwq_set_launch": [_h, C.c_int, C.c_int, C.c_int],
-    "nwq_get_launch": [_h, C.c_int, _ip, _ip],
+    "nwq_set_launch": [_h, C.c_int, C.c_int, C.c_int, C.c_int],
+    "nwq_get_launch": [_h, C.c_int, C.c_int, _ip, _ip],
     "nwq_autotune": [_h, C.c_int, _dp],
+    "nwq_autotune_fusion": [_h, C.c_int, _ip, _ip, _dp, C.c_int, _ip, _ip, _dp],
     "nwq_timing_read": [_h, C.POINTER(C.c_longlong), _dp, C.c_int],
 }
 for _name, _args in _SIG.items():
@@ -278,20 +279,50 @@ def nwq_purity(h: int) -> float:
     return out.value
 
 
-def nwq_set_launch(h: int, cls: int, ppt: int, nontemporal: int) -> None:
-    _check(lib.nwq_set_launch(h, cls, ppt, nontemporal))
+LAUNCH_BUCKETS = ("low", "high")        # lowest target bit < 6, >= 6
 
 
-def nwq_get_launch(h: int, cls: int) -> Tuple[int, int]:
+def nwq_set_launch(h: int, cls: int, bucket: int, ppt: int, nontemporal: int) -> None:
+    _check(lib.nwq_set_launch(h, cls, bucket, ppt, nontemporal))
+
+
+def nwq_get_launch(h: int, cls: int, bucket: int) -> Tuple[int, int]:
     p, t = C.c_int(), C.c_int()
-    _check(lib.nwq_get_launch(h, cls, C.byref(p), C.byref(t)))
+    _check(lib.nwq_get_launch(h, cls, bucket, C.byref(p), C.byref(t)))
     return p.value, t.value
 
 
 def nwq_autotune(h: int, reps: int = 3) -> dict:
-    ms = (C.c_double * len(TIMING_CLASSES))()
+    """{class name: {bucket name: ms per launch}} for the classes and buckets tuned."""
+    nb = len(LAUNCH_BUCKETS)
+    ms = (C.c_double * (len(TIMING_CLASSES) * nb))()
     _check(lib.nwq_autotune(h, reps, ms))
-    return {name: float(ms[i]) for i, name in enumerate(TIMING_CLASSES) if ms[i] >= 0}
+    out = {}
+    for i, name in enumerate(TIMING_CLASSES):
+        for b, bname in enumerate(LAUNCH_BUCKETS):
+            if ms[i * nb + b] >= 0:
+                out.setdefault(name, {})[bname] = float(ms[i * nb + b])
+    return out
+
+
+FUSION_CANDIDATES = 17
+
+
+def nwq_autotune_fusion(h: int, types: np.ndarray, qubits: np.ndarray, params: np.ndarray, reps: int = 1):
+    """(best width (0 = unfused), register-blocked kernel flag, {(k, rb): ms per circuit});
+    the best setting is left on the handle and the state at |0...0>."""
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    qubits = np.ascontiguousarray(qubits, dtype=np.int32)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    k, rb = C.c_int(), C.c_int()
+    ms = (C.c_double * FUSION_CANDIDATES)()
+    _check(lib.nwq_autotune_fusion(h, len(types), types.ctypes.data_as(_ip), qubits.ctypes.data_as(_ip),
+                                   params.ctypes.data_as(_dp), reps, C.byref(k), C.byref(rb), ms))
+    table = {}
+    for i in range(FUSION_CANDIDATES):
+        if ms[i] >= 0:
+            table[(0, 0) if i == 0 else (6 + (i - 1) // 2, (i - 1) % 2)] = float(ms[i])
+    return k.value, rb.value, table
 
 
 def nwq_timing_enable(h: int, enable: bool = True) -> None:

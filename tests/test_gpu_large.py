@@ -1,5 +1,6 @@
-"""Parity at full size (30-qubit state vector, 17.2 GB; 14-qubit density
-matrix, 4.3 GB) in the launch configuration the benchmark uses, where the
+"""Parity at full size (30-qubit state vector, 17.2 GB; 32 and 33 qubits,
+68.7 and 137 GB; 14-qubit density matrix, 4.3 GB) in the launch
+configuration the benchmark uses, where the
 oracle cannot hold the whole state: sampled groups are gathered before and
 after one gate and recomputed by the oracle group by group (each output
 group depends only on its own inputs), plus properties that hold at any
@@ -67,6 +68,36 @@ def test_n30_single_gate_sampled(nwq, torch, name, qubits, params):
     post = gather(torch, v, idx)
     want = tensor.groups_apply(pre, G.gate_matrix(name, qubits, params))
     assert np.max(np.abs(post - want)) <= TOL
+    st.close()
+    del v
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [32, 33])
+def test_above_30_qubits_split_launches_sampled(nwq, torch, n):
+    """32 qubits (68.7 GB) and 33 qubits (137 GB): at one group per thread a
+    pass has more work-items than one dispatch holds and is split into
+    several launches; sampled groups must still match the oracle, for both
+    target buckets, and the reset must write every entry."""
+    v = random_device_state(torch, n, seed=n)
+    st = nwq.SVState(n, tensor=v, reset=False)
+    ops = [("u3", (0,), (0.7, 1.9, -2.3)), ("u3", (n - 1,), (2.9, -1.4, 0.6)), ("rz", (n - 1,), (0.8,)),
+           ("rzz", (1, n - 2), (1.1,)), ("cx", (n - 1, 0), ()), ("x", (n - 3,), ()), ("swap", (6, n - 1), ())]
+    for ppt, nt in ((1, 0), (2, 1)):
+        for cls in (1, 2, 3, 4):
+            nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
+        for i, (name, qubits, params) in enumerate(ops):
+            idx = tensor.group_indices(sample_bases(n, qubits, seed=100 * ppt + i, count=1 << 14), list(qubits))
+            pre = gather(torch, v, idx)
+            st.apply(name, qubits, params)
+            torch.cuda.synchronize()
+            want = tensor.groups_apply(pre, G.gate_matrix(name, qubits, params))
+            assert np.max(np.abs(gather(torch, v, idx) - want)) <= TOL, (n, ppt, nt, name, qubits)
+    assert abs(float(torch.linalg.vector_norm(v)) - 1.0) <= 1e-10
+    st.reset()
+    torch.cuda.synchronize()
+    assert v[0].item() == 1 and float(torch.linalg.vector_norm(v)) == 1.0
+    assert int(torch.count_nonzero(v[(1 << n) - (1 << 20):]).item()) == 0
     st.close()
     del v
     torch.cuda.empty_cache()

@@ -202,24 +202,51 @@ def test_owned_allocation_and_reset(nwq):
 @pytest.mark.parametrize("n", [3, 10, 13])
 def test_every_launch_shape_matches_oracle(nwq, n):
     """Each kernel class under every (groups per thread, non-temporal) shape,
-    including blocks that are only partly filled (small n)."""
+    on low and high target bits, including blocks that are only partly filled
+    (small n)."""
     psi0 = W.random_state(n, seed=70 + n)
     st = nwq.SVState(n, reset=False)
-    gates = {1: ("u3", (n - 1,), (0.3, 1.1, -0.7)), 2: ("rz", (n // 2,), (0.9,)),
-             3: ("cx", (0, n - 1), ()), 4: None}
+    ops = {1: [("u3", (n - 1,), (0.3, 1.1, -0.7)), ("ry", (0,), (0.4,)), ("h", (2,), ())],
+           2: [("rz", (n // 2,), (0.9,)), ("rzz", (0, 1), (0.3,)), ("t", (n - 1,), ())],
+           3: [("cx", (0, n - 1), ()), ("x", (1,), ()), ("swap", (n - 1, n - 2), ())]}
     m2 = np.array([[0.6, 0.8j, 0, 0.1], [0.2, -0.3, 0.5j, 0], [0, 0.4, 0.1 - 0.2j, 0.7], [0.3j, 0, 0.2, -0.5]])
     for cls in (1, 2, 3, 4):
         for ppt in (1, 2, 4, 8):
             for nt in (0, 1):
-                nwq.nwq_set_launch(st.h, cls, ppt, nt)
+                nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
                 st.load(psi0)
                 if cls == 4:
                     st.apply_matrix([1, n - 1], m2)
-                    want = tensor.apply_op(psi0, m2, [1, n - 1], n)
+                    st.apply_matrix([0, 2], m2)
+                    want = tensor.apply_op(tensor.apply_op(psi0, m2, [1, n - 1], n), m2, [0, 2], n)
                 else:
-                    st.apply(*gates[cls])
-                    want = tensor.sv_apply(psi0, gates[cls], n)
+                    st.run(ops[cls])
+                    want = tensor.sv_run(ops[cls], n, psi0)
                 assert maxerr(st.numpy(), want) <= TOL, (cls, ppt, nt)
+    st.close()
+
+
+def test_launch_shape_buckets(nwq):
+    """Different shapes in the two target buckets are kept apart and give the
+    oracle's result on a circuit touching both."""
+    n = 12
+    st = nwq.SVState(n, reset=False)
+    for cls in (1, 2, 3, 4):
+        nwq.nwq_set_launch(st.h, cls, 0, 1, 0)
+        nwq.nwq_set_launch(st.h, cls, 1, 8, 1)
+        assert nwq.nwq_get_launch(st.h, cls, 0) == (1, 0)
+        assert nwq.nwq_get_launch(st.h, cls, 1) == (8, 1)
+    gates = W.random_gate_list(n, 200, seed=11)
+    psi0 = W.random_state(n, seed=12)
+    st.load(psi0)
+    st.run_circuit(gates)
+    assert maxerr(st.numpy(), tensor.sv_run(gates, n, psi0)) <= TOL
+    for bad in ((1, 2, 4, 0), (1, -2, 4, 0), (1, 0, 3, 0)):
+        with pytest.raises(nwq.NwqError) as e:
+            nwq.nwq_set_launch(st.h, *bad)
+        assert e.value.code == nwq.NWQ_EINVAL
+    with pytest.raises(nwq.NwqError):
+        nwq.nwq_get_launch(st.h, 1, -1)
     st.close()
 
 
@@ -233,9 +260,13 @@ def test_autotune_keeps_state_and_parity(nwq):
     cache = os.path.join(tempfile.mkdtemp(), "tune.json")
     chosen = autotune.tune(st.h, reps=2, cache_path=cache)
     assert set(chosen) == {"sv_1q_dense", "sv_diag", "sv_perm", "sv_2q_dense"}
+    assert all(set(v) == {"low", "high"} for v in chosen.values())
     assert maxerr(st.numpy(), psi0) <= 1e-13          # H H rounding only
     again = autotune.tune(st.h, reps=2, cache_path=cache)   # from the cache
-    assert {k: v[:2] for k, v in again.items()} == {k: v[:2] for k, v in chosen.items()}
+    shapes = lambda e: {(k, b): tuple(v[:2]) for k, per in e.items() for b, v in per.items()}
+    assert shapes(again) == shapes(chosen)
+    for (name, b), shape in shapes(chosen).items():
+        assert nwq.nwq_get_launch(st.h, autotune.CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(b)) == shape
     gates = W.random_gate_list(n, 120, seed=3)
     st.load(psi0)
     st.run_circuit(gates)
@@ -245,7 +276,7 @@ def test_autotune_keeps_state_and_parity(nwq):
     rho0 = W.random_density_matrix(4, seed=1)
     dm.load(rho0)
     ms = nwq.nwq_autotune(dm.h, 2)
-    assert set(ms) == {"dm_superop_1q"}
+    assert set(ms) == {"dm_superop_1q"} and set(ms["dm_superop_1q"]) == {"low"}   # n = 4: no bit >= 6
     assert maxerr(dm.numpy(), rho0) == 0.0
     dm.close()
 
@@ -267,3 +298,36 @@ def test_register_blocked_fused_kernel(nwq, n, k):
         if rb:
             assert nwq.nwq_fusion_phases(st.h) > 0
         st.close()
+
+
+def test_fusion_autotuner(nwq):
+    """The fusion autotuner times every candidate, keeps the fastest, leaves
+    the state at |0...0>, and the circuit then matches the oracle."""
+    n = 14
+    gates = W.brickwork_circuit(n, 8, seed=2)
+    arrays = nwq.circuit_arrays(gates)
+    st = nwq.SVState(n)
+    k, rb, table = nwq.nwq_autotune_fusion(st.h, *arrays, reps=1)
+    assert set(table) == {(0, 0)} | {(w, r) for w in range(6, 14) for r in (0, 1)}
+    assert table[(k, rb)] == min(table.values())
+    out = st.numpy()
+    assert out[0] == 1 and np.count_nonzero(out) == 1
+    st.run_circuit(gates)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    assert maxerr(st.numpy(), tensor.sv_run(gates, n, psi0)) <= TOL
+    blocks, _ = nwq.nwq_fusion_stats(st.h)
+    assert (blocks > 0) == (k > 0)
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_autotune_fusion(st.h, *arrays, reps=0)
+    assert e.value.code == nwq.NWQ_EINVAL
+    st.close()
+    small = nwq.SVState(7)
+    k, rb, table = nwq.nwq_autotune_fusion(small.h, *nwq.circuit_arrays(W.brickwork_circuit(7, 3, seed=1)))
+    assert set(table) == {(0, 0), (6, 0), (7, 0)}                   # widths up to n; no register-blocked tiles below 8
+    small.close()
+    dm = nwq.DMState(3)
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_autotune_fusion(dm.h, *nwq.circuit_arrays([("h", (0,), ())]))
+    assert e.value.code == nwq.NWQ_EKIND
+    dm.close()
