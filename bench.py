@@ -151,7 +151,8 @@ def main():
 
     if args.profile_mode is not None:
         # short, fixed work for rocprofv3: a plain copy of known size (counter
-        # calibration), then U3 and CX launches at n
+        # calibration), the launch-shape autotuner, then U3 and CX launches at
+        # n in the tuned shapes (the last 3 x 3 U3 and 3 CX dispatches)
         src = torch.empty(1 << 27, dtype=torch.complex128, device=dev)   # 2 GiB
         src.fill_(0.5)
         dst = torch.empty_like(src)
@@ -159,6 +160,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+        from paper_2401_06861_amd import autotune
+        tuned = autotune.tune(st.h, reps=1, cache_path=None)      # the timed run's shapes
+        log(f"[bench] profile mode launch shapes: {tuned}")
+        torch.cuda.synchronize()
         reps = 3 if args.profile_mode == "pmc" else 10
         for r in range(reps):
             for q in (0, 7, n - 1):

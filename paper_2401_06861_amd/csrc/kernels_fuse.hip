@@ -21,6 +21,29 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
   return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
 
+// Global index of tile entry l: low c bits in place, bit c + i of l on
+// qubit hi[i].
+__device__ __forceinline__ unsigned long long tile_index(unsigned long long base, unsigned l, unsigned cmask, int c,
+                                                         int m, const FusedBlockDev& blk) {
+  unsigned long long g = base | (l & cmask);
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
+  return g;
+}
+
+// Clang vector of two doubles: stays in registers where copies of HIP's
+// double2 struct can go through scratch.
+typedef double vd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ vd2 ldv(const double2* p) { return *reinterpret_cast<const vd2*>(p); }
+__device__ __forceinline__ void stv(double2* p, vd2 v) { *reinterpret_cast<vd2*>(p) = v; }
+
+// Tile staging in chunks of kStage entries per thread: all loads of a chunk
+// are issued before the first LDS write (and all LDS reads before the first
+// global store), so each thread keeps kStage requests in flight instead of
+// one.  Tiles of at least kStage * kFuseBlock entries take whole chunks.
+constexpr int kStage = 8;
+
 __global__ __launch_bounds__(kFuseBlock) void k_fused(double2* __restrict__ a, int nbits, FusedBlockDev blk,
                                                       const FusedOp* __restrict__ ops,
                                                       const double2* __restrict__ mats) {
@@ -39,12 +62,16 @@ __global__ __launch_bounds__(kFuseBlock) void k_fused(double2* __restrict__ a, i
       }
     }
     __syncthreads();
-    for (unsigned l = threadIdx.x; l < len; l += kFuseBlock) {
-      unsigned long long g = base | (l & cmask);
+    if (len >= kStage * kFuseBlock) {
+      for (unsigned l0 = threadIdx.x; l0 < len; l0 += kStage * kFuseBlock) {
+        vd2 r[kStage];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
-      t[l] = a[g];
+        for (int j = 0; j < kStage; ++j) r[j] = ldv(a + tile_index(base, l0 + j * kFuseBlock, cmask, c, m, blk));
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) stv(t + l0 + j * kFuseBlock, r[j]);
+      }
+    } else {
+      for (unsigned l = threadIdx.x; l < len; l += kFuseBlock) t[l] = a[tile_index(base, l, cmask, c, m, blk)];
     }
     for (int oi = 0; oi < blk.op_count; ++oi) {
       const FusedOp op = ops[blk.op_begin + oi];
@@ -107,12 +134,16 @@ __global__ __launch_bounds__(kFuseBlock) void k_fused(double2* __restrict__ a, i
       }
     }
     __syncthreads();
-    for (unsigned l = threadIdx.x; l < len; l += kFuseBlock) {
-      unsigned long long g = base | (l & cmask);
+    if (len >= kStage * kFuseBlock) {
+      for (unsigned l0 = threadIdx.x; l0 < len; l0 += kStage * kFuseBlock) {
+        vd2 r[kStage];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
-      a[g] = t[l];
+        for (int j = 0; j < kStage; ++j) r[j] = ldv(t + l0 + j * kFuseBlock);
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) stv(a + tile_index(base, l0 + j * kFuseBlock, cmask, c, m, blk), r[j]);
+      }
+    } else {
+      for (unsigned l = threadIdx.x; l < len; l += kFuseBlock) a[tile_index(base, l, cmask, c, m, blk)] = t[l];
     }
   }
 }
@@ -144,10 +175,7 @@ void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDe
 namespace nwq {
 namespace {
 
-typedef double vd2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ vd2 mkv(double a, double b) { vd2 r; r.x = a; r.y = b; return r; }
-__device__ __forceinline__ vd2 ldv(const double2* p) { return *reinterpret_cast<const vd2*>(p); }
-__device__ __forceinline__ void stv(double2* p, vd2 v) { *reinterpret_cast<vd2*>(p) = v; }
 __device__ __forceinline__ vd2 vmul(vd2 a, vd2 b) { return mkv(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)); }
 __device__ __forceinline__ vd2 vfma(vd2 a, vd2 b, vd2 c) {
   return mkv(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
@@ -276,12 +304,12 @@ __global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a0, int 
       }
     }
     __syncthreads();
-    for (unsigned l = tid; l < len; l += nt) {
-      unsigned long long g = base | (l & cmask);
+    {
+      vd2 r[16];   // the tile has exactly 16 entries per thread: issue all loads, then write LDS
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
-      t[padl(l)] = a[g];
+      for (int j = 0; j < 16; ++j) r[j] = ldv(a + tile_index(base, tid + j * nt, cmask, c, m, blk));
+#pragma unroll
+      for (int j = 0; j < 16; ++j) stv(t + padl(tid + j * nt), r[j]);
     }
     for (int pi = 0; pi < blk.op_count; ++pi) {
       const FusedPhase ph = phases[blk.op_begin + pi];
@@ -307,12 +335,12 @@ __global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a0, int 
       for (int j = 0; j < 16; ++j) stv(t + padl(dep | off[j]), v[j]);
     }
     __syncthreads();
-    for (unsigned l = tid; l < len; l += nt) {
-      unsigned long long g = base | (l & cmask);
+    {
+      vd2 r[16];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
-      a[g] = t[padl(l)];
+      for (int j = 0; j < 16; ++j) r[j] = ldv(t + padl(tid + j * nt));
+#pragma unroll
+      for (int j = 0; j < 16; ++j) stv(a + tile_index(base, tid + j * nt, cmask, c, m, blk), r[j]);
     }
   }
 }
