@@ -316,6 +316,37 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_init(double2* __restrict__ ph
     v[j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
 }
 
+// Grid-stride loops of the per-gate kernels take kU groups per thread per
+// step, all loads issued before the arithmetic; the tail takes one.
+constexpr int kU = 4;
+
+__device__ __forceinline__ void pairs_apply_g(double2* v, unsigned long long N, int q, const M2& m,
+                                              unsigned long long tid, unsigned long long nt) {
+  const unsigned long long off = 1ull << q, np = N >> 1;
+  unsigned long long p = tid;
+  for (; p + (kU - 1) * nt < np; p += kU * nt) {
+    unsigned long long i0[kU];
+    vd2 a[kU], b[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      i0[u] = ins0l(p + u * nt, q);
+      a[u] = ld(v + i0[u]);
+      b[u] = ld(v + i0[u] + off);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      st(v + i0[u], cfma(m.m0, a[u], cmul(m.m1, b[u])));
+      st(v + i0[u] + off, cfma(m.m2, a[u], cmul(m.m3, b[u])));
+    }
+  }
+  for (; p < np; p += nt) {
+    const unsigned long long i0 = ins0l(p, q);
+    const vd2 a = ld(v + i0), b = ld(v + i0 + off);
+    st(v + i0, cfma(m.m0, a, cmul(m.m1, b)));
+    st(v + i0 + off, cfma(m.m2, a, cmul(m.m3, b)));
+  }
+}
+
 __global__ __launch_bounds__(kVqeBlock) void k_vqe_gate(double2* __restrict__ states, int n, VqeOp op,
                                                         const double2* __restrict__ fixed,
                                                         const double* __restrict__ theta, int P, int dag) {
@@ -326,29 +357,64 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_gate(double2* __restrict__ st
   const unsigned long long nt = (unsigned long long)gridDim.x * kVqeBlock;
   switch (op.kind) {
     case OP_ROT:
-      pairs_apply<unsigned long long>(v, N, op.q0, rot_matrix(op.axis, th[op.param], dag != 0), tid, nt);
+      pairs_apply_g(v, N, op.q0, rot_matrix(op.axis, th[op.param], dag != 0), tid, nt);
       break;
     case OP_FIX1:
-      pairs_apply<unsigned long long>(v, N, op.q0, fixed_matrix(op.mat, fixed, dag != 0), tid, nt);
+      pairs_apply_g(v, N, op.q0, fixed_matrix(op.mat, fixed, dag != 0), tid, nt);
       break;
     case OP_RZZ: {
       vd2 e, o;
       rzz_phases(th[op.param], dag != 0, e, o);
-      for (unsigned long long j = tid; j < N; j += nt) {
+      unsigned long long j = tid;
+      for (; j + (kU - 1) * nt < N; j += kU * nt) {
+        vd2 x[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) x[u] = ld(v + j + u * nt);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const unsigned long long i = j + u * nt;
+          const unsigned par = (unsigned)(((i >> op.q0) ^ (i >> op.q1)) & 1ull);
+          st(v + i, cmul(par ? o : e, x[u]));
+        }
+      }
+      for (; j < N; j += nt) {
         const unsigned par = (unsigned)(((j >> op.q0) ^ (j >> op.q1)) & 1ull);
         st(v + j, cmul(par ? o : e, ld(v + j)));
       }
       break;
     }
-    case OP_CZ:
-      for (unsigned long long j = tid; j < N; j += nt)
-        if (((j >> op.q0) & (j >> op.q1)) & 1ull) { const vd2 x = ld(v + j); st(v + j, mk(-x.x, -x.y)); }
+    case OP_CZ: {   // negate the quarter with both bits set
+      const int lo = min(op.q0, op.q1), hi = max(op.q0, op.q1);
+      const unsigned long long o11 = (1ull << op.q0) + (1ull << op.q1);
+      for (unsigned long long p = tid; p < (N >> 2); p += nt) {
+        const unsigned long long i = ins0l(ins0l(p, lo), hi) + o11;
+        const vd2 x = ld(v + i);
+        st(v + i, mk(-x.x, -x.y));
+      }
       break;
+    }
     default: {
       const int lo = min(op.q0, op.q1), hi = max(op.q0, op.q1);
       const unsigned long long oa = 1ull << op.q0;
       const unsigned long long ob = op.kind == OP_CX ? (1ull << op.q0) + (1ull << op.q1) : (1ull << op.q1);
-      for (unsigned long long p = tid; p < (N >> 2); p += nt) {
+      const unsigned long long nq = N >> 2;
+      unsigned long long p = tid;
+      for (; p + (kU - 1) * nt < nq; p += kU * nt) {
+        unsigned long long b[kU];
+        vd2 x[kU], y[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          b[u] = ins0l(ins0l(p + u * nt, lo), hi);
+          x[u] = ld(v + b[u] + oa);
+          y[u] = ld(v + b[u] + ob);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          st(v + b[u] + oa, y[u]);
+          st(v + b[u] + ob, x[u]);
+        }
+      }
+      for (; p < nq; p += nt) {
         const unsigned long long b = ins0l(ins0l(p, lo), hi);
         const vd2 x = ld(v + b + oa), y = ld(v + b + ob);
         st(v + b + oa, y);
@@ -401,8 +467,30 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__
   double g = 0.0;
   if (op.kind == OP_ROT) {
     const M2 m = rot_matrix(op.axis, th[op.param], true);
-    const unsigned long long off = 1ull << op.q0;
-    for (unsigned long long p = tid; p < (N >> 1); p += nt) {
+    const unsigned long long off = 1ull << op.q0, np = N >> 1;
+    unsigned long long p = tid;
+    // kU pairs per step; the gradient terms are added in pair order
+    for (; p + (kU - 1) * nt < np; p += kU * nt) {
+      unsigned long long i0[kU];
+      vd2 p0[kU], p1[kU], l0[kU], l1[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        i0[u] = ins0l(p + u * nt, op.q0);
+        p0[u] = ld(pv + i0[u]);
+        p1[u] = ld(pv + i0[u] + off);
+        l0[u] = ld(lv + i0[u]);
+        l1[u] = ld(lv + i0[u] + off);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        g += pair_grad(op.axis, p0[u], p1[u], l0[u], l1[u]);
+        st(pv + i0[u], cfma(m.m0, p0[u], cmul(m.m1, p1[u])));
+        st(pv + i0[u] + off, cfma(m.m2, p0[u], cmul(m.m3, p1[u])));
+        st(lv + i0[u], cfma(m.m0, l0[u], cmul(m.m1, l1[u])));
+        st(lv + i0[u] + off, cfma(m.m2, l0[u], cmul(m.m3, l1[u])));
+      }
+    }
+    for (; p < np; p += nt) {
       const unsigned long long i0 = ins0l(p, op.q0);
       const vd2 p0 = ld(pv + i0), p1 = ld(pv + i0 + off);
       const vd2 l0 = ld(lv + i0), l1 = ld(lv + i0 + off);
@@ -415,7 +503,25 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__
   } else {   // OP_RZZ
     vd2 e, o;
     rzz_phases(th[op.param], true, e, o);
-    for (unsigned long long j = tid; j < N; j += nt) {
+    unsigned long long j = tid;
+    for (; j + (kU - 1) * nt < N; j += kU * nt) {
+      vd2 x[kU], y[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        x[u] = ld(pv + j + u * nt);
+        y[u] = ld(lv + j + u * nt);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const unsigned long long i = j + u * nt;
+        const unsigned par = (unsigned)(((i >> op.q0) ^ (i >> op.q1)) & 1ull);
+        const double t = y[u].x * x[u].y - y[u].y * x[u].x;
+        g += par ? -t : t;
+        st(pv + i, cmul(par ? o : e, x[u]));
+        st(lv + i, cmul(par ? o : e, y[u]));
+      }
+    }
+    for (; j < N; j += nt) {
       const unsigned par = (unsigned)(((j >> op.q0) ^ (j >> op.q1)) & 1ull);
       const vd2 p = ld(pv + j), l = ld(lv + j);
       const double t = l.x * p.y - l.y * p.x;
@@ -434,22 +540,39 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__
   }
 }
 
-// E[b] = sum_blocks epart; grad[b][p] = sum over slots of p (slot order) of
-// the block partials (block order).  One thread per batch element.
-__global__ __launch_bounds__(64) void k_vqe_finish(const double* __restrict__ epart, const double* __restrict__ gpart,
-                                                   int G, int nslots, const int* __restrict__ slot_param, int P,
-                                                   int B, double* __restrict__ E, double* __restrict__ grad) {
-  const int b = blockIdx.x * 64 + threadIdx.x;
-  if (b >= B) return;
-  double e = 0.0;
-  for (int k = 0; k < G; ++k) e += epart[(size_t)b * G + k];
-  E[b] = e;
+// One workgroup per state: the energy partials and each slot's gradient
+// partials are summed by one wave each (lanes stride over the partials, then
+// a fixed shuffle tree), slot sums go to ssum, and each parameter adds its
+// slots in slot order.  The order depends only on G, never on B.
+constexpr int kFinBlock = 256;
+__global__ __launch_bounds__(kFinBlock) void k_vqe_finish(const double* __restrict__ epart,
+                                                          const double* __restrict__ gpart, int G, int nslots,
+                                                          const int* __restrict__ slot_param, int P,
+                                                          double* __restrict__ ssum, double* __restrict__ E,
+                                                          double* __restrict__ grad) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  constexpr int NW = kFinBlock / kWave;
+  if (wave == 0) {
+    double e = 0.0;
+    for (int k = lane; k < G; k += kWave) e += epart[(size_t)b * G + k];
+    e = wave_sum(e);
+    if (lane == 0) E[b] = e;
+  }
   if (!grad) return;
-  for (int p = 0; p < P; ++p) grad[(size_t)b * P + p] = 0.0;
-  for (int s = 0; s < nslots; ++s) {
+  for (int s = wave; s < nslots; s += NW) {
+    const double* gp = gpart + ((size_t)b * nslots + s) * G;
     double v = 0.0;
-    for (int k = 0; k < G; ++k) v += gpart[((size_t)b * nslots + s) * G + k];
-    grad[(size_t)b * P + slot_param[s]] += v;
+    for (int k = lane; k < G; k += kWave) v += gp[k];
+    v = wave_sum(v);
+    if (lane == 0) ssum[(size_t)b * nslots + s] = v;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < P; p += kFinBlock) {
+    double g = 0.0;
+    for (int s = 0; s < nslots; ++s)
+      if (slot_param[s] == p) g += ssum[(size_t)b * nslots + s];
+    grad[(size_t)b * P + p] = g;
   }
 }
 
@@ -473,6 +596,16 @@ struct VqeBwdOp {
 
 constexpr int kBwdBlock = 256;
 constexpr int kBwdMaxOps = 128;
+constexpr int kBwdStage = 8;   // tile entries per thread staged together (loads issued before LDS writes)
+
+__device__ __forceinline__ unsigned long long bwd_index(unsigned long long base, unsigned l, unsigned cmask, int c,
+                                                        int m, const FusedBlockDev& blk) {
+  unsigned long long g = base | (l & cmask);
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
+  return g;
+}
 
 // Per-vector matrix table: for op i, entries [8i, 8i+4) hold the forward
 // matrix (2x2 row-major, or the 4 diagonal entries of RZZ / CZ indexed by
@@ -539,13 +672,27 @@ __global__ __launch_bounds__(kBwdBlock) void k_vqe_bwd_tile(double2* __restrict_
       }
     }
     __syncthreads();
-    for (unsigned l = tid; l < len; l += kBwdBlock) {
-      unsigned long long g = base | (l & cmask);
+    if (len >= kBwdStage * kBwdBlock) {
+      for (unsigned l0 = tid; l0 < len; l0 += kBwdStage * kBwdBlock) {
+        vd2 rp[kBwdStage], rl[kBwdStage];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
-      tp[l] = phi[g];
-      tl[l] = lam[g];
+        for (int j = 0; j < kBwdStage; ++j) {
+          const unsigned long long g = bwd_index(base, l0 + j * kBwdBlock, cmask, c, m, blk);
+          rp[j] = ld(phi + g);
+          rl[j] = ld(lam + g);
+        }
+#pragma unroll
+        for (int j = 0; j < kBwdStage; ++j) {
+          st(tp + l0 + j * kBwdBlock, rp[j]);
+          st(tl + l0 + j * kBwdBlock, rl[j]);
+        }
+      }
+    } else {
+      for (unsigned l = tid; l < len; l += kBwdBlock) {
+        const unsigned long long g = bwd_index(base, l, cmask, c, m, blk);
+        tp[l] = phi[g];
+        tl[l] = lam[g];
+      }
     }
     for (int oi = 0; oi < blk.op_count; ++oi) {
       const VqeBwdOp op = ops[blk.op_begin + oi];
@@ -597,13 +744,27 @@ __global__ __launch_bounds__(kBwdBlock) void k_vqe_bwd_tile(double2* __restrict_
       }
     }
     __syncthreads();
-    for (unsigned l = tid; l < len; l += kBwdBlock) {
-      unsigned long long g = base | (l & cmask);
+    if (len >= kBwdStage * kBwdBlock) {
+      for (unsigned l0 = tid; l0 < len; l0 += kBwdStage * kBwdBlock) {
+        vd2 rp[kBwdStage], rl[kBwdStage];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < m && ((l >> (c + i)) & 1u)) g |= 1ull << blk.hi[i];
-      phi[g] = tp[l];
-      lam[g] = tl[l];
+        for (int j = 0; j < kBwdStage; ++j) {
+          rp[j] = ld(tp + l0 + j * kBwdBlock);
+          rl[j] = ld(tl + l0 + j * kBwdBlock);
+        }
+#pragma unroll
+        for (int j = 0; j < kBwdStage; ++j) {
+          const unsigned long long g = bwd_index(base, l0 + j * kBwdBlock, cmask, c, m, blk);
+          st(phi + g, rp[j]);
+          st(lam + g, rl[j]);
+        }
+      }
+    } else {
+      for (unsigned l = tid; l < len; l += kBwdBlock) {
+        const unsigned long long g = bwd_index(base, l, cmask, c, m, blk);
+        phi[g] = tp[l];
+        lam[g] = tl[l];
+      }
     }
   }
   __syncthreads();
@@ -651,6 +812,7 @@ struct nwq_vqe {
   double* d_grad = nullptr;
   double* d_coeffs = nullptr;  // staging copy of per-vector coefficients
   double2* d_table = nullptr;  // fused path: per-vector matrix table [B][nops][8]
+  double* d_ssum = nullptr;    // per-slot gradient sums [B][nslots]
   // fused path program (built on first use)
   bool fused_built = false;
   int fused_k = 11;
@@ -665,11 +827,15 @@ namespace nwq {
 
 static int vqe_fail(int code, const std::string& m) { return set_error(code, m); }
 
+// Workgroups per state of the per-gate and fused schedules.  The partial
+// sums (and so the rounding) depend on it, so it is fixed per context and
+// never derived from B; the default fills the chip with one state (up to
+// 1024 workgroups of 4 pairs per thread), the batch adds the rest.
 static int blocks_per_state(const nwq_vqe* h) {
   if (h->cfg.blocks_per_state > 0) return h->cfg.blocks_per_state;
   const unsigned long long pairs = 1ull << (h->n - 1);
   const unsigned long long b = (pairs + kVqeBlock * 4 - 1) / (kVqeBlock * 4);
-  return (int)std::max<unsigned long long>(1, std::min<unsigned long long>(b, 64));
+  return (int)std::max<unsigned long long>(1, std::min<unsigned long long>(b, 1024));
 }
 
 static size_t lds_bytes(const nwq_vqe* h, int threads, bool want_grad) {
@@ -712,10 +878,10 @@ static int ensure_global(nwq_vqe* h, int B) {
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   h->graphs.clear();
   for (void* p : {(void*)h->d_phi, (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta,
-                  (void*)h->d_E, (void*)h->d_grad, (void*)h->d_coeffs, (void*)h->d_table})
+                  (void*)h->d_E, (void*)h->d_grad, (void*)h->d_coeffs, (void*)h->d_table, (void*)h->d_ssum})
     if (p) (void)hipFree(p);
   h->d_phi = h->d_lam = h->d_table = nullptr;
-  h->d_epart = h->d_gpart = h->d_theta = h->d_E = h->d_grad = h->d_coeffs = nullptr;
+  h->d_epart = h->d_gpart = h->d_theta = h->d_E = h->d_grad = h->d_coeffs = h->d_ssum = nullptr;
   h->Bcap = 0;
   const size_t N = 1ull << h->n;
   const int G = blocks_per_state(h);
@@ -728,6 +894,7 @@ static int ensure_global(nwq_vqe* h, int B) {
   if (!rc) rc = check_hip(hipMalloc(&h->d_grad, (size_t)B * std::max(1, h->P) * sizeof(double)), "hipMalloc(vqe grad)");
   if (!rc) rc = check_hip(hipMalloc(&h->d_coeffs, (size_t)B * std::max(1, h->nterms) * sizeof(double)), "hipMalloc(vqe coeffs)");
   if (!rc) rc = check_hip(hipMalloc(&h->d_table, (size_t)B * std::max(1, h->nops) * 8 * sizeof(double2)), "hipMalloc(vqe table)");
+  if (!rc) rc = check_hip(hipMalloc(&h->d_ssum, (size_t)B * std::max(1, h->nslots) * sizeof(double)), "hipMalloc(vqe slot sums)");
   if (rc) return rc;
   h->Bcap = B;
   return NWQ_OK;
@@ -756,8 +923,8 @@ static int launch_global(nwq_vqe* h, int B, const double* theta, const double* c
       }
     }
   }
-  hipLaunchKernelGGL(k_vqe_finish, dim3((B + 63) / 64), dim3(64), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
-                     h->d_slot_param, h->P, B, E, grad);
+  hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
+                     h->d_slot_param, h->P, h->d_ssum, E, grad);
   return check_hip(hipGetLastError(), "vqe per-gate schedule");
 }
 
@@ -908,8 +1075,8 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
                          h->d_table, stride, h->nslots, h->d_gpart);
     }
   }
-  hipLaunchKernelGGL(k_vqe_finish, dim3((B + 63) / 64), dim3(64), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
-                     h->d_slot_param, h->P, B, E, grad);
+  hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
+                     h->d_slot_param, h->P, h->d_ssum, E, grad);
   return check_hip(hipGetLastError(), "vqe fused schedule");
 }
 
@@ -1044,7 +1211,7 @@ int nwq_vqe_destroy(nwq_vqe_handle h) {
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   for (void* p : {(void*)h->d_ops, (void*)h->d_fixed, (void*)h->d_terms, (void*)h->d_slot_param, (void*)h->d_phi,
                   (void*)h->d_lam, (void*)h->d_epart, (void*)h->d_gpart, (void*)h->d_theta, (void*)h->d_E,
-                  (void*)h->d_grad, (void*)h->d_coeffs, (void*)h->d_table, h->d_fused})
+                  (void*)h->d_grad, (void*)h->d_coeffs, (void*)h->d_table, (void*)h->d_ssum, h->d_fused})
     if (p) (void)hipFree(p);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
@@ -1167,10 +1334,10 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms) {
     for (int t : {64, 128, 256, 512, 1024})
       if (lds_fits(h, t, with_grad != 0)) cands.push_back({1, t, 0});
   const unsigned long long pairs = 1ull << (h->n - 1);
-  for (int bps : {0, 8, 16, 32, 64, 128, 256})
+  for (int bps : {0, 8, 16, 32, 64, 128, 256, 512, 1024})
     if (bps == 0 || (unsigned long long)bps * 256 <= pairs) cands.push_back({2, h->cfg.threads, bps});
   if (h->n >= 13)
-    for (int bps : {0, 16, 32, 64, 128})
+    for (int bps : {0, 16, 32, 64, 128, 256, 512, 1024})
       if (bps == 0 || (unsigned long long)bps * 256 <= pairs) cands.push_back({3, h->cfg.threads, bps});
   const VqeConfig saved = h->cfg;
   double best = 1e300;

@@ -22,8 +22,8 @@ executor and a virtual clock):
   a class launches again as soon as its previous batch completes, taking
   every request of that class that became ready meanwhile, so requests that
   arrive while others are on the GPU join the next batch of their class;
-  classes run concurrently on their own streams, DM requests on a worker
-  thread with its own stream;
+  classes run concurrently on their own streams, DM requests on worker
+  threads with a stream each;
 * a failing request (bad parameters) completes with an error and does not
   affect the others of its batch.
 
@@ -35,6 +35,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import math
+import threading
 import time
 from collections import OrderedDict, deque
 from dataclasses import dataclass, field
@@ -233,10 +234,10 @@ def summarize(results: List[ServeResult]) -> dict:
 # ---------------------------------------------------------------------------
 class GpuExecutor:
     """Runs SV batches through nwq_vqe_eval_coeffs (one VQE context and one
-    stream per shape class) and DM jobs through the DM engine on a worker
-    thread with its own stream."""
+    stream per shape class) and DM jobs through the DM engine on worker
+    threads, each with its own stream."""
 
-    def __init__(self, dm_workers: int = 1, sv_mode: int = 0):
+    def __init__(self, dm_workers: int = 4, sv_mode: int = 0):
         import torch
         import workloads as W
         from . import nwq, vqe
@@ -246,7 +247,7 @@ class GpuExecutor:
         self.streams: Dict[Tuple, Any] = {}
         self.sv_mode = sv_mode
         self.pool = cf.ThreadPoolExecutor(max_workers=dm_workers)
-        self.dm_stream = torch.cuda.Stream()
+        self._tls = threading.local()          # one stream per DM worker thread
 
     # --- policy hooks
     def footprint(self, r) -> int:
@@ -305,11 +306,19 @@ class GpuExecutor:
         return ("sv", ev, E, G, t, c)
 
     # --- DM jobs
+    def _dm_stream(self):
+        s = getattr(self._tls, "stream", None)
+        if s is None:
+            self.torch.cuda.set_device(self.dev)
+            s = self._tls.stream = self.torch.cuda.Stream(device=self.dev)
+        return s
+
     def _dm_job(self, r):
         torch = self.torch
         try:
-            with torch.cuda.stream(self.dm_stream):
-                st = self.nwq.DMState(r.n, stream=self.dm_stream)
+            stream = self._dm_stream()
+            with torch.cuda.stream(stream):
+                st = self.nwq.DMState(r.n, stream=stream)
                 st.run(self.W.noisy_tfim_circuit(r.n, r.steps))
                 Z = st.expvals(self.W.single_site_terms(r.n, "Z"))
                 pur = st.purity()
