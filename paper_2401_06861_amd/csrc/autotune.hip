@@ -1,8 +1,9 @@
 // Launch-shape autotuner for the streaming gate kernels of a handle.
 //
-// For each kernel class and target bucket (lowest target bit below 6, or at
-// or above it) it times every candidate (groups per thread in {1, 2, 4, 8} x
-// non-temporal hint off/on) with HIP events on the handle's own stream and
+// For each kernel class and target bucket (lowest target bit 0-2, 3-11 or
+// 12 and up) it times every candidate (groups per thread in {1, 2, 4, 8},
+// and 16 for the 1q, diagonal and permutation kernels, x non-temporal hint
+// off/on) with HIP events on the handle's own stream and
 // state, and keeps the fastest.  Candidates apply self-inverse operations in
 // pairs on up to three target bits of the bucket (H H for the dense 1-qubit
 // kernel, Z Z for the diagonal kernel, CX CX for the permutation kernel, CZ
@@ -21,7 +22,11 @@ namespace nwq {
 namespace {
 
 struct Cand { int ppt, nt; };
-const Cand kCands[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {1, 1}, {2, 1}, {4, 1}, {8, 1}};
+const Cand kCands[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}};
+
+// 16 groups per thread is offered to the kernels with at most two streams
+// per group (the 4x4 kernel would run out of registers).
+bool allows16(int cls) { return cls == KC_SV1Q || cls == KC_DIAG || cls == KC_PERM; }
 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
 
@@ -68,8 +73,9 @@ extern "C" {
 int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) {
   if (!h) return set_error(NWQ_EINVAL, "NULL handle");
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
-  if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0 or 1");
-  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8");
+  if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0, 1 or 2");
+  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && !(ppt == 16 && allows16(cls)))
+    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3)");
   for (int b = 0; b < kBuckets; ++b) {
     if (bucket >= 0 && b != bucket) continue;
     h->cfg[cls][b].ppt = ppt;
@@ -81,7 +87,7 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
 int nwq_get_launch(nwq_handle h, int cls, int bucket, int* ppt, int* nontemporal) {
   if (!h) return set_error(NWQ_EINVAL, "NULL handle");
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
-  if (bucket < 0 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be 0 or 1");
+  if (bucket < 0 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be 0, 1 or 2");
   if (ppt) *ppt = h->cfg[cls][bucket].ppt;
   if (nontemporal) *nontemporal = h->cfg[cls][bucket].nt;
   return NWQ_OK;
@@ -111,9 +117,9 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
   if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
   for (const Job& j : jobs) {
     for (int b = 0; b < kBuckets && !rc; ++b) {
-      // target bits of this bucket: low bucket 0, 2, 5; high bucket 6, middle, top
+      // target bits of this bucket: {0, 1, 2}, {3, 7, 11}, {12, middle, top}
       std::vector<int> qs;
-      const int cand_q[2][3] = {{0, 2, kLowBits - 1}, {kLowBits, (kLowBits + j.lo_max) / 2, j.lo_max}};
+      const int cand_q[kBuckets][3] = {{0, 1, 2}, {3, 7, 11}, {12, (12 + j.lo_max) / 2, j.lo_max}};
       for (int q : cand_q[b])
         if (q >= 0 && q <= j.lo_max && bucket_of(q) == b && std::find(qs.begin(), qs.end(), q) == qs.end())
           qs.push_back(q);
@@ -121,6 +127,7 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
       double best = 1e300;
       LaunchCfg best_c = h->cfg[j.cls][b];
       for (const Cand& c : kCands) {
+        if (c.ppt == 16 && !allows16(j.cls)) continue;
         LaunchCfg cfg;
         cfg.ppt = c.ppt;
         cfg.nt = c.nt;

@@ -11,7 +11,8 @@
 // only in address arithmetic, and an optional non-temporal hint (the data is
 // touched once per pass).  The launch shape (groups per thread PPT and the
 // hint) is a template choice picked per kernel class and target bucket by
-// the autotuner.
+// the autotuner; the 4x4 kernel stops at 8 groups per thread (register
+// budget).
 #include "nwq_internal.h"
 
 namespace nwq {
@@ -69,11 +70,17 @@ __global__ __launch_bounds__(kBlock) void k_sv_1q(double2* __restrict__ a, unsig
   if (start + (unsigned long long)(PPT - 1) * kBlock < npairs) {
     vd2 x0[PPT], x1[PPT];
     unsigned long long i0[PPT];
+    // up to 8 groups: the two loads of a group back to back; 16 groups: all
+    // lower members, then all upper members (longer runs per stream)
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       i0[j] = insert0(start + (unsigned long long)j * kBlock, q);
       x0[j] = gld<NTM>(a + i0[j]);
-      x1[j] = gld<NTM>(a + i0[j] + off);
+      if constexpr (PPT < 16) x1[j] = gld<NTM>(a + i0[j] + off);
+    }
+    if constexpr (PPT >= 16) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) x1[j] = gld<NTM>(a + i0[j] + off);
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -301,26 +308,31 @@ void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len) {
     default: NWQ_LAUNCH_NT(KERNEL, 4, units, __VA_ARGS__); break;        \
   }
 
+// Kernels with at most two streams per group also take 16 groups per thread.
+#define NWQ_PPT_SWITCH16(KERNEL, units, ...)                             \
+  if (cfg.ppt == 16) NWQ_LAUNCH_NT(KERNEL, 16, units, __VA_ARGS__);      \
+  else NWQ_PPT_SWITCH(KERNEL, units, __VA_ARGS__)
+
 void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, const LaunchCfg& cfg) {
   const unsigned long long np = 1ull << (nbits - 1);
-  NWQ_PPT_SWITCH(k_sv_1q, np, s, a, np, q, m);
+  NWQ_PPT_SWITCH16(k_sv_1q, np, s, a, np, q, m);
 }
 
 void launch_sv_diag(hipStream_t s, double2* a, int nbits, int q0, int q1, const Diag4& d, const LaunchCfg& cfg) {
   const unsigned long long len = 1ull << nbits;
-  NWQ_PPT_SWITCH(k_sv_diag, len, s, a, len, q0, q1, d);
+  NWQ_PPT_SWITCH16(k_sv_diag, len, s, a, len, q0, q1, d);
 }
 
 void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, const LaunchCfg& cfg) {
   const unsigned long long np = 1ull << (nbits - 1);
-  NWQ_PPT_SWITCH(k_sv_swap1, np, s, a, np, q);
+  NWQ_PPT_SWITCH16(k_sv_swap1, np, s, a, np, q);
 }
 
 void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb, unsigned long long offA,
                      unsigned long long offB, const LaunchCfg& cfg) {
   const unsigned long long nq = 1ull << (nbits - 2);
   const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
-  NWQ_PPT_SWITCH(k_sv_swap2, nq, s, a, nq, lo, hi, offA, offB);
+  NWQ_PPT_SWITCH16(k_sv_swap2, nq, s, a, nq, lo, hi, offA, offB);
 }
 
 void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, const LaunchCfg& cfg) {

@@ -31,17 +31,17 @@ struct QSet {
 // Streaming launch shape chosen by the autotuner (per kernel class and
 // target bucket).
 struct LaunchCfg {
-  int ppt = 4;                       // pairs / groups / elements per thread (1, 2, 4, 8)
+  int ppt = 4;                       // pairs / groups / elements per thread (1, 2, 4, 8; 16 where allowed)
   int nt = 0;                        // 1: non-temporal loads and stores
 };
 
-// Launch shapes are kept in two buckets per class, by the lowest target bit
-// of the launch: below kLowBits the partner amplitudes of a group share
-// 1 KiB spans (a few cache lines read by one wave), at or above it each
-// group reads 2 or 4 separate streams; the best shape differs between them.
-constexpr int kLowBits = 6;
-constexpr int kBuckets = 2;
-inline int bucket_of(int lowest_bit) { return lowest_bit < kLowBits ? 0 : 1; }
+// Launch shapes are kept in three buckets per class, by the lowest target
+// bit of the launch: below 3 the partner amplitudes of a group share one
+// 128-byte line (a non-temporal hint then costs a second fetch of the line);
+// from 3 to 11 the streams of a group are within 64 KiB of each other; from
+// 12 up they are far apart.  The best shape differs between them.
+constexpr int kBuckets = 3;
+inline int bucket_of(int lowest_bit) { return lowest_bit < 3 ? 0 : (lowest_bit < 12 ? 1 : 2); }
 
 // Kernel classes (also the timing classes of nwq_timing_read).
 enum KClass {

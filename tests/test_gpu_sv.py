@@ -211,7 +211,7 @@ def test_every_launch_shape_matches_oracle(nwq, n):
            3: [("cx", (0, n - 1), ()), ("x", (1,), ()), ("swap", (n - 1, n - 2), ())]}
     m2 = np.array([[0.6, 0.8j, 0, 0.1], [0.2, -0.3, 0.5j, 0], [0, 0.4, 0.1 - 0.2j, 0.7], [0.3j, 0, 0.2, -0.5]])
     for cls in (1, 2, 3, 4):
-        for ppt in (1, 2, 4, 8):
+        for ppt in (1, 2, 4, 8, 16) if cls != 4 else (1, 2, 4, 8):
             for nt in (0, 1):
                 nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
                 st.load(psi0)
@@ -227,21 +227,22 @@ def test_every_launch_shape_matches_oracle(nwq, n):
 
 
 def test_launch_shape_buckets(nwq):
-    """Different shapes in the two target buckets are kept apart and give the
-    oracle's result on a circuit touching both."""
-    n = 12
+    """Different shapes in the three target buckets are kept apart and give
+    the oracle's result on a circuit touching all of them."""
+    n = 14
     st = nwq.SVState(n, reset=False)
     for cls in (1, 2, 3, 4):
-        nwq.nwq_set_launch(st.h, cls, 0, 1, 0)
-        nwq.nwq_set_launch(st.h, cls, 1, 8, 1)
-        assert nwq.nwq_get_launch(st.h, cls, 0) == (1, 0)
-        assert nwq.nwq_get_launch(st.h, cls, 1) == (8, 1)
-    gates = W.random_gate_list(n, 200, seed=11)
+        shapes = [(1, 0), (8, 1), (16 if cls != 4 else 2, 1)]
+        for b, (ppt, nt) in enumerate(shapes):
+            nwq.nwq_set_launch(st.h, cls, b, ppt, nt)
+        for b, shape in enumerate(shapes):
+            assert nwq.nwq_get_launch(st.h, cls, b) == shape
+    gates = W.random_gate_list(n, 300, seed=11)
     psi0 = W.random_state(n, seed=12)
     st.load(psi0)
     st.run_circuit(gates)
     assert maxerr(st.numpy(), tensor.sv_run(gates, n, psi0)) <= TOL
-    for bad in ((1, 2, 4, 0), (1, -2, 4, 0), (1, 0, 3, 0)):
+    for bad in ((1, 3, 4, 0), (1, -2, 4, 0), (1, 0, 3, 0), (4, 0, 16, 0), (6, -1, 16, 1)):
         with pytest.raises(nwq.NwqError) as e:
             nwq.nwq_set_launch(st.h, *bad)
         assert e.value.code == nwq.NWQ_EINVAL
@@ -260,7 +261,7 @@ def test_autotune_keeps_state_and_parity(nwq):
     cache = os.path.join(tempfile.mkdtemp(), "tune.json")
     chosen = autotune.tune(st.h, reps=2, cache_path=cache)
     assert set(chosen) == {"sv_1q_dense", "sv_diag", "sv_perm", "sv_2q_dense"}
-    assert all(set(v) == {"low", "high"} for v in chosen.values())
+    assert all(set(v) == {"low", "mid", "high"} for v in chosen.values())
     assert maxerr(st.numpy(), psi0) <= 1e-13          # H H rounding only
     again = autotune.tune(st.h, reps=2, cache_path=cache)   # from the cache
     shapes = lambda e: {(k, b): tuple(v[:2]) for k, per in e.items() for b, v in per.items()}
@@ -276,7 +277,7 @@ def test_autotune_keeps_state_and_parity(nwq):
     rho0 = W.random_density_matrix(4, seed=1)
     dm.load(rho0)
     ms = nwq.nwq_autotune(dm.h, 2)
-    assert set(ms) == {"dm_superop_1q"} and set(ms["dm_superop_1q"]) == {"low"}   # n = 4: no bit >= 6
+    assert set(ms) == {"dm_superop_1q"} and set(ms["dm_superop_1q"]) == {"low", "mid"}   # n = 4: bits 0..3
     assert maxerr(dm.numpy(), rho0) == 0.0
     dm.close()
 
