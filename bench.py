@@ -345,8 +345,10 @@ def sweep_n32_leg(nwq, torch, tuned):
 
 def dm_leg(nwq, torch):
     log("[bench] DM n=14 noisy gate leg")
+    from paper_2401_06861_amd import autotune
     n = 14
     st = nwq.DMState(n)
+    tuned = autotune.tune(st.h, reps=2, cache_path=None)
     nbytes = 32 * (1 << (2 * n))
     out = {}
     for label, ops, cls in (("1q_u3_dep_ad_pd", [("u3", (3,), (0.3, 0.2, 0.1)), ("depolarize", (3,), (1e-3,)),
@@ -365,6 +367,8 @@ def dm_leg(nwq, torch):
         c, ms = nwq.nwq_timing_read(st.h, reset=True)[cls]
         avg = ms / max(c, 1)
         out[label] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
+    out["launch_shapes"] = {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
+                            for k, per in tuned.items()}
     st.close()
     return out
 

@@ -261,18 +261,19 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * ------------------------------------------------------------------------- */
 
 /* Kernel class ids are the timing classes below (1 sv_1q_dense, 2 sv_diag,
- * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q).  A launch shape is the number
- * of pairs / groups per thread (1, 2, 4 or 8; also 16 for classes 1, 2 and
- * 3) and a non-temporal hint on the loads and stores (0 or 1).  Each class
- * keeps one shape per bucket of the launch's lowest target bit: bucket 0 for
- * bits 0..2 (partner amplitudes in one 128-byte line), 1 for bits 3..11, 2
- * for bits 12 and up.  nwq_set_launch with bucket -1 sets all three. */
+ * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).  A launch
+ * shape is the number of pairs / groups per thread (1, 2, 4 or 8; also 16 for
+ * classes 1, 2 and 3; class 7 takes only 1) and a non-temporal hint on the
+ * loads and stores (0 or 1).  Each class keeps one shape per bucket of the
+ * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
+ * one 128-byte line), 1 for bits 3..11, 2 for bits 12 and up.
+ * nwq_set_launch with bucket -1 sets all three. */
 #define NWQ_LAUNCH_BUCKETS 3
 int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal);
 int nwq_get_launch(nwq_handle h, int cls, int bucket, int* ppt, int* nontemporal);
 
 /* Autotuner: for each class that applies to the handle (SV: 1, 2, 3, 4;
- * DM: 6) and each bucket, time every launch shape with HIP events on the
+ * DM: 6, 7) and each bucket, time every launch shape with HIP events on the
  * handle's stream and state (self-inverse operations applied in pairs on up
  * to three target bits of the bucket, so the state is unchanged up to the
  * rounding of H H), keep the fastest, and write its time per launch in ms to

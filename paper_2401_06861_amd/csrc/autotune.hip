@@ -8,7 +8,8 @@
 // pairs on up to three target bits of the bucket (H H for the dense 1-qubit
 // kernel, Z Z for the diagonal kernel, CX CX for the permutation kernel, CZ
 // as a dense 4x4 twice for the 2-qubit kernel, and on a density matrix
-// Z (x) conj(Z) twice for the 1-qubit superoperator kernel), so the state is
+// Z (x) conj(Z) twice for the 1-qubit superoperator kernel and the diagonal
+// superoperator of Z (x) Z twice for the 16 x 16 kernel), so the state is
 // unchanged except for the rounding of H H.
 //
 // The fusion autotuner times a caller's circuit under every fusion width and
@@ -55,6 +56,17 @@ void run_2q(nwq_state* h, const LaunchCfg& c, int q) {
   launch_sv_2q(h->stream, h->data, h->nbits, q, t, m, c);
   launch_sv_2q(h->stream, h->data, h->nbits, q, t, m, c);
 }
+void run_dm2(nwq_state* h, const LaunchCfg& c, int q) {
+  // (Z (x) Z) (x) conj(Z (x) Z) on (a, b, a + n, b + n): diagonal +-1, self-inverse
+  const int t = q + 1;
+  const int vq[4] = {q, t, q + h->n, t + h->n};
+  std::vector<double2> S(256, make_double2(0.0, 0.0));
+  for (int u = 0; u < 16; ++u) S[17 * u] = make_double2(__builtin_popcount(u) % 2 ? -1.0 : 1.0, 0.0);
+  void* dev = nullptr;
+  if (arena_put(h, S.data(), S.size() * sizeof(double2), &dev) != NWQ_OK) return;
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev), c);
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev), c);
+}
 void run_dm1(nwq_state* h, const LaunchCfg& c, int q) {
   Mat4 m{};   // Z (x) conj(Z) on (column q, row q + n): diag(1, -1, -1, 1)
   const double dz[4] = {1, -1, -1, 1};
@@ -76,6 +88,7 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
   if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0, 1 or 2");
   if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && !(ppt == 16 && allows16(cls)))
     return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3)");
+  if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   for (int b = 0; b < kBuckets; ++b) {
     if (bucket >= 0 && b != bucket) continue;
     h->cfg[cls][b].ppt = ppt;
@@ -111,6 +124,7 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
     }
   } else {
     jobs.push_back({KC_DM1, run_dm1, h->n - 1});
+    if (h->n >= 2) jobs.push_back({KC_DM2, run_dm2, h->n - 2});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
@@ -128,6 +142,7 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
       LaunchCfg best_c = h->cfg[j.cls][b];
       for (const Cand& c : kCands) {
         if (c.ppt == 16 && !allows16(j.cls)) continue;
+        if (j.cls == KC_DM2 && c.ppt != 1) continue;   // one group per thread; only the hint varies
         LaunchCfg cfg;
         cfg.ppt = c.ppt;
         cfg.nt = c.nt;

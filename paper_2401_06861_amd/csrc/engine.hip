@@ -326,7 +326,8 @@ int dm_flush(nwq_state* h) {
   if (rc != NWQ_OK) return rc;
   const int vq[4] = {h->pend_q[0], h->pend_q[1], h->pend_q[0] + n, h->pend_q[1] + n};
   timing_begin(h, KC_DM2);
-  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev));
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev),
+               h->shape(KC_DM2, std::min(h->pend_q[0], h->pend_q[1])));
   timing_end(h);
   h->pend_active = false;
   return last_launch("dm_superop_2q");
@@ -386,6 +387,7 @@ static int create_common(int kind, int n, void* dev_ptr, void* stream, nwq_handl
   if (n < 1 || n > nmax)
     return set_error(NWQ_ERANGE, "n=" + std::to_string(n) + " outside [1, " + std::to_string(nmax) + "]");
   std::unique_ptr<nwq_state> h(new nwq_state());
+  for (int b = 0; b < kBuckets; ++b) h->cfg[KC_DM2][b].ppt = 1;   // one 16-entry group per thread
   h->kind = kind;
   h->n = n;
   h->nbits = kind == NWQ_KIND_SV ? n : 2 * n;

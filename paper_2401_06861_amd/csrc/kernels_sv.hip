@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_sv_2q(double2* __restrict__ a, unsig
 // k-qubit dense operator (k = 3 or 4; the 16 x 16 case is the fused
 // two-qubit gate + channel superoperator of the density matrix).  The
 // matrix lives in device memory and is read with wave-uniform addresses.
-template <int K>
+template <int K, bool NTM>
 __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsigned long long ngroups,
                                                   QSet qs, const double2* __restrict__ M) {
   constexpr int D = 1 << K;
@@ -255,14 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsig
     for (int j = 0; j < K; ++j)
       if ((u >> j) & 1) o += qs.off[j];
     idx[u] = base + o;
-    v[u] = gld<false>(a + idx[u]);
+    v[u] = gld<NTM>(a + idx[u]);
   }
 #pragma unroll
   for (int r = 0; r < D; ++r) {
     vd2 acc = cmul(tov(M[r * D]), v[0]);
 #pragma unroll
     for (int c = 1; c < D; ++c) acc = cfma(tov(M[r * D + c]), v[c], acc);
-    gst<false>(a + idx[r], acc);
+    gst<NTM>(a + idx[r], acc);
   }
 }
 
@@ -341,7 +341,8 @@ void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Ma
   NWQ_PPT_SWITCH(k_sv_2q, nq, s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m);
 }
 
-void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits, const double2* dev_matrix) {
+void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits, const double2* dev_matrix,
+                  const LaunchCfg& cfg) {
   QSet qs{};
   int sorted[4];
   for (int j = 0; j < k; ++j) {
@@ -356,10 +357,15 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     }
   for (int j = 0; j < k; ++j) qs.sorted[j] = sorted[j];
   const unsigned long long ng = 1ull << (nbits - k);
-  if (k == 3)
-    hipLaunchKernelGGL(k_sv_kq<3>, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
-  else
-    hipLaunchKernelGGL(k_sv_kq<4>, dim3(grid_for(ng, kBlock)), dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+  // one group per thread (16 loads in flight at k = 4); only the hint is tunable
+  const dim3 grid(grid_for(ng, kBlock));
+  if (k == 3) {
+    if (cfg.nt) hipLaunchKernelGGL((k_sv_kq<3, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+    else hipLaunchKernelGGL((k_sv_kq<3, false>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+  } else {
+    if (cfg.nt) hipLaunchKernelGGL((k_sv_kq<4, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+    else hipLaunchKernelGGL((k_sv_kq<4, false>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+  }
 }
 
 }  // namespace nwq

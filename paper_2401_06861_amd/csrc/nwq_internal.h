@@ -57,8 +57,8 @@ void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, const LaunchCf
 void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb,
                      unsigned long long offA, unsigned long long offB, const LaunchCfg& cfg);
 void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, const LaunchCfg& cfg);
-void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits,
-                  const double2* dev_matrix);
+void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits, const double2* dev_matrix,
+                  const LaunchCfg& cfg);
 
 // ---- reductions (kernels_reduce.hip) --------------------------------------
 // One pass of the tiled Pauli-term kernel.  `terms` is a device table of

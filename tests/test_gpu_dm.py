@@ -138,6 +138,29 @@ def test_noise_free_dm_equals_sv_outer_product(nwq):
     dm.close()
 
 
+@pytest.mark.parametrize("nt", [0, 1])
+def test_superop_launch_shapes(nwq, nt):
+    """Noisy 1- and 2-qubit gates with each hint on both superoperator
+    kernels, on low and high qubits."""
+    n = 7
+    rho0 = W.random_density_matrix(n, seed=40 + nt)
+    st = nwq.DMState(n, reset=False)
+    for cls in (6, 7):
+        nwq.nwq_set_launch(st.h, cls, -1, 1, nt)
+        assert nwq.nwq_get_launch(st.h, cls, 2) == (1, nt)
+    ops = [("u3", (0,), (0.3, 1.2, -0.4)), ("depolarize", (0,), (0.05,)), ("amp_damp", (6,), (0.1,)),
+           ("rzz", (1, 5), (0.7,)), ("depolarize2", (1, 5), (0.02,)), ("cx", (6, 2), ()), ("depolarize2", (2, 6), (0.03,))]
+    st.load(rho0)
+    st.run(ops)
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    assert maxerr(st.numpy(), want) <= TOL
+    with pytest.raises(nwq.NwqError):
+        nwq.nwq_set_launch(st.h, 7, -1, 4, nt)
+    st.close()
+
+
 def test_dm_errors(nwq):
     n = 3
     rho0 = W.random_density_matrix(n, seed=2)

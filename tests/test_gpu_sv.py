@@ -277,7 +277,8 @@ def test_autotune_keeps_state_and_parity(nwq):
     rho0 = W.random_density_matrix(4, seed=1)
     dm.load(rho0)
     ms = nwq.nwq_autotune(dm.h, 2)
-    assert set(ms) == {"dm_superop_1q"} and set(ms["dm_superop_1q"]) == {"low", "mid"}   # n = 4: bits 0..3
+    assert set(ms) == {"dm_superop_1q", "dm_superop_2q"}
+    assert set(ms["dm_superop_1q"]) == {"low", "mid"} and set(ms["dm_superop_2q"]) == {"low"}   # n = 4
     assert maxerr(dm.numpy(), rho0) == 0.0
     dm.close()
 
