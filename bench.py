@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--depth", type=int, default=40)
     ap.add_argument("--fuse-k", type=int, default=None,
                     help="fusion width for the fused leg (default: picked by the fusion autotuner)")
+    ap.add_argument("--fuse-kernel", type=int, default=1, choices=[0, 1, 2],
+                    help="fused kernel with --fuse-k: 0 per-gate LDS, 1 / 2 register-blocked with 4 / 3 bits")
     ap.add_argument("--tune-depth", type=int, default=10, help="brickwork depth the fusion autotuner times")
     ap.add_argument("--no-n32", action="store_true", help="skip the n=32 sweep")
     ap.add_argument("--no-extras", action="store_true", help="only the timed step")
@@ -252,7 +254,7 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
         k, rb, table = nwq.nwq_autotune_fusion(st.h, *nwq.circuit_arrays(W.brickwork_circuit(n, args.tune_depth, seed=0)))
         log(f"[bench] fusion autotuner picked k={k} rb={rb} in {time.perf_counter() - t0:.1f}s")
     else:
-        k, rb = args.fuse_k, 1
+        k, rb = args.fuse_k, args.fuse_kernel
         nwq.nwq_set_fusion(st.h, k)
         nwq.nwq_set_fusion_kernel(st.h, rb)
     log(f"[bench] fused leg k={k} rb={rb}")
@@ -277,13 +279,15 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
     c, ms = tim["sv_fused"]
     N = 1 << n
     avg = ms / max(c, 1)
-    res = {"k": k, "kernel": "register-blocked (4 register bits per phase)" if rb else "one LDS pass per gate",
+    kname = ["one LDS pass per gate", "register-blocked (4 register bits per phase)",
+             "register-blocked (3 register bits per phase)"][rb]
+    res = {"k": k, "kernel": kname,
            "blocks": blocks, "phases": phases, "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
            "circuit_ms": round(dt * 1e3, 2), "speedup_vs_one_kernel_per_gate": round(unfused_ms / (dt * 1e3), 2),
            "avg_block_ms": round(avg, 3), "block_hbm_GBs": round(32 * N / (avg * 1e-3) / 1e9, 1)}
     if table is not None:
         res["autotuner"] = {"depth": args.tune_depth,
-                            "ms_per_circuit": {("unfused" if kk == 0 else f"k{kk}_{'rb' if r else 'lds'}"): round(v, 1)
+                            "ms_per_circuit": {("unfused" if kk == 0 else f"k{kk}_{nwq.FUSION_KERNELS[r]}"): round(v, 1)
                                                for (kk, r), v in sorted(table.items())}}
     return res
 

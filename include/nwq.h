@@ -141,11 +141,14 @@ int nwq_set_fusion(nwq_handle h, int k, int* k_out);
  * gates (both 0 when fusion was off). */
 int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates);
 
-/* Kernel for fused blocks of at least 2^8 amplitudes: 1 (default) =
- * register-blocked (each thread holds 16 amplitudes over 4 tile bits and
- * applies runs of gates on those bits in registers, one LDS exchange per
- * run), 0 = one LDS pass per gate.  Smaller tiles always use the latter. */
-int nwq_set_fusion_kernel(nwq_handle h, int register_blocked);
+/* Kernel for fused blocks: 1 (default) = register-blocked with 4 register
+ * bits (each thread holds 16 amplitudes over 4 tile bits and applies runs of
+ * gates on those bits in registers, one LDS exchange per run), 2 =
+ * register-blocked with 3 register bits (8 amplitudes per thread, twice the
+ * threads per tile), 0 = one LDS pass per gate.  With 1 or 2, tiles smaller
+ * than 2^8 are padded to 2^8 on registers of at least 8 qubits.  Other values:
+ * NWQ_EINVAL. */
+int nwq_set_fusion_kernel(nwq_handle h, int kernel);
 
 /* Number of register phases (LDS exchanges) of the last fused
  * nwq_apply_circuit (0 when no register-blocked block ran). */
@@ -285,13 +288,13 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms);
 /* Fusion autotuner (SV handles): runs the given circuit (arrays as for
  * nwq_apply_circuit) from |0...0> once untimed and reps times timed under
  * each candidate: unfused, and every fusion width from 6 to min(13, n) with
- * the per-gate LDS kernel and, for widths of 8 and up, the register-blocked
- * kernel.  Keeps the fastest on the handle and returns it in *best_k
- * (0 = unfused) and *best_rb (the nwq_set_fusion_kernel value).  If ms_out
- * is non-NULL it receives NWQ_FUSION_CANDIDATES times in ms per circuit
- * (-1 for candidates not run): index 0 unfused, 1 + 2 * (k - 6) + rb for
- * width k.  Overwrites the state and leaves it at |0...0>; synchronises. */
-#define NWQ_FUSION_CANDIDATES 17
+ * each fused kernel (the register-blocked ones only on 8 or more qubits).
+ * Keeps the fastest on the handle and returns it in *best_k (0 = unfused)
+ * and *best_rb (the nwq_set_fusion_kernel value).  If ms_out is non-NULL it
+ * receives NWQ_FUSION_CANDIDATES times in ms per circuit (-1 for candidates
+ * not run): index 0 unfused, 1 + 3 * (k - 6) + kernel for width k.
+ * Overwrites the state and leaves it at |0...0>; synchronises. */
+#define NWQ_FUSION_CANDIDATES 25
 int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* qubits,
                         const double* params, int reps, int* best_k, int* best_rb, double* ms_out);
 

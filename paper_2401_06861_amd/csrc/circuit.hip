@@ -128,10 +128,10 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
 }
 
 // Split a block's gates (tile-local bits) into register phases: greedily
-// take, in order, every gate whose bits fit the phase's 4 register bits and
-// that no earlier left-out gate shares a bit with; pad the set to 4 bits.
+// take, in order, every gate whose bits fit the phase's rbits register bits
+// and that no earlier left-out gate shares a bit with; pad the set to rbits.
 std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
-                                      const std::vector<int>& nq, int k) {
+                                      const std::vector<int>& nq, int k, int rbits) {
   std::vector<Phase> out;
   std::vector<int> rem = order;
   while (!rem.empty()) {
@@ -146,7 +146,7 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
         keep.push_back(gi);
         continue;
       }
-      if (__builtin_popcount(S | B) <= 4) {
+      if (__builtin_popcount(S | B) <= rbits) {
         S |= B;
         ph.gates.push_back(gi);
       } else {
@@ -154,10 +154,11 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
         keep.push_back(gi);
       }
     }
-    for (int b = 0; b < k && __builtin_popcount(S) < 4; ++b) S |= 1u << b;
+    for (int b = 0; b < k && __builtin_popcount(S) < rbits; ++b) S |= 1u << b;
     int r = 0;
     for (int b = 0; b < k; ++b)
       if ((S >> b) & 1u) ph.reg[r++] = b;
+    for (; r < 4; ++r) ph.reg[r] = -1;
     out.push_back(std::move(ph));
     rem.swap(keep);
   }
@@ -171,16 +172,17 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   std::vector<FusedPhase> phases;
   std::vector<FusedOp> ops;
   std::vector<double2> mats;
-  struct Launch { FusedBlockDev d; bool rb; };
+  struct Launch { FusedBlockDev d; bool rb; int rbits; };
   std::vector<Launch> launches;
   for (Block b : blocks) {
-    if (h->fuse_rb && b.c + b.m < 8 && h->n >= 8) pad_block(b, h->n, 8);
+    if (h->fuse_rb != 0 && b.c + b.m < 8 && h->n >= 8) pad_block(b, h->n, 8);
     FusedBlockDev d{};
     d.c = b.c;
     d.m = b.m;
     for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
     const int k = b.c + b.m;
-    const bool rb = h->fuse_rb && k >= 8;
+    const bool rb = h->fuse_rb != 0 && k >= 8;
+    const int rbits = h->fuse_rb == 2 ? 3 : 4;
     if (!rb) {
       d.op_begin = (int)ops.size();
       for (int gi : b.gates) {
@@ -190,7 +192,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
           ops.push_back(op);
       }
       d.op_count = (int)ops.size() - d.op_begin;
-      if (d.op_count > 0) launches.push_back({d, false});
+      if (d.op_count > 0) launches.push_back({d, false, 0});
       continue;
     }
     std::vector<std::array<int, 2>> lb(gates.size());
@@ -204,12 +206,12 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
     }
     if (order.empty()) continue;
     d.op_begin = (int)phases.size();
-    for (const Phase& ph : plan_phases(order, lb, nq, k)) {
+    for (const Phase& ph : plan_phases(order, lb, nq, k, rbits)) {
       FusedPhase fp{};
-      for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i];
+      for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i] < 0 ? 0 : ph.reg[i];
       fp.op_begin = (int)ops.size();
       auto ridx = [&](int bit) {
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < rbits; ++i)
           if (ph.reg[i] == bit) return i;
         return -1;
       };
@@ -222,7 +224,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
       phases.push_back(fp);
     }
     d.op_count = (int)phases.size() - d.op_begin;
-    launches.push_back({d, true});
+    launches.push_back({d, true, rbits});
   }
   const size_t ph_bytes = phases.size() * sizeof(FusedPhase);
   const size_t ops_off = (ph_bytes + 255) & ~size_t(255);
@@ -261,7 +263,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   const double2* dmats = reinterpret_cast<const double2*>(static_cast<char*>(dev) + mats_off);
   for (const Launch& L : launches) {
     timing_begin(h, KC_FUSED);
-    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats);
+    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats, L.rbits);
     else launch_fused_block(h->stream, h->data, h->nbits, L.d, dops, dmats, h->fuse_k);
     timing_end(h);
     const int rc = check_hip(hipGetLastError(), "fused_block");
@@ -336,9 +338,10 @@ int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qu
   return NWQ_OK;
 }
 
-int nwq_set_fusion_kernel(nwq_handle h, int register_blocked) {
+int nwq_set_fusion_kernel(nwq_handle h, int kernel) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
-  h->fuse_rb = register_blocked != 0;
+  if (kernel < 0 || kernel > 2) return set_error(NWQ_EINVAL, "fusion kernel must be 0, 1 or 2");
+  h->fuse_rb = kernel;
   return NWQ_OK;
 }
 
@@ -366,19 +369,22 @@ int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* 
   std::vector<Cand> cands = {{0, 0}};
   for (int k = 6; k <= std::min(13, h->n); ++k) {
     cands.push_back({k, 0});
-    if (h->n >= 8) cands.push_back({k, 1});
+    if (h->n >= 8) {
+      cands.push_back({k, 1});
+      cands.push_back({k, 2});
+    }
   }
   const int saved_k = h->fuse_k;
-  const bool saved_rb = h->fuse_rb;
+  const int saved_rb = h->fuse_rb;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
   double best = 1e300;
-  Cand pick{saved_k, saved_rb ? 1 : 0};
+  Cand pick{saved_k, saved_rb};
   for (const Cand& c : cands) {
     if (rc) break;
     h->fuse_k = c.k;
-    h->fuse_rb = c.rb != 0;
+    h->fuse_rb = c.rb;
     double total = 0.0;
     for (int r = 0; r <= reps && !rc; ++r) {   // r == 0 is the untimed run
       rc = nwq_reset(h);
@@ -393,7 +399,7 @@ int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* 
     }
     if (rc) break;
     const double per = total / reps;
-    if (ms_out) ms_out[c.k == 0 ? 0 : 1 + 2 * (c.k - 6) + c.rb] = per;
+    if (ms_out) ms_out[c.k == 0 ? 0 : 1 + 3 * (c.k - 6) + c.rb] = per;
     if (per < best) {
       best = per;
       pick = c;
@@ -407,7 +413,7 @@ int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* 
     return rc;
   }
   h->fuse_k = pick.k;
-  h->fuse_rb = pick.rb != 0;
+  h->fuse_rb = pick.rb;
   *best_k = pick.k;
   *best_rb = pick.rb;
   return nwq_reset(h);

@@ -47,7 +47,7 @@ struct nwq_state {
   // SV fusion
   int fuse_k = 0;                  // 0 = off
   int last_blocks = 0, last_fused_gates = 0, last_phases = 0;
-  bool fuse_rb = true;             // register-blocked fused kernel for tiles of >= 2^8
+  int fuse_rb = 1;                 // fused kernel: 0 one LDS pass per gate, 1 / 2 register-blocked with 4 / 3 register bits
   void* fuse_dev = nullptr;        // device copy of the compiled block program
   size_t fuse_cap = 0;
 
@@ -82,7 +82,7 @@ std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
 int local_bit(const Block& b, int q);
 void pad_block(Block& b, int n, int k_target);
 std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
-                               const std::vector<int>& nq, int k);
+                               const std::vector<int>& nq, int k, int rbits);
 
 void gate_matrix(int type, const double* p, cd* m);
 int arena_put(nwq_state* h, const void* src, size_t bytes, void** dev_out);

@@ -164,13 +164,17 @@ void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDe
 }  // namespace nwq
 
 // ===========================================================================
-// Register-blocked variant.  Each of the 2^(k-4) threads of a tile holds 16
-// amplitudes that differ on 4 tile bits (the phase's register bits); every
-// gate of the phase acts on those bits only and runs in registers.  Between
-// phases the tile is exchanged through LDS (one write, one barrier, one
-// read), so LDS traffic is one tile pass per phase instead of one per gate.
-// LDS rows are padded by one entry every 16 so that lanes whose local
+// Register-blocked variant.  Each of the 2^(k-R) threads of a tile holds 2^R
+// amplitudes that differ on R tile bits (the phase's register bits, R = 3 or
+// 4); every gate of the phase acts on those bits only and runs in registers.
+// Between phases the tile is exchanged through LDS (one write, one barrier,
+// one read), so LDS traffic is one tile pass per phase instead of one per
+// gate.  LDS rows are padded by one entry every 16 so that lanes whose local
 // indices differ by multiples of 16 land in different banks.
+//
+// R trades registers for phases: R = 4 applies more gates per exchange but
+// needs 256 VGPRs (2 waves per SIMD); R = 3 fits 128 VGPRs and halves the LDS
+// per wave, so 4 waves per SIMD hide the LDS and HBM latency of each other.
 // ===========================================================================
 namespace nwq {
 namespace {
@@ -182,11 +186,11 @@ __device__ __forceinline__ vd2 vfma(vd2 a, vd2 b, vd2 c) {
 }
 __device__ __forceinline__ unsigned padl(unsigned l) { return l + (l >> 4); }
 
-template <int B>
-__device__ __forceinline__ void rb_dense1(vd2 (&v)[16], const double2* __restrict__ M) {
+template <int NV, int B>
+__device__ __forceinline__ void rb_dense1(vd2 (&v)[NV], const double2* __restrict__ M) {
   const vd2 m0 = ldv(M), m1 = ldv(M + 1), m2 = ldv(M + 2), m3 = ldv(M + 3);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < NV; ++j) {
     if (j & (1 << B)) continue;
     const vd2 a = v[j], b = v[j | (1 << B)];
     v[j] = vfma(m0, a, vmul(m1, b));
@@ -195,10 +199,10 @@ __device__ __forceinline__ void rb_dense1(vd2 (&v)[16], const double2* __restric
 }
 
 // Dense 4x4 with operator index u = bit B0 + 2 bit B1.
-template <int B0, int B1>
-__device__ __forceinline__ void rb_dense2(vd2 (&v)[16], const double2* __restrict__ M) {
+template <int NV, int B0, int B1>
+__device__ __forceinline__ void rb_dense2(vd2 (&v)[NV], const double2* __restrict__ M) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < NV; ++j) {
     if (j & ((1 << B0) | (1 << B1))) continue;
     const int idx[4] = {j, j | (1 << B0), j | (1 << B1), j | (1 << B0) | (1 << B1)};
     vd2 x[4];
@@ -215,10 +219,10 @@ __device__ __forceinline__ void rb_dense2(vd2 (&v)[16], const double2* __restric
 }
 
 // Exchange of members (base | OA) and (base | OB) of each quad over bits B0, B1.
-template <int B0, int B1, int OA, int OB>
-__device__ __forceinline__ void rb_swap2(vd2 (&v)[16]) {
+template <int NV, int B0, int B1, int OA, int OB>
+__device__ __forceinline__ void rb_swap2(vd2 (&v)[NV]) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < NV; ++j) {
     if (j & ((1 << B0) | (1 << B1))) continue;
     const vd2 t = v[j | OA];
     v[j | OA] = v[j | OB];
@@ -226,71 +230,89 @@ __device__ __forceinline__ void rb_swap2(vd2 (&v)[16]) {
   }
 }
 
-template <int B0, int B1>
-__device__ __forceinline__ void rb_pair_ops(int kind, vd2 (&v)[16], const double2* M) {
-  if (kind == 2) rb_dense2<B0, B1>(v, M);
-  else if (kind == 3) rb_swap2<B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(v);      // CX: control B0, target B1
-  else rb_swap2<B0, B1, (1 << B0), (1 << B1)>(v);                                  // SWAP
+template <int NV, int B0, int B1>
+__device__ __forceinline__ void rb_pair_ops(int kind, vd2 (&v)[NV], const double2* M) {
+  if (kind == 2) rb_dense2<NV, B0, B1>(v, M);
+  else if (kind == 3) rb_swap2<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(v);   // CX: control B0, target B1
+  else rb_swap2<NV, B0, B1, (1 << B0), (1 << B1)>(v);                               // SWAP
 }
 
-__device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[16], const double2* __restrict__ mats) {
+template <int R>
+__device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[1 << R], const double2* __restrict__ mats) {
+  constexpr int NV = 1 << R;
   const double2* M = mats + op.mat;
   switch (op.kind) {
     case 0:
       switch (op.lo) {
-        case 0: rb_dense1<0>(v, M); break;
-        case 1: rb_dense1<1>(v, M); break;
-        case 2: rb_dense1<2>(v, M); break;
-        default: rb_dense1<3>(v, M); break;
+        case 0: rb_dense1<NV, 0>(v, M); break;
+        case 1: rb_dense1<NV, 1>(v, M); break;
+        case 2: rb_dense1<NV, 2>(v, M); break;
+        default:
+          if constexpr (R == 4) rb_dense1<NV, 3>(v, M);
+          break;
       }
       break;
     case 1: {   // 1q diagonal on register bit lo
       const vd2 d0 = ldv(M), d1 = ldv(M + 1);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = vmul(((j >> op.lo) & 1) ? d1 : d0, v[j]);
+      for (int j = 0; j < NV; ++j) v[j] = vmul(((j >> op.lo) & 1) ? d1 : d0, v[j]);
       break;
     }
     case 4: {   // 2q diagonal on register bits o0 (u bit 0), o1 (u bit 1)
       const vd2 d0 = ldv(M), d1 = ldv(M + 1), d2 = ldv(M + 2), d3 = ldv(M + 3);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < NV; ++j) {
         const bool a = (j >> op.o0) & 1, b = (j >> op.o1) & 1;
         v[j] = vmul(b ? (a ? d3 : d2) : (a ? d1 : d0), v[j]);
       }
       break;
     }
     default: {  // 2 dense 4x4, 3 CX, 5 SWAP: register bits (o0, o1) in operator order
-      switch (op.o0 * 4 + op.o1) {
-        case 1: rb_pair_ops<0, 1>(op.kind, v, M); break;
-        case 2: rb_pair_ops<0, 2>(op.kind, v, M); break;
-        case 3: rb_pair_ops<0, 3>(op.kind, v, M); break;
-        case 4: rb_pair_ops<1, 0>(op.kind, v, M); break;
-        case 6: rb_pair_ops<1, 2>(op.kind, v, M); break;
-        case 7: rb_pair_ops<1, 3>(op.kind, v, M); break;
-        case 8: rb_pair_ops<2, 0>(op.kind, v, M); break;
-        case 9: rb_pair_ops<2, 1>(op.kind, v, M); break;
-        case 11: rb_pair_ops<2, 3>(op.kind, v, M); break;
-        case 12: rb_pair_ops<3, 0>(op.kind, v, M); break;
-        case 13: rb_pair_ops<3, 1>(op.kind, v, M); break;
-        default: rb_pair_ops<3, 2>(op.kind, v, M); break;   // 14
+      if constexpr (R == 4) {
+        switch (op.o0 * 4 + op.o1) {
+          case 1: rb_pair_ops<NV, 0, 1>(op.kind, v, M); break;
+          case 2: rb_pair_ops<NV, 0, 2>(op.kind, v, M); break;
+          case 3: rb_pair_ops<NV, 0, 3>(op.kind, v, M); break;
+          case 4: rb_pair_ops<NV, 1, 0>(op.kind, v, M); break;
+          case 6: rb_pair_ops<NV, 1, 2>(op.kind, v, M); break;
+          case 7: rb_pair_ops<NV, 1, 3>(op.kind, v, M); break;
+          case 8: rb_pair_ops<NV, 2, 0>(op.kind, v, M); break;
+          case 9: rb_pair_ops<NV, 2, 1>(op.kind, v, M); break;
+          case 11: rb_pair_ops<NV, 2, 3>(op.kind, v, M); break;
+          case 12: rb_pair_ops<NV, 3, 0>(op.kind, v, M); break;
+          case 13: rb_pair_ops<NV, 3, 1>(op.kind, v, M); break;
+          default: rb_pair_ops<NV, 3, 2>(op.kind, v, M); break;   // 14
+        }
+      } else {
+        switch (op.o0 * 4 + op.o1) {
+          case 1: rb_pair_ops<NV, 0, 1>(op.kind, v, M); break;
+          case 2: rb_pair_ops<NV, 0, 2>(op.kind, v, M); break;
+          case 4: rb_pair_ops<NV, 1, 0>(op.kind, v, M); break;
+          case 6: rb_pair_ops<NV, 1, 2>(op.kind, v, M); break;
+          case 8: rb_pair_ops<NV, 2, 0>(op.kind, v, M); break;
+          default: rb_pair_ops<NV, 2, 1>(op.kind, v, M); break;   // 9
+        }
       }
       break;
     }
   }
 }
 
-__global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a0, int nbits, FusedBlockDev blk,
-                                                  const FusedPhase* __restrict__ phases,
-                                                  const FusedOp* __restrict__ ops,
-                                                  const double2* __restrict__ mats0,
-                                                  unsigned long long state_stride, int mat_stride) {
+template <int R>
+__global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __restrict__ a0, int nbits,
+                                                                  FusedBlockDev blk,
+                                                                  const FusedPhase* __restrict__ phases,
+                                                                  const FusedOp* __restrict__ ops,
+                                                                  const double2* __restrict__ mats0,
+                                                                  unsigned long long state_stride, int mat_stride) {
+  constexpr int NV = 1 << R;
   extern __shared__ double2 t[];
   // batch element blockIdx.y: its own state and its own matrix table
   double2* __restrict__ a = a0 + (size_t)blockIdx.y * state_stride;
   const double2* __restrict__ mats = mats0 + (size_t)blockIdx.y * mat_stride;
   const int c = blk.c, m = blk.m, k = c + m;
   const unsigned len = 1u << k;
-  const unsigned nt = len >> 4;
+  const unsigned nt = len >> R;
   const unsigned long long ntiles = 1ull << (nbits - k);
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
@@ -305,42 +327,46 @@ __global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a0, int 
     }
     __syncthreads();
     {
-      vd2 r[16];   // the tile has exactly 16 entries per thread: issue all loads, then write LDS
+      vd2 r[NV];   // the tile has exactly NV entries per thread: issue all loads, then write LDS
 #pragma unroll
-      for (int j = 0; j < 16; ++j) r[j] = ldv(a + tile_index(base, tid + j * nt, cmask, c, m, blk));
+      for (int j = 0; j < NV; ++j) r[j] = ldv(a + tile_index(base, tid + j * nt, cmask, c, m, blk));
 #pragma unroll
-      for (int j = 0; j < 16; ++j) stv(t + padl(tid + j * nt), r[j]);
+      for (int j = 0; j < NV; ++j) stv(t + padl(tid + j * nt), r[j]);
     }
     for (int pi = 0; pi < blk.op_count; ++pi) {
       const FusedPhase ph = phases[blk.op_begin + pi];
       // thread bits -> the tile bits outside the phase's register bits (ascending)
-      const unsigned regmask = (1u << ph.reg[0]) | (1u << ph.reg[1]) | (1u << ph.reg[2]) | (1u << ph.reg[3]);
+      unsigned regmask = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) regmask |= 1u << ph.reg[r];
       unsigned dep = 0;
       for (int p = 0, i = 0; p < k; ++p) {
         if ((regmask >> p) & 1u) continue;
         dep |= ((tid >> i) & 1u) << p;
         ++i;
       }
-      unsigned off[16];
+      unsigned off[NV];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        off[j] = ((j & 1) << ph.reg[0]) | (((j >> 1) & 1) << ph.reg[1]) | (((j >> 2) & 1) << ph.reg[2]) |
-                 (((j >> 3) & 1) << ph.reg[3]);
+      for (int j = 0; j < NV; ++j) {
+        off[j] = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) off[j] |= ((j >> r) & 1) << ph.reg[r];
+      }
       __syncthreads();
-      vd2 v[16];
+      vd2 v[NV];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = ldv(t + padl(dep | off[j]));
-      for (int oi = 0; oi < ph.op_count; ++oi) rb_apply(ops[ph.op_begin + oi], v, mats);
+      for (int j = 0; j < NV; ++j) v[j] = ldv(t + padl(dep | off[j]));
+      for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(ops[ph.op_begin + oi], v, mats);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) stv(t + padl(dep | off[j]), v[j]);
+      for (int j = 0; j < NV; ++j) stv(t + padl(dep | off[j]), v[j]);
     }
     __syncthreads();
     {
-      vd2 r[16];
+      vd2 r[NV];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) r[j] = ldv(t + padl(tid + j * nt));
+      for (int j = 0; j < NV; ++j) r[j] = ldv(t + padl(tid + j * nt));
 #pragma unroll
-      for (int j = 0; j < 16; ++j) stv(a + tile_index(base, tid + j * nt, cmask, c, m, blk), r[j]);
+      for (int j = 0; j < NV; ++j) stv(a + tile_index(base, tid + j * nt, cmask, c, m, blk), r[j]);
     }
   }
 }
@@ -350,15 +376,22 @@ __global__ __launch_bounds__(512) void k_fused_rb(double2* __restrict__ a0, int 
 size_t fused_rb_lds_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << k) / 16); }
 
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
-                     const FusedOp* ops, const double2* mats, int batch, int mat_stride, int max_grid) {
+                     const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid) {
   const int k = blk.c + blk.m;
   const unsigned long long ntiles = 1ull << (nbits - k);
   const unsigned long long cap = max_grid > 0 ? (unsigned long long)max_grid : (1ull << 20);
   const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
   const size_t lds = fused_rb_lds_bytes(k);
-  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused_rb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_fused_rb, dim3(grid, batch), dim3(1u << (k - 4)), lds, s, a, nbits, blk, phases, ops, mats,
-                     batch > 1 ? (1ull << nbits) : 0ull, mat_stride);
+  const unsigned long long stride = batch > 1 ? (1ull << nbits) : 0ull;
+  if (rbits == 3) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused_rb<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_fused_rb<3>, dim3(grid, batch), dim3(1u << (k - 3)), lds, s, a, nbits, blk, phases, ops, mats,
+                       stride, mat_stride);
+  } else {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused_rb<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_fused_rb<4>, dim3(grid, batch), dim3(1u << (k - 4)), lds, s, a, nbits, blk, phases, ops, mats,
+                       stride, mat_stride);
+  }
 }
 
 }  // namespace nwq

@@ -109,9 +109,10 @@ struct FusedBlockDev {
 void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk,
                         const FusedOp* ops, const double2* mats, int lds_k);
 // Register-blocked blocks: blk.op_begin / op_count index a phase table; each
-// phase holds 4 register bits (tile-local, ascending) and a range of ops whose
-// lo / o0 / o1 fields are register-bit indices 0..3.  Tiles of 2^k amplitudes,
-// 8 <= k <= 13, 2^(k-4) threads.  Op kinds as FusedOp plus 5 = SWAP (o0, o1).
+// phase holds rbits (3 or 4) register bits (tile-local, ascending; unused
+// entries of reg ignored) and a range of ops whose lo / o0 / o1 fields are
+// register-bit indices below rbits.  Tiles of 2^k amplitudes, 8 <= k <= 13,
+// 2^(k-rbits) threads.  Op kinds as FusedOp plus 5 = SWAP (o0, o1).
 struct FusedPhase {
   int reg[4];
   int op_begin, op_count;
@@ -121,7 +122,8 @@ size_t fused_rb_lds_bytes(int k);
 // batch > 1: blockIdx.y = batch element b works on a + b * 2^nbits with the
 // matrix table mats + b * mat_stride; max_grid caps the tiles' grid (0 = 2^20).
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
-                     const FusedOp* ops, const double2* mats, int batch = 1, int mat_stride = 0, int max_grid = 0);
+                     const FusedOp* ops, const double2* mats, int rbits, int batch = 1, int mat_stride = 0,
+                     int max_grid = 0);
 
 // ---- error handling (engine.hip) ------------------------------------------
 int set_error(int code, const std::string& msg);

@@ -816,6 +816,7 @@ struct nwq_vqe {
   // fused path program (built on first use)
   bool fused_built = false;
   int fused_k = 11;
+  int fused_rbits = 4;         // register bits per phase of the forward kernel
   std::vector<nwq::FusedBlockDev> fwd_blocks, bwd_blocks;
   void* d_fused = nullptr;     // [forward phases][forward ops][backward ops]
   size_t fused_ops_off = 0, fused_bwd_off = 0;
@@ -966,12 +967,12 @@ static int build_fused(nwq_vqe* h) {
     d.m = b.m;
     for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
     d.op_begin = (int)phases.size();
-    for (const Phase& ph : plan_phases(b.gates, lb, nq, kb)) {
+    for (const Phase& ph : plan_phases(b.gates, lb, nq, kb, h->fused_rbits)) {
       FusedPhase fp{};
-      for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i];
+      for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i] < 0 ? 0 : ph.reg[i];
       fp.op_begin = (int)fops.size();
       auto ridx = [&](int bit) {
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < h->fused_rbits; ++i)
           if (ph.reg[i] == bit) return i;
         return -1;
       };
@@ -1065,7 +1066,7 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
   hipLaunchKernelGGL(k_vqe_mats, dim3((h->nops + 255) / 256, B), dim3(256), 0, s, h->d_ops, h->nops, h->d_fixed,
                      theta, h->P, h->d_table);
   for (const FusedBlockDev& d : h->fwd_blocks)
-    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, B, stride, G);
+    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, h->fused_rbits, B, stride, G);
   hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
                      coeffs, h->d_epart, grad != nullptr ? 1 : 0);
   if (grad != nullptr) {

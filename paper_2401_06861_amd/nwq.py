@@ -210,8 +210,9 @@ def nwq_fusion_stats(h: int) -> Tuple[int, int]:
     return b.value, g.value
 
 
-def nwq_set_fusion_kernel(h: int, register_blocked: bool) -> None:
-    _check(lib.nwq_set_fusion_kernel(h, int(bool(register_blocked))))
+def nwq_set_fusion_kernel(h: int, kernel: int) -> None:
+    """0: one LDS pass per gate; 1: register-blocked, 4 register bits; 2: register-blocked, 3 bits."""
+    _check(lib.nwq_set_fusion_kernel(h, int(kernel)))
 
 
 def nwq_fusion_phases(h: int) -> int:
@@ -305,11 +306,13 @@ def nwq_autotune(h: int, reps: int = 3) -> dict:
     return out
 
 
-FUSION_CANDIDATES = 17
+FUSION_CANDIDATES = 25
+FUSION_KERNELS = ("lds", "rb4", "rb3")   # nwq_set_fusion_kernel values 0, 1, 2
 
 
 def nwq_autotune_fusion(h: int, types: np.ndarray, qubits: np.ndarray, params: np.ndarray, reps: int = 1):
-    """(best width (0 = unfused), register-blocked kernel flag, {(k, rb): ms per circuit});
+    """(best width (0 = unfused), fused kernel (0 per-gate LDS, 1 / 2 register-blocked with 4 / 3
+    register bits), {(k, kernel): ms per circuit});
     the best setting is left on the handle and the state at |0...0>."""
     types = np.ascontiguousarray(types, dtype=np.int32)
     qubits = np.ascontiguousarray(qubits, dtype=np.int32)
@@ -321,7 +324,7 @@ def nwq_autotune_fusion(h: int, types: np.ndarray, qubits: np.ndarray, params: n
     table = {}
     for i in range(FUSION_CANDIDATES):
         if ms[i] >= 0:
-            table[(0, 0) if i == 0 else (6 + (i - 1) // 2, (i - 1) % 2)] = float(ms[i])
+            table[(0, 0) if i == 0 else (6 + (i - 1) // 3, (i - 1) % 3)] = float(ms[i])
     return k.value, rb.value, table
 
 

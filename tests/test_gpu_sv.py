@@ -290,7 +290,7 @@ def test_register_blocked_fused_kernel(nwq, n, k):
     gates = W.random_gate_list(n, 300, seed=7 * n + k) + W.brickwork_circuit(n, 6, seed=n)
     psi0 = W.random_state(n, seed=n)
     want = tensor.sv_run(gates, n, psi0)
-    for rb in (1, 0):
+    for rb in (2, 1, 0):
         st = nwq.SVState(n, reset=False)
         st.load(psi0)
         st.set_fusion(k)
@@ -310,7 +310,7 @@ def test_fusion_autotuner(nwq):
     arrays = nwq.circuit_arrays(gates)
     st = nwq.SVState(n)
     k, rb, table = nwq.nwq_autotune_fusion(st.h, *arrays, reps=1)
-    assert set(table) == {(0, 0)} | {(w, r) for w in range(6, 14) for r in (0, 1)}
+    assert set(table) == {(0, 0)} | {(w, r) for w in range(6, 14) for r in (0, 1, 2)}
     assert table[(k, rb)] == min(table.values())
     out = st.numpy()
     assert out[0] == 1 and np.count_nonzero(out) == 1
@@ -322,6 +322,9 @@ def test_fusion_autotuner(nwq):
     assert (blocks > 0) == (k > 0)
     with pytest.raises(nwq.NwqError) as e:
         nwq.nwq_autotune_fusion(st.h, *arrays, reps=0)
+    assert e.value.code == nwq.NWQ_EINVAL
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_set_fusion_kernel(st.h, 3)
     assert e.value.code == nwq.NWQ_EINVAL
     st.close()
     small = nwq.SVState(7)
