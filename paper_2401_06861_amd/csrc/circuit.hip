@@ -165,6 +165,21 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
   return out;
 }
 
+// Global offsets of the tile entries j * 2^(k - rbits), j < 2^rbits: the low
+// c bits stay in place, tile bit c + i lands on qubit hi[i].
+void fill_entry_offsets(FusedBlockDev& d, int rbits) {
+  const int k = d.c + d.m;
+  for (int j = 0; j < 16; ++j) {
+    d.joff[j] = 0;
+    if (j >= (1 << rbits)) continue;
+    const unsigned l = (unsigned)j << (k - rbits);
+    unsigned long long g = l & ((1u << d.c) - 1u);
+    for (int i = 0; i < d.m; ++i)
+      if ((l >> (d.c + i)) & 1u) g |= 1ull << d.hi[i];
+    d.joff[j] = g;
+  }
+}
+
 static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   const std::vector<Block> blocks = plan_blocks(gates, h->n, h->fuse_k);
   if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
@@ -224,6 +239,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
       phases.push_back(fp);
     }
     d.op_count = (int)phases.size() - d.op_begin;
+    fill_entry_offsets(d, rbits);
     launches.push_back({d, true, rbits});
   }
   const size_t ph_bytes = phases.size() * sizeof(FusedPhase);

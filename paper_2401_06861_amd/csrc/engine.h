@@ -81,6 +81,7 @@ struct Phase {
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
 int local_bit(const Block& b, int q);
 void pad_block(Block& b, int n, int k_target);
+void fill_entry_offsets(FusedBlockDev& d, int rbits);
 std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
                                const std::vector<int>& nq, int k, int rbits);
 

@@ -316,6 +316,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   const unsigned long long ntiles = 1ull << (nbits - k);
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
+  const unsigned long long glane = tile_index(0ull, tid, cmask, c, m, blk);   // thread part of entry indices
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     unsigned long long base = tile << c;
 #pragma unroll
@@ -325,40 +326,41 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
         base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
       }
     }
+    double2* __restrict__ at = a + (base + glane);
     __syncthreads();
     {
       vd2 r[NV];   // the tile has exactly NV entries per thread: issue all loads, then write LDS
 #pragma unroll
-      for (int j = 0; j < NV; ++j) r[j] = ldv(a + tile_index(base, tid + j * nt, cmask, c, m, blk));
+      for (int j = 0; j < NV; ++j) r[j] = ldv(at + blk.joff[j]);
 #pragma unroll
       for (int j = 0; j < NV; ++j) stv(t + padl(tid + j * nt), r[j]);
     }
     for (int pi = 0; pi < blk.op_count; ++pi) {
       const FusedPhase ph = phases[blk.op_begin + pi];
-      // thread bits -> the tile bits outside the phase's register bits (ascending)
-      unsigned regmask = 0;
+      // thread bits -> the tile bits outside the phase's register bits: insert
+      // a zero at each (ascending) register position
+      unsigned dep = tid;
 #pragma unroll
-      for (int r = 0; r < R; ++r) regmask |= 1u << ph.reg[r];
-      unsigned dep = 0;
-      for (int p = 0, i = 0; p < k; ++p) {
-        if ((regmask >> p) & 1u) continue;
-        dep |= ((tid >> i) & 1u) << p;
-        ++i;
-      }
-      unsigned off[NV];
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        off[j] = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) off[j] |= ((j >> r) & 1) << ph.reg[r];
-      }
+      for (int r = 0; r < R; ++r) dep = ((dep >> ph.reg[r]) << (ph.reg[r] + 1)) | (dep & ((1u << ph.reg[r]) - 1u));
+      // padl(dep | off) = padl(dep) + padl(off) for disjoint bit sets
+      double2* __restrict__ tl = t + padl(dep);
       __syncthreads();
       vd2 v[NV];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) v[j] = ldv(t + padl(dep | off[j]));
+      for (int j = 0; j < NV; ++j) {
+        unsigned off = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
+        v[j] = ldv(tl + padl(off));
+      }
       for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(ops[ph.op_begin + oi], v, mats);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) stv(t + padl(dep | off[j]), v[j]);
+      for (int j = 0; j < NV; ++j) {
+        unsigned off = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
+        stv(tl + padl(off), v[j]);
+      }
     }
     __syncthreads();
     {
@@ -366,7 +368,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
 #pragma unroll
       for (int j = 0; j < NV; ++j) r[j] = ldv(t + padl(tid + j * nt));
 #pragma unroll
-      for (int j = 0; j < NV; ++j) stv(a + tile_index(base, tid + j * nt, cmask, c, m, blk), r[j]);
+      for (int j = 0; j < NV; ++j) stv(at + blk.joff[j], r[j]);
     }
   }
 }

@@ -105,6 +105,9 @@ struct FusedBlockDev {
   int c, m;                 // tile = low c bits + m high bits
   int hi[8];
   int op_begin, op_count;   // range in the op table
+  // register-blocked kernels: global offset of tile entry j * 2^(k - rbits)
+  // (the per-thread part of an entry's index is added to it)
+  unsigned long long joff[16];
 };
 void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk,
                         const FusedOp* ops, const double2* mats, int lds_k);

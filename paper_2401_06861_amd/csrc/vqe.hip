@@ -997,6 +997,7 @@ static int build_fused(nwq_vqe* h) {
       phases.push_back(fp);
     }
     d.op_count = (int)phases.size() - d.op_begin;
+    fill_entry_offsets(d, h->fused_rbits);
     h->fwd_blocks.push_back(d);
   }
   for (auto bit = padded.rbegin(); bit != padded.rend(); ++bit) {
