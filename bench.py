@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-vqe", action="store_true", help="skip the batched VQE leg")
     ap.add_argument("--vqe-sizes", default="8:4,12:8,16:8,20:8", help="n:L pairs for the VQE leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=600)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-mode", choices=["trace", "pmc"], default=None)
     return ap.parse_args()
@@ -438,33 +438,41 @@ def vqe_leg(torch, sizes=None, B=256):
 
 def serving_leg(torch, num):
     """Continuous-batching server on a Poisson stream: 70% SV VQE (n 10..24,
-    L 4..8, half with gradient, 1..4 optimiser steps), 30% noisy DM TFIM
-    (n 6..12, 10 Trotter steps).  First all requests arrive at once
-    (saturation throughput), then at 0.8 x that rate (latency)."""
+    L 4..8, half with gradient, 1..20 optimiser steps with the state resident
+    between them), 30% noisy DM TFIM (n 6..12, 10 Trotter steps).  First all
+    requests arrive at once (saturation throughput), then Poisson arrivals at
+    0.5, 0.8 and 0.95 x that rate (latency)."""
     import workloads as W
     from paper_2401_06861_amd.serving import GpuExecutor, Server, summarize
-    log(f"[bench] serving leg, {num} requests")
-    kw = dict(num=num, seed=7, sv_n=(10, 24), dm_n=(6, 12), L_range=(4, 8), opt_steps=(1, 4), dm_steps=10)
+    log(f"[bench] serving leg, {num} requests per run")
+    kw = dict(num=num, seed=7, sv_n=(10, 24), dm_n=(6, 12), L_range=(4, 8), opt_steps=(1, 20), dm_steps=10)
     ex = GpuExecutor()
     budget = 64 << 30
-    warm = W.serving_trace(rate=1e9, **{**kw, "num": 40, "seed": 8})
+    warm = W.serving_trace(rate=1e9, **{**kw, "num": 60, "seed": 8})
     Server(ex, budget).run(warm)                       # contexts, graphs, allocator warm
-    sat_trace = W.serving_trace(rate=1e9, **kw)
     t0 = time.perf_counter()
-    sat = summarize(Server(ex, budget).run(sat_trace))
+    sat = summarize(Server(ex, budget).run(W.serving_trace(rate=1e9, **kw)))
     log(f"[bench] saturation {sat['throughput_req_per_s']:.1f} req/s in {time.perf_counter() - t0:.1f}s")
-    rate = 0.8 * sat["throughput_req_per_s"]
-    srv = Server(ex, budget)
-    res = srv.run(W.serving_trace(rate=rate, **kw))
-    lat = summarize(res)
+    loads = {}
+    main = None
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat["throughput_req_per_s"]
+        srv = Server(ex, budget)
+        lat = summarize(srv.run(W.serving_trace(rate=rate, **kw)))
+        log(f"[bench] load {frac}: p50 {lat['p50_ms']:.1f} ms p99 {lat['p99_ms']:.1f} ms")
+        loads[str(frac)] = {"offered_req_per_s": round(rate, 2), "throughput_req_per_s": round(lat["throughput_req_per_s"], 2),
+                            "p50_ms": round(lat["p50_ms"], 2), "p99_ms": round(lat["p99_ms"], 2),
+                            "batches": len(srv.batches),
+                            "mean_batch": round(sum(b for _, b in srv.batches) / max(len(srv.batches), 1), 2),
+                            "errors": lat["errors"]}
+        if frac == 0.8:
+            main = loads[str(frac)]
     ex.close()
     torch.cuda.empty_cache()
-    return {"requests": num, "mix": "70% SV VQE n10-24 L4-8 (half +grad, 1-4 steps), 30% DM TFIM n6-12",
+    return {"requests": num, "mix": "70% SV VQE n10-24 L4-8 (half +grad, 1-20 steps), 30% DM TFIM n6-12",
             "budget_GB": budget / 1e9, "saturation_req_per_s": round(sat["throughput_req_per_s"], 2),
-            "offered_req_per_s": round(rate, 2), "throughput_req_per_s": round(lat["throughput_req_per_s"], 2),
-            "p50_ms": round(lat["p50_ms"], 2), "p99_ms": round(lat["p99_ms"], 2),
-            "batches": len(srv.batches), "mean_batch": round(sum(b for _, b in srv.batches) / max(len(srv.batches), 1), 2),
-            "errors": lat["errors"]}
+            "offered_req_per_s": main["offered_req_per_s"], "throughput_req_per_s": main["throughput_req_per_s"],
+            "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "errors": main["errors"], "by_load": loads}
 
 
 if __name__ == "__main__":

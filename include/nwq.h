@@ -176,6 +176,16 @@ int nwq_apply_channel(nwq_handle h, const int* qubits, int k,
 /* Depolarising channel on k = 1 or 2 qubits:
  *   rho <- (1 - p) rho + p I/2^k (x) Tr_qubits(rho),  0 <= p <= 1. */
 int nwq_depolarize(nwq_handle h, const int* qubits, int k, double p);
+/* The same with a choice of convention (the paper names depolarisation
+ * without fixing one):
+ *   NWQ_DEPOL_REPLACE: as nwq_depolarize;
+ *   NWQ_DEPOL_PAULI:   rho <- (1 - p) rho + p / (4^k - 1) sum_{P != I} P rho P
+ *                      (uniform Pauli errors of total probability p).
+ * The two agree at p_PAULI = p_REPLACE (4^k - 1) / 4^k.  NWQ_EINVAL for
+ * another convention value. */
+#define NWQ_DEPOL_REPLACE 0
+#define NWQ_DEPOL_PAULI 1
+int nwq_depolarize_ex(nwq_handle h, const int* qubits, int k, double p, int convention);
 /* Amplitude damping: K0 = [[1,0],[0,sqrt(1-g)]], K1 = [[0,sqrt g],[0,0]]. */
 int nwq_amp_damp(nwq_handle h, int q, double gamma);
 /* Phase damping: K0 = [[1,0],[0,sqrt(1-l)]], K1 = [[0,0],[0,sqrt l]]. */

@@ -115,7 +115,7 @@ def dm_apply(rho: np.ndarray, op, n: int) -> np.ndarray:
     return dm_apply_gate(rho, op, n)
 
 
-G_CHANNELS = ("depolarize", "depolarize2", "amp_damp", "phase_damp")
+G_CHANNELS = G.CHANNELS
 
 
 def dm_run(ops: Iterable, n: int, rho0: np.ndarray | None = None) -> np.ndarray:

@@ -171,8 +171,20 @@ def kraus_phase_damp(lam: float) -> List[np.ndarray]:
 
 def kraus_depolarize_nc(p: float) -> List[np.ndarray]:
     """Alternative (Nielsen & Chuang) depolarising convention
-    (1-p) rho + (p/3) sum_{P in X,Y,Z} P rho P, kept for comparison."""
+    (1-p) rho + (p/3) sum_{P in X,Y,Z} P rho P."""
     return [math.sqrt(1 - p) * I2] + [math.sqrt(p / 3) * P for P in (X, Y, Z)]
+
+
+def kraus_depolarize2_nc(p: float) -> List[np.ndarray]:
+    """Two-qubit form of the same convention: (1-p) rho + (p/15) times the
+    sum of P rho P over the 15 non-identity two-qubit Paulis."""
+    out = [math.sqrt(1 - p) * np.eye(4, dtype=np.complex128)]
+    for a in "IXYZ":
+        for b in "IXYZ":
+            if a == "I" and b == "I":
+                continue
+            out.append(math.sqrt(p / 15) * np.kron(PAULI[a], PAULI[b]))
+    return out
 
 
 def channel_kraus(name: str, params: Sequence[float]) -> List[np.ndarray]:
@@ -184,4 +196,11 @@ def channel_kraus(name: str, params: Sequence[float]) -> List[np.ndarray]:
         return kraus_amp_damp(params[0])
     if name == "phase_damp":
         return kraus_phase_damp(params[0])
+    if name == "depolarize_nc":
+        return kraus_depolarize_nc(params[0])
+    if name == "depolarize2_nc":
+        return kraus_depolarize2_nc(params[0])
     raise ValueError(f"unknown channel {name}")
+
+
+CHANNELS = ("depolarize", "depolarize2", "amp_damp", "phase_damp", "depolarize_nc", "depolarize2_nc")

@@ -91,7 +91,7 @@ def dm_kraus(rho: np.ndarray, kraus, qubits, n: int) -> np.ndarray:
 
 def dm_apply(rho: np.ndarray, op, n: int) -> np.ndarray:
     name, qubits, params = op
-    if name in ("depolarize", "depolarize2", "amp_damp", "phase_damp"):
+    if name in G.CHANNELS:
         return dm_kraus(rho, G.channel_kraus(name, params), qubits, n)
     return dm_kraus(rho, [G.gate_matrix(name, qubits, params)], qubits, n)
 

@@ -563,14 +563,24 @@ int nwq_apply_channel(nwq_handle h, const int* qubits, int k, const double* krau
 }
 
 int nwq_depolarize(nwq_handle h, const int* qubits, int k, double p) {
+  return nwq_depolarize_ex(h, qubits, k, p, NWQ_DEPOL_REPLACE);
+}
+
+int nwq_depolarize_ex(nwq_handle h, const int* qubits, int k, double p, int convention) {
   if (!(p >= 0.0 && p <= 1.0)) return set_error(NWQ_EINVAL, "depolarising p outside [0, 1]");
   if (k < 1 || k > 2) return set_error(NWQ_EINVAL, "depolarising channel on k = 1 or 2 qubits");
-  // Pauli-twirl Kraus form: sqrt(1 - (4^k - 1) p / 4^k) I and sqrt(p / 4^k) P
+  if (convention != NWQ_DEPOL_REPLACE && convention != NWQ_DEPOL_PAULI)
+    return set_error(NWQ_EINVAL, "depolarising convention must be NWQ_DEPOL_REPLACE or NWQ_DEPOL_PAULI");
+  // Kraus form over the 4^k Paulis: identity weight w0, every other Pauli w.
+  // Replacement: w0 = sqrt(1 - (4^k - 1) p / 4^k), w = sqrt(p / 4^k) (Pauli twirl);
+  // uniform Pauli errors: w0 = sqrt(1 - p), w = sqrt(p / (4^k - 1)).
   const cd I1(0, 1);
   const cd paulis[4][4] = {{1.0, 0.0, 0.0, 1.0}, {0.0, 1.0, 1.0, 0.0}, {0.0, -I1, I1, 0.0}, {1.0, 0.0, 0.0, -1.0}};
   const int d = 1 << k, npl = d * d;
   std::vector<double> kr((size_t)npl * d * d * 2, 0.0);
-  const double w0 = std::sqrt(std::max(0.0, 1.0 - (npl - 1) * p / npl)), w = std::sqrt(p / npl);
+  const bool repl = convention == NWQ_DEPOL_REPLACE;
+  const double w0 = std::sqrt(std::max(0.0, repl ? 1.0 - (npl - 1) * p / npl : 1.0 - p));
+  const double w = std::sqrt(repl ? p / npl : p / (npl - 1));
   for (int t = 0; t < npl; ++t) {
     const double wt = t == 0 ? w0 : w;
     const int a = t % 4, b = t / 4;   // factor a on qubits[0], b on qubits[1]

@@ -69,6 +69,7 @@ _SIG = {
     "nwq_fusion_plan": [C.c_int, C.c_int, C.c_int, _ip, _ip, _ip, _ip, _ip],
     "nwq_apply_channel": [_h, _ip, C.c_int, _dp, C.c_int],
     "nwq_depolarize": [_h, _ip, C.c_int, C.c_double],
+    "nwq_depolarize_ex": [_h, _ip, C.c_int, C.c_double, C.c_int],
     "nwq_amp_damp": [_h, C.c_int, C.c_double],
     "nwq_phase_damp": [_h, C.c_int, C.c_double],
     "nwq_expval_pauli_sum": [_h, C.c_int, _up, _up, _dp, _dp],
@@ -244,6 +245,13 @@ def nwq_depolarize(h: int, qubits: Sequence[int], p: float) -> None:
     _check(lib.nwq_depolarize(h, _ints(qubits), len(qubits), p))
 
 
+DEPOL_REPLACE, DEPOL_PAULI = 0, 1
+
+
+def nwq_depolarize_ex(h: int, qubits: Sequence[int], p: float, convention: int) -> None:
+    _check(lib.nwq_depolarize_ex(h, _ints(qubits), len(qubits), p, convention))
+
+
 def nwq_amp_damp(h: int, q: int, gamma: float) -> None:
     _check(lib.nwq_amp_damp(h, q, gamma))
 
@@ -389,6 +397,8 @@ class _State:
         for name, q, p in gates:
             if name == "depolarize" or name == "depolarize2":
                 nwq_depolarize(self.h, q, p[0])
+            elif name == "depolarize_nc" or name == "depolarize2_nc":
+                nwq_depolarize_ex(self.h, q, p[0], DEPOL_PAULI)
             elif name == "amp_damp":
                 nwq_amp_damp(self.h, q[0], p[0])
             elif name == "phase_damp":

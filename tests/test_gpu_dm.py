@@ -161,6 +161,27 @@ def test_superop_launch_shapes(nwq, nt):
     st.close()
 
 
+def test_depolarizing_conventions(nwq):
+    """Both depolarising conventions on one and two qubits against the
+    oracle's Kraus sets, alone and fused after a gate."""
+    n = 4
+    rho0 = W.random_density_matrix(n, seed=77)
+    st = nwq.DMState(n, reset=False)
+    ops = [("depolarize_nc", (2,), (0.2,)), ("h", (1,), ()), ("depolarize_nc", (1,), (0.05,)),
+           ("depolarize2_nc", (3, 0), (0.3,)), ("cz", (0, 2), ()), ("depolarize2_nc", (0, 2), (0.01,)),
+           ("depolarize", (1,), (0.1,))]
+    st.load(rho0)
+    st.run(ops)
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    assert maxerr(st.numpy(), want) <= TOL
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_depolarize_ex(st.h, (0,), 0.1, 2)
+    assert e.value.code == nwq.NWQ_EINVAL
+    st.close()
+
+
 def test_dm_errors(nwq):
     n = 3
     rho0 = W.random_density_matrix(n, seed=2)

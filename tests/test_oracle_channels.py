@@ -27,7 +27,8 @@ def apply1(kraus, rho):
     return sum(K @ rho @ K.conj().T for K in kraus)
 
 
-@pytest.mark.parametrize("name", ["depolarize", "amp_damp", "phase_damp", "depolarize2"])
+@pytest.mark.parametrize("name", ["depolarize", "amp_damp", "phase_damp", "depolarize2", "depolarize_nc",
+                                  "depolarize2_nc"])
 def test_cptp(name):
     for p in (0.0, 1e-3, 0.3, 1.0):
         ks = G.channel_kraus(name, (p,))
@@ -151,3 +152,21 @@ def test_superop_groups_match_kraus():
         idx = tensor.group_indices(base, vq)
         got = tensor.groups_apply(vec[idx], tensor.dm_superop(ks))
         assert close(got, want[idx], 1e-14)
+
+
+def test_pauli_error_convention():
+    """The uniform-Pauli-error form (1-p) rho + p/(4^k-1) sum_{P != I} P rho P
+    is the replacement form at p' = p 4^k / (4^k - 1), because the Pauli
+    twirl sum_P P rho P over all 4^k Paulis is 2^k Tr(rho) I; on one qubit
+    the Bloch vector shrinks by 1 - 4p/3."""
+    rng = np.random.default_rng(9)
+    for p in (0.0, 0.01, 0.3, 0.75):
+        r = rng.standard_normal(3)
+        r *= 0.9 / np.linalg.norm(r)
+        assert close(bloch(apply1(G.kraus_depolarize_nc(p), from_bloch(r))), (1 - 4 * p / 3) * r)
+        n = 3
+        rho = W.random_density_matrix(n, seed=int(100 * p) + 1)
+        for name, qs, scale in (("depolarize", (1,), 4 / 3), ("depolarize2", (2, 0), 16 / 15)):
+            a = dense.dm_apply(rho, (name + "_nc", qs, (p,)), n)
+            b = dense.dm_apply(rho, (name, qs, (p * scale,)), n)
+            assert close(a, b, 1e-13)

@@ -40,7 +40,7 @@ GATE_ARITY = {
 # Channel names: (number of qubits, number of params).
 CHANNEL_ARITY = {
     "depolarize": (1, 1), "amp_damp": (1, 1), "phase_damp": (1, 1),
-    "depolarize2": (2, 1),
+    "depolarize2": (2, 1), "depolarize_nc": (1, 1), "depolarize2_nc": (2, 1),
 }
 
 
