@@ -777,6 +777,246 @@ __global__ __launch_bounds__(kBwdBlock) void k_vqe_bwd_tile(double2* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-blocked backward sweep.  The block's reversed gates are split into
+// phases over R register bits (as in the forward kernel); per phase each
+// thread holds the 2^R amplitudes of phi and of lambda that differ on those
+// bits and un-applies the phase's gates in registers, accumulating each
+// parametrised gate's Im<lambda|P|phi> before un-applying it.  Tiles of phi
+// and lambda are exchanged through LDS between phases.
+// ---------------------------------------------------------------------------
+struct VqeBwdRop {
+  int kind;    // 0 rotation, 1 RZZ, 2 fixed 2x2, 3 CX, 4 CZ, 5 SWAP
+  int r0, r1;  // register-bit indices in operator order (r1 for 2-qubit ops)
+  int axis;    // rotation axis
+  int slot;    // gradient slot or -1
+  int mat;     // index of the adjoint matrix in the per-vector table (double2 units)
+  int pad0, pad1;
+};
+
+constexpr int kBwdRbMaxWaves = 4;   // tiles of at most 2^11 entries at 3 register bits
+
+__device__ __forceinline__ unsigned padl_b(unsigned l) { return l + (l >> 4); }
+// one padded tile of 2^k entries (one extra entry per 16)
+inline size_t bwd_rb_tile_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << k) / 16); }
+
+template <int NV, int B>
+__device__ __forceinline__ void bw_rot(vd2 (&p)[NV], vd2 (&l)[NV], const double2* __restrict__ M, int axis,
+                                       bool grad, double& g) {
+  const vd2 m0 = ld(M), m1 = ld(M + 1), m2 = ld(M + 2), m3 = ld(M + 3);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    if (grad) g += pair_grad(axis, p[j], p[k], l[j], l[k]);
+    const vd2 p0 = p[j], p1 = p[k], l0 = l[j], l1 = l[k];
+    p[j] = cfma(m0, p0, cmul(m1, p1));
+    p[k] = cfma(m2, p0, cmul(m3, p1));
+    l[j] = cfma(m0, l0, cmul(m1, l1));
+    l[k] = cfma(m2, l0, cmul(m3, l1));
+  }
+}
+
+// Diagonal 2-qubit op on register bits B0 (u bit 0), B1 (u bit 1); with grad,
+// the ZZ generator's term Im(conj(l) p) times its eigenvalue.
+template <int NV, int B0, int B1>
+__device__ __forceinline__ void bw_diag2(vd2 (&p)[NV], vd2 (&l)[NV], const double2* __restrict__ M, bool grad,
+                                         double& g) {
+  const vd2 d[4] = {ld(M), ld(M + 1), ld(M + 2), ld(M + 3)};
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int a = (j >> B0) & 1, b = (j >> B1) & 1;
+    if (grad) {
+      const double t = l[j].x * p[j].y - l[j].y * p[j].x;
+      g += (a != b) ? -t : t;
+    }
+    p[j] = cmul(d[a + 2 * b], p[j]);
+    l[j] = cmul(d[a + 2 * b], l[j]);
+  }
+}
+
+template <int NV, int B0, int B1, int OA, int OB>
+__device__ __forceinline__ void bw_swap(vd2 (&p)[NV], vd2 (&l)[NV]) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    if (j & ((1 << B0) | (1 << B1))) continue;
+    vd2 t = p[j | OA];
+    p[j | OA] = p[j | OB];
+    p[j | OB] = t;
+    t = l[j | OA];
+    l[j | OA] = l[j | OB];
+    l[j | OB] = t;
+  }
+}
+
+template <int NV, int B0, int B1>
+__device__ __forceinline__ void bw_pair(const VqeBwdRop& op, vd2 (&p)[NV], vd2 (&l)[NV], const double2* M,
+                                        double& g) {
+  if (op.kind == 1 || op.kind == 4) bw_diag2<NV, B0, B1>(p, l, M, op.kind == 1, g);
+  else if (op.kind == 3) bw_swap<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(p, l);   // CX: control B0
+  else bw_swap<NV, B0, B1, (1 << B0), (1 << B1)>(p, l);                                  // SWAP
+}
+
+template <int R>
+__device__ __forceinline__ void bw_apply(const VqeBwdRop& op, vd2 (&p)[1 << R], vd2 (&l)[1 << R],
+                                         const double2* __restrict__ table, double& g) {
+  constexpr int NV = 1 << R;
+  const double2* M = table + op.mat;
+  if (op.kind == 0 || op.kind == 2) {
+    const bool grad = op.kind == 0;
+    switch (op.r0) {
+      case 0: bw_rot<NV, 0>(p, l, M, op.axis, grad, g); break;
+      case 1: bw_rot<NV, 1>(p, l, M, op.axis, grad, g); break;
+      case 2: bw_rot<NV, 2>(p, l, M, op.axis, grad, g); break;
+      default:
+        if constexpr (R == 4) bw_rot<NV, 3>(p, l, M, op.axis, grad, g);
+        break;
+    }
+    return;
+  }
+  if constexpr (R == 4) {
+    switch (op.r0 * 4 + op.r1) {
+      case 1: bw_pair<NV, 0, 1>(op, p, l, M, g); break;
+      case 2: bw_pair<NV, 0, 2>(op, p, l, M, g); break;
+      case 3: bw_pair<NV, 0, 3>(op, p, l, M, g); break;
+      case 4: bw_pair<NV, 1, 0>(op, p, l, M, g); break;
+      case 6: bw_pair<NV, 1, 2>(op, p, l, M, g); break;
+      case 7: bw_pair<NV, 1, 3>(op, p, l, M, g); break;
+      case 8: bw_pair<NV, 2, 0>(op, p, l, M, g); break;
+      case 9: bw_pair<NV, 2, 1>(op, p, l, M, g); break;
+      case 11: bw_pair<NV, 2, 3>(op, p, l, M, g); break;
+      case 12: bw_pair<NV, 3, 0>(op, p, l, M, g); break;
+      case 13: bw_pair<NV, 3, 1>(op, p, l, M, g); break;
+      default: bw_pair<NV, 3, 2>(op, p, l, M, g); break;   // 14
+    }
+  } else {
+    switch (op.r0 * 4 + op.r1) {
+      case 1: bw_pair<NV, 0, 1>(op, p, l, M, g); break;
+      case 2: bw_pair<NV, 0, 2>(op, p, l, M, g); break;
+      case 4: bw_pair<NV, 1, 0>(op, p, l, M, g); break;
+      case 6: bw_pair<NV, 1, 2>(op, p, l, M, g); break;
+      case 8: bw_pair<NV, 2, 0>(op, p, l, M, g); break;
+      default: bw_pair<NV, 2, 1>(op, p, l, M, g); break;   // 9
+    }
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* __restrict__ phi0,
+                                                                      double2* __restrict__ lam0, int n,
+                                                                      FusedBlockDev blk,
+                                                                      const FusedPhase* __restrict__ phases,
+                                                                      const VqeBwdRop* __restrict__ ops,
+                                                                      const double2* __restrict__ table0,
+                                                                      int mat_stride, int nslots,
+                                                                      double* __restrict__ gpart) {
+  constexpr int NV = 1 << R;
+  extern __shared__ double2 sh[];
+  __shared__ double acc[kBwdMaxOps][kBwdRbMaxWaves];
+  const int c = blk.c, m = blk.m, k = c + m;
+  const unsigned len = 1u << k;
+  const unsigned nt = len >> R;
+  double2* tp = sh;
+  double2* tl = sh + padl_b(len);
+  const unsigned long long N = 1ull << n;
+  double2* __restrict__ phi = phi0 + (size_t)blockIdx.y * N;
+  double2* __restrict__ lam = lam0 + (size_t)blockIdx.y * N;
+  const double2* __restrict__ table = table0 + (size_t)blockIdx.y * mat_stride;
+  const unsigned long long ntiles = 1ull << (n - k);
+  const unsigned cmask = (1u << c) - 1u;
+  const unsigned tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int NW = (int)(nt + kWave - 1) / kWave;
+  const int op0 = phases[blk.op_begin].op_begin;
+  const FusedPhase last = phases[blk.op_begin + blk.op_count - 1];
+  const int nops = last.op_begin + last.op_count - op0;
+  for (int i = tid; i < nops * kBwdRbMaxWaves; i += nt) acc[i / kBwdRbMaxWaves][i % kBwdRbMaxWaves] = 0.0;
+  const unsigned long long glane = bwd_index(0ull, tid, cmask, c, m, blk);
+  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    unsigned long long base = tile << c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < m) {
+        const int q = blk.hi[i];
+        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
+      }
+    }
+    double2* __restrict__ ap = phi + (base + glane);
+    double2* __restrict__ al = lam + (base + glane);
+    __syncthreads();
+    {
+      vd2 rp[NV], rl[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        rp[j] = ld(ap + blk.joff[j]);
+        rl[j] = ld(al + blk.joff[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        st(tp + padl_b(tid + j * nt), rp[j]);
+        st(tl + padl_b(tid + j * nt), rl[j]);
+      }
+    }
+    for (int pi = 0; pi < blk.op_count; ++pi) {
+      const FusedPhase ph = phases[blk.op_begin + pi];
+      unsigned dep = tid;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dep = ((dep >> ph.reg[r]) << (ph.reg[r] + 1)) | (dep & ((1u << ph.reg[r]) - 1u));
+      double2* __restrict__ sp = tp + padl_b(dep);
+      double2* __restrict__ sl = tl + padl_b(dep);
+      __syncthreads();
+      vd2 vp[NV], vl[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        unsigned off = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
+        vp[j] = ld(sp + padl_b(off));
+        vl[j] = ld(sl + padl_b(off));
+      }
+      for (int oi = 0; oi < ph.op_count; ++oi) {
+        const VqeBwdRop op = ops[ph.op_begin + oi];
+        double g = 0.0;
+        bw_apply<R>(op, vp, vl, table, g);
+        if (op.slot >= 0) {
+          const double w = wave_sum(g);
+          if (lane == 0) acc[ph.op_begin + oi - op0][wave] += w;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        unsigned off = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
+        st(sp + padl_b(off), vp[j]);
+        st(sl + padl_b(off), vl[j]);
+      }
+    }
+    __syncthreads();
+    {
+      vd2 rp[NV], rl[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        rp[j] = ld(tp + padl_b(tid + j * nt));
+        rl[j] = ld(tl + padl_b(tid + j * nt));
+      }
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        st(ap + blk.joff[j], rp[j]);
+        st(al + blk.joff[j], rl[j]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int oi = tid; oi < nops; oi += nt) {
+    const int slot = ops[op0 + oi].slot;
+    if (slot < 0) continue;
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += acc[oi][w];
+    gpart[((size_t)blockIdx.y * nslots + slot) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -817,6 +1057,8 @@ struct nwq_vqe {
   bool fused_built = false;
   int fused_k = 11;
   int fused_rbits = 4;         // register bits per phase of the forward kernel
+  bool bwd_rb = false;         // backward sweep register-blocked (3 bits) when every tile has >= 2^9 entries
+  size_t fused_rop_off = 0;    // offset of the register-blocked backward ops in d_fused
   std::vector<nwq::FusedBlockDev> fwd_blocks, bwd_blocks;
   void* d_fused = nullptr;     // [forward phases][forward ops][backward ops]
   size_t fused_ops_off = 0, fused_bwd_off = 0;
@@ -1000,7 +1242,59 @@ static int build_fused(nwq_vqe* h) {
     fill_entry_offsets(d, h->fused_rbits);
     h->fwd_blocks.push_back(d);
   }
-  for (auto bit = padded.rbegin(); bit != padded.rend(); ++bit) {
+  // Backward: register-blocked with 3 register bits when every tile gives at
+  // least one full wave (2^(k-3) >= 64), else one LDS pass per gate.
+  constexpr int kBwdBits = 3;
+  h->bwd_rb = true;
+  for (const Block& b : padded) h->bwd_rb = h->bwd_rb && (b.c + b.m) - kBwdBits >= 6;
+  std::vector<VqeBwdRop> rops;
+  for (auto bit = padded.rbegin(); h->bwd_rb && bit != padded.rend(); ++bit) {
+    const Block& b = *bit;
+    const int kb = b.c + b.m;
+    std::vector<std::array<int, 2>> lb(g.size());
+    std::vector<int> nq(g.size(), 1);
+    std::vector<int> rev(b.gates.rbegin(), b.gates.rend());
+    for (int gi : rev) {
+      lb[gi] = {local_bit(b, g[gi].q[0]), g[gi].nq == 2 ? local_bit(b, g[gi].q[1]) : 0};
+      nq[gi] = g[gi].nq;
+    }
+    for (size_t s0 = 0; s0 < rev.size(); s0 += kBwdMaxOps) {
+      const std::vector<int> chunk(rev.begin() + s0, rev.begin() + std::min(rev.size(), s0 + kBwdMaxOps));
+      FusedBlockDev d{};
+      d.c = b.c;
+      d.m = b.m;
+      for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
+      d.op_begin = (int)phases.size();
+      for (const Phase& ph : plan_phases(chunk, lb, nq, kb, kBwdBits)) {
+        FusedPhase fp{};
+        for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i] < 0 ? 0 : ph.reg[i];
+        fp.op_begin = (int)rops.size();
+        auto ridx = [&](int bit) {
+          for (int i = 0; i < kBwdBits; ++i)
+            if (ph.reg[i] == bit) return i;
+          return -1;
+        };
+        for (int gi : ph.gates) {
+          const VqeOp& op = h->ops[gi];
+          VqeBwdRop o{};
+          o.r0 = ridx(lb[gi][0]);
+          o.r1 = nq[gi] == 2 ? ridx(lb[gi][1]) : 0;
+          o.axis = op.axis;
+          o.slot = op.slot;
+          o.mat = 8 * gi + 4;
+          o.kind = op.kind == OP_ROT ? 0 : op.kind == OP_RZZ ? 1 : op.kind == OP_FIX1 ? 2 : op.kind == OP_CX ? 3
+                 : op.kind == OP_CZ ? 4 : 5;
+          rops.push_back(o);
+        }
+        fp.op_count = (int)rops.size() - fp.op_begin;
+        phases.push_back(fp);
+      }
+      d.op_count = (int)phases.size() - d.op_begin;
+      fill_entry_offsets(d, kBwdBits);
+      h->bwd_blocks.push_back(d);
+    }
+  }
+  for (auto bit = padded.rbegin(); !h->bwd_rb && bit != padded.rend(); ++bit) {
     const Block& b = *bit;
     std::vector<VqeBwdOp> rev;
     for (auto it = b.gates.rbegin(); it != b.gates.rend(); ++it) {
@@ -1033,13 +1327,20 @@ static int build_fused(nwq_vqe* h) {
   const size_t ph_bytes = phases.size() * sizeof(FusedPhase);
   h->fused_ops_off = (ph_bytes + 255) & ~size_t(255);
   h->fused_bwd_off = (h->fused_ops_off + fops.size() * sizeof(FusedOp) + 255) & ~size_t(255);
-  const size_t total = h->fused_bwd_off + bops.size() * sizeof(VqeBwdOp) + 16;
+  h->fused_rop_off = (h->fused_bwd_off + bops.size() * sizeof(VqeBwdOp) + 255) & ~size_t(255);
+  const size_t total = h->fused_rop_off + rops.size() * sizeof(VqeBwdRop) + 16;
   std::vector<char> prog(total, 0);
   if (!phases.empty()) std::memcpy(prog.data(), phases.data(), ph_bytes);
   if (!fops.empty()) std::memcpy(prog.data() + h->fused_ops_off, fops.data(), fops.size() * sizeof(FusedOp));
   if (!bops.empty()) std::memcpy(prog.data() + h->fused_bwd_off, bops.data(), bops.size() * sizeof(VqeBwdOp));
+  if (!rops.empty()) std::memcpy(prog.data() + h->fused_rop_off, rops.data(), rops.size() * sizeof(VqeBwdRop));
+  // dynamic LDS above 64 KiB is enabled here, outside any graph capture
+  const size_t max_rb_lds = 2 * bwd_rb_tile_bytes(std::min(h->fused_k, n) < 8 ? 8 : std::min(h->fused_k, n));
   int rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)max_bwd_lds), "hipFuncSetAttribute");
+  if (!rc && h->bwd_rb)
+    rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)max_rb_lds), "hipFuncSetAttribute");
   if (!rc) rc = check_hip(hipMalloc(&h->d_fused, total), "hipMalloc(vqe fused program)");
   if (!rc) rc = check_hip(hipMemcpy(h->d_fused, prog.data(), total, hipMemcpyHostToDevice), "hipMemcpy(vqe fused program)");
   if (rc) return rc;
@@ -1071,10 +1372,17 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
   hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
                      coeffs, h->d_epart, grad != nullptr ? 1 : 0);
   if (grad != nullptr) {
+    const VqeBwdRop* dro = reinterpret_cast<const VqeBwdRop*>(static_cast<char*>(h->d_fused) + h->fused_rop_off);
     for (const FusedBlockDev& d : h->bwd_blocks) {
-      const size_t lds = 2 * sizeof(double2) << (d.c + d.m);
-      hipLaunchKernelGGL(k_vqe_bwd_tile, grid, dim3(kBwdBlock), lds, s, h->d_phi, h->d_lam, h->n, d, dbo,
-                         h->d_table, stride, h->nslots, h->d_gpart);
+      const int kb = d.c + d.m;
+      if (h->bwd_rb) {
+        hipLaunchKernelGGL(k_vqe_bwd_rb<3>, grid, dim3(1u << (kb - 3)), 2 * bwd_rb_tile_bytes(kb), s, h->d_phi,
+                           h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart);
+      } else {
+        const size_t lds = 2 * sizeof(double2) << kb;
+        hipLaunchKernelGGL(k_vqe_bwd_tile, grid, dim3(kBwdBlock), lds, s, h->d_phi, h->d_lam, h->n, d, dbo,
+                           h->d_table, stride, h->nslots, h->d_gpart);
+      }
     }
   }
   hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
