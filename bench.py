@@ -226,6 +226,7 @@ def main():
     if not args.no_extras:
         out["fused"] = fused_leg(nwq, st, arrays, n, args, ms_per_step)
         out["sweep"] = sweep_leg(nwq, st, n)
+        out["measure"] = measure_leg(nwq, st, n)
         del st, psi
         torch.cuda.empty_cache()
         if n == 30 and not args.no_n32:
@@ -314,6 +315,42 @@ def sweep_leg(nwq, st, n):
             avg = ms / c
             res[f"{name}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(bytes_per / (avg * 1e-3) / 1e9, 1)}
     return res
+
+
+def measure_leg(nwq, st, n, shots=1 << 20):
+    """Outcome probabilities of the final brickwork state, readout noise with
+    per-qubit confusion (P(1|0) = 1%, P(0|1) = 2%), and shot sampling."""
+    import torch
+    import workloads as W
+    log("[bench] measurement leg")
+    N = 1 << n
+    st.reset()
+    nwq.nwq_apply_circuit(st.h, *nwq.circuit_arrays(W.brickwork_circuit(n, 4, seed=0)))
+    p = torch.empty(N, dtype=torch.float64, device="cuda")
+    work = torch.empty(nwq.nwq_sample_workspace_bytes(n) // 8, dtype=torch.int64, device="cuda")
+    u = torch.rand(shots, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    outs = torch.empty(shots, dtype=torch.int64, device="cuda")
+    conf = [[[0.99, 0.02], [0.01, 0.98]]] * n
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    tp = timed(lambda: nwq.nwq_probabilities(st.h, p))
+    tr = timed(lambda: nwq.nwq_readout_noise(n, p, conf), reps=1)
+    ts = timed(lambda: nwq.nwq_sample(n, p, u, outs, work))
+    passes = (n + 3) // 4
+    return {"n": n, "shots": shots,
+            "probabilities_ms": round(tp * 1e3, 3), "probabilities_GBs": round(24 * N / tp / 1e9, 1),
+            "readout_ms": round(tr * 1e3, 3), "readout_passes": passes,
+            "readout_GBs": round(16 * N * passes / tr / 1e9, 1),
+            "sample_ms": round(ts * 1e3, 3), "sample_scan_GBs": round(24 * N / ts / 1e9, 1),
+            "shots_per_s": round(shots / ts, 1)}
 
 
 def sweep_n32_leg(nwq, torch, tuned):

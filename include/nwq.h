@@ -309,6 +309,42 @@ int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* 
                         const double* params, int reps, int* best_k, int* best_rb, double* ms_out);
 
 /* ---------------------------------------------------------------------------
+ * Measurement: outcome probabilities, readout noise, shot sampling
+ * (provider semantics of Sec. II; measurement noise of the Sec. III device
+ * noise model).  Outcome j is the basis index (qubit q = bit q of j).
+ * ------------------------------------------------------------------------- */
+
+/* probs_dev[j] = |a_j|^2 (SV) or Re rho_jj (DM) for j < 2^n: a caller-owned
+ * device array of 2^n doubles.  Flushes deferred work, then runs
+ * asynchronously on the handle's stream. */
+int nwq_probabilities(nwq_handle h, double* probs_dev);
+
+/* Readout noise on an outcome distribution of 2^n doubles (device, in
+ * place): for each qubit q a confusion matrix C_q with
+ * C_q[r][t] = P(read r | true t), given as confusion[4q .. 4q+3] =
+ * C[0][0], C[0][1], C[1][0], C[1][1]; p <- (C_{n-1} (x) ... (x) C_0) p.
+ * Entries must lie in [0, 1] and each column sum to 1 (within 1e-12), else
+ * NWQ_EINVAL before any launch.  Identity matrices are skipped; the others
+ * run four qubits per pass.  Asynchronous on `stream` (hipStream_t). */
+int nwq_readout_noise(int n, double* probs_dev, const double* confusion, void* stream);
+
+/* Workspace of nwq_sample in bytes (0 if n is outside [1, 34]). */
+size_t nwq_sample_workspace_bytes(int n);
+
+/* Shot sampling from an outcome distribution of 2^n doubles (device; the
+ * entries should sum to 1 and must sum to at most 4).  Each p_j is quantised
+ * to q_j = floor(p_j 2^61) (p_j <= 0 or NaN gives 0, p_j >= 1 gives 2^61);
+ * the inclusive integer CDF C_j = q_0 + ... + q_j is built in work_dev
+ * (its first 2^n uint64 entries, left there for the caller); shot s with
+ * uniform u_dev[s] in [0, 1) returns out_dev[s] = the smallest j with
+ * C_j > floor(floor(u 2^53) Q / 2^53), Q = C_{2^n-1} (-1 if Q = 0).  u is
+ * clamped into [0, 1 - 2^-53].  work_bytes must be at least
+ * nwq_sample_workspace_bytes(n).  0 <= shots < 2^31.  Asynchronous on
+ * `stream`.  The result depends on the inputs only (exact integer sums). */
+int nwq_sample(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
+               void* work_dev, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 

@@ -81,6 +81,10 @@ _SIG = {
     "nwq_get_launch": [_h, C.c_int, C.c_int, _ip, _ip],
     "nwq_autotune": [_h, C.c_int, _dp],
     "nwq_autotune_fusion": [_h, C.c_int, _ip, _ip, _dp, C.c_int, _ip, _ip, _dp],
+    "nwq_probabilities": [_h, C.c_void_p],
+    "nwq_readout_noise": [C.c_int, C.c_void_p, _dp, C.c_void_p],
+    "nwq_sample_workspace_bytes": [C.c_int],
+    "nwq_sample": [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
     "nwq_timing_read": [_h, C.POINTER(C.c_longlong), _dp, C.c_int],
 }
 for _name, _args in _SIG.items():
@@ -89,6 +93,7 @@ for _name, _args in _SIG.items():
     _f.restype = C.c_int
 lib.nwq_last_error.argtypes = []
 lib.nwq_last_error.restype = C.c_char_p
+lib.nwq_sample_workspace_bytes.restype = C.c_size_t
 
 EXPORTED = tuple(_SIG) + ("nwq_last_error",)
 
@@ -336,6 +341,34 @@ def nwq_autotune_fusion(h: int, types: np.ndarray, qubits: np.ndarray, params: n
     return k.value, rb.value, table
 
 
+# ------------------------------------------------------------ measurement
+def nwq_probabilities(h: int, probs) -> None:
+    """probs: float64 cuda tensor of 2^n entries (written on the handle's stream)."""
+    _check(lib.nwq_probabilities(h, probs.data_ptr()))
+
+
+def nwq_readout_noise(n: int, probs, confusion, stream=None) -> None:
+    """confusion: n x 2 x 2 array, C[q][r][t] = P(read r | true t)."""
+    import torch
+    cm = np.ascontiguousarray(np.asarray(confusion, dtype=np.float64).reshape(n, 4))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.nwq_readout_noise(n, probs.data_ptr(), cm.ctypes.data_as(_dp), s.cuda_stream))
+
+
+def nwq_sample_workspace_bytes(n: int) -> int:
+    return int(lib.nwq_sample_workspace_bytes(n))
+
+
+def nwq_sample(n: int, probs, u, out, work, stream=None) -> None:
+    """probs: float64 cuda [2^n]; u: float64 cuda [shots]; out: int64 cuda
+    [shots]; work: cuda tensor of at least nwq_sample_workspace_bytes(n)
+    bytes (its first 2^n int64 entries hold the integer CDF afterwards)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.nwq_sample(n, probs.data_ptr(), u.data_ptr(), u.numel(), out.data_ptr(), work.data_ptr(),
+                          work.numel() * work.element_size(), s.cuda_stream))
+
+
 def nwq_timing_enable(h: int, enable: bool = True) -> None:
     _check(lib.nwq_timing_enable(h, int(bool(enable))))
 
@@ -421,6 +454,13 @@ class _State:
     def purity(self) -> float:
         return nwq_purity(self.h)
 
+    def probabilities(self):
+        """Outcome probabilities as a float64 cuda tensor of 2^n entries."""
+        import torch
+        p = torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device)
+        nwq_probabilities(self.h, p)
+        return p
+
     def numpy(self) -> np.ndarray:
         out = np.empty(self.tensor.numel(), dtype=np.complex128)
         nwq_get_state(self.h, out)
@@ -431,6 +471,16 @@ class _State:
 
     def flush(self):
         nwq_flush(self.h)
+
+
+def sample_shots(n: int, probs, u, work=None):
+    """Outcome indices (int64 cuda tensor) for the uniforms u drawn from probs."""
+    import torch
+    if work is None:
+        work = torch.empty(nwq_sample_workspace_bytes(n) // 8, dtype=torch.int64, device=probs.device)
+    out = torch.empty(u.numel(), dtype=torch.int64, device=probs.device)
+    nwq_sample(n, probs, u, out, work)
+    return out
 
 
 class SVState(_State):
