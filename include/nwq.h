@@ -132,6 +132,26 @@ int nwq_apply_matrix(nwq_handle h, const int* qubits, int k, const double* m);
 int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types,
                       const int* qubits, const double* params);
 
+/* OpenQASM 2.0 front-end (host only).  Accepts the header, include lines,
+ * qreg / creg (quantum registers laid out in declaration order), the qelib1
+ * gates id x y z h s sdg t tdg rx ry rz u1 u2 u3 u p cx CX cz swap rzz and
+ * the built-in U with register broadcast, parameter expressions (numbers,
+ * pi, + - * / ^, unary minus, parentheses, sin cos tan exp ln sqrt), and
+ * skips barrier and measure.  u1(l) = p(l) = U3(0, 0, l); u2(f, l) =
+ * U3(pi/2, f, l); rotations keep this library's exp(-i theta P / 2)
+ * convention (equal to the textual qelib1 definitions up to a global
+ * phase).  Gate definitions, if, reset and opaque give NWQ_EINVAL; every
+ * error message names the line.
+ *
+ * nwq_qasm_parse writes the number of qubits and gates, and the first
+ * min(capacity, gates) gates in the arrays of nwq_apply_circuit (call with
+ * capacity 0 to size them).  nwq_apply_qasm parses and applies the program
+ * (NWQ_ERANGE if its qubit count differs from the handle's); with fusion
+ * enabled the whole program goes through the block planner. */
+int nwq_qasm_parse(const char* text, int* n_qubits, int* n_gates, int capacity, int* types, int* qubits,
+                   double* params);
+int nwq_apply_qasm(nwq_handle h, const char* text);
+
 /* Fused-block width for nwq_apply_circuit on SV handles: 0 = off (one
  * kernel per gate), else the number of qubits a block may touch (6..13).
  * Returns the value in effect through *k_out when non-NULL. */
@@ -190,6 +210,14 @@ int nwq_depolarize_ex(nwq_handle h, const int* qubits, int k, double p, int conv
 int nwq_amp_damp(nwq_handle h, int q, double gamma);
 /* Phase damping: K0 = [[1,0],[0,sqrt(1-l)]], K1 = [[0,0],[0,sqrt l]]. */
 int nwq_phase_damp(nwq_handle h, int q, double lambda);
+/* Thermal relaxation of qubit q over a duration t, from the device
+ * calibration values T1 and T2 (Sec. III device noise model): the excited
+ * population decays as e^{-t/T1} into |0> and the coherences as e^{-t/T2}.
+ * Applied as amplitude damping with gamma = 1 - e^{-t/T1} followed by phase
+ * damping with lambda = 1 - e^{-t (2/T2 - 1/T1)} (fused with the pending gate
+ * like any channel).  Requires T1 > 0, 0 < T2 <= 2 T1, t >= 0 (NWQ_EINVAL);
+ * DM handles only (NWQ_EKIND). */
+int nwq_thermal_relax(nwq_handle h, int q, double t1, double t2, double t);
 
 /* ---------------------------------------------------------------------------
  * Observables (Sec. III: magnetisation, energy)

@@ -108,8 +108,31 @@ def dm_apply_kraus(rho: np.ndarray, kraus: Sequence[np.ndarray], qubits, n: int)
     return out
 
 
+def thermal_relax(rho: np.ndarray, q: int, t1: float, t2: float, t: float, n: int) -> np.ndarray:
+    """Thermal relaxation of qubit q for a time t (Sec. III device noise),
+    written as the solution of the relaxation equations: the excited
+    population decays as e^{-t/T1} into the ground state and the coherences
+    decay as e^{-t/T2}.  On entries rho[r, c] with (r_q, c_q) the bits of
+    qubit q in the row and column index:
+      (0, 0): rho[r, c] + (1 - e^{-t/T1}) rho[r + 2^q, c + 2^q]
+      (1, 1): e^{-t/T1} rho[r, c]
+      (0, 1), (1, 0): e^{-t/T2} rho[r, c]."""
+    e1, e2 = np.exp(-t / t1), np.exp(-t / t2)
+    dim = 1 << n
+    r = np.arange(dim)[:, None]
+    c = np.arange(dim)[None, :]
+    rq, cq = (r >> q) & 1, (c >> q) & 1
+    out = np.where(rq != cq, e2 * rho, np.where(rq == 1, e1 * rho, rho)).astype(np.complex128)
+    up = 1 << q
+    lo = np.nonzero((np.arange(dim) >> q) & 1 == 0)[0]
+    out[np.ix_(lo, lo)] += (1 - e1) * rho[np.ix_(lo + up, lo + up)]
+    return out
+
+
 def dm_apply(rho: np.ndarray, op, n: int) -> np.ndarray:
     name, qubits, params = op
+    if name == "thermal_relax":
+        return thermal_relax(rho, qubits[0], params[0], params[1], params[2], n)
     if name in G_CHANNELS:
         return dm_apply_kraus(rho, G.channel_kraus(name, params), qubits, n)
     return dm_apply_gate(rho, op, n)

@@ -91,6 +91,9 @@ def dm_kraus(rho: np.ndarray, kraus, qubits, n: int) -> np.ndarray:
 
 def dm_apply(rho: np.ndarray, op, n: int) -> np.ndarray:
     name, qubits, params = op
+    if name == "thermal_relax":
+        from . import dense
+        return dense.thermal_relax(rho, qubits[0], params[0], params[1], params[2], n)
     if name in G.CHANNELS:
         return dm_kraus(rho, G.channel_kraus(name, params), qubits, n)
     return dm_kraus(rho, [G.gate_matrix(name, qubits, params)], qubits, n)

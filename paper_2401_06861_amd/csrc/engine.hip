@@ -597,6 +597,22 @@ int nwq_depolarize_ex(nwq_handle h, const int* qubits, int k, double p, int conv
   return nwq_apply_channel(h, qubits, k, kr.data(), npl);
 }
 
+int nwq_thermal_relax(nwq_handle h, int q, double t1, double t2, double t) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (h->kind != NWQ_KIND_DM) return set_error(NWQ_EKIND, "thermal relaxation applies to density-matrix handles");
+  if (!(t1 > 0.0) || !(t2 > 0.0) || !(t >= 0.0) || !std::isfinite(t))
+    return set_error(NWQ_EINVAL, "thermal relaxation needs T1 > 0, T2 > 0, t >= 0");
+  if (t2 > 2.0 * t1 * (1.0 + 1e-12)) return set_error(NWQ_EINVAL, "thermal relaxation needs T2 <= 2 T1");
+  // Populations: amplitude damping with 1 - gamma = e^{-t/T1}.  Coherences:
+  // sqrt(1 - gamma) sqrt(1 - lambda) = e^{-t/T2}, so the remaining pure
+  // dephasing is 1 - lambda = e^{-t (2/T2 - 1/T1)}.
+  const double gamma = -std::expm1(-t / t1);
+  const double lambda = std::max(0.0, -std::expm1(-t * (2.0 / t2 - 1.0 / t1)));
+  int rc = nwq_amp_damp(h, q, gamma);
+  if (!rc) rc = nwq_phase_damp(h, q, lambda);
+  return rc;
+}
+
 int nwq_amp_damp(nwq_handle h, int q, double g) {
   if (!(g >= 0.0 && g <= 1.0)) return set_error(NWQ_EINVAL, "amplitude damping gamma outside [0, 1]");
   const double kr[16] = {1, 0, 0, 0, 0, 0, std::sqrt(1 - g), 0,

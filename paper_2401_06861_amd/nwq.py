@@ -70,6 +70,7 @@ _SIG = {
     "nwq_apply_channel": [_h, _ip, C.c_int, _dp, C.c_int],
     "nwq_depolarize": [_h, _ip, C.c_int, C.c_double],
     "nwq_depolarize_ex": [_h, _ip, C.c_int, C.c_double, C.c_int],
+    "nwq_thermal_relax": [_h, C.c_int, C.c_double, C.c_double, C.c_double],
     "nwq_amp_damp": [_h, C.c_int, C.c_double],
     "nwq_phase_damp": [_h, C.c_int, C.c_double],
     "nwq_expval_pauli_sum": [_h, C.c_int, _up, _up, _dp, _dp],
@@ -81,6 +82,8 @@ _SIG = {
     "nwq_get_launch": [_h, C.c_int, C.c_int, _ip, _ip],
     "nwq_autotune": [_h, C.c_int, _dp],
     "nwq_autotune_fusion": [_h, C.c_int, _ip, _ip, _dp, C.c_int, _ip, _ip, _dp],
+    "nwq_qasm_parse": [C.c_char_p, _ip, _ip, C.c_int, _ip, _ip, _dp],
+    "nwq_apply_qasm": [_h, C.c_char_p],
     "nwq_probabilities": [_h, C.c_void_p],
     "nwq_readout_noise": [C.c_int, C.c_void_p, _dp, C.c_void_p],
     "nwq_sample_workspace_bytes": [C.c_int],
@@ -257,6 +260,10 @@ def nwq_depolarize_ex(h: int, qubits: Sequence[int], p: float, convention: int) 
     _check(lib.nwq_depolarize_ex(h, _ints(qubits), len(qubits), p, convention))
 
 
+def nwq_thermal_relax(h: int, q: int, t1: float, t2: float, t: float) -> None:
+    _check(lib.nwq_thermal_relax(h, q, t1, t2, t))
+
+
 def nwq_amp_damp(h: int, q: int, gamma: float) -> None:
     _check(lib.nwq_amp_damp(h, q, gamma))
 
@@ -339,6 +346,24 @@ def nwq_autotune_fusion(h: int, types: np.ndarray, qubits: np.ndarray, params: n
         if ms[i] >= 0:
             table[(0, 0) if i == 0 else (6 + (i - 1) // 3, (i - 1) % 3)] = float(ms[i])
     return k.value, rb.value, table
+
+
+# ------------------------------------------------------------ OpenQASM 2.0
+def nwq_qasm_parse(text: str):
+    """(n_qubits, types, qubits[2*i], params[3*i]) of an OpenQASM 2.0 program."""
+    src = text.encode()
+    nq, ng = C.c_int(), C.c_int()
+    _check(lib.nwq_qasm_parse(src, C.byref(nq), C.byref(ng), 0, None, None, None))
+    types = np.zeros(ng.value, dtype=np.int32)
+    qs = np.zeros(2 * ng.value, dtype=np.int32)
+    ps = np.zeros(3 * ng.value, dtype=np.float64)
+    _check(lib.nwq_qasm_parse(src, C.byref(nq), C.byref(ng), ng.value, types.ctypes.data_as(_ip),
+                              qs.ctypes.data_as(_ip), ps.ctypes.data_as(_dp)))
+    return nq.value, types, qs, ps
+
+
+def nwq_apply_qasm(h: int, text: str) -> None:
+    _check(lib.nwq_apply_qasm(h, text.encode()))
 
 
 # ------------------------------------------------------------ measurement
@@ -432,6 +457,8 @@ class _State:
                 nwq_depolarize(self.h, q, p[0])
             elif name == "depolarize_nc" or name == "depolarize2_nc":
                 nwq_depolarize_ex(self.h, q, p[0], DEPOL_PAULI)
+            elif name == "thermal_relax":
+                nwq_thermal_relax(self.h, q[0], p[0], p[1], p[2])
             elif name == "amp_damp":
                 nwq_amp_damp(self.h, q[0], p[0])
             elif name == "phase_damp":

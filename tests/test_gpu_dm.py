@@ -182,6 +182,33 @@ def test_depolarizing_conventions(nwq):
     st.close()
 
 
+def test_thermal_relaxation_against_definition(nwq):
+    """The engine's amplitude + phase damping mapping of (T1, T2, t) against
+    the oracle's relaxation map written from its definition, fused after
+    gates, on several qubits and durations, including T2 = 2 T1."""
+    n = 4
+    rho0 = W.random_density_matrix(n, seed=91)
+    st = nwq.DMState(n, reset=False)
+    ops = [("thermal_relax", (0,), (50.0, 70.0, 3.0)), ("h", (2,), ()), ("thermal_relax", (2,), (30.0, 60.0, 9.0)),
+           ("cx", (2, 3), ()), ("thermal_relax", (3,), (80.0, 20.0, 25.0)), ("thermal_relax", (1,), (5.0, 4.0, 0.0))]
+    st.load(rho0)
+    st.run(ops)
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    assert maxerr(st.numpy(), want) <= TOL
+    for bad in ((10.0, 25.0, 1.0), (0.0, 1.0, 1.0), (10.0, 5.0, -1.0)):
+        with pytest.raises(nwq.NwqError) as e:
+            nwq.nwq_thermal_relax(st.h, 0, *bad)
+        assert e.value.code == nwq.NWQ_EINVAL
+    st.close()
+    sv = nwq.SVState(2)
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_thermal_relax(sv.h, 0, 10.0, 10.0, 1.0)
+    assert e.value.code == nwq.NWQ_EKIND
+    sv.close()
+
+
 def test_dm_errors(nwq):
     n = 3
     rho0 = W.random_density_matrix(n, seed=2)

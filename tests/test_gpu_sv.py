@@ -336,3 +336,26 @@ def test_fusion_autotuner(nwq):
         nwq.nwq_autotune_fusion(dm.h, *nwq.circuit_arrays([("h", (0,), ())]))
     assert e.value.code == nwq.NWQ_EKIND
     dm.close()
+
+
+@pytest.mark.parametrize("fuse", [0, 8])
+def test_apply_qasm_program(nwq, fuse):
+    """An OpenQASM 2.0 program through the library's front-end against the
+    oracle's reader and tensor simulator; with fusion the whole program goes
+    through the block planner."""
+    from oracle import qasm
+    n = 11
+    text = W.qasm_text(W.random_gate_list(n, 200, seed=31) + W.brickwork_circuit(n, 3, seed=2), n, split=4, seed=1)
+    st = nwq.SVState(n)
+    st.set_fusion(fuse)
+    nwq.nwq_apply_qasm(st.h, text)
+    nq, gates = qasm.parse(text)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    assert maxerr(st.numpy(), tensor.sv_run(gates, n, psi0)) <= TOL
+    if fuse:
+        assert nwq.nwq_fusion_stats(st.h)[0] > 0
+    with pytest.raises(nwq.NwqError) as e:
+        nwq.nwq_apply_qasm(st.h, "OPENQASM 2.0;\nqreg q[3];\nh q[0];\n")
+    assert e.value.code == nwq.NWQ_ERANGE
+    st.close()

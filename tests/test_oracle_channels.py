@@ -170,3 +170,42 @@ def test_pauli_error_convention():
             a = dense.dm_apply(rho, (name + "_nc", qs, (p,)), n)
             b = dense.dm_apply(rho, (name, qs, (p * scale,)), n)
             assert close(a, b, 1e-13)
+
+
+def choi(channel, n=1):
+    """Choi matrix sum_{ij} |i><j| (x) E(|i><j|) of a one-qubit map."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    for i in range(2):
+        for j in range(2):
+            E = np.zeros((2, 2), dtype=np.complex128)
+            E[i, j] = 1
+            out += np.kron(E, channel(E))
+    return out
+
+
+def test_thermal_relaxation_definition():
+    """Closed forms of the relaxation map: identity at t = 0, relaxation to
+    |0><0| for t >> T1, Bloch components z -> 1 - (1 - z) e^{-t/T1} and
+    x, y -> x e^{-t/T2}; trace preserving; completely positive exactly when
+    T2 <= 2 T1 (the Choi matrix turns indefinite beyond), which is the
+    physical range; on a qubit of a larger register it acts on that qubit
+    only."""
+    rho = from_bloch([0.3, -0.4, 0.5])
+    assert close(dense.thermal_relax(rho, 0, 50.0, 70.0, 0.0, 1), rho)
+    assert close(dense.thermal_relax(rho, 0, 1.0, 1.5, 200.0, 1), from_bloch([0, 0, 1]), 1e-12)
+    t1, t2, t = 40.0, 55.0, 7.0
+    out = bloch(dense.thermal_relax(rho, 0, t1, t2, t, 1))
+    e1, e2 = math.exp(-t / t1), math.exp(-t / t2)
+    assert close(out, [0.3 * e2, -0.4 * e2, 1 - (1 - 0.5) * e1])
+    ch = lambda E: dense.thermal_relax(E, 0, t1, t2, t, 1)
+    assert np.min(np.linalg.eigvalsh(choi(ch))) >= -1e-14
+    bad = lambda E: dense.thermal_relax(E, 0, 10.0, 30.0, 5.0, 1)      # T2 > 2 T1
+    assert np.min(np.linalg.eigvalsh(choi(bad))) < -1e-6
+    n = 3
+    rho3 = W.random_density_matrix(n, seed=8)
+    out3 = dense.thermal_relax(rho3, 1, t1, t2, t, n)
+    assert abs(np.trace(out3) - 1) <= 1e-14
+    # the partial trace over qubit 1 is unchanged (the map is local and trace preserving)
+    red_in = rho3.reshape(2, 2, 2, 2, 2, 2)
+    red_out = out3.reshape(2, 2, 2, 2, 2, 2)
+    assert close(np.einsum("ajbcjd->abcd", red_in), np.einsum("ajbcjd->abcd", red_out), 1e-14)

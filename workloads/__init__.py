@@ -41,6 +41,7 @@ GATE_ARITY = {
 CHANNEL_ARITY = {
     "depolarize": (1, 1), "amp_damp": (1, 1), "phase_damp": (1, 1),
     "depolarize2": (2, 1), "depolarize_nc": (1, 1), "depolarize2_nc": (2, 1),
+    "thermal_relax": (1, 3),   # (T1, T2, duration), T2 <= 2 T1
 }
 
 
@@ -158,6 +159,43 @@ def random_gate_list(n: int, count: int, seed: int) -> List[Gate]:
         ps = tuple(float(x) for x in rng.uniform(-math.pi, math.pi, size=npar))
         gates.append((name, qs, ps))
     return gates
+
+
+def qasm_text(gates: List[Gate], n: int, split: int = 0, seed: int = 0) -> str:
+    """An OpenQASM 2.0 program for a gate list on n qubits.  With split > 0
+    the qubits are declared as two registers a[split], b[n - split] (qubit q
+    is a[q] below split, b[q - split] above).  Angles are written as exact
+    decimal literals, some as multiples of pi, some with a unary minus or
+    parentheses, and comments, barriers and measurements are sprinkled in,
+    so a reader sees the syntax it has to accept."""
+    rng = np.random.default_rng(seed)
+    if split:
+        def ref(q):
+            return f"a[{q}]" if q < split else f"b[{q - split}]"
+        decl = [f"qreg a[{split}];", f"qreg b[{n - split}];", f"creg c[{n}];"]
+    else:
+        def ref(q):
+            return f"q[{q}]"
+        decl = [f"qreg q[{n}];", f"creg c[{n}];"]
+    lines = ["// generated", "OPENQASM 2.0;", 'include "qelib1.inc";'] + decl
+    for i, (name, qs, ps) in enumerate(gates):
+        args = []
+        for x in ps:
+            style = rng.integers(4)
+            if style == 0:
+                args.append(repr(float(x)))
+            elif style == 1:
+                args.append(f"({float(x)!r})")
+            elif style == 2:
+                args.append(f"{float(x) / math.pi!r}*pi")
+            else:
+                args.append(f"-({-float(x)!r})")
+        head = name + (f"({', '.join(args)})" if args else "")
+        lines.append(f"{head} {', '.join(ref(q) for q in qs)};")
+        if i % 7 == 3:
+            lines.append(f"barrier {ref(qs[0])};  // a barrier")
+    lines.append("measure " + ref(0) + " -> c[0];")
+    return "\n".join(lines) + "\n"
 
 
 # --------------------------------------------------------------------------
