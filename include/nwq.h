@@ -307,7 +307,7 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * classes 1, 2 and 3; class 7 takes only 1) and a non-temporal hint on the
  * loads and stores (0 or 1).  Each class keeps one shape per bucket of the
  * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
- * one 128-byte line), 1 for bits 3..11, 2 for bits 12 and up.
+ * one 128-byte line), 1 for bits 3..10, 2 for bits 11 and up.
  * nwq_set_launch with bucket -1 sets all three. */
 #define NWQ_LAUNCH_BUCKETS 3
 int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal);

@@ -33,9 +33,9 @@ def _load(path: str) -> dict:
 
 def tune(h: int, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, force: bool = False) -> dict:
     """Launch shapes for handle h: {class name: {bucket: [ppt, nontemporal, ms or None]}}
-    (buckets "low", "mid" and "high" of the lowest target bit: 0-2, 3-11, 12 and up)."""
+    (buckets "low", "mid" and "high" of the lowest target bit: 0-2, 3-10, 11 and up)."""
     kind, n, _ = nwq.nwq_info(h)
-    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|buckets3"
+    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|buckets3b"
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         for name, per_bucket in cache[key].items():

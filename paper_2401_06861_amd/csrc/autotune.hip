@@ -1,7 +1,7 @@
 // Launch-shape autotuner for the streaming gate kernels of a handle.
 //
-// For each kernel class and target bucket (lowest target bit 0-2, 3-11 or
-// 12 and up) it times every candidate (groups per thread in {1, 2, 4, 8},
+// For each kernel class and target bucket (lowest target bit 0-2, 3-10 or
+// 11 and up) it times every candidate (groups per thread in {1, 2, 4, 8},
 // and 16 for the 1q, diagonal and permutation kernels, x non-temporal hint
 // off/on) with HIP events on the handle's own stream and
 // state, and keeps the fastest.  Candidates apply self-inverse operations in
@@ -131,9 +131,9 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
   if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
   for (const Job& j : jobs) {
     for (int b = 0; b < kBuckets && !rc; ++b) {
-      // target bits of this bucket: {0, 1, 2}, {3, 7, 11}, {12, middle, top}
+      // target bits of this bucket: {0, 1, 2}, {3, 6, 10}, {11, middle, top}
       std::vector<int> qs;
-      const int cand_q[kBuckets][3] = {{0, 1, 2}, {3, 7, 11}, {12, (12 + j.lo_max) / 2, j.lo_max}};
+      const int cand_q[kBuckets][3] = {{0, 1, 2}, {3, 6, 10}, {11, (11 + j.lo_max) / 2, j.lo_max}};
       for (int q : cand_q[b])
         if (q >= 0 && q <= j.lo_max && bucket_of(q) == b && std::find(qs.begin(), qs.end(), q) == qs.end())
           qs.push_back(q);

@@ -38,10 +38,12 @@ struct LaunchCfg {
 // Launch shapes are kept in three buckets per class, by the lowest target
 // bit of the launch: below 3 the partner amplitudes of a group share one
 // 128-byte line (a non-temporal hint then costs a second fetch of the line);
-// from 3 to 11 the streams of a group are within 64 KiB of each other; from
-// 12 up they are far apart.  The best shape differs between them.
+// from 3 to 10 the streams of a group are within 16 KiB of each other; from
+// 11 up they are 32 KiB or more apart.  The best shape differs between them
+// (on MI355X at 30 qubits: 1 group per thread, 16 with the hint, 4 with the
+// hint for the 2x2 kernel).
 constexpr int kBuckets = 3;
-inline int bucket_of(int lowest_bit) { return lowest_bit < 3 ? 0 : (lowest_bit < 12 ? 1 : 2); }
+inline int bucket_of(int lowest_bit) { return lowest_bit < 3 ? 0 : (lowest_bit < 11 ? 1 : 2); }
 
 // Kernel classes (also the timing classes of nwq_timing_read).
 enum KClass {

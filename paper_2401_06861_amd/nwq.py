@@ -300,7 +300,7 @@ def nwq_purity(h: int) -> float:
     return out.value
 
 
-LAUNCH_BUCKETS = ("low", "mid", "high")   # lowest target bit 0-2, 3-11, 12 and up
+LAUNCH_BUCKETS = ("low", "mid", "high")   # lowest target bit 0-2, 3-10, 11 and up
 
 
 def nwq_set_launch(h: int, cls: int, bucket: int, ppt: int, nontemporal: int) -> None:

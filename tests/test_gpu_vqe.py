@@ -237,3 +237,30 @@ def test_fused_generic_program(V, torch):
             g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n)
             assert np.max(np.abs(G[b].cpu().numpy() - g_ps)) <= 1e-10
         ctx.close()
+
+
+@pytest.mark.parametrize("n,mode", [(10, 1), (13, 2), (13, 3)])
+def test_graph_replays_with_eager_work_between(V, torch, n, mode):
+    """The captured schedule replayed several times with new parameters,
+    with eager per-circuit evaluations between the replays: every replay
+    matches the eager result, and replaying the same parameters again gives
+    the same bits."""
+    L = 2
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=4 * 3)
+    ctx = V.VQE(n, prog, W.tfim_hamiltonian(n, 1.0, h))
+    ctx.set_config(mode, 256, 0)
+    t = torch.from_numpy(theta).cuda()
+    first = []
+    for r in range(3):
+        chunk = t[4 * r: 4 * r + 4]
+        E, G = ctx.eval(chunk)
+        first.append((E.clone(), G.clone()))
+        for b in range(4):
+            e1, g1 = ctx.eval_single(chunk[b])                      # eager work between replays
+            assert abs(e1.item() - E[b].item()) <= 1e-12
+            assert torch.max(torch.abs(g1[0] - G[b])).item() <= 1e-12
+    for r in range(3):
+        E, G = ctx.eval(t[4 * r: 4 * r + 4])
+        assert torch.equal(E, first[r][0]) and torch.equal(G, first[r][1])
+    ctx.close()
