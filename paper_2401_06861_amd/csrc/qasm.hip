@@ -68,6 +68,7 @@ class Parser {
   int line_ = 1;
   int nq_ = 0;
   int err_ = NWQ_EINVAL;
+  int depth_ = 0;         // nesting of parentheses, signs and powers in an expression
   struct Reg { int base, size; };
   std::map<std::string, Reg> qregs_;
   std::map<std::string, int> cregs_;
@@ -188,16 +189,34 @@ class Parser {
   }
   bool power(double& v) {
     if (!unary(v)) return false;
-    if (accept('^')) { double r; if (!power(r)) return false; v = std::pow(v, r); }
+    if (accept('^')) {
+      double r;
+      if (++depth_ > 64) return false;
+      const bool ok = power(r);
+      --depth_;
+      if (!ok) return false;
+      v = std::pow(v, r);
+    }
     return true;
   }
   bool unary(double& v) {
-    if (accept('-')) { if (!unary(v)) return false; v = -v; return true; }
-    if (accept('+')) return unary(v);
+    if (accept('-') || accept('+')) {
+      const bool neg = src_[i_ - 1] == '-';
+      if (++depth_ > 64) return false;
+      const bool ok = unary(v);
+      --depth_;
+      if (ok && neg) v = -v;
+      return ok;
+    }
     return primary(v);
   }
   bool primary(double& v) {
-    if (accept('(')) return expr(v) && expect(')');
+    if (accept('(')) {
+      if (++depth_ > 64) return false;   // bounded nesting
+      const bool ok = expr(v) && expect(')');
+      --depth_;
+      return ok;
+    }
     if (number(v)) return true;
     std::string id;
     if (!ident(id)) return false;
