@@ -15,7 +15,7 @@ through fused k-qubit LDS blocks, a per-target-qubit U3/CX sweep, the noisy
 density-matrix gate at n=14, and the oracle on the host CPU.
 
     python bench.py [--steps K] [--warmup W] [--n 30] [--depth 40]
-    python bench.py --profile-mode {trace,pmc}   (short runs for rocprofv3)
+    python bench.py --profile-mode {trace,pmc,fused,vqe}   (short runs for rocprofv3)
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-requests", type=int, default=600)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--profile-mode", choices=["trace", "pmc"], default=None)
+    ap.add_argument("--profile-mode", choices=["trace", "pmc", "fused", "vqe"], default=None)
     return ap.parse_args()
 
 
@@ -151,6 +151,34 @@ def main():
     psi = torch.empty(N, dtype=torch.complex128, device=dev)
     st = nwq.SVState(n, tensor=psi, stream=stream)
 
+    if args.profile_mode == "fused":
+        # the brickwork (depth 8) through fused blocks at k=12, 4 register bits, twice
+        nwq.nwq_set_fusion(st.h, 12)
+        nwq.nwq_set_fusion_kernel(st.h, 1)
+        short = nwq.circuit_arrays(W.brickwork_circuit(n, 8, seed=0))
+        for _ in range(2):
+            st.reset()
+            nwq.nwq_apply_circuit(st.h, *short)
+        torch.cuda.synchronize()
+        log(f"[bench] profile mode done: {nwq.nwq_fusion_stats(st.h)} blocks/gates per run")
+        print(json.dumps({"profile_mode": args.profile_mode, "n": n}))
+        return
+    if args.profile_mode == "vqe":
+        # fused-graph VQE energy + gradient: n=20, B=256 and n=24, B=1 (L=8), three evaluations each
+        from paper_2401_06861_amd import vqe as V
+        del st, psi
+        torch.cuda.empty_cache()
+        for nv, B in ((20, 256), (24, 1)):
+            theta, h = W.vqe_batch(nv, 8, B=B)
+            ctx = V.VQE(nv, W.hea_ansatz(nv, 8), W.tfim_hamiltonian(nv, 1.0, h))
+            t = torch.from_numpy(theta).cuda()
+            for _ in range(3):
+                ctx.eval(t)
+            torch.cuda.synchronize()
+            log(f"[bench] profile mode vqe n={nv} B={B} config {ctx.get_config()}")
+            ctx.close()
+        print(json.dumps({"profile_mode": args.profile_mode}))
+        return
     if args.profile_mode is not None:
         # short, fixed work for rocprofv3: a plain copy of known size (counter
         # calibration), the launch-shape autotuner, then U3 and CX launches at

@@ -540,19 +540,33 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__
   }
 }
 
-// One workgroup per state: the energy partials and each slot's gradient
-// partials are summed by one wave each (lanes stride over the partials, then
-// a fixed shuffle tree), slot sums go to ssum, and each parameter adds its
-// slots in slot order.  The order depends only on G, never on B.
+// Closing reductions in a fixed order that depends only on G: each slot's G
+// gradient partials are summed by one wave (lanes stride over the partials,
+// then a fixed shuffle tree) into ssum; then one workgroup per state sums
+// the energy partials the same way and each parameter adds its slots in slot
+// order.
 constexpr int kFinBlock = 256;
-__global__ __launch_bounds__(kFinBlock) void k_vqe_finish(const double* __restrict__ epart,
-                                                          const double* __restrict__ gpart, int G, int nslots,
+
+// Slot sums: workgroup (chunk, b) gives one slot to each wave.
+__global__ __launch_bounds__(kFinBlock) void k_vqe_slot_sums(const double* __restrict__ gpart, int G, int nslots,
+                                                             double* __restrict__ ssum) {
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int s = blockIdx.x * (kFinBlock / kWave) + threadIdx.x / kWave;
+  if (s >= nslots) return;
+  const double* gp = gpart + ((size_t)b * nslots + s) * G;
+  double v = 0.0;
+  for (int k = lane; k < G; k += kWave) v += gp[k];
+  v = wave_sum(v);
+  if (lane == 0) ssum[(size_t)b * nslots + s] = v;
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_vqe_finish(const double* __restrict__ epart, int G, int nslots,
                                                           const int* __restrict__ slot_param, int P,
-                                                          double* __restrict__ ssum, double* __restrict__ E,
+                                                          const double* __restrict__ ssum, double* __restrict__ E,
                                                           double* __restrict__ grad) {
   const int b = blockIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  constexpr int NW = kFinBlock / kWave;
   if (wave == 0) {
     double e = 0.0;
     for (int k = lane; k < G; k += kWave) e += epart[(size_t)b * G + k];
@@ -560,14 +574,6 @@ __global__ __launch_bounds__(kFinBlock) void k_vqe_finish(const double* __restri
     if (lane == 0) E[b] = e;
   }
   if (!grad) return;
-  for (int s = wave; s < nslots; s += NW) {
-    const double* gp = gpart + ((size_t)b * nslots + s) * G;
-    double v = 0.0;
-    for (int k = lane; k < G; k += kWave) v += gp[k];
-    v = wave_sum(v);
-    if (lane == 0) ssum[(size_t)b * nslots + s] = v;
-  }
-  __syncthreads();
   for (int p = threadIdx.x; p < P; p += kFinBlock) {
     double g = 0.0;
     for (int s = 0; s < nslots; ++s)
@@ -1166,7 +1172,10 @@ static int launch_global(nwq_vqe* h, int B, const double* theta, const double* c
       }
     }
   }
-  hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
+  if (grad != nullptr && h->nslots > 0)
+    hipLaunchKernelGGL(k_vqe_slot_sums, dim3((h->nslots + kFinBlock / kWave - 1) / (kFinBlock / kWave), B),
+                       dim3(kFinBlock), 0, s, h->d_gpart, G, h->nslots, h->d_ssum);
+  hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, G, h->nslots,
                      h->d_slot_param, h->P, h->d_ssum, E, grad);
   return check_hip(hipGetLastError(), "vqe per-gate schedule");
 }
@@ -1385,7 +1394,10 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
       }
     }
   }
-  hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, h->d_gpart, G, h->nslots,
+  if (grad != nullptr && h->nslots > 0)
+    hipLaunchKernelGGL(k_vqe_slot_sums, dim3((h->nslots + kFinBlock / kWave - 1) / (kFinBlock / kWave), B),
+                       dim3(kFinBlock), 0, s, h->d_gpart, G, h->nslots, h->d_ssum);
+  hipLaunchKernelGGL(k_vqe_finish, dim3(B), dim3(kFinBlock), 0, s, h->d_epart, G, h->nslots,
                      h->d_slot_param, h->P, h->d_ssum, E, grad);
   return check_hip(hipGetLastError(), "vqe fused schedule");
 }
