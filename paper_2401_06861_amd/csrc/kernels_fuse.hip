@@ -252,8 +252,9 @@ __device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[1 << R], co
           break;
       }
       break;
-    case 1: {   // 1q diagonal on register bit lo
-      const vd2 d0 = ldv(M), d1 = ldv(M + 1);
+    case 1:     // 1q diagonal on register bit lo: entries M[0], M[1]
+    case 6: {   // the same with the entries of a 2x2 table entry: M[0], M[3]
+      const vd2 d0 = ldv(M), d1 = ldv(M + (op.kind == 6 ? 3 : 1));
 #pragma unroll
       for (int j = 0; j < NV; ++j) v[j] = vmul(((j >> op.lo) & 1) ? d1 : d0, v[j]);
       break;

@@ -97,7 +97,8 @@ void launch_reduce_rows(hipStream_t s, const double* partials, int rows, int gri
 
 // ---- fused LDS blocks (kernels_fuse.hip) ----------------------------------
 struct FusedOp {            // one gate inside a fused block, tile-local bits
-  int kind;                 // 0: 1q dense, 1: 1q diag, 2: 2q dense, 3: 2q member swap, 4: 2q diag
+  int kind;                 // 0: 1q dense, 1: 1q diag, 2: 2q dense, 3: 2q member swap, 4: 2q diag,
+                            // 6: 1q diag read from a 2x2 entry (M[0], M[3]; register-blocked kernels only)
   int lo, hi;               // sorted tile-local bit positions (hi unused for 1q)
   int o0, o1;               // kind 2: local offsets of q0, q1; kind 3: offsets swapped; kind 4: local bits of q0, q1
   int mat;                  // start of its matrix in the block program's matrix table (double2 units)

@@ -806,21 +806,47 @@ __device__ __forceinline__ unsigned padl_b(unsigned l) { return l + (l >> 4); }
 // one padded tile of 2^k entries (one extra entry per 16)
 inline size_t bwd_rb_tile_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << k) / 16); }
 
-template <int NV, int B>
-__device__ __forceinline__ void bw_rot(vd2 (&p)[NV], vd2 (&l)[NV], const double2* __restrict__ M, int axis,
-                                       bool grad, double& g) {
+// Im(conj(a) b)
+__device__ __forceinline__ double imcb(vd2 a, vd2 b) { return a.x * b.y - a.y * b.x; }
+// Re(conj(a) b)
+__device__ __forceinline__ double recb(vd2 a, vd2 b) { return a.x * b.x + a.y * b.y; }
+
+// Rotation about axis AX (0 X, 1 Y, 2 Z; -1: fixed gate, no gradient) on
+// register bit B: the generator's term Im<l|P|p> of the pair (as in
+// pair_grad, one axis only), then the adjoint 2x2 on both vectors; RZ's
+// adjoint is diagonal (M[0], M[3]).
+template <int NV, int B, int AX>
+__device__ __forceinline__ void bw_rot(vd2 (&p)[NV], vd2 (&l)[NV], const double2* __restrict__ M, double& g) {
   const vd2 m0 = ld(M), m1 = ld(M + 1), m2 = ld(M + 2), m3 = ld(M + 3);
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     if (j & (1 << B)) continue;
     const int k = j | (1 << B);
-    if (grad) g += pair_grad(axis, p[j], p[k], l[j], l[k]);
     const vd2 p0 = p[j], p1 = p[k], l0 = l[j], l1 = l[k];
-    p[j] = cfma(m0, p0, cmul(m1, p1));
-    p[k] = cfma(m2, p0, cmul(m3, p1));
-    l[j] = cfma(m0, l0, cmul(m1, l1));
-    l[k] = cfma(m2, l0, cmul(m3, l1));
+    if constexpr (AX == 0) g += imcb(l0, p1) + imcb(l1, p0);
+    if constexpr (AX == 1) g += recb(l1, p0) - recb(l0, p1);
+    if constexpr (AX == 2) g += imcb(l0, p0) - imcb(l1, p1);
+    if constexpr (AX == 2) {
+      p[j] = cmul(m0, p0);
+      p[k] = cmul(m3, p1);
+      l[j] = cmul(m0, l0);
+      l[k] = cmul(m3, l1);
+    } else {
+      p[j] = cfma(m0, p0, cmul(m1, p1));
+      p[k] = cfma(m2, p0, cmul(m3, p1));
+      l[j] = cfma(m0, l0, cmul(m1, l1));
+      l[k] = cfma(m2, l0, cmul(m3, l1));
+    }
   }
+}
+
+template <int NV, int B>
+__device__ __forceinline__ void bw_rot_any(const VqeBwdRop& op, vd2 (&p)[NV], vd2 (&l)[NV],
+                                           const double2* __restrict__ M, double& g) {
+  if (op.kind == 2) bw_rot<NV, B, -1>(p, l, M, g);
+  else if (op.axis == 0) bw_rot<NV, B, 0>(p, l, M, g);
+  else if (op.axis == 1) bw_rot<NV, B, 1>(p, l, M, g);
+  else bw_rot<NV, B, 2>(p, l, M, g);
 }
 
 // Diagonal 2-qubit op on register bits B0 (u bit 0), B1 (u bit 1); with grad,
@@ -869,13 +895,12 @@ __device__ __forceinline__ void bw_apply(const VqeBwdRop& op, vd2 (&p)[1 << R], 
   constexpr int NV = 1 << R;
   const double2* M = table + op.mat;
   if (op.kind == 0 || op.kind == 2) {
-    const bool grad = op.kind == 0;
     switch (op.r0) {
-      case 0: bw_rot<NV, 0>(p, l, M, op.axis, grad, g); break;
-      case 1: bw_rot<NV, 1>(p, l, M, op.axis, grad, g); break;
-      case 2: bw_rot<NV, 2>(p, l, M, op.axis, grad, g); break;
+      case 0: bw_rot_any<NV, 0>(op, p, l, M, g); break;
+      case 1: bw_rot_any<NV, 1>(op, p, l, M, g); break;
+      case 2: bw_rot_any<NV, 2>(op, p, l, M, g); break;
       default:
-        if constexpr (R == 4) bw_rot<NV, 3>(p, l, M, op.axis, grad, g);
+        if constexpr (R == 4) bw_rot_any<NV, 3>(op, p, l, M, g);
         break;
     }
     return;
@@ -1233,7 +1258,9 @@ static int build_fused(nwq_vqe* h) {
         f.mat = 8 * gi;
         const int r0 = ridx(lb[gi][0]), r1 = nq[gi] == 2 ? ridx(lb[gi][1]) : 0;
         f.lo = r0;
-        if (op.kind == OP_ROT || op.kind == OP_FIX1) {
+        if (op.kind == OP_ROT && op.axis == 2) {
+          f.kind = 6;   // RZ: diagonal of its 2x2 table entry
+        } else if (op.kind == OP_ROT || op.kind == OP_FIX1) {
           f.kind = 0;
         } else if (op.kind == OP_RZZ || op.kind == OP_CZ) {
           f.kind = 4; f.o0 = r0; f.o1 = r1;
