@@ -186,69 +186,88 @@ __device__ __forceinline__ vd2 vfma(vd2 a, vd2 b, vd2 c) {
 }
 __device__ __forceinline__ unsigned padl(unsigned l) { return l + (l >> 4); }
 
+// Every gate helper reads the register set x and writes all of y; x and y may be
+// the same array.  With 4 register bits the op loop alternates two register
+// sets, so each gate's results land directly in the registers the next gate
+// reads (an in-place update ends every op with a copy of all 16 amplitudes
+// back into the loop-carried registers).  With 3 register bits the second set
+// would push the kernel past 128 VGPRs, so it updates in place.
+constexpr int kCopyOp = 7;   // kernel-internal: y = x (pads an odd gate count)
+
 template <int NV, int B>
-__device__ __forceinline__ void rb_dense1(vd2 (&v)[NV], const double2* __restrict__ M) {
+__device__ __forceinline__ void rb_dense1(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
   const vd2 m0 = ldv(M), m1 = ldv(M + 1), m2 = ldv(M + 2), m3 = ldv(M + 3);
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     if (j & (1 << B)) continue;
-    const vd2 a = v[j], b = v[j | (1 << B)];
-    v[j] = vfma(m0, a, vmul(m1, b));
-    v[j | (1 << B)] = vfma(m2, a, vmul(m3, b));
+    const vd2 a = x[j], b = x[j | (1 << B)];
+    y[j] = vfma(m0, a, vmul(m1, b));
+    y[j | (1 << B)] = vfma(m2, a, vmul(m3, b));
   }
 }
 
 // Dense 4x4 with operator index u = bit B0 + 2 bit B1.
 template <int NV, int B0, int B1>
-__device__ __forceinline__ void rb_dense2(vd2 (&v)[NV], const double2* __restrict__ M) {
+__device__ __forceinline__ void rb_dense2(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     if (j & ((1 << B0) | (1 << B1))) continue;
     const int idx[4] = {j, j | (1 << B0), j | (1 << B1), j | (1 << B0) | (1 << B1)};
-    vd2 x[4];
+    vd2 in[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = v[idx[u]];
+    for (int u = 0; u < 4; ++u) in[u] = x[idx[u]];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      vd2 acc = vmul(ldv(M + 4 * r), x[0]);
+      vd2 acc = vmul(ldv(M + 4 * r), in[0]);
 #pragma unroll
-      for (int c = 1; c < 4; ++c) acc = vfma(ldv(M + 4 * r + c), x[c], acc);
-      v[idx[r]] = acc;
+      for (int c = 1; c < 4; ++c) acc = vfma(ldv(M + 4 * r + c), in[c], acc);
+      y[idx[r]] = acc;
     }
   }
 }
 
 // Exchange of members (base | OA) and (base | OB) of each quad over bits B0, B1.
 template <int NV, int B0, int B1, int OA, int OB>
-__device__ __forceinline__ void rb_swap2(vd2 (&v)[NV]) {
+__device__ __forceinline__ void rb_swap2(const vd2 (&x)[NV], vd2 (&y)[NV]) {
+  constexpr int Q = (1 << B0) | (1 << B1);
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    if (j & ((1 << B0) | (1 << B1))) continue;
-    const vd2 t = v[j | OA];
-    v[j | OA] = v[j | OB];
-    v[j | OB] = t;
+    if (j & Q) continue;
+    const vd2 a = x[j | OA], b = x[j | OB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int m = ((u & 1) ? (1 << B0) : 0) | ((u & 2) ? (1 << B1) : 0);
+      if (m != OA && m != OB) y[j | m] = x[j | m];
+    }
+    y[j | OA] = b;
+    y[j | OB] = a;
   }
 }
 
 template <int NV, int B0, int B1>
-__device__ __forceinline__ void rb_pair_ops(int kind, vd2 (&v)[NV], const double2* M) {
-  if (kind == 2) rb_dense2<NV, B0, B1>(v, M);
-  else if (kind == 3) rb_swap2<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(v);   // CX: control B0, target B1
-  else rb_swap2<NV, B0, B1, (1 << B0), (1 << B1)>(v);                               // SWAP
+__device__ __forceinline__ void rb_pair_ops(int kind, const vd2 (&x)[NV], vd2 (&y)[NV], const double2* M) {
+  if (kind == 2) rb_dense2<NV, B0, B1>(x, y, M);
+  else if (kind == 3) rb_swap2<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(x, y);   // CX: control B0, target B1
+  else rb_swap2<NV, B0, B1, (1 << B0), (1 << B1)>(x, y);                               // SWAP
 }
 
 template <int R>
-__device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[1 << R], const double2* __restrict__ mats) {
+__device__ __forceinline__ void rb_apply(const FusedOp& op, const vd2 (&x)[1 << R], vd2 (&y)[1 << R],
+                                         const double2* __restrict__ mats) {
   constexpr int NV = 1 << R;
   const double2* M = mats + op.mat;
   switch (op.kind) {
+    case kCopyOp:
+#pragma unroll
+      for (int j = 0; j < NV; ++j) y[j] = x[j];
+      break;
     case 0:
       switch (op.lo) {
-        case 0: rb_dense1<NV, 0>(v, M); break;
-        case 1: rb_dense1<NV, 1>(v, M); break;
-        case 2: rb_dense1<NV, 2>(v, M); break;
+        case 0: rb_dense1<NV, 0>(x, y, M); break;
+        case 1: rb_dense1<NV, 1>(x, y, M); break;
+        case 2: rb_dense1<NV, 2>(x, y, M); break;
         default:
-          if constexpr (R == 4) rb_dense1<NV, 3>(v, M);
+          if constexpr (R == 4) rb_dense1<NV, 3>(x, y, M);
           break;
       }
       break;
@@ -256,7 +275,7 @@ __device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[1 << R], co
     case 6: {   // the same with the entries of a 2x2 table entry: M[0], M[3]
       const vd2 d0 = ldv(M), d1 = ldv(M + (op.kind == 6 ? 3 : 1));
 #pragma unroll
-      for (int j = 0; j < NV; ++j) v[j] = vmul(((j >> op.lo) & 1) ? d1 : d0, v[j]);
+      for (int j = 0; j < NV; ++j) y[j] = vmul(((j >> op.lo) & 1) ? d1 : d0, x[j]);
       break;
     }
     case 4: {   // 2q diagonal on register bits o0 (u bit 0), o1 (u bit 1)
@@ -264,38 +283,50 @@ __device__ __forceinline__ void rb_apply(const FusedOp& op, vd2 (&v)[1 << R], co
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
         const bool a = (j >> op.o0) & 1, b = (j >> op.o1) & 1;
-        v[j] = vmul(b ? (a ? d3 : d2) : (a ? d1 : d0), v[j]);
+        y[j] = vmul(b ? (a ? d3 : d2) : (a ? d1 : d0), x[j]);
       }
       break;
     }
     default: {  // 2 dense 4x4, 3 CX, 5 SWAP: register bits (o0, o1) in operator order
       if constexpr (R == 4) {
         switch (op.o0 * 4 + op.o1) {
-          case 1: rb_pair_ops<NV, 0, 1>(op.kind, v, M); break;
-          case 2: rb_pair_ops<NV, 0, 2>(op.kind, v, M); break;
-          case 3: rb_pair_ops<NV, 0, 3>(op.kind, v, M); break;
-          case 4: rb_pair_ops<NV, 1, 0>(op.kind, v, M); break;
-          case 6: rb_pair_ops<NV, 1, 2>(op.kind, v, M); break;
-          case 7: rb_pair_ops<NV, 1, 3>(op.kind, v, M); break;
-          case 8: rb_pair_ops<NV, 2, 0>(op.kind, v, M); break;
-          case 9: rb_pair_ops<NV, 2, 1>(op.kind, v, M); break;
-          case 11: rb_pair_ops<NV, 2, 3>(op.kind, v, M); break;
-          case 12: rb_pair_ops<NV, 3, 0>(op.kind, v, M); break;
-          case 13: rb_pair_ops<NV, 3, 1>(op.kind, v, M); break;
-          default: rb_pair_ops<NV, 3, 2>(op.kind, v, M); break;   // 14
+          case 1: rb_pair_ops<NV, 0, 1>(op.kind, x, y, M); break;
+          case 2: rb_pair_ops<NV, 0, 2>(op.kind, x, y, M); break;
+          case 3: rb_pair_ops<NV, 0, 3>(op.kind, x, y, M); break;
+          case 4: rb_pair_ops<NV, 1, 0>(op.kind, x, y, M); break;
+          case 6: rb_pair_ops<NV, 1, 2>(op.kind, x, y, M); break;
+          case 7: rb_pair_ops<NV, 1, 3>(op.kind, x, y, M); break;
+          case 8: rb_pair_ops<NV, 2, 0>(op.kind, x, y, M); break;
+          case 9: rb_pair_ops<NV, 2, 1>(op.kind, x, y, M); break;
+          case 11: rb_pair_ops<NV, 2, 3>(op.kind, x, y, M); break;
+          case 12: rb_pair_ops<NV, 3, 0>(op.kind, x, y, M); break;
+          case 13: rb_pair_ops<NV, 3, 1>(op.kind, x, y, M); break;
+          default: rb_pair_ops<NV, 3, 2>(op.kind, x, y, M); break;   // 14
         }
       } else {
         switch (op.o0 * 4 + op.o1) {
-          case 1: rb_pair_ops<NV, 0, 1>(op.kind, v, M); break;
-          case 2: rb_pair_ops<NV, 0, 2>(op.kind, v, M); break;
-          case 4: rb_pair_ops<NV, 1, 0>(op.kind, v, M); break;
-          case 6: rb_pair_ops<NV, 1, 2>(op.kind, v, M); break;
-          case 8: rb_pair_ops<NV, 2, 0>(op.kind, v, M); break;
-          default: rb_pair_ops<NV, 2, 1>(op.kind, v, M); break;   // 9
+          case 1: rb_pair_ops<NV, 0, 1>(op.kind, x, y, M); break;
+          case 2: rb_pair_ops<NV, 0, 2>(op.kind, x, y, M); break;
+          case 4: rb_pair_ops<NV, 1, 0>(op.kind, x, y, M); break;
+          case 6: rb_pair_ops<NV, 1, 2>(op.kind, x, y, M); break;
+          case 8: rb_pair_ops<NV, 2, 0>(op.kind, x, y, M); break;
+          default: rb_pair_ops<NV, 2, 1>(op.kind, x, y, M); break;   // 9
         }
       }
       break;
     }
+  }
+}
+
+// Writes the 2^R registers of a phase back to their LDS entries.
+template <int R>
+__device__ __forceinline__ void rb_store_phase(double2* __restrict__ tl, const FusedPhase& ph, const vd2 (&v)[1 << R]) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    unsigned off = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
+    stv(tl + padl(off), v[j]);
   }
 }
 
@@ -354,14 +385,21 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
         for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
         v[j] = ldv(tl + padl(off));
       }
-      for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(ops[ph.op_begin + oi], v, mats);
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        unsigned off = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
-        stv(tl + padl(off), v[j]);
+      const FusedOp* __restrict__ po = ops + ph.op_begin;
+      if constexpr (R == 4) {
+        // two gates per trip, v -> w -> v; an odd count ends with a copy
+        vd2 w[NV];
+        for (int oi = 0; oi < ph.op_count; oi += 2) {
+          rb_apply<R>(po[oi], v, w, mats);
+          FusedOp o2{};
+          o2.kind = kCopyOp;
+          if (oi + 1 < ph.op_count) o2 = po[oi + 1];
+          rb_apply<R>(o2, w, v, mats);
+        }
+      } else {
+        for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(po[oi], v, v, mats);
       }
+      rb_store_phase<R>(tl, ph, v);
     }
     __syncthreads();
     {
