@@ -99,6 +99,111 @@ __global__ __launch_bounds__(kBlock) void k_sv_1q(double2* __restrict__ a, unsig
   }
 }
 
+// ---------------------------------------------------------------------------
+// Lane-exchange kernels for gates whose partner amplitudes sit in the same
+// 128-byte line (target bits below 3).  Pair-per-thread addressing there has
+// each load instruction touch every line of its span twice (the two members
+// of a pair in separate instructions) and runs at about 5.5 TB/s; here every
+// load and store is one fully coalesced 1 KiB access per wave (lane l holds
+// entry 64 m + l) and the pair partner comes from lane l ^ X through DPP row
+// permutations (X = 1, 2, 4, 8) or ds_bpermute (other X).  Valid when the
+// length is a multiple of 64 and the gate's bits are lane bits (below 6).
+// ---------------------------------------------------------------------------
+template <int X>
+__device__ __forceinline__ int lane_xor32(int v) {
+  // DPP controls: quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E, [3,2,1,0] = 0x1B;
+  // row_half_mirror (lane ^ 7 within 8) = 0x141; row_mirror (lane ^ 15 within 16) = 0x140
+  if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+  else if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+  else if constexpr (X == 4)   // (l ^ 7) ^ 3
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF, 0xF, true);
+  else   // X == 8: (l ^ 15) ^ 7
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true), 0x141, 0xF, 0xF, true);
+}
+template <int X>
+__device__ __forceinline__ double lane_xor(double d, int src_byte) {
+  const long long b = __double_as_longlong(d);
+  int lo = (int)(unsigned)(b & 0xffffffffll), hi = (int)(b >> 32);
+  if constexpr (X == 0) {   // run-time pattern: src_byte = 4 * (l ^ X)
+    lo = __builtin_amdgcn_ds_bpermute(src_byte, lo);
+    hi = __builtin_amdgcn_ds_bpermute(src_byte, hi);
+  } else {
+    lo = lane_xor32<X>(lo);
+    hi = lane_xor32<X>(hi);
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+template <int X>
+__device__ __forceinline__ vd2 lane_xor_v(vd2 v, int src_byte) {
+  return mk(lane_xor<X>(v.x, src_byte), lane_xor<X>(v.y, src_byte));
+}
+
+// 1-qubit dense gate on target T < 3: the lane holding member b of its pair
+// (b = bit T of its index) writes M[b][b] own + M[b][1-b] partner.
+template <int T, int EPT, bool NTM>
+__global__ __launch_bounds__(kBlock) void k_sv_1q_lane(double2* __restrict__ a, unsigned long long u0,
+                                                       unsigned long long len, Mat2 m) {
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+  const bool up = (threadIdx.x >> T) & 1;
+  const vd2 cs = up ? tov(m.m[3]) : tov(m.m[0]), cp = up ? tov(m.m[2]) : tov(m.m[1]);
+  if (start + (unsigned long long)(EPT - 1) * kBlock < len) {
+    vd2 v[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) v[j] = gld<NTM>(a + start + (unsigned long long)j * kBlock);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+      gst<NTM>(a + start + (unsigned long long)j * kBlock, cfma(cs, v[j], cmul(cp, lane_xor_v<(1 << T)>(v[j], 0))));
+  } else {
+    // len is a multiple of 64: a wave is either wholly inside or wholly past the end
+    for (int j = 0; j < EPT; ++j) {
+      const unsigned long long i = start + (unsigned long long)j * kBlock;
+      if (i >= len) break;
+      const vd2 v = gld<NTM>(a + i);
+      gst<NTM>(a + i, cfma(cs, v, cmul(cp, lane_xor_v<(1 << T)>(v, 0))));
+    }
+  }
+}
+
+// Permutation of lane-bit members (X, CX and SWAP with both bits below 6 and
+// the lower below 3): lane l with (l & Q) in {oa, ob} takes lane l ^ X
+// (X = oa ^ ob), the others keep their entry.  MASKED: only moving lanes
+// store; used when the moved runs are at least 4 entries (64 bytes) long,
+// since shorter partial-line writes cost more than writing the lines whole.
+template <int X, int EPT, bool NTM, bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_sv_perm_lane(double2* __restrict__ a, unsigned long long u0,
+                                                         unsigned long long len, int xr, int Q, int oa, int ob) {
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+  const int l = threadIdx.x & 63;
+  const bool mv = (l & Q) == oa || (l & Q) == ob;
+  const int src = (l ^ xr) << 2;
+  if (start + (unsigned long long)(EPT - 1) * kBlock < len) {
+    vd2 v[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) v[j] = gld<NTM>(a + start + (unsigned long long)j * kBlock);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const vd2 p = lane_xor_v<X>(v[j], src);
+      if constexpr (MASKED) {
+        if (mv) gst<NTM>(a + start + (unsigned long long)j * kBlock, p);
+      } else {
+        gst<NTM>(a + start + (unsigned long long)j * kBlock, mv ? p : v[j]);
+      }
+    }
+  } else {
+    for (int j = 0; j < EPT; ++j) {
+      const unsigned long long i = start + (unsigned long long)j * kBlock;
+      if (i >= len) break;
+      const vd2 v = gld<NTM>(a + i);
+      const vd2 p = lane_xor_v<X>(v, src);
+      if constexpr (MASKED) {
+        if (mv) gst<NTM>(a + i, p);
+      } else {
+        gst<NTM>(a + i, mv ? p : v);
+      }
+    }
+  }
+}
+
 // Diagonal gate on one or two qubits: a_i <- d[u(i)] a_i, u = bit q0 + 2 bit q1
 // (q1 < 0: one qubit).  Entries are chosen with selects, not an indexed load.
 template <int EPT, bool NTM>
@@ -313,7 +418,85 @@ void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len) {
   if (cfg.ppt == 16) NWQ_LAUNCH_NT(KERNEL, 16, units, __VA_ARGS__);      \
   else NWQ_PPT_SWITCH(KERNEL, units, __VA_ARGS__)
 
+// Lane-exchange launches: units are entries; the entries per thread (1, 2 or
+// 4) come from the tuned groups per thread (8 and 16 map to 4).
+namespace {
+inline int lane_ept(const LaunchCfg& cfg) { return cfg.ppt >= 4 ? 4 : (cfg.ppt == 2 ? 2 : 1); }
+
+template <int T, int E>
+void launch_1q_lane_e(hipStream_t s, double2* a, unsigned long long len, const Mat2& m, bool nt) {
+  const unsigned long long per = kMaxItems * E;
+  for (unsigned long long u0 = 0; u0 < len; u0 += per) {
+    const unsigned long long cnt = len - u0 < per ? len - u0 : per;
+    const dim3 grid(grid_for(cnt, kBlock * E));
+    if (nt) hipLaunchKernelGGL((k_sv_1q_lane<T, E, true>), grid, dim3(kBlock), 0, s, a, u0, len, m);
+    else hipLaunchKernelGGL((k_sv_1q_lane<T, E, false>), grid, dim3(kBlock), 0, s, a, u0, len, m);
+  }
+}
+template <int T>
+void launch_1q_lane_t(hipStream_t s, double2* a, unsigned long long len, const Mat2& m, const LaunchCfg& cfg) {
+  switch (lane_ept(cfg)) {
+    case 1: launch_1q_lane_e<T, 1>(s, a, len, m, cfg.nt); break;
+    case 2: launch_1q_lane_e<T, 2>(s, a, len, m, cfg.nt); break;
+    default: launch_1q_lane_e<T, 4>(s, a, len, m, cfg.nt); break;
+  }
+}
+
+template <int X, int E, bool MASKED>
+void launch_perm_lane_e(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob, bool nt) {
+  const unsigned long long per = kMaxItems * E;
+  for (unsigned long long u0 = 0; u0 < len; u0 += per) {
+    const unsigned long long cnt = len - u0 < per ? len - u0 : per;
+    const dim3 grid(grid_for(cnt, kBlock * E));
+    if (nt) hipLaunchKernelGGL((k_sv_perm_lane<X, E, true, MASKED>), grid, dim3(kBlock), 0, s, a, u0, len, xr, Q, oa, ob);
+    else hipLaunchKernelGGL((k_sv_perm_lane<X, E, false, MASKED>), grid, dim3(kBlock), 0, s, a, u0, len, xr, Q, oa, ob);
+  }
+}
+template <int X, bool MASKED>
+void launch_perm_lane_x(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob,
+                        const LaunchCfg& cfg) {
+  switch (lane_ept(cfg)) {
+    case 1: launch_perm_lane_e<X, 1, MASKED>(s, a, len, xr, Q, oa, ob, cfg.nt); break;
+    case 2: launch_perm_lane_e<X, 2, MASKED>(s, a, len, xr, Q, oa, ob, cfg.nt); break;
+    default: launch_perm_lane_e<X, 4, MASKED>(s, a, len, xr, Q, oa, ob, cfg.nt); break;
+  }
+}
+// lane l with (l & Q) in {oa, ob} takes lane l ^ (oa ^ ob); every bit involved is below 6
+template <bool MASKED>
+void launch_perm_lane_m(hipStream_t s, double2* a, unsigned long long len, int Q, int oa, int ob, const LaunchCfg& cfg) {
+  const int x = oa ^ ob;
+  switch (x) {
+    case 1: launch_perm_lane_x<1, MASKED>(s, a, len, x, Q, oa, ob, cfg); break;
+    case 2: launch_perm_lane_x<2, MASKED>(s, a, len, x, Q, oa, ob, cfg); break;
+    case 4: launch_perm_lane_x<4, MASKED>(s, a, len, x, Q, oa, ob, cfg); break;
+    case 8: launch_perm_lane_x<8, MASKED>(s, a, len, x, Q, oa, ob, cfg); break;
+    default: launch_perm_lane_x<0, MASKED>(s, a, len, x, Q, oa, ob, cfg); break;
+  }
+}
+void launch_perm_lane(hipStream_t s, double2* a, unsigned long long len, int Q, int oa, int ob, const LaunchCfg& cfg) {
+  // moving lanes come in runs of 2^b, b the lowest lane bit that changes whether a lane moves
+  int b = 6;
+  for (int l = 0; l < 64; ++l)
+    for (int t = 0; t < b; ++t) {
+      const int k = l ^ (1 << t);
+      const bool ml = (l & Q) == oa || (l & Q) == ob, mk = (k & Q) == oa || (k & Q) == ob;
+      if (ml != mk) b = t;
+    }
+  if (b >= 2) launch_perm_lane_m<true>(s, a, len, Q, oa, ob, cfg);
+  else launch_perm_lane_m<false>(s, a, len, Q, oa, ob, cfg);
+}
+// the lane kernels need whole 256-entry blocks (lane bits = index bits 0..5)
+constexpr int kLaneMinBits = 8;
+}  // namespace
+
 void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, const LaunchCfg& cfg) {
+  if (q < 3 && nbits >= kLaneMinBits) {
+    const unsigned long long len = 1ull << nbits;
+    if (q == 0) launch_1q_lane_t<0>(s, a, len, m, cfg);
+    else if (q == 1) launch_1q_lane_t<1>(s, a, len, m, cfg);
+    else launch_1q_lane_t<2>(s, a, len, m, cfg);
+    return;
+  }
   const unsigned long long np = 1ull << (nbits - 1);
   NWQ_PPT_SWITCH16(k_sv_1q, np, s, a, np, q, m);
 }
@@ -324,14 +507,22 @@ void launch_sv_diag(hipStream_t s, double2* a, int nbits, int q0, int q1, const 
 }
 
 void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, const LaunchCfg& cfg) {
+  if (q < 3 && nbits >= kLaneMinBits) {   // every lane takes lane ^ 2^q
+    launch_perm_lane(s, a, 1ull << nbits, 1 << q, 0, 1 << q, cfg);
+    return;
+  }
   const unsigned long long np = 1ull << (nbits - 1);
   NWQ_PPT_SWITCH16(k_sv_swap1, np, s, a, np, q);
 }
 
 void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb, unsigned long long offA,
                      unsigned long long offB, const LaunchCfg& cfg) {
-  const unsigned long long nq = 1ull << (nbits - 2);
   const int lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+  if (lo < 3 && hi < 6 && nbits >= kLaneMinBits) {
+    launch_perm_lane(s, a, 1ull << nbits, (1 << qa) | (1 << qb), (int)offA, (int)offB, cfg);
+    return;
+  }
+  const unsigned long long nq = 1ull << (nbits - 2);
   NWQ_PPT_SWITCH16(k_sv_swap2, nq, s, a, nq, lo, hi, offA, offB);
 }
 

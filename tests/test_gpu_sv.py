@@ -226,6 +226,34 @@ def test_every_launch_shape_matches_oracle(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n", [8, 10])
+def test_lane_exchange_kernels(nwq, n):
+    """Gates whose bits are all lane bits (below 6, the lower below 3) run with
+    lane exchanges: dense 1q and X on targets 0..2, CX and SWAP on every
+    ordered pair of bits 0..5 with a bit below 3 (DPP partners at distance
+    1, 2, 4, 8 and ds_bpermute otherwise; whole-line and masked stores), under
+    every entries-per-thread and hint choice."""
+    psi0 = W.random_state(n, seed=90 + n)
+    st = nwq.SVState(n, reset=False)
+    ops = [("u3", (q,), (0.3 + q, 1.1, -0.7)) for q in range(3)] + [("x", (q,), ()) for q in range(3)]
+    for a, b in itertools.permutations(range(6), 2):
+        if min(a, b) < 3:
+            ops.append(("cx", (a, b), ()))
+            ops.append(("swap", (a, b), ()))
+    for ppt in (1, 2, 4, 16):
+        for nt in (0, 1):
+            nwq.nwq_set_launch(st.h, 1, -1, ppt, nt)
+            nwq.nwq_set_launch(st.h, 3, -1, ppt, nt)
+            st.load(psi0)
+            state = psi0
+            for op in ops:
+                st.apply(*op)
+                state = tensor.sv_apply(state, op, n)
+                err = maxerr(st.numpy(), state)
+                assert err <= TOL, (op, ppt, nt, err)
+    st.close()
+
+
 def test_launch_shape_buckets(nwq):
     """Different shapes in the three target buckets are kept apart and give
     the oracle's result on a circuit touching all of them."""
