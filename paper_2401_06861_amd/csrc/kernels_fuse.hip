@@ -349,7 +349,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
   const unsigned long long glane = tile_index(0ull, tid, cmask, c, m, blk);   // thread part of entry indices
-  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  auto tile_ptr = [&](unsigned long long tile) {
     unsigned long long base = tile << c;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -358,14 +358,29 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
         base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
       }
     }
-    double2* __restrict__ at = a + (base + glane);
+    return a + (base + glane);
+  };
+  // The tile has exactly NV entries per thread.  They are loaded one tile
+  // ahead: the loads of the next tile are in flight while this one runs its
+  // phases (tiles are disjoint, so the early read is safe).
+  vd2 pf[NV];
+  if (blockIdx.x < ntiles) {
+    double2* __restrict__ a0p = tile_ptr(blockIdx.x);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) pf[j] = ldv(a0p + blk.joff[j]);
+  }
+  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    double2* __restrict__ at = tile_ptr(tile);
     __syncthreads();
     {
-      vd2 r[NV];   // the tile has exactly NV entries per thread: issue all loads, then write LDS
 #pragma unroll
-      for (int j = 0; j < NV; ++j) r[j] = ldv(at + blk.joff[j]);
+      for (int j = 0; j < NV; ++j) stv(t + padl(tid + j * nt), pf[j]);
+      const unsigned long long nx = tile + gridDim.x;
+      if (nx < ntiles) {
+        double2* __restrict__ an = tile_ptr(nx);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) stv(t + padl(tid + j * nt), r[j]);
+        for (int j = 0; j < NV; ++j) pf[j] = ldv(an + blk.joff[j]);
+      }
     }
     for (int pi = 0; pi < blk.op_count; ++pi) {
       const FusedPhase ph = phases[blk.op_begin + pi];
@@ -420,7 +435,10 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
                      const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid) {
   const int k = blk.c + blk.m;
   const unsigned long long ntiles = 1ull << (nbits - k);
-  const unsigned long long cap = max_grid > 0 ? (unsigned long long)max_grid : (1ull << 20);
+  // about four tiles per workgroup (so that the next tile's loads overlap
+  // this one's phases), at least 2048 workgroups
+  const unsigned long long cap = max_grid > 0 ? (unsigned long long)max_grid
+                                              : (ntiles / 4 > 2048 ? ntiles / 4 : 2048);
   const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
   const size_t lds = fused_rb_lds_bytes(k);
   const unsigned long long stride = batch > 1 ? (1ull << nbits) : 0ull;
