@@ -232,8 +232,10 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
       };
       for (int gi : ph.gates) {
         FusedOp op;
-        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true))
+        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true)) {
+          op.code = rb_op_code(op);
           ops.push_back(op);
+        }
       }
       fp.op_count = (int)ops.size() - fp.op_begin;
       phases.push_back(fp);

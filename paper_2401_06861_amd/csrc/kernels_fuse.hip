@@ -192,8 +192,6 @@ __device__ __forceinline__ unsigned padl(unsigned l) { return l + (l >> 4); }
 // reads (an in-place update ends every op with a copy of all 16 amplitudes
 // back into the loop-carried registers).  With 3 register bits the second set
 // would push the kernel past 128 VGPRs, so it updates in place.
-constexpr int kCopyOp = 7;   // kernel-internal: y = x (pads an odd gate count)
-
 template <int NV, int B>
 __device__ __forceinline__ void rb_dense1(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
   const vd2 m0 = ldv(M), m1 = ldv(M + 1), m2 = ldv(M + 2), m3 = ldv(M + 3);
@@ -244,78 +242,81 @@ __device__ __forceinline__ void rb_swap2(const vd2 (&x)[NV], vd2 (&y)[NV]) {
   }
 }
 
-template <int NV, int B0, int B1>
-__device__ __forceinline__ void rb_pair_ops(int kind, const vd2 (&x)[NV], vd2 (&y)[NV], const double2* M) {
-  if (kind == 2) rb_dense2<NV, B0, B1>(x, y, M);
-  else if (kind == 3) rb_swap2<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(x, y);   // CX: control B0, target B1
-  else rb_swap2<NV, B0, B1, (1 << B0), (1 << B1)>(x, y);                               // SWAP
+// 1q diagonal on register bit B: entries d0 (bit 0), d1 (bit 1).
+template <int NV, int B>
+__device__ __forceinline__ void rb_diag1(const vd2 (&x)[NV], vd2 (&y)[NV], vd2 d0, vd2 d1) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) y[j] = vmul(((j >> B) & 1) ? d1 : d0, x[j]);
 }
 
-template <int R>
-__device__ __forceinline__ void rb_apply(const FusedOp& op, const vd2 (&x)[1 << R], vd2 (&y)[1 << R],
-                                         const double2* __restrict__ mats) {
+// 2q diagonal on register bits B0 (u bit 0), B1 (u bit 1): entries M[u].
+template <int NV, int B0, int B1>
+__device__ __forceinline__ void rb_diag2(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
+  const vd2 d[4] = {ldv(M), ldv(M + 1), ldv(M + 2), ldv(M + 3)};
+#pragma unroll
+  for (int j = 0; j < NV; ++j) y[j] = vmul(d[((j >> B0) & 1) + 2 * ((j >> B1) & 1)], x[j]);
+}
+
+// The case bodies of rb_apply; bit positions at or above R never occur for
+// that R (the guard keeps their templates from being instantiated).
+template <int R, int B>
+__device__ __forceinline__ void rb_c1(int sel, const vd2 (&x)[1 << R], vd2 (&y)[1 << R], const double2* M) {
+  if constexpr (B < R) {
+    if (sel == 0) rb_dense1<(1 << R), B>(x, y, M);
+    else rb_diag1<(1 << R), B>(x, y, ldv(M), ldv(M + (sel == 1 ? 1 : 3)));
+  }
+}
+template <int R, int B0, int B1>
+__device__ __forceinline__ void rb_c2(int sel, const vd2 (&x)[1 << R], vd2 (&y)[1 << R], const double2* M) {
   constexpr int NV = 1 << R;
-  const double2* M = mats + op.mat;
-  switch (op.kind) {
-    case kCopyOp:
+  if constexpr (B0 < R && B1 < R) {
+    if (sel == 0) rb_dense2<NV, B0, B1>(x, y, M);
+    else if (sel == 1) rb_swap2<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(x, y);   // CX: control B0, target B1
+    else if (sel == 2) rb_swap2<NV, B0, B1, (1 << B0), (1 << B1)>(x, y);                 // SWAP
+    else rb_diag2<NV, B0, B1>(x, y, M);
+  }
+}
+
+// One gate: a single switch over the op's code (rb_op_code); every case is
+// specialised on its register bits, so diagonals select their entries at
+// compile time.
+template <int R>
+__device__ __forceinline__ void rb_apply(int code, const double2* __restrict__ M, const vd2 (&x)[1 << R],
+                                         vd2 (&y)[1 << R]) {
+  constexpr int NV = 1 << R;
+#define NWQ_RB1(BASE, SEL) \
+  case BASE + 0: rb_c1<R, 0>(SEL, x, y, M); break; \
+  case BASE + 1: rb_c1<R, 1>(SEL, x, y, M); break; \
+  case BASE + 2: rb_c1<R, 2>(SEL, x, y, M); break; \
+  case BASE + 3: rb_c1<R, 3>(SEL, x, y, M); break;
+#define NWQ_RB2(BASE, SEL) \
+  case BASE + 1: rb_c2<R, 0, 1>(SEL, x, y, M); break; \
+  case BASE + 2: rb_c2<R, 0, 2>(SEL, x, y, M); break; \
+  case BASE + 3: rb_c2<R, 0, 3>(SEL, x, y, M); break; \
+  case BASE + 4: rb_c2<R, 1, 0>(SEL, x, y, M); break; \
+  case BASE + 6: rb_c2<R, 1, 2>(SEL, x, y, M); break; \
+  case BASE + 7: rb_c2<R, 1, 3>(SEL, x, y, M); break; \
+  case BASE + 8: rb_c2<R, 2, 0>(SEL, x, y, M); break; \
+  case BASE + 9: rb_c2<R, 2, 1>(SEL, x, y, M); break; \
+  case BASE + 11: rb_c2<R, 2, 3>(SEL, x, y, M); break; \
+  case BASE + 12: rb_c2<R, 3, 0>(SEL, x, y, M); break; \
+  case BASE + 13: rb_c2<R, 3, 1>(SEL, x, y, M); break; \
+  case BASE + 14: rb_c2<R, 3, 2>(SEL, x, y, M); break;
+  switch (code) {
+    NWQ_RB1(0, 0)
+    NWQ_RB1(4, 1)
+    NWQ_RB1(8, 2)
+    NWQ_RB2(16, 0)
+    NWQ_RB2(32, 1)
+    NWQ_RB2(48, 2)
+    NWQ_RB2(64, 3)
+    default:   // kRbCodeCopy
 #pragma unroll
       for (int j = 0; j < NV; ++j) y[j] = x[j];
       break;
-    case 0:
-      switch (op.lo) {
-        case 0: rb_dense1<NV, 0>(x, y, M); break;
-        case 1: rb_dense1<NV, 1>(x, y, M); break;
-        case 2: rb_dense1<NV, 2>(x, y, M); break;
-        default:
-          if constexpr (R == 4) rb_dense1<NV, 3>(x, y, M);
-          break;
-      }
-      break;
-    case 1:     // 1q diagonal on register bit lo: entries M[0], M[1]
-    case 6: {   // the same with the entries of a 2x2 table entry: M[0], M[3]
-      const vd2 d0 = ldv(M), d1 = ldv(M + (op.kind == 6 ? 3 : 1));
-#pragma unroll
-      for (int j = 0; j < NV; ++j) y[j] = vmul(((j >> op.lo) & 1) ? d1 : d0, x[j]);
-      break;
-    }
-    case 4: {   // 2q diagonal on register bits o0 (u bit 0), o1 (u bit 1)
-      const vd2 d0 = ldv(M), d1 = ldv(M + 1), d2 = ldv(M + 2), d3 = ldv(M + 3);
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const bool a = (j >> op.o0) & 1, b = (j >> op.o1) & 1;
-        y[j] = vmul(b ? (a ? d3 : d2) : (a ? d1 : d0), x[j]);
-      }
-      break;
-    }
-    default: {  // 2 dense 4x4, 3 CX, 5 SWAP: register bits (o0, o1) in operator order
-      if constexpr (R == 4) {
-        switch (op.o0 * 4 + op.o1) {
-          case 1: rb_pair_ops<NV, 0, 1>(op.kind, x, y, M); break;
-          case 2: rb_pair_ops<NV, 0, 2>(op.kind, x, y, M); break;
-          case 3: rb_pair_ops<NV, 0, 3>(op.kind, x, y, M); break;
-          case 4: rb_pair_ops<NV, 1, 0>(op.kind, x, y, M); break;
-          case 6: rb_pair_ops<NV, 1, 2>(op.kind, x, y, M); break;
-          case 7: rb_pair_ops<NV, 1, 3>(op.kind, x, y, M); break;
-          case 8: rb_pair_ops<NV, 2, 0>(op.kind, x, y, M); break;
-          case 9: rb_pair_ops<NV, 2, 1>(op.kind, x, y, M); break;
-          case 11: rb_pair_ops<NV, 2, 3>(op.kind, x, y, M); break;
-          case 12: rb_pair_ops<NV, 3, 0>(op.kind, x, y, M); break;
-          case 13: rb_pair_ops<NV, 3, 1>(op.kind, x, y, M); break;
-          default: rb_pair_ops<NV, 3, 2>(op.kind, x, y, M); break;   // 14
-        }
-      } else {
-        switch (op.o0 * 4 + op.o1) {
-          case 1: rb_pair_ops<NV, 0, 1>(op.kind, x, y, M); break;
-          case 2: rb_pair_ops<NV, 0, 2>(op.kind, x, y, M); break;
-          case 4: rb_pair_ops<NV, 1, 0>(op.kind, x, y, M); break;
-          case 6: rb_pair_ops<NV, 1, 2>(op.kind, x, y, M); break;
-          case 8: rb_pair_ops<NV, 2, 0>(op.kind, x, y, M); break;
-          default: rb_pair_ops<NV, 2, 1>(op.kind, x, y, M); break;   // 9
-        }
-      }
-      break;
-    }
   }
+#undef NWQ_RB1
+#undef NWQ_RB2
 }
 
 // Writes the 2^R registers of a phase back to their LDS entries.
@@ -405,14 +406,16 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
         // two gates per trip, v -> w -> v; an odd count ends with a copy
         vd2 w[NV];
         for (int oi = 0; oi < ph.op_count; oi += 2) {
-          rb_apply<R>(po[oi], v, w, mats);
-          FusedOp o2{};
-          o2.kind = kCopyOp;
-          if (oi + 1 < ph.op_count) o2 = po[oi + 1];
-          rb_apply<R>(o2, w, v, mats);
+          rb_apply<R>(po[oi].code, mats + po[oi].mat, v, w);
+          int c2 = kRbCodeCopy, m2 = 0;
+          if (oi + 1 < ph.op_count) {
+            c2 = po[oi + 1].code;
+            m2 = po[oi + 1].mat;
+          }
+          rb_apply<R>(c2, mats + m2, w, v);
         }
       } else {
-        for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(po[oi], v, v, mats);
+        for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(po[oi].code, mats + po[oi].mat, v, v);
       }
       rb_store_phase<R>(tl, ph, v);
     }

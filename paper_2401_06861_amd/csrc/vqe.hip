@@ -1269,6 +1269,7 @@ static int build_fused(nwq_vqe* h) {
         } else {
           f.kind = 5; f.o0 = r0; f.o1 = r1;
         }
+        f.code = rb_op_code(f);
         fops.push_back(f);
       }
       fp.op_count = (int)fops.size() - fp.op_begin;
