@@ -79,6 +79,7 @@ struct Phase {
   std::vector<int> gates;
 };
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
+void fold_phase_permutations(std::vector<FusedOp>& ops, int rbits, int* ld_perm, int* st_perm);
 int local_bit(const Block& b, int q);
 void pad_block(Block& b, int n, int k_target);
 void fill_entry_offsets(FusedBlockDev& d, int rbits);

@@ -323,12 +323,7 @@ __device__ __forceinline__ void rb_apply(int code, const double2* __restrict__ M
 template <int R>
 __device__ __forceinline__ void rb_store_phase(double2* __restrict__ tl, const FusedPhase& ph, const vd2 (&v)[1 << R]) {
 #pragma unroll
-  for (int j = 0; j < (1 << R); ++j) {
-    unsigned off = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
-    stv(tl + padl(off), v[j]);
-  }
+  for (int j = 0; j < (1 << R); ++j) stv(tl + ph.st_off[j], v[j]);
 }
 
 template <int R>
@@ -395,12 +390,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
       __syncthreads();
       vd2 v[NV];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        unsigned off = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
-        v[j] = ldv(tl + padl(off));
-      }
+      for (int j = 0; j < NV; ++j) v[j] = ldv(tl + ph.ld_off[j]);
       const FusedOp* __restrict__ po = ops + ph.op_begin;
       if constexpr (R == 4) {
         // two gates per trip, v -> w -> v; an odd count ends with a copy

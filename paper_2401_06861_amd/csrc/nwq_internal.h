@@ -140,7 +140,26 @@ struct FusedPhase {
   int reg[4];
   int op_begin, op_count;
   int pad0, pad1;
+  // Register-blocked SV kernel: the padded LDS offset (over the phase's
+  // register bits) that register j is loaded from and stored to.  Permutation
+  // gates at the start or the end of a phase are folded into these.
+  unsigned short ld_off[16], st_off[16];
 };
+// ld_perm[j] / st_perm[j]: register-bit index whose entry register j loads /
+// stores (nullptr: identity); offsets padded by one entry per 16.
+inline void fill_phase_offsets(FusedPhase& fp, int rbits, const int* ld_perm, const int* st_perm) {
+  auto off = [&](int p) {
+    unsigned o = 0;
+    for (int r = 0; r < rbits; ++r)
+      if ((p >> r) & 1) o |= 1u << fp.reg[r];
+    return (unsigned short)(o + (o >> 4));
+  };
+  for (int j = 0; j < 16; ++j) {
+    const bool in = j < (1 << rbits);
+    fp.ld_off[j] = in ? off(ld_perm ? ld_perm[j] : j) : 0;
+    fp.st_off[j] = in ? off(st_perm ? st_perm[j] : j) : 0;
+  }
+}
 size_t fused_rb_lds_bytes(int k);
 // batch > 1: blockIdx.y = batch element b works on a + b * 2^nbits with the
 // matrix table mats + b * mat_stride; max_grid caps the tiles' grid (0 = 2^20).

@@ -1273,6 +1273,7 @@ static int build_fused(nwq_vqe* h) {
         fops.push_back(f);
       }
       fp.op_count = (int)fops.size() - fp.op_begin;
+      fill_phase_offsets(fp, h->fused_rbits, nullptr, nullptr);
       phases.push_back(fp);
     }
     d.op_count = (int)phases.size() - d.op_begin;
