@@ -437,6 +437,27 @@ def dm_leg(nwq, torch):
         c, ms = nwq.nwq_timing_read(st.h, reset=True)[cls]
         avg = ms / max(c, 1)
         out[label] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
+    # per-qubit sweep: each noisy gate on low, middle and high qubits (row and column bits q, q+n)
+    sweep = {}
+    for label, qs_list, cls in (("1q", [(0,), (1,), (2,), (7,), (n - 1,)], "dm_superop_1q"),
+                                ("2q", [(0, 1), (2, 3), (6, 7), (n - 2, n - 1)], "dm_superop_2q")):
+        for qs in qs_list:
+            ops = ([("u3", qs, (0.3, 0.2, 0.1)), ("depolarize", qs, (1e-3,)), ("amp_damp", qs, (1e-3,)),
+                    ("phase_damp", qs, (2e-3,))] if label == "1q"
+                   else [("rzz", qs, (0.2,)), ("depolarize2", qs, (1e-2,))])
+            st.run(ops)
+            st.flush()
+            torch.cuda.synchronize()
+            nwq.nwq_timing_read(st.h, reset=True)
+            nwq.nwq_timing_enable(st.h, True)
+            for _ in range(3):
+                st.run(ops)
+                st.flush()
+            nwq.nwq_timing_enable(st.h, False)
+            c, ms = nwq.nwq_timing_read(st.h, reset=True)[cls]
+            avg = ms / max(c, 1)
+            sweep[f"{label}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
+    out["sweep"] = sweep
     out["launch_shapes"] = {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
                             for k, per in tuned.items()}
     st.close()

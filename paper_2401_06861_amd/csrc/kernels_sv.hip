@@ -204,6 +204,62 @@ __global__ __launch_bounds__(kBlock) void k_sv_perm_lane(double2* __restrict__ a
   }
 }
 
+// Dense 4x4 with one bit L < 3 (a lane bit) and the other H >= 6 (DM
+// superoperator of a 1q gate on a low qubit: bits q and q + n).  A lane holds
+// the two entries of its index with bit H = 0 and 1 (two coalesced streams);
+// the other two members of each quad sit in lane l ^ 2^L.  Member u of a quad
+// has bit0(u) on q0 and bit1(u) on q1 (operator order); LOW_IS_Q0 says which
+// of them is L.  Each lane writes its own two entries, rows u(bl, h), from
+// eight coefficients chosen once per thread by its bit bl.
+template <int L, bool LOW_IS_Q0, int EPT, bool NTM>
+__global__ __launch_bounds__(kBlock) void k_sv_2q_lane(double2* __restrict__ a, unsigned long long u0,
+                                                       unsigned long long nhalf, int H, Mat4 m) {
+  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+  const unsigned long long off = 1ull << H;
+  const int bl = (threadIdx.x >> L) & 1;
+  auto u = [&](int b, int h) { return LOW_IS_Q0 ? (b + 2 * h) : (h + 2 * b); };
+  // c[h][h2][0]: coefficient of own entry h2, c[h][h2][1]: of the partner's entry h2, for output h
+  vd2 c[2][2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      c[h][h2][0] = bl ? tov(m.m[4 * u(1, h) + u(1, h2)]) : tov(m.m[4 * u(0, h) + u(0, h2)]);
+      c[h][h2][1] = bl ? tov(m.m[4 * u(1, h) + u(0, h2)]) : tov(m.m[4 * u(0, h) + u(1, h2)]);
+    }
+  auto out = [&](int h, vd2 e0, vd2 e1, vd2 p0, vd2 p1) {
+    return cfma(c[h][0][0], e0, cfma(c[h][1][0], e1, cfma(c[h][0][1], p0, cmul(c[h][1][1], p1))));
+  };
+  if (start + (unsigned long long)(EPT - 1) * kBlock < nhalf) {
+    vd2 e0[EPT], e1[EPT];
+    unsigned long long i0[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      i0[j] = insert0(start + (unsigned long long)j * kBlock, H);
+      e0[j] = gld<NTM>(a + i0[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) e1[j] = gld<NTM>(a + i0[j] + off);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const vd2 p0 = lane_xor_v<(1 << L)>(e0[j], 0), p1 = lane_xor_v<(1 << L)>(e1[j], 0);
+      gst<NTM>(a + i0[j], out(0, e0[j], e1[j], p0, p1));
+      gst<NTM>(a + i0[j] + off, out(1, e0[j], e1[j], p0, p1));
+    }
+  } else {
+    // nhalf is a multiple of 64: a wave is either wholly inside or wholly past the end
+    for (int j = 0; j < EPT; ++j) {
+      const unsigned long long p = start + (unsigned long long)j * kBlock;
+      if (p >= nhalf) break;
+      const unsigned long long i = insert0(p, H);
+      const vd2 e0 = gld<NTM>(a + i), e1 = gld<NTM>(a + i + off);
+      const vd2 p0 = lane_xor_v<(1 << L)>(e0, 0), p1 = lane_xor_v<(1 << L)>(e1, 0);
+      gst<NTM>(a + i, out(0, e0, e1, p0, p1));
+      gst<NTM>(a + i + off, out(1, e0, e1, p0, p1));
+    }
+  }
+}
+
 // Diagonal gate on one or two qubits: a_i <- d[u(i)] a_i, u = bit q0 + 2 bit q1
 // (q1 < 0: one qubit).  Entries are chosen with selects, not an indexed load.
 template <int EPT, bool NTM>
@@ -526,9 +582,43 @@ void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb, unsig
   NWQ_PPT_SWITCH16(k_sv_swap2, nq, s, a, nq, lo, hi, offA, offB);
 }
 
+namespace {
+template <int L, bool LQ0, int E>
+void launch_2q_lane_e(hipStream_t s, double2* a, unsigned long long nhalf, int H, const Mat4& m, bool nt) {
+  const unsigned long long per = kMaxItems * E;
+  for (unsigned long long u0 = 0; u0 < nhalf; u0 += per) {
+    const unsigned long long cnt = nhalf - u0 < per ? nhalf - u0 : per;
+    const dim3 grid(grid_for(cnt, kBlock * E));
+    if (nt) hipLaunchKernelGGL((k_sv_2q_lane<L, LQ0, E, true>), grid, dim3(kBlock), 0, s, a, u0, nhalf, H, m);
+    else hipLaunchKernelGGL((k_sv_2q_lane<L, LQ0, E, false>), grid, dim3(kBlock), 0, s, a, u0, nhalf, H, m);
+  }
+}
+template <int L, bool LQ0>
+void launch_2q_lane_l(hipStream_t s, double2* a, unsigned long long nhalf, int H, const Mat4& m, const LaunchCfg& cfg) {
+  switch (lane_ept(cfg)) {
+    case 1: launch_2q_lane_e<L, LQ0, 1>(s, a, nhalf, H, m, cfg.nt); break;
+    case 2: launch_2q_lane_e<L, LQ0, 2>(s, a, nhalf, H, m, cfg.nt); break;
+    default: launch_2q_lane_e<L, LQ0, 4>(s, a, nhalf, H, m, cfg.nt); break;
+  }
+}
+template <bool LQ0>
+void launch_2q_lane(hipStream_t s, double2* a, unsigned long long nhalf, int L, int H, const Mat4& m,
+                    const LaunchCfg& cfg) {
+  if (L == 0) launch_2q_lane_l<0, LQ0>(s, a, nhalf, H, m, cfg);
+  else if (L == 1) launch_2q_lane_l<1, LQ0>(s, a, nhalf, H, m, cfg);
+  else launch_2q_lane_l<2, LQ0>(s, a, nhalf, H, m, cfg);
+}
+}  // namespace
+
 void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, const LaunchCfg& cfg) {
   const unsigned long long nq = 1ull << (nbits - 2);
   const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+  if (lo < 3 && hi >= 6 && nbits >= kLaneMinBits) {   // lane bit lo, stream bit hi
+    const unsigned long long nhalf = 1ull << (nbits - 1);
+    if (q0 == lo) launch_2q_lane<true>(s, a, nhalf, lo, hi, m, cfg);
+    else launch_2q_lane<false>(s, a, nhalf, lo, hi, m, cfg);
+    return;
+  }
   NWQ_PPT_SWITCH(k_sv_2q, nq, s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m);
 }
 

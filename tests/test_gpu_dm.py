@@ -161,6 +161,30 @@ def test_superop_launch_shapes(nwq, nt):
     st.close()
 
 
+@pytest.mark.parametrize("n", [6, 7])
+def test_low_qubit_superoperators_every_shape(nwq, n):
+    """Noisy 1q gates on qubits 0..2 (4x4 superoperator on bits q and q + n:
+    the lane-exchange kernel) and a noisy 2q gate, under every groups-per-
+    thread and hint choice of the 1q superoperator class."""
+    rho0 = W.random_density_matrix(n, seed=60 + n)
+    st = nwq.DMState(n, reset=False)
+    ops = []
+    for q in range(3):
+        ops += [("u3", (q,), (0.3 + q, 1.2, -0.4)), ("depolarize", (q,), (0.05,)), ("amp_damp", (q,), (0.1,)),
+                ("phase_damp", (q,), (0.07,))]
+    ops += [("rzz", (0, 1), (0.7,)), ("depolarize2", (0, 1), (0.02,))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    for ppt in (1, 2, 4, 8):
+        for nt in (0, 1):
+            nwq.nwq_set_launch(st.h, 6, -1, ppt, nt)
+            st.load(rho0)
+            st.run(ops)
+            assert maxerr(st.numpy(), want) <= TOL, (ppt, nt)
+    st.close()
+
+
 def test_depolarizing_conventions(nwq):
     """Both depolarising conventions on one and two qubits against the
     oracle's Kraus sets, alone and fused after a gate."""

@@ -254,6 +254,29 @@ def test_lane_exchange_kernels(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n", [8, 11])
+def test_lane_exchange_dense_4x4(nwq, n):
+    """Dense 4x4 operators with one bit below 3 and the other at or above 6
+    (the lane-exchange 4x4 kernel, either bit first in operator order), under
+    every entries-per-thread and hint choice."""
+    rng = np.random.default_rng(300 + n)
+    psi0 = W.random_state(n, seed=80 + n)
+    st = nwq.SVState(n, reset=False)
+    pairs = [(lo, hi) for lo in range(3) for hi in (6, n - 1)] + [(hi, lo) for lo in range(3) for hi in (6, n - 1)]
+    mats = [rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)) for _ in pairs]
+    for ppt in (1, 2, 4, 8):
+        for nt in (0, 1):
+            nwq.nwq_set_launch(st.h, 4, -1, ppt, nt)
+            st.load(psi0)
+            state = psi0
+            for qs, m in zip(pairs, mats):
+                st.apply_matrix(list(qs), m)
+                state = tensor.apply_op(state, m, list(qs), n)
+                err = maxerr(st.numpy(), state) / max(1.0, float(np.max(np.abs(state))))
+                assert err <= TOL, (qs, ppt, nt, err)
+    st.close()
+
+
 def test_launch_shape_buckets(nwq):
     """Different shapes in the three target buckets are kept apart and give
     the oracle's result on a circuit touching all of them."""
