@@ -427,6 +427,64 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsig
   }
 }
 
+// 16 x 16 operator whose two lower bits s0 < s1 lie inside a 256-entry run
+// (s0 < 3, s1 < 8) and whose two upper bits s2 < s3 (>= 8) select runs: the
+// noisy two-qubit DM superoperator on low qubits.  One-group-per-thread
+// addressing there reads 16- to 64-byte pieces of every line in separate
+// instructions (4.3 TB/s at qubits (0, 1)).  Here a workgroup stages 16 whole
+// runs (4 run quads x the 4 combinations of s2, s3; 64 KiB) through LDS with
+// coalesced 4 KiB loads and stores; each thread then applies the operator to
+// one group read from LDS.  LDS entry e is stored at e ^ (((e >> swa) ^
+// (e >> swb)) & 7) (swb = 0: no second term), an XOR swizzle within aligned
+// 8-entry groups picked per (s0, s1) so that every 8 lanes of a group read hit
+// distinct 16-byte bank groups.
+struct KqStaged {
+  int h0, h1;           // s2 - 8, s3 - 8
+  int s0, s1;           // the lower bits
+  int swa, swb;         // swizzle shifts
+  int idx_off[16];      // member u (operator order): 256 * (run bits of u) + (bits of u at s0, s1)
+};
+__device__ __forceinline__ unsigned kq_swz(unsigned e, int a, int b) {
+  return e ^ (((e >> a) ^ (b ? (e >> b) : 0u)) & 7u);
+}
+template <bool NTM>
+__global__ __launch_bounds__(kBlock) void k_sv_kq4_staged(double2* __restrict__ a, KqStaged ks,
+                                                          const double2* __restrict__ M) {
+  __shared__ vd2 t[16 * 256];
+  const unsigned tid = threadIdx.x;
+  // run of staged slab i = 4 rq + hc: run quad 4 blockIdx + rq, combination hc of (s2, s3)
+  auto run_of = [&](int i) {
+    unsigned long long q = (unsigned long long)blockIdx.x * 4 + (unsigned)(i >> 2);
+    q = insert0(insert0(q, ks.h0), ks.h1);
+    return q | ((unsigned long long)(i & 1) << ks.h0) | ((unsigned long long)((i >> 1) & 1) << ks.h1);
+  };
+  {
+    vd2 r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r[i] = gld<NTM>(a + (run_of(i) << 8) + tid);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[kq_swz((unsigned)i * 256u + tid, ks.swa, ks.swb)] = r[i];
+  }
+  __syncthreads();
+  {
+    const unsigned rq = tid >> 6, lam = tid & 63u;
+    const unsigned base = rq * 1024u + (unsigned)insert0(insert0(lam, ks.s0), ks.s1);
+    vd2 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = t[kq_swz(base + (unsigned)ks.idx_off[u], ks.swa, ks.swb)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      vd2 acc = cmul(tov(M[r * 16]), v[0]);
+#pragma unroll
+      for (int c = 1; c < 16; ++c) acc = cfma(tov(M[r * 16 + c]), v[c], acc);
+      t[kq_swz(base + (unsigned)ks.idx_off[r], ks.swa, ks.swb)] = acc;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) gst<NTM>(a + (run_of(i) << 8) + tid, t[kq_swz((unsigned)i * 256u + tid, ks.swa, ks.swb)]);
+}
+
 inline unsigned grid_for(unsigned long long units, int per_block) {
   return (unsigned)((units + per_block - 1) / per_block);
 }
@@ -622,6 +680,38 @@ void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Ma
   NWQ_PPT_SWITCH(k_sv_2q, nq, s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m);
 }
 
+namespace {
+// Swizzle shifts (a in 1..7, b in 0..7, b = 0: none) under which the reads of
+// every 8 consecutive lanes of the staged 16 x 16 kernel hit distinct 16-byte
+// slots of a 128-byte LDS row (checked for each member pattern of the lower
+// bits); the first conflict-free pair is taken, else the one with the fewest
+// conflicts.
+void kq_pick_swizzle(KqStaged& ks) {
+  auto ins = [](unsigned p, int q) { return ((p >> q) << (q + 1)) | (p & ((1u << q) - 1u)); };
+  int best = 1 << 30;
+  for (int sa = 1; sa < 8; ++sa)
+    for (int sb = 0; sb < 8; ++sb) {
+      int cost = 0;
+      for (unsigned g0 = 0; g0 < 64; g0 += 8)
+        for (unsigned low = 0; low < 4; ++low) {
+          int cnt[8] = {0};
+          for (unsigned l = g0; l < g0 + 8; ++l) {
+            const unsigned e = ins(ins(l, ks.s0), ks.s1) | ((low & 1u) << ks.s0) | ((low >> 1) << ks.s1);
+            const unsigned f = e ^ (((e >> sa) ^ (sb ? (e >> sb) : 0u)) & 7u);
+            ++cnt[f & 7u];
+          }
+          for (int x = 0; x < 8; ++x) cost += cnt[x] > 1 ? cnt[x] - 1 : 0;
+        }
+      if (cost < best) {
+        best = cost;
+        ks.swa = sa;
+        ks.swb = sb;
+      }
+      if (best == 0) return;
+    }
+}
+}  // namespace
+
 void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits, const double2* dev_matrix,
                   const LaunchCfg& cfg) {
   QSet qs{};
@@ -638,6 +728,27 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     }
   for (int j = 0; j < k; ++j) qs.sorted[j] = sorted[j];
   const unsigned long long ng = 1ull << (nbits - k);
+  if (k == 4 && sorted[0] < 3 && sorted[1] < 8 && sorted[2] >= 8 && nbits >= 12) {
+    KqStaged ks{};
+    ks.h0 = sorted[2] - 8;
+    ks.h1 = sorted[3] - 8;
+    ks.s0 = sorted[0];
+    ks.s1 = sorted[1];
+    for (int u = 0; u < 16; ++u) {
+      int o = 0;
+      for (int j = 0; j < 4; ++j) {
+        if (!((u >> j) & 1)) continue;
+        if (qubits[j] < 8) o |= 1 << qubits[j];
+        else o |= (qubits[j] == sorted[2] ? 1 : 2) << 8;
+      }
+      ks.idx_off[u] = o;
+    }
+    kq_pick_swizzle(ks);
+    const dim3 grid((unsigned)(1ull << (nbits - 12)));   // 16 runs of 256 entries per workgroup
+    if (cfg.nt) hipLaunchKernelGGL(k_sv_kq4_staged<true>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    else hipLaunchKernelGGL(k_sv_kq4_staged<false>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    return;
+  }
   // one group per thread (16 loads in flight at k = 4); only the hint is tunable
   const dim3 grid(grid_for(ng, kBlock));
   if (k == 3) {

@@ -185,6 +185,28 @@ def test_low_qubit_superoperators_every_shape(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n", [8, 9])
+def test_staged_two_qubit_superoperators(nwq, n):
+    """Noisy 2q gates whose superoperator has its two lower bits inside a
+    256-entry run and the lowest below 3 (qubit pairs with both qubits below
+    8, lowest below 3: the LDS-staged 16 x 16 kernel), in both operator
+    orders and with each hint, plus one pair outside that case."""
+    rho0 = W.random_density_matrix(n, seed=70 + n)
+    st = nwq.DMState(n, reset=False)
+    ops = []
+    for a, b in [(0, 1), (1, 0), (1, 2), (2, 5), (0, 7), (6, 2), (3, 4), (0, n - 1)]:
+        ops += [("rzz", (a, b), (0.7,)), ("cx", (a, b), ()), ("depolarize2", (a, b), (0.02,))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    for nt in (0, 1):
+        nwq.nwq_set_launch(st.h, 7, -1, 1, nt)
+        st.load(rho0)
+        st.run(ops)
+        assert maxerr(st.numpy(), want) <= TOL, nt
+    st.close()
+
+
 def test_depolarizing_conventions(nwq):
     """Both depolarising conventions on one and two qubits against the
     oracle's Kraus sets, alone and fused after a gate."""
