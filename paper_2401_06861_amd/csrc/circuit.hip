@@ -165,62 +165,6 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
   return out;
 }
 
-// Register-bit mask of a register-blocked op, and whether it only permutes
-// registers (CX, SWAP).
-static unsigned rb_op_bits(const FusedOp& op) {
-  return (op.kind == 0 || op.kind == 1 || op.kind == 6) ? (1u << op.lo) : ((1u << op.o0) | (1u << op.o1));
-}
-static bool rb_op_perm(const FusedOp& op) { return op.kind == 3 || op.kind == 5; }
-// Index map of a permutation op on register indices: the entry at j moves to
-// P(j).  CX (control o0, target o1) flips o1 where o0 is set; SWAP exchanges
-// bits o0 and o1.  Both are involutions.
-static int rb_perm_apply(const FusedOp& op, int j) {
-  const int a = (j >> op.o0) & 1, b = (j >> op.o1) & 1;
-  if (op.kind == 3) return j ^ (a << op.o1);
-  return a == b ? j : j ^ ((1 << op.o0) | (1 << op.o1));
-}
-
-// Fold the permutation gates that can open or close a phase into its LDS
-// offsets instead of moving registers.  A permutation moves past a following
-// (preceding) non-permutation gate on other register bits, since the two
-// commute.  The trailing run T_1..T_m then means that register j holds the
-// entry of index T_m(...T_1(j)), so it is stored there; the leading run
-// L_1..L_l means that register j must hold the entry the data had at
-// (L_l...L_1)^-1 (j) = L_1(...L_l(j)), so it is loaded from there.  The
-// remaining ops keep their order.
-void fold_phase_permutations(std::vector<FusedOp>& ops, int rbits, int* ld_perm, int* st_perm) {
-  const int nv = 1 << rbits;
-  for (int j = 0; j < 16; ++j) ld_perm[j] = st_perm[j] = j;
-  bool moved = true;
-  while (moved) {   // permutations towards the end
-    moved = false;
-    for (size_t i = 0; i + 1 < ops.size(); ++i)
-      if (rb_op_perm(ops[i]) && !rb_op_perm(ops[i + 1]) && !(rb_op_bits(ops[i]) & rb_op_bits(ops[i + 1]))) {
-        std::swap(ops[i], ops[i + 1]);
-        moved = true;
-      }
-  }
-  size_t end = ops.size();
-  while (end > 0 && rb_op_perm(ops[end - 1])) --end;
-  for (int j = 0; j < nv; ++j)
-    for (size_t i = end; i < ops.size(); ++i) st_perm[j] = rb_perm_apply(ops[i], st_perm[j]);
-  ops.resize(end);
-  moved = true;
-  while (moved) {   // the rest towards the start
-    moved = false;
-    for (size_t i = ops.size(); i-- > 1;)
-      if (rb_op_perm(ops[i]) && !rb_op_perm(ops[i - 1]) && !(rb_op_bits(ops[i]) & rb_op_bits(ops[i - 1]))) {
-        std::swap(ops[i], ops[i - 1]);
-        moved = true;
-      }
-  }
-  size_t lead = 0;
-  while (lead < ops.size() && rb_op_perm(ops[lead])) ++lead;
-  for (int j = 0; j < nv; ++j)
-    for (size_t i = lead; i-- > 0;) ld_perm[j] = rb_perm_apply(ops[i], ld_perm[j]);
-  ops.erase(ops.begin(), ops.begin() + (long)lead);
-}
-
 // Global offsets of the tile entries j * 2^(k - rbits), j < 2^rbits: the low
 // c bits stay in place, tile bit c + i lands on qubit hi[i].
 void fill_entry_offsets(FusedBlockDev& d, int rbits) {
@@ -295,7 +239,13 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
         }
       }
       int ld_perm[16], st_perm[16];
-      fold_phase_permutations(pops, rbits, ld_perm, st_perm);
+      fold_permutations(
+          pops, rbits, [](const FusedOp& o) { return o.kind == 3 || o.kind == 5; },
+          [](const FusedOp& o) {
+            return (o.kind == 0 || o.kind == 1 || o.kind == 6) ? (1u << o.lo) : ((1u << o.o0) | (1u << o.o1));
+          },
+          [](const FusedOp& o, int j) { return o.kind == 3 ? reg_cx(o.o0, o.o1, j) : reg_swap(o.o0, o.o1, j); },
+          ld_perm, st_perm);
       ops.insert(ops.end(), pops.begin(), pops.end());
       fp.op_count = (int)ops.size() - fp.op_begin;
       fill_phase_offsets(fp, rbits, ld_perm, st_perm);

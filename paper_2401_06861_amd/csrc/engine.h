@@ -4,6 +4,7 @@
 #pragma once
 
 #include <array>
+#include <utility>
 #include <vector>
 
 #include "nwq_internal.h"
@@ -79,7 +80,57 @@ struct Phase {
   std::vector<int> gates;
 };
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
-void fold_phase_permutations(std::vector<FusedOp>& ops, int rbits, int* ld_perm, int* st_perm);
+// Fold the permutation gates that can open or close a register phase into its
+// LDS offsets instead of moving registers.  A permutation moves past a
+// following (preceding) non-permutation gate on other register bits, since the
+// two commute (for adjoint sweeps too: the gradient term of a gate is
+// unchanged when both vectors are transformed by a unitary that commutes with
+// its generator).  The trailing run T_1..T_m then means that register j holds
+// the entry of index T_m(...T_1(j)), so it is stored there; the leading run
+// L_1..L_l means that register j must hold the entry the data had at
+// (L_l...L_1)^-1 (j) = L_1(...L_l(j)) (the gates are involutions), so it is
+// loaded from there.  The remaining ops keep their order.  is_perm(op),
+// bits(op) (register-bit mask) and apply(op, j) (index map of a permutation)
+// describe the op type.
+template <class Op, class IsPerm, class Bits, class Apply>
+void fold_permutations(std::vector<Op>& ops, int rbits, IsPerm is_perm, Bits bits, Apply apply, int* ld_perm,
+                       int* st_perm) {
+  const int nv = 1 << rbits;
+  for (int j = 0; j < 16; ++j) ld_perm[j] = st_perm[j] = j;
+  bool moved = true;
+  while (moved) {   // permutations towards the end
+    moved = false;
+    for (size_t i = 0; i + 1 < ops.size(); ++i)
+      if (is_perm(ops[i]) && !is_perm(ops[i + 1]) && !(bits(ops[i]) & bits(ops[i + 1]))) {
+        std::swap(ops[i], ops[i + 1]);
+        moved = true;
+      }
+  }
+  size_t end = ops.size();
+  while (end > 0 && is_perm(ops[end - 1])) --end;
+  for (int j = 0; j < nv; ++j)
+    for (size_t i = end; i < ops.size(); ++i) st_perm[j] = apply(ops[i], st_perm[j]);
+  ops.resize(end);
+  moved = true;
+  while (moved) {   // the rest towards the start
+    moved = false;
+    for (size_t i = ops.size(); i-- > 1;)
+      if (is_perm(ops[i]) && !is_perm(ops[i - 1]) && !(bits(ops[i]) & bits(ops[i - 1]))) {
+        std::swap(ops[i], ops[i - 1]);
+        moved = true;
+      }
+  }
+  size_t lead = 0;
+  while (lead < ops.size() && is_perm(ops[lead])) ++lead;
+  for (int j = 0; j < nv; ++j)
+    for (size_t i = lead; i-- > 0;) ld_perm[j] = apply(ops[i], ld_perm[j]);
+  ops.erase(ops.begin(), ops.begin() + (long)lead);
+}
+// Index map of CX (control c, target t: flips t where c is set) and SWAP on register indices.
+inline int reg_cx(int c, int t, int j) { return j ^ (((j >> c) & 1) << t); }
+inline int reg_swap(int a, int b, int j) {
+  return ((j >> a) & 1) == ((j >> b) & 1) ? j : j ^ ((1 << a) | (1 << b));
+}
 int local_bit(const Block& b, int q);
 void pad_block(Block& b, int n, int k_target);
 void fill_entry_offsets(FusedBlockDev& d, int rbits);

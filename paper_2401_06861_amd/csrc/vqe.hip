@@ -797,8 +797,15 @@ struct VqeBwdRop {
   int axis;    // rotation axis
   int slot;    // gradient slot or -1
   int mat;     // index of the adjoint matrix in the per-vector table (double2 units)
-  int pad0, pad1;
+  int code;    // switch index: 4 v + r0 for 2x2 ops (v = axis, 3 = fixed);
+               // 16 + 16 w + 4 r0 + r1 for 2q ops (w: 0 RZZ, 1 CZ, 2 CX, 3 SWAP)
+  int pad1;
 };
+inline int bwd_rop_code(const VqeBwdRop& o) {
+  if (o.kind == 0 || o.kind == 2) return 4 * (o.kind == 2 ? 3 : o.axis) + o.r0;
+  const int w = o.kind == 1 ? 0 : o.kind == 4 ? 1 : o.kind == 3 ? 2 : 3;
+  return 16 + 16 * w + 4 * o.r0 + o.r1;
+}
 
 constexpr int kBwdRbMaxWaves = 4;   // tiles of at most 2^11 entries at 3 register bits
 
@@ -840,15 +847,6 @@ __device__ __forceinline__ void bw_rot(vd2 (&p)[NV], vd2 (&l)[NV], const double2
   }
 }
 
-template <int NV, int B>
-__device__ __forceinline__ void bw_rot_any(const VqeBwdRop& op, vd2 (&p)[NV], vd2 (&l)[NV],
-                                           const double2* __restrict__ M, double& g) {
-  if (op.kind == 2) bw_rot<NV, B, -1>(p, l, M, g);
-  else if (op.axis == 0) bw_rot<NV, B, 0>(p, l, M, g);
-  else if (op.axis == 1) bw_rot<NV, B, 1>(p, l, M, g);
-  else bw_rot<NV, B, 2>(p, l, M, g);
-}
-
 // Diagonal 2-qubit op on register bits B0 (u bit 0), B1 (u bit 1); with grad,
 // the ZZ generator's term Im(conj(l) p) times its eigenvalue.
 template <int NV, int B0, int B1>
@@ -881,55 +879,56 @@ __device__ __forceinline__ void bw_swap(vd2 (&p)[NV], vd2 (&l)[NV]) {
   }
 }
 
-template <int NV, int B0, int B1>
-__device__ __forceinline__ void bw_pair(const VqeBwdRop& op, vd2 (&p)[NV], vd2 (&l)[NV], const double2* M,
-                                        double& g) {
-  if (op.kind == 1 || op.kind == 4) bw_diag2<NV, B0, B1>(p, l, M, op.kind == 1, g);
-  else if (op.kind == 3) bw_swap<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(p, l);   // CX: control B0
-  else bw_swap<NV, B0, B1, (1 << B0), (1 << B1)>(p, l);                                  // SWAP
+template <int R, int B, int AX>
+__device__ __forceinline__ void bw_c1(vd2 (&p)[1 << R], vd2 (&l)[1 << R], const double2* M, double& g) {
+  if constexpr (B < R) bw_rot<(1 << R), B, AX>(p, l, M, g);
+}
+template <int R, int B0, int B1, int W>
+__device__ __forceinline__ void bw_c2(vd2 (&p)[1 << R], vd2 (&l)[1 << R], const double2* M, double& g) {
+  constexpr int NV = 1 << R;
+  if constexpr (B0 < R && B1 < R) {
+    if constexpr (W == 0) bw_diag2<NV, B0, B1>(p, l, M, true, g);                             // RZZ
+    else if constexpr (W == 1) bw_diag2<NV, B0, B1>(p, l, M, false, g);                       // CZ
+    else if constexpr (W == 2) bw_swap<NV, B0, B1, (1 << B0), (1 << B0) | (1 << B1)>(p, l);  // CX: control B0
+    else bw_swap<NV, B0, B1, (1 << B0), (1 << B1)>(p, l);                                    // SWAP
+  }
 }
 
+// One adjoint gate: a single switch over its code (bwd_rop_code).
 template <int R>
-__device__ __forceinline__ void bw_apply(const VqeBwdRop& op, vd2 (&p)[1 << R], vd2 (&l)[1 << R],
-                                         const double2* __restrict__ table, double& g) {
-  constexpr int NV = 1 << R;
-  const double2* M = table + op.mat;
-  if (op.kind == 0 || op.kind == 2) {
-    switch (op.r0) {
-      case 0: bw_rot_any<NV, 0>(op, p, l, M, g); break;
-      case 1: bw_rot_any<NV, 1>(op, p, l, M, g); break;
-      case 2: bw_rot_any<NV, 2>(op, p, l, M, g); break;
-      default:
-        if constexpr (R == 4) bw_rot_any<NV, 3>(op, p, l, M, g);
-        break;
-    }
-    return;
+__device__ __forceinline__ void bw_apply(int code, vd2 (&p)[1 << R], vd2 (&l)[1 << R], const double2* __restrict__ M,
+                                         double& g) {
+#define NWQ_BW1(V, AX) \
+  case 4 * V + 0: bw_c1<R, 0, AX>(p, l, M, g); break; \
+  case 4 * V + 1: bw_c1<R, 1, AX>(p, l, M, g); break; \
+  case 4 * V + 2: bw_c1<R, 2, AX>(p, l, M, g); break; \
+  case 4 * V + 3: bw_c1<R, 3, AX>(p, l, M, g); break;
+#define NWQ_BW2(W) \
+  case 16 + 16 * W + 1: bw_c2<R, 0, 1, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 2: bw_c2<R, 0, 2, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 3: bw_c2<R, 0, 3, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 4: bw_c2<R, 1, 0, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 6: bw_c2<R, 1, 2, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 7: bw_c2<R, 1, 3, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 8: bw_c2<R, 2, 0, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 9: bw_c2<R, 2, 1, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 11: bw_c2<R, 2, 3, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 12: bw_c2<R, 3, 0, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 13: bw_c2<R, 3, 1, W>(p, l, M, g); break; \
+  case 16 + 16 * W + 14: bw_c2<R, 3, 2, W>(p, l, M, g); break;
+  switch (code) {
+    NWQ_BW1(0, 0)
+    NWQ_BW1(1, 1)
+    NWQ_BW1(2, 2)
+    NWQ_BW1(3, -1)
+    NWQ_BW2(0)
+    NWQ_BW2(1)
+    NWQ_BW2(2)
+    NWQ_BW2(3)
+    default: break;
   }
-  if constexpr (R == 4) {
-    switch (op.r0 * 4 + op.r1) {
-      case 1: bw_pair<NV, 0, 1>(op, p, l, M, g); break;
-      case 2: bw_pair<NV, 0, 2>(op, p, l, M, g); break;
-      case 3: bw_pair<NV, 0, 3>(op, p, l, M, g); break;
-      case 4: bw_pair<NV, 1, 0>(op, p, l, M, g); break;
-      case 6: bw_pair<NV, 1, 2>(op, p, l, M, g); break;
-      case 7: bw_pair<NV, 1, 3>(op, p, l, M, g); break;
-      case 8: bw_pair<NV, 2, 0>(op, p, l, M, g); break;
-      case 9: bw_pair<NV, 2, 1>(op, p, l, M, g); break;
-      case 11: bw_pair<NV, 2, 3>(op, p, l, M, g); break;
-      case 12: bw_pair<NV, 3, 0>(op, p, l, M, g); break;
-      case 13: bw_pair<NV, 3, 1>(op, p, l, M, g); break;
-      default: bw_pair<NV, 3, 2>(op, p, l, M, g); break;   // 14
-    }
-  } else {
-    switch (op.r0 * 4 + op.r1) {
-      case 1: bw_pair<NV, 0, 1>(op, p, l, M, g); break;
-      case 2: bw_pair<NV, 0, 2>(op, p, l, M, g); break;
-      case 4: bw_pair<NV, 1, 0>(op, p, l, M, g); break;
-      case 6: bw_pair<NV, 1, 2>(op, p, l, M, g); break;
-      case 8: bw_pair<NV, 2, 0>(op, p, l, M, g); break;
-      default: bw_pair<NV, 2, 1>(op, p, l, M, g); break;   // 9
-    }
-  }
+#undef NWQ_BW1
+#undef NWQ_BW2
 }
 
 template <int R>
@@ -999,16 +998,13 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
       vd2 vp[NV], vl[NV];
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        unsigned off = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
-        vp[j] = ld(sp + padl_b(off));
-        vl[j] = ld(sl + padl_b(off));
+        vp[j] = ld(sp + ph.ld_off[j]);
+        vl[j] = ld(sl + ph.ld_off[j]);
       }
       for (int oi = 0; oi < ph.op_count; ++oi) {
         const VqeBwdRop op = ops[ph.op_begin + oi];
         double g = 0.0;
-        bw_apply<R>(op, vp, vl, table, g);
+        bw_apply<R>(op.code, vp, vl, table + op.mat, g);
         if (op.slot >= 0) {
           const double w = wave_sum(g);
           if (lane == 0) acc[ph.op_begin + oi - op0][wave] += w;
@@ -1016,11 +1012,8 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
       }
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        unsigned off = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) off |= ((j >> r) & 1) << ph.reg[r];
-        st(sp + padl_b(off), vp[j]);
-        st(sl + padl_b(off), vl[j]);
+        st(sp + ph.st_off[j], vp[j]);
+        st(sl + ph.st_off[j], vl[j]);
       }
     }
     __syncthreads();
@@ -1312,6 +1305,7 @@ static int build_fused(nwq_vqe* h) {
             if (ph.reg[i] == bit) return i;
           return -1;
         };
+        std::vector<VqeBwdRop> pops;
         for (int gi : ph.gates) {
           const VqeOp& op = h->ops[gi];
           VqeBwdRop o{};
@@ -1322,9 +1316,20 @@ static int build_fused(nwq_vqe* h) {
           o.mat = 8 * gi + 4;
           o.kind = op.kind == OP_ROT ? 0 : op.kind == OP_RZZ ? 1 : op.kind == OP_FIX1 ? 2 : op.kind == OP_CX ? 3
                  : op.kind == OP_CZ ? 4 : 5;
-          rops.push_back(o);
+          o.code = bwd_rop_code(o);
+          pops.push_back(o);
         }
+        int ld_perm[16], st_perm[16];
+        fold_permutations(
+            pops, kBwdBits, [](const VqeBwdRop& o) { return o.kind == 3 || o.kind == 5; },
+            [](const VqeBwdRop& o) {
+              return (o.kind == 0 || o.kind == 2) ? (1u << o.r0) : ((1u << o.r0) | (1u << o.r1));
+            },
+            [](const VqeBwdRop& o, int j) { return o.kind == 3 ? reg_cx(o.r0, o.r1, j) : reg_swap(o.r0, o.r1, j); },
+            ld_perm, st_perm);
+        rops.insert(rops.end(), pops.begin(), pops.end());
         fp.op_count = (int)rops.size() - fp.op_begin;
+        fill_phase_offsets(fp, kBwdBits, ld_perm, st_perm);
         phases.push_back(fp);
       }
       d.op_count = (int)phases.size() - d.op_begin;
