@@ -458,6 +458,28 @@ def dm_leg(nwq, torch):
             avg = ms / max(c, 1)
             sweep[f"{label}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
     out["sweep"] = sweep
+    # the whole noisy TFIM workload at n=14: 10 Trotter steps, each gate followed by its
+    # channels (one superoperator pass per noisy gate), then Tr(rho Z_i), purity and trace
+    import workloads as W
+    circ = W.noisy_tfim_circuit(n, 10)
+    zterms = W.single_site_terms(n, "Z")
+
+    def run_all():
+        st.reset()
+        st.run(circ)
+        z = st.expvals(zterms)
+        return z, st.purity(), st.trace()
+
+    run_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z, pur, tr = run_all()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gates = sum(1 for g in circ if g[0] in W.GATE_ARITY)
+    out["tfim_n14_10_steps"] = {"ms": round(dt * 1e3, 2), "noisy_gate_passes": gates,
+                                "GBs": round(gates * nbytes / dt / 1e9, 1), "purity": pur,
+                                "trace_re": tr[0], "z0": float(z[0])}
     out["launch_shapes"] = {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
                             for k, per in tuned.items()}
     st.close()
