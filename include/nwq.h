@@ -313,14 +313,23 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
 int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal);
 int nwq_get_launch(nwq_handle h, int cls, int bucket, int* ppt, int* nontemporal);
 
+/* Per-target shapes: a launch whose lowest target bit is `bit` (0..63) uses
+ * the shape set for that bit, if any, else its bucket's.  nwq_set_launch
+ * clears the per-target shapes of the buckets it sets; ppt 0 here clears one.
+ * nwq_get_launch_target returns the shape a launch on that bit would use. */
+#define NWQ_LAUNCH_TARGET_BITS 64
+int nwq_set_launch_target(nwq_handle h, int cls, int bit, int ppt, int nontemporal);
+int nwq_get_launch_target(nwq_handle h, int cls, int bit, int* ppt, int* nontemporal);
+
 /* Autotuner: for each class that applies to the handle (SV: 1, 2, 3, 4;
- * DM: 6, 7) and each bucket, time every launch shape with HIP events on the
- * handle's stream and state (self-inverse operations applied in pairs on up
- * to three target bits of the bucket, so the state is unchanged up to the
- * rounding of H H), keep the fastest, and write its time per launch in ms to
- * best_ms[class * NWQ_LAUNCH_BUCKETS + bucket] (NWQ_TIMING_CLASSES *
- * NWQ_LAUNCH_BUCKETS entries, -1 where not tuned; best_ms may be NULL).
- * Flushes deferred work first; synchronises. */
+ * DM: 6, 7) and each lowest target bit, time every launch shape with HIP
+ * events on the handle's stream and state (self-inverse operations applied in
+ * pairs, so the state is unchanged up to the rounding of H H).  Each target
+ * bit keeps its fastest shape; each bucket keeps the shape with the least
+ * total time over its bits.  The mean over a bucket's bits of their best time
+ * per launch (ms) goes to best_ms[class * NWQ_LAUNCH_BUCKETS + bucket]
+ * (NWQ_TIMING_CLASSES * NWQ_LAUNCH_BUCKETS entries, -1 where not tuned;
+ * best_ms may be NULL).  Flushes deferred work first; synchronises. */
 int nwq_autotune(nwq_handle h, int reps, double* best_ms);
 
 /* Fusion autotuner (SV handles): runs the given circuit (arrays as for

@@ -33,24 +33,32 @@ def _load(path: str) -> dict:
 
 def tune(h: int, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, force: bool = False) -> dict:
     """Launch shapes for handle h: {class name: {bucket: [ppt, nontemporal, ms or None]}}
-    (buckets "low", "mid" and "high" of the lowest target bit: 0-2, 3-10, 11 and up)."""
+    (buckets "low", "mid" and "high" of the lowest target bit: 0-2, 3-10, 11 and up).
+    The per-target shapes the tuner picks are cached too (under "targets") and
+    applied on a cache hit."""
     kind, n, _ = nwq.nwq_info(h)
-    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|buckets3b"
+    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|targets1"
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
-        for name, per_bucket in cache[key].items():
+        for name, per_bucket in cache[key]["buckets"].items():
             for bname, (ppt, nt, _) in per_bucket.items():
                 nwq.nwq_set_launch(h, CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(bname), int(ppt), int(nt))
-        return cache[key]
+        for name, per_bit in cache[key]["targets"].items():
+            for bit, (ppt, nt) in enumerate(per_bit):
+                nwq.nwq_set_launch_target(h, CLASS_IDS[name], bit, int(ppt), int(nt))
+        return cache[key]["buckets"]
     ms = nwq.nwq_autotune(h, reps)
     entry = {}
+    targets = {}
     for name, per_bucket in ms.items():
         for bname, t in per_bucket.items():
             ppt, nt = nwq.nwq_get_launch(h, CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(bname))
             entry.setdefault(name, {})[bname] = [ppt, nt, t]
+        # per lowest target qubit (the superoperator classes are looked up by qubit too)
+        targets[name] = [list(nwq.nwq_get_launch_target(h, CLASS_IDS[name], b)) for b in range(n)]
     if cache_path:
         cache = _load(cache_path)
-        cache[key] = entry
+        cache[key] = {"buckets": entry, "targets": targets}
         os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:

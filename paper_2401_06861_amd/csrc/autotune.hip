@@ -23,7 +23,9 @@ namespace nwq {
 namespace {
 
 struct Cand { int ppt, nt; };
-const Cand kCands[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}};
+// Without the hint only 1 and 4 groups per thread are offered: on the MI355X
+// the other hint-free shapes never won a target bit at 30 qubits.
+const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0}};
 
 // 16 groups per thread is offered to the kernels with at most two streams
 // per group (the 4x4 kernel would run out of registers).
@@ -94,6 +96,35 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
     h->cfg[cls][b].ppt = ppt;
     h->cfg[cls][b].nt = nontemporal ? 1 : 0;
   }
+  for (int q = 0; q < kMaxTargetBits; ++q)   // the bucket's shape now holds for each of its targets
+    if (bucket < 0 || bucket_of(q) == bucket) h->tset[cls][q] = false;
+  return NWQ_OK;
+}
+
+int nwq_set_launch_target(nwq_handle h, int cls, int bit, int ppt, int nontemporal) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
+  if (bit < 0 || bit >= kMaxTargetBits) return set_error(NWQ_EINVAL, "target bit out of range");
+  if (ppt == 0) {
+    h->tset[cls][bit] = false;
+    return NWQ_OK;
+  }
+  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && !(ppt == 16 && allows16(cls)))
+    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3)");
+  if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
+  h->tcfg[cls][bit].ppt = ppt;
+  h->tcfg[cls][bit].nt = nontemporal ? 1 : 0;
+  h->tset[cls][bit] = true;
+  return NWQ_OK;
+}
+
+int nwq_get_launch_target(nwq_handle h, int cls, int bit, int* ppt, int* nontemporal) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
+  if (bit < 0 || bit >= kMaxTargetBits) return set_error(NWQ_EINVAL, "target bit out of range");
+  const LaunchCfg& c = h->shape(cls, bit);
+  if (ppt) *ppt = c.ppt;
+  if (nontemporal) *nontemporal = c.nt;
   return NWQ_OK;
 }
 
@@ -129,45 +160,62 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+  // Every lowest target bit is timed under every candidate shape (reps timed
+  // pairs; one warm-up pair per candidate).  Each target keeps its fastest
+  // shape; each bucket keeps the shape with the least total time over its
+  // targets.
   for (const Job& j : jobs) {
-    for (int b = 0; b < kBuckets && !rc; ++b) {
-      // target bits of this bucket: {0, 1, 2}, {3, 6, 10}, {11, middle, top}
-      std::vector<int> qs;
-      const int cand_q[kBuckets][3] = {{0, 1, 2}, {3, 6, 10}, {11, (11 + j.lo_max) / 2, j.lo_max}};
-      for (int q : cand_q[b])
-        if (q >= 0 && q <= j.lo_max && bucket_of(q) == b && std::find(qs.begin(), qs.end(), q) == qs.end())
-          qs.push_back(q);
-      if (qs.empty()) continue;
-      double best = 1e300;
-      LaunchCfg best_c = h->cfg[j.cls][b];
-      for (const Cand& c : kCands) {
-        if (c.ppt == 16 && !allows16(j.cls)) continue;
-        if (j.cls == KC_DM2 && c.ppt != 1) continue;   // one group per thread; only the hint varies
-        LaunchCfg cfg;
-        cfg.ppt = c.ppt;
-        cfg.nt = c.nt;
-        for (int q : qs) j.run(h, cfg, q);   // warm-up
+    const int nq = std::min(j.lo_max + 1, kMaxTargetBits);
+    std::vector<LaunchCfg> cands;
+    for (const Cand& c : kCands) {
+      if (c.ppt == 16 && !allows16(j.cls)) continue;
+      if (j.cls == KC_DM2 && c.ppt != 1) continue;   // one group per thread; only the hint varies
+      LaunchCfg cfg;
+      cfg.ppt = c.ppt;
+      cfg.nt = c.nt;
+      cands.push_back(cfg);
+    }
+    std::vector<double> t(cands.size() * (size_t)nq, 0.0);   // ms per launch [cand][q]
+    for (size_t ci = 0; ci < cands.size() && !rc; ++ci)
+      for (int q = 0; q < nq && !rc; ++q) {
+        if (q == 0) j.run(h, cands[ci], q);   // warm-up
         rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
-        for (int r = 0; r < reps && !rc; ++r)
-          for (int q : qs) j.run(h, cfg, q);
+        for (int r = 0; r < reps && !rc; ++r) j.run(h, cands[ci], q);
         if (!rc) rc = check_hip(hipGetLastError(), "autotune launch");
         if (!rc) rc = check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
         if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0.f;
         if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        if (rc) break;
-        const double per = ms / (2.0 * reps * (double)qs.size());   // per launch
-        if (per < best) {
-          best = per;
-          best_c = cfg;
+        t[ci * nq + q] = ms / (2.0 * reps);
+      }
+    if (rc) break;
+    double bsum[kBuckets] = {0.0, 0.0, 0.0};
+    int bcnt[kBuckets] = {0, 0, 0};
+    for (int q = 0; q < nq; ++q) {
+      size_t best = 0;
+      for (size_t ci = 1; ci < cands.size(); ++ci)
+        if (t[ci * nq + q] < t[best * nq + q]) best = ci;
+      h->tcfg[j.cls][q] = cands[best];
+      h->tset[j.cls][q] = true;
+      bsum[bucket_of(q)] += t[best * nq + q];
+      ++bcnt[bucket_of(q)];
+    }
+    for (int b = 0; b < kBuckets; ++b) {
+      if (bcnt[b] == 0) continue;
+      size_t best = 0;
+      double best_total = 1e300;
+      for (size_t ci = 0; ci < cands.size(); ++ci) {
+        double tot = 0.0;
+        for (int q = 0; q < nq; ++q)
+          if (bucket_of(q) == b) tot += t[ci * nq + q];
+        if (tot < best_total) {
+          best_total = tot;
+          best = ci;
         }
       }
-      if (!rc) {
-        h->cfg[j.cls][b] = best_c;
-        if (best_ms) best_ms[j.cls * kBuckets + b] = best;
-      }
+      h->cfg[j.cls][b] = cands[best];
+      if (best_ms) best_ms[j.cls * kBuckets + b] = bsum[b] / bcnt[b];
     }
-    if (rc) break;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

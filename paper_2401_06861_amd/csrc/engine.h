@@ -25,7 +25,13 @@ struct nwq_state {
 
   // launch shapes per kernel class and target bucket (autotuned)
   nwq::LaunchCfg cfg[nwq::KC_COUNT][nwq::kBuckets];
-  const nwq::LaunchCfg& shape(int cls, int lowest_bit) const { return cfg[cls][nwq::bucket_of(lowest_bit)]; }
+  // per-target shapes chosen by the autotuner; a target without one uses its bucket's
+  nwq::LaunchCfg tcfg[nwq::KC_COUNT][nwq::kMaxTargetBits];
+  bool tset[nwq::KC_COUNT][nwq::kMaxTargetBits] = {};
+  const nwq::LaunchCfg& shape(int cls, int lowest_bit) const {
+    if (lowest_bit >= 0 && lowest_bit < nwq::kMaxTargetBits && tset[cls][lowest_bit]) return tcfg[cls][lowest_bit];
+    return cfg[cls][nwq::bucket_of(lowest_bit)];
+  }
 
   // reduction scratch
   double* partials = nullptr;

@@ -67,6 +67,17 @@ __global__ __launch_bounds__(kBlock) void k_sv_1q(double2* __restrict__ a, unsig
   const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * PPT) + threadIdx.x;
   const unsigned long long off = 1ull << q;
   const vd2 m0 = tov(m.m[0]), m1 = tov(m.m[1]), m2 = tov(m.m[2]), m3 = tov(m.m[3]);
+  if constexpr (PPT == 1) {
+    // one path only: when the two paths below coincide the compiler merges their
+    // stores and the merged store loses its non-temporal hint
+    if (start < npairs) {
+      const unsigned long long i = insert0(start, q);
+      const vd2 v0 = gld<NTM>(a + i), v1 = gld<NTM>(a + i + off);
+      gst<NTM>(a + i, cfma(m0, v0, cmul(m1, v1)));
+      gst<NTM>(a + i + off, cfma(m2, v0, cmul(m3, v1)));
+    }
+    return;
+  }
   if (start + (unsigned long long)(PPT - 1) * kBlock < npairs) {
     vd2 x0[PPT], x1[PPT];
     unsigned long long i0[PPT];
@@ -146,6 +157,13 @@ __global__ __launch_bounds__(kBlock) void k_sv_1q_lane(double2* __restrict__ a, 
   const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
   const bool up = (threadIdx.x >> T) & 1;
   const vd2 cs = up ? tov(m.m[3]) : tov(m.m[0]), cp = up ? tov(m.m[2]) : tov(m.m[1]);
+  if constexpr (EPT == 1) {   // one path only (see k_sv_1q)
+    if (start < len) {
+      const vd2 v = gld<NTM>(a + start);
+      gst<NTM>(a + start, cfma(cs, v, cmul(cp, lane_xor_v<(1 << T)>(v, 0))));
+    }
+    return;
+  }
   if (start + (unsigned long long)(EPT - 1) * kBlock < len) {
     vd2 v[EPT];
 #pragma unroll
@@ -176,6 +194,18 @@ __global__ __launch_bounds__(kBlock) void k_sv_perm_lane(double2* __restrict__ a
   const int l = threadIdx.x & 63;
   const bool mv = (l & Q) == oa || (l & Q) == ob;
   const int src = (l ^ xr) << 2;
+  if constexpr (EPT == 1) {   // one path only (see k_sv_1q)
+    if (start < len) {
+      const vd2 v = gld<NTM>(a + start);
+      const vd2 p = lane_xor_v<X>(v, src);
+      if constexpr (MASKED) {
+        if (mv) gst<NTM>(a + start, p);
+      } else {
+        gst<NTM>(a + start, mv ? p : v);
+      }
+    }
+    return;
+  }
   if (start + (unsigned long long)(EPT - 1) * kBlock < len) {
     vd2 v[EPT];
 #pragma unroll
@@ -230,6 +260,16 @@ __global__ __launch_bounds__(kBlock) void k_sv_2q_lane(double2* __restrict__ a, 
   auto out = [&](int h, vd2 e0, vd2 e1, vd2 p0, vd2 p1) {
     return cfma(c[h][0][0], e0, cfma(c[h][1][0], e1, cfma(c[h][0][1], p0, cmul(c[h][1][1], p1))));
   };
+  if constexpr (EPT == 1) {   // one path only (see k_sv_1q)
+    if (start < nhalf) {
+      const unsigned long long i = insert0(start, H);
+      const vd2 e0 = gld<NTM>(a + i), e1 = gld<NTM>(a + i + off);
+      const vd2 p0 = lane_xor_v<(1 << L)>(e0, 0), p1 = lane_xor_v<(1 << L)>(e1, 0);
+      gst<NTM>(a + i, out(0, e0, e1, p0, p1));
+      gst<NTM>(a + i + off, out(1, e0, e1, p0, p1));
+    }
+    return;
+  }
   if (start + (unsigned long long)(EPT - 1) * kBlock < nhalf) {
     vd2 e0[EPT], e1[EPT];
     unsigned long long i0[EPT];

@@ -43,6 +43,7 @@ struct LaunchCfg {
 // (on MI355X at 30 qubits: 1 group per thread, 16 with the hint, 4 with the
 // hint for the 2x2 kernel).
 constexpr int kBuckets = 3;
+constexpr int kMaxTargetBits = 64;   // lowest target bits with their own tuned launch shape
 inline int bucket_of(int lowest_bit) { return lowest_bit < 3 ? 0 : (lowest_bit < 11 ? 1 : 2); }
 
 // Kernel classes (also the timing classes of nwq_timing_read).

@@ -80,6 +80,8 @@ _SIG = {
     "nwq_timing_enable": [_h, C.c_int],
     "nwq_set_launch": [_h, C.c_int, C.c_int, C.c_int, C.c_int],
     "nwq_get_launch": [_h, C.c_int, C.c_int, _ip, _ip],
+    "nwq_set_launch_target": [_h, C.c_int, C.c_int, C.c_int, C.c_int],
+    "nwq_get_launch_target": [_h, C.c_int, C.c_int, _ip, _ip],
     "nwq_autotune": [_h, C.c_int, _dp],
     "nwq_autotune_fusion": [_h, C.c_int, _ip, _ip, _dp, C.c_int, _ip, _ip, _dp],
     "nwq_qasm_parse": [C.c_char_p, _ip, _ip, C.c_int, _ip, _ip, _dp],
@@ -310,6 +312,20 @@ def nwq_set_launch(h: int, cls: int, bucket: int, ppt: int, nontemporal: int) ->
 def nwq_get_launch(h: int, cls: int, bucket: int) -> Tuple[int, int]:
     p, t = C.c_int(), C.c_int()
     _check(lib.nwq_get_launch(h, cls, bucket, C.byref(p), C.byref(t)))
+    return p.value, t.value
+
+
+LAUNCH_TARGET_BITS = 64
+
+
+def nwq_set_launch_target(h: int, cls: int, bit: int, ppt: int, nontemporal: int) -> None:
+    """Shape of launches whose lowest target bit is `bit` (ppt 0 clears it)."""
+    _check(lib.nwq_set_launch_target(h, cls, bit, ppt, nontemporal))
+
+
+def nwq_get_launch_target(h: int, cls: int, bit: int) -> Tuple[int, int]:
+    p, t = C.c_int(), C.c_int()
+    _check(lib.nwq_get_launch_target(h, cls, bit, C.byref(p), C.byref(t)))
     return p.value, t.value
 
 

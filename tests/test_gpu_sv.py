@@ -302,6 +302,39 @@ def test_launch_shape_buckets(nwq):
     st.close()
 
 
+def test_per_target_launch_shapes(nwq):
+    """A shape set for one lowest target bit overrides its bucket's for that
+    bit only; nwq_set_launch on the bucket clears it; a circuit run with a
+    different shape on every bit matches the oracle."""
+    n = 14
+    st = nwq.SVState(n, reset=False)
+    cycle = [(1, 1), (2, 1), (4, 0), (8, 1), (16, 1), (1, 0)]
+    for cls in (1, 2, 3, 4):
+        nwq.nwq_set_launch(st.h, cls, -1, 4, 1)
+        for q in range(n):
+            ppt, nt = cycle[(q + cls) % len(cycle)]
+            if cls == 4 and ppt == 16:
+                ppt = 8
+            nwq.nwq_set_launch_target(st.h, cls, q, ppt, nt)
+            assert nwq.nwq_get_launch_target(st.h, cls, q) == (ppt, nt)
+        assert nwq.nwq_get_launch(st.h, cls, 2) == (4, 1)
+    gates = W.random_gate_list(n, 300, seed=21)
+    psi0 = W.random_state(n, seed=22)
+    st.load(psi0)
+    st.run_circuit(gates)
+    assert maxerr(st.numpy(), tensor.sv_run(gates, n, psi0)) <= TOL
+    nwq.nwq_set_launch(st.h, 1, 1, 2, 0)               # bucket 1 (bits 3..10) back to one shape
+    assert nwq.nwq_get_launch_target(st.h, 1, 5) == (2, 0)
+    assert nwq.nwq_get_launch_target(st.h, 1, 12) == cycle[(12 + 1) % len(cycle)]
+    nwq.nwq_set_launch_target(st.h, 1, 12, 0, 0)       # cleared: the bucket's shape again
+    assert nwq.nwq_get_launch_target(st.h, 1, 12) == (4, 1)
+    for bad in ((1, 64, 4, 0), (1, -1, 4, 0), (1, 3, 3, 0), (4, 3, 16, 0), (7, 3, 2, 1)):
+        with pytest.raises(nwq.NwqError) as e:
+            nwq.nwq_set_launch_target(st.h, *bad)
+        assert e.value.code == nwq.NWQ_EINVAL
+    st.close()
+
+
 def test_autotune_keeps_state_and_parity(nwq):
     from paper_2401_06861_amd import autotune
     import tempfile, os
@@ -319,6 +352,13 @@ def test_autotune_keeps_state_and_parity(nwq):
     assert shapes(again) == shapes(chosen)
     for (name, b), shape in shapes(chosen).items():
         assert nwq.nwq_get_launch(st.h, autotune.CLASS_IDS[name], nwq.LAUNCH_BUCKETS.index(b)) == shape
+    import json
+    cached = json.load(open(cache))
+    (entry,) = cached.values()
+    for name, per_bit in entry["targets"].items():   # per-target shapes restored from the cache
+        assert len(per_bit) == n
+        for bit, shape in enumerate(per_bit):
+            assert nwq.nwq_get_launch_target(st.h, autotune.CLASS_IDS[name], bit) == tuple(shape)
     gates = W.random_gate_list(n, 120, seed=3)
     st.load(psi0)
     st.run_circuit(gates)
