@@ -326,7 +326,7 @@ def sweep_leg(nwq, st, n):
     import torch
     N = 1 << n
     res = {}
-    for name, qs_list, bytes_per in (("u3", [(q,) for q in (0, 1, 2, 3, 5, 6, 10, 20, n - 1)], 32 * N),
+    for name, qs_list, bytes_per in (("u3", [(q,) for q in (0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 20, n - 1)], 32 * N),
                                      ("cx", [(0, 1), (1, 2), (2, 3), (3, 4), (5, 6), (14, 15), (n - 2, n - 1)],
                                       16 * N),
                                      ("rz", [(0,), (n - 1,)], 32 * N), ("rzz", [(0, 1), (n - 2, n - 1)], 32 * N)):

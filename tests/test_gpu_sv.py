@@ -228,14 +228,15 @@ def test_every_launch_shape_matches_oracle(nwq, n):
 
 @pytest.mark.parametrize("n", [8, 10])
 def test_lane_exchange_kernels(nwq, n):
-    """Gates whose bits are all lane bits (below 6, the lower below 3) run with
-    lane exchanges: dense 1q and X on targets 0..2, CX and SWAP on every
+    """Dense 1q gates on every target (LDS partner exchange on targets 0..8),
+    and gates whose bits are all lane bits (below 6, the lower below 3) with
+    lane exchanges: X on targets 0..2, CX and SWAP on every
     ordered pair of bits 0..5 with a bit below 3 (DPP partners at distance
     1, 2, 4, 8 and ds_bpermute otherwise; whole-line and masked stores), under
     every entries-per-thread and hint choice."""
     psi0 = W.random_state(n, seed=90 + n)
     st = nwq.SVState(n, reset=False)
-    ops = [("u3", (q,), (0.3 + q, 1.1, -0.7)) for q in range(3)] + [("x", (q,), ()) for q in range(3)]
+    ops = [("u3", (q,), (0.3 + q, 1.1, -0.7)) for q in range(n)] + [("x", (q,), ()) for q in range(3)]
     for a, b in itertools.permutations(range(6), 2):
         if min(a, b) < 3:
             ops.append(("cx", (a, b), ()))
