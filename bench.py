@@ -480,6 +480,21 @@ def dm_leg(nwq, torch):
     out["tfim_n14_10_steps"] = {"ms": round(dt * 1e3, 2), "noisy_gate_passes": gates,
                                 "GBs": round(gates * nbytes / dt / 1e9, 1), "purity": pur,
                                 "trace_re": tr[0], "z0": float(z[0])}
+    # the same with the 1q superoperators queued and run as fused blocks over the 28 bits
+    fused = {}
+    for k in (10, 12):
+        st.set_fusion(k)
+        nwq.nwq_set_fusion_kernel(st.h, 1)
+        run_all()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        zf, purf, _ = run_all()
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t0
+        fused[f"k{k}"] = {"ms": round(dtf * 1e3, 2), "max_abs_dz_vs_unfused": float(np.max(np.abs(zf - z))),
+                          "dpurity": abs(purf - pur)}
+    st.set_fusion(0)
+    out["tfim_n14_10_steps_fused"] = fused
     out["launch_shapes"] = {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
                             for k, per in tuned.items()}
     st.close()

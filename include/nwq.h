@@ -152,8 +152,13 @@ int nwq_qasm_parse(const char* text, int* n_qubits, int* n_gates, int capacity, 
                    double* params);
 int nwq_apply_qasm(nwq_handle h, const char* text);
 
-/* Fused-block width for nwq_apply_circuit on SV handles: 0 = off (one
- * kernel per gate), else the number of qubits a block may touch (6..13).
+/* Fused-block width: 0 = off (one kernel per gate), else the number of bits
+ * a block may touch (6..13).  SV handles: nwq_apply_circuit runs its gates
+ * through fused blocks.  DM handles: each 1q gate with the channels composed
+ * after it (a 4x4 superoperator on bits q and q + n of vec(rho)) is queued,
+ * and the queue runs as fused blocks over the 2n bits when a 2q
+ * superoperator, a read or nwq_flush needs the state (a reset or
+ * nwq_set_state drops it); changing the width on a DM handle flushes first.
  * Returns the value in effect through *k_out when non-NULL. */
 int nwq_set_fusion(nwq_handle h, int k, int* k_out);
 

@@ -89,10 +89,22 @@ int local_bit(const Block& b, int q) {
 // Encode one gate as a FusedOp (bits are tile-local for the per-gate LDS
 // kernel, register-bit indices for the register-blocked kernel) and append
 // its matrix entries.  Returns false for the identity (nothing to do).
-static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats, FusedOp& op, bool reg) {
+static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats, FusedOp& op, bool reg,
+                      const std::vector<cd>* side) {
+  op = FusedOp{};
+  if (g.type == kGateMat4) {   // dense 4x4 from the side table, operator order (q[0], q[1])
+    op.mat = (int)mats.size();
+    op.lo = std::min(b0, b1);
+    op.hi = std::max(b0, b1);
+    op.kind = 2;
+    op.o0 = reg ? b0 : (1 << b0);
+    op.o1 = reg ? b1 : (1 << b1);
+    const cd* M = side->data() + 16 * (size_t)g.p[0];
+    for (int i = 0; i < 16; ++i) mats.push_back(make_double2(M[i].real(), M[i].imag()));
+    return true;
+  }
   cd m[16];
   gate_matrix(g.type, g.p, m);
-  op = FusedOp{};
   op.mat = (int)mats.size();
   op.lo = g.nq == 2 ? std::min(b0, b1) : b0;
   op.hi = g.nq == 2 ? std::max(b0, b1) : 0;
@@ -180,8 +192,11 @@ void fill_entry_offsets(FusedBlockDev& d, int rbits) {
   }
 }
 
-static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
-  const std::vector<Block> blocks = plan_blocks(gates, h->n, h->fuse_k);
+// Runs a gate list through fused blocks over `nbits` bits of the vector (the
+// qubit count for a state vector; 2n for the vectorised density matrix, whose
+// queued 1q superoperators arrive as kGateMat4 gates with matrices in `side`).
+int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side) {
+  const std::vector<Block> blocks = plan_blocks(gates, nbits, h->fuse_k);
   if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
   // Program: [phase table][op table][matrix table] in one upload.
   std::vector<FusedPhase> phases;
@@ -190,7 +205,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
   struct Launch { FusedBlockDev d; bool rb; int rbits; };
   std::vector<Launch> launches;
   for (Block b : blocks) {
-    if (h->fuse_rb != 0 && b.c + b.m < 8 && h->n >= 8) pad_block(b, h->n, 8);
+    if (h->fuse_rb != 0 && b.c + b.m < 8 && nbits >= 8) pad_block(b, nbits, 8);
     FusedBlockDev d{};
     d.c = b.c;
     d.m = b.m;
@@ -203,7 +218,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
       for (int gi : b.gates) {
         const PGate& g = gates[gi];
         FusedOp op;
-        if (encode_op(g, local_bit(b, g.q[0]), g.nq == 2 ? local_bit(b, g.q[1]) : 0, mats, op, false))
+        if (encode_op(g, local_bit(b, g.q[0]), g.nq == 2 ? local_bit(b, g.q[1]) : 0, mats, op, false, side))
           ops.push_back(op);
       }
       d.op_count = (int)ops.size() - d.op_begin;
@@ -233,7 +248,7 @@ static int apply_fused(nwq_state* h, const std::vector<PGate>& gates) {
       std::vector<FusedOp> pops;
       for (int gi : ph.gates) {
         FusedOp op;
-        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true)) {
+        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
           op.code = rb_op_code(op);
           pops.push_back(op);
         }
@@ -352,7 +367,7 @@ int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qu
   h->last_blocks = 0;
   h->last_fused_gates = 0;
   h->last_phases = 0;
-  if (h->kind == NWQ_KIND_SV && h->fuse_k > 0 && n_gates > 0) return apply_fused(h, gates);
+  if (h->kind == NWQ_KIND_SV && h->fuse_k > 0 && n_gates > 0) return apply_fused(h, gates, h->n, nullptr);
   for (const PGate& g : gates) {
     int rc;
     if (h->kind == NWQ_KIND_SV) {
@@ -377,7 +392,10 @@ int nwq_set_fusion_kernel(nwq_handle h, int kernel) {
 int nwq_set_fusion(nwq_handle h, int k, int* k_out) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
   if (k != 0 && (k < 6 || k > 13)) return set_error(NWQ_EINVAL, "fusion width must be 0 or in [6, 13]");
-  if (h->kind != NWQ_KIND_SV && k != 0) return set_error(NWQ_EKIND, "fusion applies to state-vector handles");
+  if (h->kind == NWQ_KIND_DM) {   // queued superoperators are flushed under the old width first
+    const int rc = flush_all(h);
+    if (rc) return rc;
+  }
   h->fuse_k = k;
   if (k_out) *k_out = k;
   return NWQ_OK;

@@ -56,6 +56,10 @@ struct nwq_state {
   int last_blocks = 0, last_fused_gates = 0, last_phases = 0;
   int fuse_rb = 1;                 // fused kernel: 0 one LDS pass per gate, 1 / 2 register-blocked with 4 / 3 register bits
   void* fuse_dev = nullptr;        // device copy of the compiled block program
+  // DM with fusion on: 1q superoperators (4x4 on bits q, q + n) wait here and
+  // run as fused blocks when a 2q superoperator or a read needs the state
+  std::vector<int> dmq_q;
+  std::vector<nwq::cd> dmq_S;
   size_t fuse_cap = 0;
 
   // timing
@@ -86,6 +90,9 @@ struct Phase {
   std::vector<int> gates;
 };
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
+// internal gate type: dense 4x4 whose matrix is entry p[0] of a side table
+constexpr int kGateMat4 = 1000;
+int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side);
 // Fold the permutation gates that can open or close a register phase into its
 // LDS offsets instead of moving registers.  A permutation moves past a
 // following (preceding) non-permutation gate on other register bits, since the

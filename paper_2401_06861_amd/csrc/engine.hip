@@ -306,9 +306,49 @@ static void superop(const cd* kraus, int nk, int k, std::vector<cd>& S) {
   }
 }
 
+// Runs the queued 1q superoperators: through fused blocks over the 2n bits
+// of vec(rho) when there are two or more, else as one pass.
+static int dm_run_queue(nwq_state* h) {
+  const size_t cnt = h->dmq_q.size();
+  if (cnt == 0) return NWQ_OK;
+  int rc = NWQ_OK;
+  if (cnt == 1) {
+    Mat4 M;
+    for (int i = 0; i < 16; ++i) M.m[i] = d2(h->dmq_S[i]);
+    const int q = h->dmq_q[0];
+    timing_begin(h, KC_DM1);
+    launch_sv_2q(h->stream, h->data, h->nbits, q, q + h->n, M, h->shape(KC_DM1, q));
+    timing_end(h);
+    rc = last_launch("dm_superop_1q");
+  } else {
+    std::vector<PGate> gates(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+      PGate& g = gates[i];
+      g.type = kGateMat4;
+      g.nq = 2;
+      g.q[0] = h->dmq_q[i];              // column bit: u bit 0
+      g.q[1] = h->dmq_q[i] + h->n;       // row bit: u bit 1
+      g.p[0] = (double)i;
+      g.p[1] = g.p[2] = 0.0;
+    }
+    rc = apply_fused(h, gates, h->nbits, &h->dmq_S);
+  }
+  h->dmq_q.clear();
+  h->dmq_S.clear();
+  return rc;
+}
+
 int dm_flush(nwq_state* h) {
   if (!h->pend_active) return NWQ_OK;
   const int k = h->pend_k, n = h->n;
+  if (k == 1 && h->fuse_k > 0) {   // queue it for the next fused run
+    h->dmq_q.push_back(h->pend_q[0]);
+    h->dmq_S.insert(h->dmq_S.end(), h->pend_S.begin(), h->pend_S.end());
+    h->pend_active = false;
+    return NWQ_OK;
+  }
+  int rc = dm_run_queue(h);   // queued work comes first
+  if (rc) return rc;
   if (k == 1) {
     Mat4 M;
     for (int i = 0; i < 16; ++i) M.m[i] = d2(h->pend_S[i]);
@@ -322,7 +362,7 @@ int dm_flush(nwq_state* h) {
   std::vector<double2> buf(256);
   for (int i = 0; i < 256; ++i) buf[i] = d2(h->pend_S[i]);
   void* dev = nullptr;
-  int rc = arena_put(h, buf.data(), buf.size() * sizeof(double2), &dev);
+  rc = arena_put(h, buf.data(), buf.size() * sizeof(double2), &dev);
   if (rc != NWQ_OK) return rc;
   const int vq[4] = {h->pend_q[0], h->pend_q[1], h->pend_q[0] + n, h->pend_q[1] + n};
   timing_begin(h, KC_DM2);
@@ -365,8 +405,9 @@ int dm_apply_unitary(nwq_state* h, const int* q, int k, const cd* U) {
 }
 
 int flush_all(nwq_state* h) {
-  if (h->kind == NWQ_KIND_DM) return dm_flush(h);
-  return NWQ_OK;
+  if (h->kind != NWQ_KIND_DM) return NWQ_OK;
+  const int rc = dm_flush(h);
+  return rc ? rc : dm_run_queue(h);
 }
 
 }  // namespace nwq
@@ -455,6 +496,8 @@ int nwq_reset(nwq_handle h) {
   int rc = check_handle(h);
   if (rc) return rc;
   h->pend_active = false;   // pending work on the old state is discarded
+  h->dmq_q.clear();
+  h->dmq_S.clear();
   timing_begin(h, KC_RESET);
   launch_fill_basis0(h->stream, h->data, h->len);
   timing_end(h);
@@ -480,6 +523,8 @@ int nwq_set_state(nwq_handle h, const double* host, size_t n_doubles) {
   if (host == nullptr || n_doubles != 2 * h->len)
     return set_error(NWQ_EINVAL, "host buffer must hold " + std::to_string(2 * h->len) + " doubles");
   h->pend_active = false;
+  h->dmq_q.clear();
+  h->dmq_S.clear();
   NWQ_TRY_HIP(hipMemcpyAsync(h->data, host, h->len * sizeof(double2), hipMemcpyHostToDevice, h->stream),
               "hipMemcpyAsync(set_state)");
   NWQ_TRY_HIP(hipStreamSynchronize(h->stream), "hipStreamSynchronize(set_state)");

@@ -207,6 +207,52 @@ def test_staged_two_qubit_superoperators(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n,k,kernel", [(4, 8, 1), (5, 8, 2), (6, 10, 1), (7, 12, 1), (7, 8, 0), (8, 12, 2)])
+def test_fused_superoperator_queue(nwq, n, k, kernel):
+    """With fusion on, the 1q superoperators (gate + channels, 4x4 on bits
+    q and q + n) queue up and run as fused blocks over the 2n bits of vec(rho)
+    when a 2q superoperator or a read needs the state; every fused kernel
+    matches the oracle.  Reads in the middle, switching fusion off with work
+    queued, and a reset that drops queued work are covered too."""
+    rng = np.random.default_rng(500 + n)
+    rho0 = W.random_density_matrix(n, seed=90 + n)
+    ops = W.noisy_tfim_circuit(n, 2)
+    for _ in range(3 * n):   # 1q noisy gates on random qubits
+        q = (int(rng.integers(n)),)
+        ops += [("u3", q, tuple(float(x) for x in rng.uniform(-3, 3, 3))), ("depolarize", q, (0.03,)),
+                ("amp_damp", q, (0.05,))]
+    ops += [("cx", (0, n - 1), ()), ("depolarize2", (0, n - 1), (0.01,)), ("ry", (n - 1,), (0.4,))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    st = nwq.DMState(n, reset=False)
+    st.set_fusion(k)
+    nwq.nwq_set_fusion_kernel(st.h, kernel)
+    st.load(rho0)
+    half = len(ops) // 2
+    st.run(ops[:half])
+    mid = rho0
+    for op in ops[:half]:
+        mid = tensor.dm_apply(mid, op, n)
+    assert maxerr(st.numpy(), mid) <= TOL            # a read runs the queue
+    st.run(ops[half:])
+    assert maxerr(st.numpy(), want) <= TOL
+    assert nwq.nwq_fusion_stats(st.h)[0] >= 1
+    st.load(rho0)
+    st.run(ops[:half])
+    st.set_fusion(0)                                 # queued work runs before fusion goes off
+    st.run(ops[half:])
+    assert maxerr(st.numpy(), want) <= TOL
+    st.set_fusion(k)
+    st.load(rho0)
+    st.run([("u3", (0,), (0.3, 0.2, 0.1)), ("depolarize", (0,), (0.2,)), ("rx", (1,), (0.5,))])
+    st.reset()                                       # drops the queued work
+    zero = np.zeros_like(rho0)
+    zero[0, 0] = 1.0
+    assert maxerr(st.numpy(), zero) == 0.0
+    st.close()
+
+
 def test_depolarizing_conventions(nwq):
     """Both depolarising conventions on one and two qubits against the
     oracle's Kraus sets, alone and fused after a gate."""
@@ -274,7 +320,7 @@ def test_dm_errors(nwq):
         nwq.nwq_depolarize(st.h, [0], 1.5)
     assert e.value.code == nwq.NWQ_EINVAL
     with pytest.raises(nwq.NwqError) as e:
-        nwq.nwq_set_fusion(st.h, 8)
-    assert e.value.code == nwq.NWQ_EKIND
+        nwq.nwq_set_fusion(st.h, 5)
+    assert e.value.code == nwq.NWQ_EINVAL
     assert maxerr(st.numpy(), rho0) == 0.0
     st.close()
