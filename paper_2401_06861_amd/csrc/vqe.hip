@@ -808,6 +808,7 @@ inline int bwd_rop_code(const VqeBwdRop& o) {
 }
 
 constexpr int kBwdRbMaxWaves = 4;   // tiles of at most 2^11 entries at 3 register bits
+constexpr int kBwdMaxTileBits = 11;
 
 __device__ __forceinline__ unsigned padl_b(unsigned l) { return l + (l >> 4); }
 // one padded tile of 2^k entries (one extra entry per 16)
@@ -1079,7 +1080,7 @@ struct nwq_vqe {
   double* d_ssum = nullptr;    // per-slot gradient sums [B][nslots]
   // fused path program (built on first use)
   bool fused_built = false;
-  int fused_k = 11;
+  int fused_k = 12;
   int fused_rbits = 4;         // register bits per phase of the forward kernel
   bool bwd_rb = false;         // backward sweep register-blocked (3 bits) when every tile has >= 2^9 entries
   size_t fused_rop_off = 0;    // offset of the register-blocked backward ops in d_fused
@@ -1224,7 +1225,6 @@ static int build_fused(nwq_vqe* h) {
   for (const Block& b : padded) {
     const int kb = b.c + b.m;
     if (kb < 8) return set_error(NWQ_EINVAL, "fused VQE path needs tiles of at least 2^8 amplitudes");
-    max_bwd_lds = std::max(max_bwd_lds, (size_t)2 * sizeof(double2) << kb);
     std::vector<std::array<int, 2>> lb(g.size());
     std::vector<int> nq(g.size(), 1);
     for (int gi : b.gates) {
@@ -1276,10 +1276,23 @@ static int build_fused(nwq_vqe* h) {
   // Backward: register-blocked with 3 register bits when every tile gives at
   // least one full wave (2^(k-3) >= 64), else one LDS pass per gate.
   constexpr int kBwdBits = 3;
+  // The backward sweep plans its own blocks when the forward width exceeds
+  // what its kernels take (tiles of at most 2^11: 256 threads x 8 amplitudes):
+  // any partition of the reversed gate list gives the same sweep.
+  std::vector<Block> bpadded;
+  const int kbw = std::min(k, kBwdMaxTileBits);
+  if (kbw == k) {
+    bpadded = padded;
+  } else {
+    bpadded = plan_blocks(g, n, std::max(kbw, 6));
+    if (bpadded.empty() && h->nops > 0) return set_error(NWQ_EINVAL, "fusion planner made no progress");
+    for (Block& b : bpadded) pad_block(b, n, std::max(kbw, 8));
+  }
+  for (const Block& b : bpadded) max_bwd_lds = std::max(max_bwd_lds, (size_t)2 * sizeof(double2) << (b.c + b.m));
   h->bwd_rb = true;
-  for (const Block& b : padded) h->bwd_rb = h->bwd_rb && (b.c + b.m) - kBwdBits >= 6;
+  for (const Block& b : bpadded) h->bwd_rb = h->bwd_rb && (b.c + b.m) - kBwdBits >= 6;
   std::vector<VqeBwdRop> rops;
-  for (auto bit = padded.rbegin(); h->bwd_rb && bit != padded.rend(); ++bit) {
+  for (auto bit = bpadded.rbegin(); h->bwd_rb && bit != bpadded.rend(); ++bit) {
     const Block& b = *bit;
     const int kb = b.c + b.m;
     std::vector<std::array<int, 2>> lb(g.size());
@@ -1337,7 +1350,7 @@ static int build_fused(nwq_vqe* h) {
       h->bwd_blocks.push_back(d);
     }
   }
-  for (auto bit = padded.rbegin(); !h->bwd_rb && bit != padded.rend(); ++bit) {
+  for (auto bit = bpadded.rbegin(); !h->bwd_rb && bit != bpadded.rend(); ++bit) {
     const Block& b = *bit;
     std::vector<VqeBwdOp> rev;
     for (auto it = b.gates.rbegin(); it != b.gates.rend(); ++it) {
@@ -1378,7 +1391,8 @@ static int build_fused(nwq_vqe* h) {
   if (!bops.empty()) std::memcpy(prog.data() + h->fused_bwd_off, bops.data(), bops.size() * sizeof(VqeBwdOp));
   if (!rops.empty()) std::memcpy(prog.data() + h->fused_rop_off, rops.data(), rops.size() * sizeof(VqeBwdRop));
   // dynamic LDS above 64 KiB is enabled here, outside any graph capture
-  const size_t max_rb_lds = 2 * bwd_rb_tile_bytes(std::min(h->fused_k, n) < 8 ? 8 : std::min(h->fused_k, n));
+  const int kbt = std::min(std::min(h->fused_k, kBwdMaxTileBits), n);
+  const size_t max_rb_lds = 2 * bwd_rb_tile_bytes(kbt < 8 ? 8 : kbt);
   int rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)max_bwd_lds), "hipFuncSetAttribute");
   if (!rc && h->bwd_rb)
@@ -1392,7 +1406,9 @@ static int build_fused(nwq_vqe* h) {
 }
 
 static int fused_grid(const nwq_vqe* h) {
-  const int k = std::min(std::max(h->fused_k, 8), h->n);
+  // workgroups per state, shared by the forward and backward launches (the
+  // gradient partials have one slot per workgroup): sized on the backward tiles
+  const int k = std::min(std::max(std::min(h->fused_k, kBwdMaxTileBits), 8), h->n);
   const unsigned long long ntiles = 1ull << (h->n - k);
   return (int)std::max<unsigned long long>(1, std::min<unsigned long long>(ntiles, blocks_per_state(h)));
 }
