@@ -310,7 +310,11 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).  A launch
  * shape is the number of pairs / groups per thread (1, 2, 4 or 8; also 16 for
  * classes 1, 2 and 3; class 7 takes only 1) and a non-temporal hint on the
- * loads and stores (0 or 1).  Each class keeps one shape per bucket of the
+ * loads and stores (0 or 1).  Class 1 also takes 32, 64 and 128: on targets
+ * from 9 up these select a kernel where a workgroup of 256, 512 or 1024
+ * threads holds the lower members of its pairs in one half and the upper
+ * members in the other, one entry per thread, and exchanges them through LDS
+ * (targets 0..8 always use an LDS partner exchange, with the hint only).  Each class keeps one shape per bucket of the
  * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
  * one 128-byte line), 1 for bits 3..10, 2 for bits 11 and up.
  * nwq_set_launch with bucket -1 sets all three. */

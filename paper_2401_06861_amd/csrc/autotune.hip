@@ -25,11 +25,19 @@ namespace {
 struct Cand { int ppt, nt; };
 // Without the hint only 1 and 4 groups per thread are offered: on the MI355X
 // the other hint-free shapes never won a target bit at 30 qubits.
-const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0}};
+const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0}, {32, 1}, {64, 1}, {128, 1}};
 
 // 16 groups per thread is offered to the kernels with at most two streams
 // per group (the 4x4 kernel would run out of registers).
 bool allows16(int cls) { return cls == KC_SV1Q || cls == KC_DIAG || cls == KC_PERM; }
+// Shapes 32, 64 and 128 select the split-workgroup exchange kernel of the
+// dense 1q class (256, 512 or 1024 threads; targets from 9 up).
+bool allows_x2(int cls) { return cls == KC_SV1Q; }
+bool valid_ppt(int cls, int ppt) {
+  if (ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8) return true;
+  if (ppt == 16) return allows16(cls);
+  return (ppt == 32 || ppt == 64 || ppt == 128) && allows_x2(cls);
+}
 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
 
@@ -88,8 +96,9 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
   if (!h) return set_error(NWQ_EINVAL, "NULL handle");
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
   if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0, 1 or 2");
-  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && !(ppt == 16 && allows16(cls)))
-    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3)");
+  if (!valid_ppt(cls, ppt))
+    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; "
+                                 "32, 64 or 128 for class 1)");
   if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   for (int b = 0; b < kBuckets; ++b) {
     if (bucket >= 0 && b != bucket) continue;
@@ -109,8 +118,9 @@ int nwq_set_launch_target(nwq_handle h, int cls, int bit, int ppt, int nontempor
     h->tset[cls][bit] = false;
     return NWQ_OK;
   }
-  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && !(ppt == 16 && allows16(cls)))
-    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3)");
+  if (!valid_ppt(cls, ppt))
+    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; "
+                                 "32, 64 or 128 for class 1)");
   if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   h->tcfg[cls][bit].ppt = ppt;
   h->tcfg[cls][bit].nt = nontemporal ? 1 : 0;
@@ -168,7 +178,7 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
     const int nq = std::min(j.lo_max + 1, kMaxTargetBits);
     std::vector<LaunchCfg> cands;
     for (const Cand& c : kCands) {
-      if (c.ppt == 16 && !allows16(j.cls)) continue;
+      if (!valid_ppt(j.cls, c.ppt)) continue;
       if (j.cls == KC_DM2 && c.ppt != 1) continue;   // one group per thread; only the hint varies
       LaunchCfg cfg;
       cfg.ppt = c.ppt;

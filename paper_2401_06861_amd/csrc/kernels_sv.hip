@@ -170,6 +170,29 @@ __global__ __launch_bounds__(NB) void k_sv_1q_xlds(double2* __restrict__ a, unsi
   gst<NTM>(a + i, cfma(cs, v, cmul(cp, p)));
 }
 
+// 1-qubit dense gate on a high target q: a workgroup of NB threads takes H =
+// NB / 2 consecutive pairs; its first H threads hold their lower members and
+// the other H their upper members (2^q further on), one coalesced entry per
+// thread, and each reads its partner from the workgroup's copy in LDS.  With
+// the pair-per-thread kernel each thread keeps two streams in flight; here
+// each wave streams one run.  At n=30: 6.5-6.7 TB/s on most targets from 9
+// up (the best NB varies by target), against 5.8-6.2 for pairs per thread.
+template <int NB, bool NTM>
+__global__ __launch_bounds__(NB) void k_sv_1q_x2(double2* __restrict__ a, unsigned long long u0, int q, Mat2 m) {
+  constexpr unsigned H = NB / 2;
+  __shared__ vd2 t[NB];
+  const unsigned tid = threadIdx.x;
+  const unsigned up = tid / H;
+  const unsigned long long p = u0 + (unsigned long long)blockIdx.x * H + (tid % H);
+  const unsigned long long i = insert0(p, q) + ((unsigned long long)up << q);
+  const vd2 v = gld<NTM>(a + i);
+  t[tid] = v;
+  __syncthreads();
+  const vd2 w = t[tid ^ H];
+  const vd2 cs = up ? tov(m.m[3]) : tov(m.m[0]), cp = up ? tov(m.m[2]) : tov(m.m[1]);
+  gst<NTM>(a + i, cfma(cs, v, cmul(cp, w)));
+}
+
 // Permutation of lane-bit members (X, CX and SWAP with both bits below 6 and
 // the lower below 3): lane l with (l & Q) in {oa, ob} takes lane l ^ X
 // (X = oa ^ ob), the others keep their entry.  MASKED: only moving lanes
@@ -575,6 +598,17 @@ void launch_1q_xlds(hipStream_t s, double2* a, unsigned long long len, int q, co
   }
 }
 
+template <int NB>
+void launch_1q_x2(hipStream_t s, double2* a, unsigned long long npairs, int q, const Mat2& m, bool nt) {
+  const unsigned long long per = kMaxItems / 2;   // pairs per launch (two threads each)
+  for (unsigned long long u0 = 0; u0 < npairs; u0 += per) {
+    const unsigned long long cnt = npairs - u0 < per ? npairs - u0 : per;   // whole workgroups
+    const dim3 grid((unsigned)(cnt / (NB / 2)));
+    if (nt) hipLaunchKernelGGL((k_sv_1q_x2<NB, true>), grid, dim3(NB), 0, s, a, u0, q, m);
+    else hipLaunchKernelGGL((k_sv_1q_x2<NB, false>), grid, dim3(NB), 0, s, a, u0, q, m);
+  }
+}
+
 template <int X, int E, bool MASKED>
 void launch_perm_lane_e(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob, bool nt) {
   const unsigned long long per = kMaxItems * E;
@@ -630,6 +664,14 @@ void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, co
   }
   if (q == 8 && nbits >= 9) {
     launch_1q_xlds<512>(s, a, 1ull << nbits, q, m, cfg.nt != 0);
+    return;
+  }
+  // shapes 32 / 64 / 128: split-workgroup exchange with 256 / 512 / 1024 threads
+  if (cfg.ppt >= 32 && nbits >= 10) {
+    const unsigned long long np = 1ull << (nbits - 1);
+    if (cfg.ppt == 32) launch_1q_x2<256>(s, a, np, q, m, cfg.nt != 0);
+    else if (cfg.ppt == 64) launch_1q_x2<512>(s, a, np, q, m, cfg.nt != 0);
+    else launch_1q_x2<1024>(s, a, np, q, m, cfg.nt != 0);
     return;
   }
   const unsigned long long np = 1ull << (nbits - 1);

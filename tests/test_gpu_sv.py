@@ -211,7 +211,7 @@ def test_every_launch_shape_matches_oracle(nwq, n):
            3: [("cx", (0, n - 1), ()), ("x", (1,), ()), ("swap", (n - 1, n - 2), ())]}
     m2 = np.array([[0.6, 0.8j, 0, 0.1], [0.2, -0.3, 0.5j, 0], [0, 0.4, 0.1 - 0.2j, 0.7], [0.3j, 0, 0.2, -0.5]])
     for cls in (1, 2, 3, 4):
-        for ppt in (1, 2, 4, 8, 16) if cls != 4 else (1, 2, 4, 8):
+        for ppt in {1: (1, 2, 4, 8, 16, 32, 64, 128), 4: (1, 2, 4, 8)}.get(cls, (1, 2, 4, 8, 16)):
             for nt in (0, 1):
                 nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
                 st.load(psi0)
@@ -309,11 +309,13 @@ def test_per_target_launch_shapes(nwq):
     different shape on every bit matches the oracle."""
     n = 14
     st = nwq.SVState(n, reset=False)
-    cycle = [(1, 1), (2, 1), (4, 0), (8, 1), (16, 1), (1, 0)]
+    cycle = [(1, 1), (2, 1), (4, 0), (8, 1), (16, 1), (1, 0), (32, 1), (64, 0), (128, 1)]
     for cls in (1, 2, 3, 4):
         nwq.nwq_set_launch(st.h, cls, -1, 4, 1)
         for q in range(n):
             ppt, nt = cycle[(q + cls) % len(cycle)]
+            if cls != 1 and ppt >= 32:
+                ppt = 2
             if cls == 4 and ppt == 16:
                 ppt = 8
             nwq.nwq_set_launch_target(st.h, cls, q, ppt, nt)
@@ -329,7 +331,7 @@ def test_per_target_launch_shapes(nwq):
     assert nwq.nwq_get_launch_target(st.h, 1, 12) == cycle[(12 + 1) % len(cycle)]
     nwq.nwq_set_launch_target(st.h, 1, 12, 0, 0)       # cleared: the bucket's shape again
     assert nwq.nwq_get_launch_target(st.h, 1, 12) == (4, 1)
-    for bad in ((1, 64, 4, 0), (1, -1, 4, 0), (1, 3, 3, 0), (4, 3, 16, 0), (7, 3, 2, 1)):
+    for bad in ((1, 64, 4, 0), (1, -1, 4, 0), (1, 3, 3, 0), (4, 3, 16, 0), (7, 3, 2, 1), (2, 3, 32, 1)):
         with pytest.raises(nwq.NwqError) as e:
             nwq.nwq_set_launch_target(st.h, *bad)
         assert e.value.code == nwq.NWQ_EINVAL
