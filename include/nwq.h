@@ -314,7 +314,12 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * from 9 up these select a kernel where a workgroup of 256, 512 or 1024
  * threads holds the lower members of its pairs in one half and the upper
  * members in the other, one entry per thread, and exchanges them through LDS
- * (targets 0..8 always use an LDS partner exchange, with the hint only).  Each class keeps one shape per bucket of the
+ * (targets 0..8 always use an LDS partner exchange, with the hint only).
+ * Class 3 takes them too: X, CX and SWAP then run with one moved member per
+ * thread, the two members of a group in the two halves of a workgroup of 256,
+ * 512 or 1024 threads, each written to its partner's place after a barrier
+ * (gates whose bits are all lane bits keep their lane exchange, with up to 4
+ * entries per thread).  Each class keeps one shape per bucket of the
  * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
  * one 128-byte line), 1 for bits 3..10, 2 for bits 11 and up.
  * nwq_set_launch with bucket -1 sets all three. */

@@ -30,9 +30,10 @@ const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0}, 
 // 16 groups per thread is offered to the kernels with at most two streams
 // per group (the 4x4 kernel would run out of registers).
 bool allows16(int cls) { return cls == KC_SV1Q || cls == KC_DIAG || cls == KC_PERM; }
-// Shapes 32, 64 and 128 select the split-workgroup exchange kernel of the
-// dense 1q class (256, 512 or 1024 threads; targets from 9 up).
-bool allows_x2(int cls) { return cls == KC_SV1Q; }
+// Shapes 32, 64 and 128 select the split-workgroup kernels (256, 512 or 1024
+// threads) of the dense 1q class (targets from 9 up) and of the permutation
+// class (where no lane exchange applies).
+bool allows_x2(int cls) { return cls == KC_SV1Q || cls == KC_PERM; }
 bool valid_ppt(int cls, int ppt) {
   if (ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8) return true;
   if (ppt == 16) return allows16(cls);

@@ -394,6 +394,25 @@ __global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, un
   }
 }
 
+// Permutations (X, CX, SWAP) in the split-workgroup layout: the first half
+// of a workgroup reads the member at offA of each of NB/2 consecutive groups,
+// the second half the member at offB; once every member has been read (the
+// barrier) each thread writes its value to its partner's place.  One-qubit
+// groups (X) pass qhi = -1.
+template <int NB, bool NTM>
+__global__ __launch_bounds__(NB) void k_sv_swap_x2(double2* __restrict__ a, unsigned long long u0, int qlo, int qhi,
+                                                   unsigned long long offA, unsigned long long offB) {
+  constexpr unsigned H = NB / 2;
+  const unsigned tid = threadIdx.x;
+  const bool up = tid >= H;
+  const unsigned long long p = u0 + (unsigned long long)blockIdx.x * H + (tid % H);
+  unsigned long long b = insert0(p, qlo);
+  if (qhi >= 0) b = insert0(b, qhi);
+  const vd2 v = gld<NTM>(a + b + (up ? offB : offA));
+  __syncthreads();
+  gst<NTM>(a + b + (up ? offA : offB), v);
+}
+
 // Two-qubit dense gate: quads over the sorted bit pair; member u sits at
 // base + bit0(u) 2^{q0} + bit1(u) 2^{q1} (operator order); out = M v.
 template <int PPT, bool NTM>
@@ -609,6 +628,25 @@ void launch_1q_x2(hipStream_t s, double2* a, unsigned long long npairs, int q, c
   }
 }
 
+template <int NB>
+void launch_swap_x2(hipStream_t s, double2* a, unsigned long long ngroups, int qlo, int qhi, unsigned long long offA,
+                    unsigned long long offB, bool nt) {
+  const unsigned long long per = kMaxItems / 2;   // groups per launch (two threads each)
+  for (unsigned long long u0 = 0; u0 < ngroups; u0 += per) {
+    const unsigned long long cnt = ngroups - u0 < per ? ngroups - u0 : per;   // whole workgroups
+    const dim3 grid((unsigned)(cnt / (NB / 2)));
+    if (nt) hipLaunchKernelGGL((k_sv_swap_x2<NB, true>), grid, dim3(NB), 0, s, a, u0, qlo, qhi, offA, offB);
+    else hipLaunchKernelGGL((k_sv_swap_x2<NB, false>), grid, dim3(NB), 0, s, a, u0, qlo, qhi, offA, offB);
+  }
+}
+// shapes 32 / 64 / 128 of the permutation class: split workgroups of 256 / 512 / 1024 threads
+void launch_swap_x2_cfg(hipStream_t s, double2* a, unsigned long long ngroups, int qlo, int qhi,
+                        unsigned long long offA, unsigned long long offB, const LaunchCfg& cfg) {
+  if (cfg.ppt == 32) launch_swap_x2<256>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt != 0);
+  else if (cfg.ppt == 64) launch_swap_x2<512>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt != 0);
+  else launch_swap_x2<1024>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt != 0);
+}
+
 template <int X, int E, bool MASKED>
 void launch_perm_lane_e(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob, bool nt) {
   const unsigned long long per = kMaxItems * E;
@@ -689,6 +727,10 @@ void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, const LaunchCf
     return;
   }
   const unsigned long long np = 1ull << (nbits - 1);
+  if (cfg.ppt >= 32 && nbits >= 10) {   // 512 pairs fill the largest split workgroup
+    launch_swap_x2_cfg(s, a, np, q, -1, 0, 1ull << q, cfg);
+    return;
+  }
   NWQ_PPT_SWITCH16(k_sv_swap1, np, s, a, np, q);
 }
 
@@ -700,6 +742,10 @@ void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb, unsig
     return;
   }
   const unsigned long long nq = 1ull << (nbits - 2);
+  if (cfg.ppt >= 32 && nbits >= 11) {   // 512 quads fill the largest split workgroup
+    launch_swap_x2_cfg(s, a, nq, lo, hi, offA, offB, cfg);
+    return;
+  }
   NWQ_PPT_SWITCH16(k_sv_swap2, nq, s, a, nq, lo, hi, offA, offB);
 }
 

@@ -208,10 +208,10 @@ def test_every_launch_shape_matches_oracle(nwq, n):
     st = nwq.SVState(n, reset=False)
     ops = {1: [("u3", (n - 1,), (0.3, 1.1, -0.7)), ("ry", (0,), (0.4,)), ("h", (2,), ())],
            2: [("rz", (n // 2,), (0.9,)), ("rzz", (0, 1), (0.3,)), ("t", (n - 1,), ())],
-           3: [("cx", (0, n - 1), ()), ("x", (1,), ()), ("swap", (n - 1, n - 2), ())]}
+           3: [("cx", (0, n - 1), ()), ("x", (1,), ()), ("swap", (n - 1, n - 2), ()), ("x", (n - 2,), ())]}
     m2 = np.array([[0.6, 0.8j, 0, 0.1], [0.2, -0.3, 0.5j, 0], [0, 0.4, 0.1 - 0.2j, 0.7], [0.3j, 0, 0.2, -0.5]])
     for cls in (1, 2, 3, 4):
-        for ppt in {1: (1, 2, 4, 8, 16, 32, 64, 128), 4: (1, 2, 4, 8)}.get(cls, (1, 2, 4, 8, 16)):
+        for ppt in {1: (1, 2, 4, 8, 16, 32, 64, 128), 3: (1, 2, 4, 8, 16, 32, 64, 128), 4: (1, 2, 4, 8)}.get(cls, (1, 2, 4, 8, 16)):
             for nt in (0, 1):
                 nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
                 st.load(psi0)
@@ -314,7 +314,7 @@ def test_per_target_launch_shapes(nwq):
         nwq.nwq_set_launch(st.h, cls, -1, 4, 1)
         for q in range(n):
             ppt, nt = cycle[(q + cls) % len(cycle)]
-            if cls != 1 and ppt >= 32:
+            if cls in (2, 4) and ppt >= 32:
                 ppt = 2
             if cls == 4 and ppt == 16:
                 ppt = 8
