@@ -309,17 +309,22 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
 /* Kernel class ids are the timing classes below (1 sv_1q_dense, 2 sv_diag,
  * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).  A launch
  * shape is the number of pairs / groups per thread (1, 2, 4 or 8; also 16 for
- * classes 1, 2 and 3; class 7 takes only 1) and a non-temporal hint on the
- * loads and stores (0 or 1).  Class 1 also takes 32, 64 and 128: on targets
+ * classes 1, 2 and 3; class 7 takes only 1) and a flags word (the argument
+ * named nontemporal): bit 0 puts a non-temporal hint on the loads and stores;
+ * bit 1, taken only with shapes 32, 64 and 128, orders the workgroups so
+ * that each of the chip's 8 XCDs streams one contiguous eighth of the launch
+ * (workgroup i takes block (i mod 8) G/8 + floor(i / 8) of G; launches whose
+ * G is not a multiple of 8 keep dispatch order).  Flags other than 0 and 1
+ * (0..3 with those shapes) are NWQ_EINVAL.  Class 1 also takes 32, 64 and 128: on targets
  * from 9 up these select a kernel where a workgroup of 256, 512 or 1024
  * threads holds the lower members of its pairs in one half and the upper
  * members in the other, one entry per thread, and exchanges them through LDS
- * (targets 0..8 always use an LDS partner exchange, with the hint only).
+ * (targets 0..8 always use an LDS partner exchange, with the flags only).
  * Class 3 takes them too: X, CX and SWAP then run with one moved member per
  * thread, the two members of a group in the two halves of a workgroup of 256,
  * 512 or 1024 threads, each written to its partner's place after a barrier
- * (gates whose bits are all lane bits keep their lane exchange, with up to 4
- * entries per thread).  Each class keeps one shape per bucket of the
+ * (gates whose bits are all lane bits keep their lane exchange, one entry per
+ * thread).  Each class keeps one shape per bucket of the
  * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
  * one 128-byte line), 1 for bits 3..10, 2 for bits 11 and up.
  * nwq_set_launch with bucket -1 sets all three. */

@@ -37,7 +37,7 @@ def tune(h: int, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, force
     The per-target shapes the tuner picks are cached too (under "targets") and
     applied on a cache hit."""
     kind, n, _ = nwq.nwq_info(h)
-    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|targets1"
+    key = f"{_device_key()}|{'sv' if kind == nwq.KIND_SV else 'dm'}|n{n}|targets2"
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         for name, per_bucket in cache[key]["buckets"].items():

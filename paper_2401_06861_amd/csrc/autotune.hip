@@ -25,7 +25,10 @@ namespace {
 struct Cand { int ppt, nt; };
 // Without the hint only 1 and 4 groups per thread are offered: on the MI355X
 // the other hint-free shapes never won a target bit at 30 qubits.
-const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0}, {32, 1}, {64, 1}, {128, 1}};
+// Shapes 32, 64 and 128 are timed in dispatch order and in XCD-contiguous
+// order (flags 3).
+const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0},
+                       {32, 1}, {64, 1}, {128, 1}, {32, 3}, {64, 3}, {128, 3}};
 
 // 16 groups per thread is offered to the kernels with at most two streams
 // per group (the 4x4 kernel would run out of registers).
@@ -39,6 +42,15 @@ bool valid_ppt(int cls, int ppt) {
   if (ppt == 16) return allows16(cls);
   return (ppt == 32 || ppt == 64 || ppt == 128) && allows_x2(cls);
 }
+// Flags: bit 0 the non-temporal hint; bit 1 the XCD-contiguous workgroup
+// order, which only the split-workgroup shapes take.
+bool valid_flags(int ppt, int flags) {
+  if (flags == 0 || flags == 1) return true;
+  return (flags == 2 || flags == 3) && ppt >= 32;
+}
+constexpr const char* kShapeMsg =
+    "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; 32, 64 or 128 for classes 1 and 3)";
+constexpr const char* kFlagsMsg = "flags must be 0 or 1 (0 to 3 with shapes 32, 64 and 128)";
 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
 
@@ -97,14 +109,13 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
   if (!h) return set_error(NWQ_EINVAL, "NULL handle");
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
   if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0, 1 or 2");
-  if (!valid_ppt(cls, ppt))
-    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; "
-                                 "32, 64 or 128 for class 1)");
+  if (!valid_ppt(cls, ppt)) return set_error(NWQ_EINVAL, kShapeMsg);
+  if (!valid_flags(ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
   if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   for (int b = 0; b < kBuckets; ++b) {
     if (bucket >= 0 && b != bucket) continue;
     h->cfg[cls][b].ppt = ppt;
-    h->cfg[cls][b].nt = nontemporal ? 1 : 0;
+    h->cfg[cls][b].nt = nontemporal;
   }
   for (int q = 0; q < kMaxTargetBits; ++q)   // the bucket's shape now holds for each of its targets
     if (bucket < 0 || bucket_of(q) == bucket) h->tset[cls][q] = false;
@@ -119,12 +130,11 @@ int nwq_set_launch_target(nwq_handle h, int cls, int bit, int ppt, int nontempor
     h->tset[cls][bit] = false;
     return NWQ_OK;
   }
-  if (!valid_ppt(cls, ppt))
-    return set_error(NWQ_EINVAL, "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; "
-                                 "32, 64 or 128 for class 1)");
+  if (!valid_ppt(cls, ppt)) return set_error(NWQ_EINVAL, kShapeMsg);
+  if (!valid_flags(ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
   if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   h->tcfg[cls][bit].ppt = ppt;
-  h->tcfg[cls][bit].nt = nontemporal ? 1 : 0;
+  h->tcfg[cls][bit].nt = nontemporal;
   h->tset[cls][bit] = true;
   return NWQ_OK;
 }

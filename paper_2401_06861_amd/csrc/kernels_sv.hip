@@ -13,6 +13,8 @@
 // hint) is a template choice picked per kernel class and target bucket by
 // the autotuner; the 4x4 kernel stops at 8 groups per thread (register
 // budget).
+#include <type_traits>
+
 #include "nwq_internal.h"
 
 namespace nwq {
@@ -26,6 +28,17 @@ typedef double vd2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned long long insert0(unsigned long long p, int q) {
   const unsigned long long lo = p & ((1ull << q) - 1ull);
   return ((p >> q) << (q + 1)) | lo;
+}
+
+// Workgroup order of the exchange kernels.  The dispatcher hands consecutive
+// workgroups to the chip's 8 XCDs in turn (each XCD with its own L2).  With
+// ORD, workgroup i takes block (i mod 8) G/8 + floor(i / 8) of the launch's G
+// blocks (G a multiple of 8; the launchers check), so each XCD streams one
+// contiguous eighth of the launch instead of every eighth block.
+template <bool ORD>
+__device__ __forceinline__ unsigned long long wg_block() {
+  if constexpr (ORD) return (unsigned long long)((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+  else return blockIdx.x;
 }
 
 __device__ __forceinline__ vd2 mk(double a, double b) { vd2 r; r.x = a; r.y = b; return r; }
@@ -156,11 +169,11 @@ __device__ __forceinline__ vd2 lane_xor_v(vd2 v, int src_byte) {
 // M[b][b] own + M[b][1-b] partner.  At n=30 this runs at 6.7-6.8 TB/s on
 // targets 0-7 (256 threads) and 6.5 TB/s on target 8 (512 threads), against
 // 5.9 TB/s for one pair per thread.
-template <int NB, bool NTM>
+template <int NB, bool NTM, bool ORD>
 __global__ __launch_bounds__(NB) void k_sv_1q_xlds(double2* __restrict__ a, unsigned long long u0, int q, Mat2 m) {
   __shared__ vd2 t[NB];
   const unsigned tid = threadIdx.x;
-  const unsigned long long i = u0 + (unsigned long long)blockIdx.x * NB + tid;
+  const unsigned long long i = u0 + wg_block<ORD>() * NB + tid;
   const vd2 v = gld<NTM>(a + i);
   t[tid] = v;
   __syncthreads();
@@ -177,13 +190,13 @@ __global__ __launch_bounds__(NB) void k_sv_1q_xlds(double2* __restrict__ a, unsi
 // the pair-per-thread kernel each thread keeps two streams in flight; here
 // each wave streams one run.  At n=30: 6.5-6.7 TB/s on most targets from 9
 // up (the best NB varies by target), against 5.8-6.2 for pairs per thread.
-template <int NB, bool NTM>
+template <int NB, bool NTM, bool ORD>
 __global__ __launch_bounds__(NB) void k_sv_1q_x2(double2* __restrict__ a, unsigned long long u0, int q, Mat2 m) {
   constexpr unsigned H = NB / 2;
   __shared__ vd2 t[NB];
   const unsigned tid = threadIdx.x;
   const unsigned up = tid / H;
-  const unsigned long long p = u0 + (unsigned long long)blockIdx.x * H + (tid % H);
+  const unsigned long long p = u0 + wg_block<ORD>() * H + (tid % H);
   const unsigned long long i = insert0(p, q) + ((unsigned long long)up << q);
   const vd2 v = gld<NTM>(a + i);
   t[tid] = v;
@@ -198,10 +211,10 @@ __global__ __launch_bounds__(NB) void k_sv_1q_x2(double2* __restrict__ a, unsign
 // (X = oa ^ ob), the others keep their entry.  MASKED: only moving lanes
 // store; used when the moved runs are at least 4 entries (64 bytes) long,
 // since shorter partial-line writes cost more than writing the lines whole.
-template <int X, int EPT, bool NTM, bool MASKED>
+template <int X, int EPT, bool NTM, bool MASKED, bool ORD>
 __global__ __launch_bounds__(kBlock) void k_sv_perm_lane(double2* __restrict__ a, unsigned long long u0,
                                                          unsigned long long len, int xr, int Q, int oa, int ob) {
-  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+  const unsigned long long start = u0 + wg_block<ORD>() * (kBlock * EPT) + threadIdx.x;
   const int l = threadIdx.x & 63;
   const bool mv = (l & Q) == oa || (l & Q) == ob;
   const int src = (l ^ xr) << 2;
@@ -399,13 +412,13 @@ __global__ __launch_bounds__(kBlock) void k_sv_swap2(double2* __restrict__ a, un
 // the second half the member at offB; once every member has been read (the
 // barrier) each thread writes its value to its partner's place.  One-qubit
 // groups (X) pass qhi = -1.
-template <int NB, bool NTM>
+template <int NB, bool NTM, bool ORD>
 __global__ __launch_bounds__(NB) void k_sv_swap_x2(double2* __restrict__ a, unsigned long long u0, int qlo, int qhi,
                                                    unsigned long long offA, unsigned long long offB) {
   constexpr unsigned H = NB / 2;
   const unsigned tid = threadIdx.x;
   const bool up = tid >= H;
-  const unsigned long long p = u0 + (unsigned long long)blockIdx.x * H + (tid % H);
+  const unsigned long long p = u0 + wg_block<ORD>() * H + (tid % H);
   unsigned long long b = insert0(p, qlo);
   if (qhi >= 0) b = insert0(b, qhi);
   const vd2 v = gld<NTM>(a + b + (up ? offB : offA));
@@ -580,7 +593,7 @@ void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len) {
     const unsigned long long per_ = kMaxItems * P;                                                          \
     for (unsigned long long u0_ = 0; u0_ < (units); u0_ += per_) {                                          \
       const unsigned long long cnt_ = (units) - u0_ < per_ ? (units) - u0_ : per_;                          \
-      if (cfg.nt)                                                                                           \
+      if (cfg.nt & 1)                                                                                       \
         hipLaunchKernelGGL((KERNEL<P, true>), dim3(grid_for(cnt_, kBlock * P)), dim3(kBlock), 0, s, a, u0_, \
                            __VA_ARGS__);                                                                    \
       else                                                                                                  \
@@ -605,56 +618,85 @@ void launch_fill_basis0(hipStream_t s, double2* a, unsigned long long len) {
 // Lane-exchange launches: units are entries; the entries per thread (1, 2 or
 // 4) come from the tuned groups per thread (8 and 16 map to 4).
 namespace {
-inline int lane_ept(const LaunchCfg& cfg) { return cfg.ppt >= 4 ? 4 : (cfg.ppt == 2 ? 2 : 1); }
+inline int lane_ept(const LaunchCfg& cfg) {
+  if (cfg.ppt >= 32) return 1;   // split-workgroup shapes: one entry per thread
+  return cfg.ppt >= 4 ? 4 : (cfg.ppt == 2 ? 2 : 1);
+}
+
+// Calls f(NT, ORD) with the hint and the workgroup order as compile-time
+// booleans (std::true_type / std::false_type).
+template <class F>
+void with_hint_order(bool nt, bool ord, F&& f) {
+  if (nt) {
+    if (ord) f(std::true_type{}, std::true_type{});
+    else f(std::true_type{}, std::false_type{});
+  } else {
+    if (ord) f(std::false_type{}, std::true_type{});
+    else f(std::false_type{}, std::false_type{});
+  }
+}
+// XCD-contiguous order when the flags ask for it and the grid splits into 8 equal parts
+inline bool use_order(int flags, const dim3& grid) { return (flags & 2) && grid.x % 8u == 0; }
 
 template <int NB>
-void launch_1q_xlds(hipStream_t s, double2* a, unsigned long long len, int q, const Mat2& m, bool nt) {
+void launch_1q_xlds(hipStream_t s, double2* a, unsigned long long len, int q, const Mat2& m, int flags) {
   for (unsigned long long u0 = 0; u0 < len; u0 += kMaxItems) {
     const unsigned long long cnt = len - u0 < kMaxItems ? len - u0 : kMaxItems;   // whole workgroups
     const dim3 grid((unsigned)(cnt / NB));
-    if (nt) hipLaunchKernelGGL((k_sv_1q_xlds<NB, true>), grid, dim3(NB), 0, s, a, u0, q, m);
-    else hipLaunchKernelGGL((k_sv_1q_xlds<NB, false>), grid, dim3(NB), 0, s, a, u0, q, m);
+    with_hint_order(flags & 1, use_order(flags, grid), [&](auto nt, auto ord) {
+      hipLaunchKernelGGL((k_sv_1q_xlds<NB, decltype(nt)::value, decltype(ord)::value>), grid, dim3(NB), 0, s, a, u0,
+                         q, m);
+    });
   }
 }
 
 template <int NB>
-void launch_1q_x2(hipStream_t s, double2* a, unsigned long long npairs, int q, const Mat2& m, bool nt) {
+void launch_1q_x2(hipStream_t s, double2* a, unsigned long long npairs, int q, const Mat2& m, int flags) {
   const unsigned long long per = kMaxItems / 2;   // pairs per launch (two threads each)
   for (unsigned long long u0 = 0; u0 < npairs; u0 += per) {
     const unsigned long long cnt = npairs - u0 < per ? npairs - u0 : per;   // whole workgroups
     const dim3 grid((unsigned)(cnt / (NB / 2)));
-    if (nt) hipLaunchKernelGGL((k_sv_1q_x2<NB, true>), grid, dim3(NB), 0, s, a, u0, q, m);
-    else hipLaunchKernelGGL((k_sv_1q_x2<NB, false>), grid, dim3(NB), 0, s, a, u0, q, m);
+    with_hint_order(flags & 1, use_order(flags, grid), [&](auto nt, auto ord) {
+      hipLaunchKernelGGL((k_sv_1q_x2<NB, decltype(nt)::value, decltype(ord)::value>), grid, dim3(NB), 0, s, a, u0, q,
+                         m);
+    });
   }
 }
 
 template <int NB>
 void launch_swap_x2(hipStream_t s, double2* a, unsigned long long ngroups, int qlo, int qhi, unsigned long long offA,
-                    unsigned long long offB, bool nt) {
+                    unsigned long long offB, int flags) {
   const unsigned long long per = kMaxItems / 2;   // groups per launch (two threads each)
   for (unsigned long long u0 = 0; u0 < ngroups; u0 += per) {
     const unsigned long long cnt = ngroups - u0 < per ? ngroups - u0 : per;   // whole workgroups
     const dim3 grid((unsigned)(cnt / (NB / 2)));
-    if (nt) hipLaunchKernelGGL((k_sv_swap_x2<NB, true>), grid, dim3(NB), 0, s, a, u0, qlo, qhi, offA, offB);
-    else hipLaunchKernelGGL((k_sv_swap_x2<NB, false>), grid, dim3(NB), 0, s, a, u0, qlo, qhi, offA, offB);
+    with_hint_order(flags & 1, use_order(flags, grid), [&](auto nt, auto ord) {
+      hipLaunchKernelGGL((k_sv_swap_x2<NB, decltype(nt)::value, decltype(ord)::value>), grid, dim3(NB), 0, s, a, u0,
+                         qlo, qhi, offA, offB);
+    });
   }
 }
 // shapes 32 / 64 / 128 of the permutation class: split workgroups of 256 / 512 / 1024 threads
 void launch_swap_x2_cfg(hipStream_t s, double2* a, unsigned long long ngroups, int qlo, int qhi,
                         unsigned long long offA, unsigned long long offB, const LaunchCfg& cfg) {
-  if (cfg.ppt == 32) launch_swap_x2<256>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt != 0);
-  else if (cfg.ppt == 64) launch_swap_x2<512>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt != 0);
-  else launch_swap_x2<1024>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt != 0);
+  if (cfg.ppt == 32) launch_swap_x2<256>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt);
+  else if (cfg.ppt == 64) launch_swap_x2<512>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt);
+  else launch_swap_x2<1024>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt);
 }
 
 template <int X, int E, bool MASKED>
-void launch_perm_lane_e(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob, bool nt) {
+void launch_perm_lane_e(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob, int flags) {
   const unsigned long long per = kMaxItems * E;
   for (unsigned long long u0 = 0; u0 < len; u0 += per) {
     const unsigned long long cnt = len - u0 < per ? len - u0 : per;
     const dim3 grid(grid_for(cnt, kBlock * E));
-    if (nt) hipLaunchKernelGGL((k_sv_perm_lane<X, E, true, MASKED>), grid, dim3(kBlock), 0, s, a, u0, len, xr, Q, oa, ob);
-    else hipLaunchKernelGGL((k_sv_perm_lane<X, E, false, MASKED>), grid, dim3(kBlock), 0, s, a, u0, len, xr, Q, oa, ob);
+    // the ordered variant exists for one entry per thread (the split-workgroup shapes)
+    const bool ord = E == 1 && use_order(flags, grid);
+    with_hint_order(flags & 1, ord, [&](auto nt, auto o) {
+      constexpr bool O = decltype(o)::value && E == 1;
+      hipLaunchKernelGGL((k_sv_perm_lane<X, E, decltype(nt)::value, MASKED, O>), grid, dim3(kBlock), 0, s, a, u0, len,
+                         xr, Q, oa, ob);
+    });
   }
 }
 template <int X, bool MASKED>
@@ -697,19 +739,19 @@ constexpr int kLaneMinBits = 8;
 void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, const LaunchCfg& cfg) {
   // targets 0-8: LDS partner exchange (only the hint of the tuned shape applies)
   if (q < 8 && nbits >= 8) {
-    launch_1q_xlds<256>(s, a, 1ull << nbits, q, m, cfg.nt != 0);
+    launch_1q_xlds<256>(s, a, 1ull << nbits, q, m, cfg.nt);
     return;
   }
   if (q == 8 && nbits >= 9) {
-    launch_1q_xlds<512>(s, a, 1ull << nbits, q, m, cfg.nt != 0);
+    launch_1q_xlds<512>(s, a, 1ull << nbits, q, m, cfg.nt);
     return;
   }
   // shapes 32 / 64 / 128: split-workgroup exchange with 256 / 512 / 1024 threads
   if (cfg.ppt >= 32 && nbits >= 10) {
     const unsigned long long np = 1ull << (nbits - 1);
-    if (cfg.ppt == 32) launch_1q_x2<256>(s, a, np, q, m, cfg.nt != 0);
-    else if (cfg.ppt == 64) launch_1q_x2<512>(s, a, np, q, m, cfg.nt != 0);
-    else launch_1q_x2<1024>(s, a, np, q, m, cfg.nt != 0);
+    if (cfg.ppt == 32) launch_1q_x2<256>(s, a, np, q, m, cfg.nt);
+    else if (cfg.ppt == 64) launch_1q_x2<512>(s, a, np, q, m, cfg.nt);
+    else launch_1q_x2<1024>(s, a, np, q, m, cfg.nt);
     return;
   }
   const unsigned long long np = 1ull << (nbits - 1);
@@ -763,9 +805,9 @@ void launch_2q_lane_e(hipStream_t s, double2* a, unsigned long long nhalf, int H
 template <int L, bool LQ0>
 void launch_2q_lane_l(hipStream_t s, double2* a, unsigned long long nhalf, int H, const Mat4& m, const LaunchCfg& cfg) {
   switch (lane_ept(cfg)) {
-    case 1: launch_2q_lane_e<L, LQ0, 1>(s, a, nhalf, H, m, cfg.nt); break;
-    case 2: launch_2q_lane_e<L, LQ0, 2>(s, a, nhalf, H, m, cfg.nt); break;
-    default: launch_2q_lane_e<L, LQ0, 4>(s, a, nhalf, H, m, cfg.nt); break;
+    case 1: launch_2q_lane_e<L, LQ0, 1>(s, a, nhalf, H, m, (cfg.nt & 1) != 0); break;
+    case 2: launch_2q_lane_e<L, LQ0, 2>(s, a, nhalf, H, m, (cfg.nt & 1) != 0); break;
+    default: launch_2q_lane_e<L, LQ0, 4>(s, a, nhalf, H, m, (cfg.nt & 1) != 0); break;
   }
 }
 template <bool LQ0>
@@ -854,17 +896,17 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     }
     kq_pick_swizzle(ks);
     const dim3 grid((unsigned)(1ull << (nbits - 12)));   // 16 runs of 256 entries per workgroup
-    if (cfg.nt) hipLaunchKernelGGL(k_sv_kq4_staged<true>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    if (cfg.nt & 1) hipLaunchKernelGGL(k_sv_kq4_staged<true>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
     else hipLaunchKernelGGL(k_sv_kq4_staged<false>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
     return;
   }
   // one group per thread (16 loads in flight at k = 4); only the hint is tunable
   const dim3 grid(grid_for(ng, kBlock));
   if (k == 3) {
-    if (cfg.nt) hipLaunchKernelGGL((k_sv_kq<3, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+    if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq<3, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
     else hipLaunchKernelGGL((k_sv_kq<3, false>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
   } else {
-    if (cfg.nt) hipLaunchKernelGGL((k_sv_kq<4, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+    if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq<4, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
     else hipLaunchKernelGGL((k_sv_kq<4, false>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
   }
 }

@@ -31,8 +31,10 @@ struct QSet {
 // Streaming launch shape chosen by the autotuner (per kernel class and
 // target bucket).
 struct LaunchCfg {
-  int ppt = 4;                       // pairs / groups / elements per thread (1, 2, 4, 8; 16 where allowed)
-  int nt = 0;                        // 1: non-temporal loads and stores
+  int ppt = 4;                       // pairs / groups / elements per thread (1, 2, 4, 8; 16 where allowed;
+                                     // 32, 64, 128: split-workgroup kernels of 256, 512, 1024 threads)
+  int nt = 0;                        // flags: bit 0 non-temporal loads and stores; bit 1 (shapes 32, 64,
+                                     // 128 only) XCD-contiguous workgroup order
 };
 
 // Launch shapes are kept in three buckets per class, by the lowest target

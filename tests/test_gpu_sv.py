@@ -212,7 +212,7 @@ def test_every_launch_shape_matches_oracle(nwq, n):
     m2 = np.array([[0.6, 0.8j, 0, 0.1], [0.2, -0.3, 0.5j, 0], [0, 0.4, 0.1 - 0.2j, 0.7], [0.3j, 0, 0.2, -0.5]])
     for cls in (1, 2, 3, 4):
         for ppt in {1: (1, 2, 4, 8, 16, 32, 64, 128), 3: (1, 2, 4, 8, 16, 32, 64, 128), 4: (1, 2, 4, 8)}.get(cls, (1, 2, 4, 8, 16)):
-            for nt in (0, 1):
+            for nt in ((0, 1, 2, 3) if ppt >= 32 else (0, 1)):
                 nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
                 st.load(psi0)
                 if cls == 4:
@@ -226,14 +226,16 @@ def test_every_launch_shape_matches_oracle(nwq, n):
     st.close()
 
 
-@pytest.mark.parametrize("n", [8, 10])
+@pytest.mark.parametrize("n", [8, 10, 12])
 def test_lane_exchange_kernels(nwq, n):
     """Dense 1q gates on every target (LDS partner exchange on targets 0..8),
     and gates whose bits are all lane bits (below 6, the lower below 3) with
     lane exchanges: X on targets 0..2, CX and SWAP on every
     ordered pair of bits 0..5 with a bit below 3 (DPP partners at distance
     1, 2, 4, 8 and ds_bpermute otherwise; whole-line and masked stores), under
-    every entries-per-thread and hint choice."""
+    every entries-per-thread and hint choice, and with one entry per thread in
+    XCD-contiguous workgroup order (flags 2 and 3; n=12 has grids of a
+    multiple of 8 workgroups, smaller n fall back to dispatch order)."""
     psi0 = W.random_state(n, seed=90 + n)
     st = nwq.SVState(n, reset=False)
     ops = [("u3", (q,), (0.3 + q, 1.1, -0.7)) for q in range(n)] + [("x", (q,), ()) for q in range(3)]
@@ -241,8 +243,8 @@ def test_lane_exchange_kernels(nwq, n):
         if min(a, b) < 3:
             ops.append(("cx", (a, b), ()))
             ops.append(("swap", (a, b), ()))
-    for ppt in (1, 2, 4, 16):
-        for nt in (0, 1):
+    for ppt in (1, 2, 4, 16, 32):
+        for nt in ((0, 1, 2, 3) if ppt >= 32 else (0, 1)):
             nwq.nwq_set_launch(st.h, 1, -1, ppt, nt)
             nwq.nwq_set_launch(st.h, 3, -1, ppt, nt)
             st.load(psi0)
@@ -309,13 +311,13 @@ def test_per_target_launch_shapes(nwq):
     different shape on every bit matches the oracle."""
     n = 14
     st = nwq.SVState(n, reset=False)
-    cycle = [(1, 1), (2, 1), (4, 0), (8, 1), (16, 1), (1, 0), (32, 1), (64, 0), (128, 1)]
+    cycle = [(1, 1), (2, 1), (4, 0), (8, 1), (16, 1), (1, 0), (32, 1), (64, 0), (128, 1), (32, 3), (64, 2), (128, 3)]
     for cls in (1, 2, 3, 4):
         nwq.nwq_set_launch(st.h, cls, -1, 4, 1)
         for q in range(n):
             ppt, nt = cycle[(q + cls) % len(cycle)]
             if cls in (2, 4) and ppt >= 32:
-                ppt = 2
+                ppt, nt = 2, nt & 1
             if cls == 4 and ppt == 16:
                 ppt = 8
             nwq.nwq_set_launch_target(st.h, cls, q, ppt, nt)
@@ -331,7 +333,8 @@ def test_per_target_launch_shapes(nwq):
     assert nwq.nwq_get_launch_target(st.h, 1, 12) == cycle[(12 + 1) % len(cycle)]
     nwq.nwq_set_launch_target(st.h, 1, 12, 0, 0)       # cleared: the bucket's shape again
     assert nwq.nwq_get_launch_target(st.h, 1, 12) == (4, 1)
-    for bad in ((1, 64, 4, 0), (1, -1, 4, 0), (1, 3, 3, 0), (4, 3, 16, 0), (7, 3, 2, 1), (2, 3, 32, 1)):
+    for bad in ((1, 64, 4, 0), (1, -1, 4, 0), (1, 3, 3, 0), (4, 3, 16, 0), (7, 3, 2, 1), (2, 3, 32, 1),
+                (1, 3, 4, 2), (3, 3, 16, 3), (1, 3, 64, 4), (3, 3, 32, -1)):
         with pytest.raises(nwq.NwqError) as e:
             nwq.nwq_set_launch_target(st.h, *bad)
         assert e.value.code == nwq.NWQ_EINVAL
