@@ -309,7 +309,7 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
 /* Kernel class ids are the timing classes below (1 sv_1q_dense, 2 sv_diag,
  * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).  A launch
  * shape is the number of pairs / groups per thread (1, 2, 4 or 8; also 16 for
- * classes 1, 2 and 3; class 7 takes only 1) and a flags word (the argument
+ * classes 1, 2 and 3; class 7 takes 1 and 128 only) and a flags word (the argument
  * named nontemporal): bit 0 puts a non-temporal hint on the loads and stores;
  * bit 1, taken only with shapes 32, 64 and 128, orders the workgroups so
  * that each of the chip's 8 XCDs streams one contiguous eighth of the launch
@@ -324,7 +324,13 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * thread, the two members of a group in the two halves of a workgroup of 256,
  * 512 or 1024 threads, each written to its partner's place after a barrier
  * (gates whose bits are all lane bits keep their lane exchange, one entry per
- * thread).  Each class keeps one shape per bucket of the
+ * thread).  Classes 4 and 6 (4x4 operators) take them as well: a quarter of
+ * the workgroup holds each member of its quads and each thread forms one row
+ * of the operator from LDS (operators with one bit below 3 and the other at
+ * or above 6 keep their lane exchange).  Class 7 takes 128: a workgroup of
+ * 1024 threads holds one member of 64 groups per wave and applies the 16 x 16
+ * operator the same way (low-qubit operators that fit the LDS-staged kernel
+ * keep it).  Each class keeps one shape per bucket of the
  * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
  * one 128-byte line), 1 for bits 3..10, 2 for bits 11 and up.
  * nwq_set_launch with bucket -1 sets all three. */

@@ -34,10 +34,13 @@ const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0},
 // per group (the 4x4 kernel would run out of registers).
 bool allows16(int cls) { return cls == KC_SV1Q || cls == KC_DIAG || cls == KC_PERM; }
 // Shapes 32, 64 and 128 select the split-workgroup kernels (256, 512 or 1024
-// threads) of the dense 1q class (targets from 9 up) and of the permutation
-// class (where no lane exchange applies).
-bool allows_x2(int cls) { return cls == KC_SV1Q || cls == KC_PERM; }
+// threads) of the dense 1q class (targets from 9 up), the permutation class
+// and the 4x4 classes (SV 2q dense, DM 1q superoperator), where no lane
+// exchange applies.
+bool allows_x2(int cls) { return cls == KC_SV1Q || cls == KC_PERM || cls == KC_SV2Q || cls == KC_DM1; }
 bool valid_ppt(int cls, int ppt) {
+  // class 7: one group per thread, or the split-workgroup kernel of 1024 threads
+  if (cls == KC_DM2) return ppt == 1 || ppt == 128;
   if (ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8) return true;
   if (ppt == 16) return allows16(cls);
   return (ppt == 32 || ppt == 64 || ppt == 128) && allows_x2(cls);
@@ -49,7 +52,8 @@ bool valid_flags(int ppt, int flags) {
   return (flags == 2 || flags == 3) && ppt >= 32;
 }
 constexpr const char* kShapeMsg =
-    "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; 32, 64 or 128 for classes 1 and 3)";
+    "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; 32, 64 or 128 for classes 1, 3, 4 "
+    "and 6); class 7 takes 1 or 128";
 constexpr const char* kFlagsMsg = "flags must be 0 or 1 (0 to 3 with shapes 32, 64 and 128)";
 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
@@ -111,7 +115,6 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
   if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0, 1 or 2");
   if (!valid_ppt(cls, ppt)) return set_error(NWQ_EINVAL, kShapeMsg);
   if (!valid_flags(ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
-  if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   for (int b = 0; b < kBuckets; ++b) {
     if (bucket >= 0 && b != bucket) continue;
     h->cfg[cls][b].ppt = ppt;
@@ -132,7 +135,6 @@ int nwq_set_launch_target(nwq_handle h, int cls, int bit, int ppt, int nontempor
   }
   if (!valid_ppt(cls, ppt)) return set_error(NWQ_EINVAL, kShapeMsg);
   if (!valid_flags(ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
-  if (cls == KC_DM2 && ppt != 1) return set_error(NWQ_EINVAL, "class 7 takes one group per thread (ppt 1)");
   h->tcfg[cls][bit].ppt = ppt;
   h->tcfg[cls][bit].nt = nontemporal;
   h->tset[cls][bit] = true;
@@ -190,7 +192,6 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
     std::vector<LaunchCfg> cands;
     for (const Cand& c : kCands) {
       if (!valid_ppt(j.cls, c.ppt)) continue;
-      if (j.cls == KC_DM2 && c.ppt != 1) continue;   // one group per thread; only the hint varies
       LaunchCfg cfg;
       cfg.ppt = c.ppt;
       cfg.nt = c.nt;

@@ -426,6 +426,36 @@ __global__ __launch_bounds__(NB) void k_sv_swap_x2(double2* __restrict__ a, unsi
   gst<NTM>(a + b + (up ? offA : offB), v);
 }
 
+// Dense 4x4 on bits (q0, q1) in the split-workgroup layout: a workgroup of
+// NB threads takes H = NB / 4 consecutive quads, quarter u of its threads
+// holding member u (bit0(u) on q0, bit1(u) on q1) of each, one coalesced
+// entry per thread.  After one barrier each thread forms row u of M times its
+// quad, read from the workgroup's copy in LDS.  H is a multiple of 64, so a
+// wave lies in one quarter and its row of M is uniform.
+template <int NB, bool NTM, bool ORD>
+__global__ __launch_bounds__(NB) void k_sv_2q_x4(double2* __restrict__ a, unsigned long long u0, int lo, int hi,
+                                                 unsigned long long o0, unsigned long long o1, Mat4 m) {
+  constexpr unsigned H = NB / 4;
+  static_assert(H % 64 == 0, "a wave must lie in one quarter");
+  __shared__ vd2 t[NB];
+  const unsigned tid = threadIdx.x, r = tid % H;
+  const unsigned u = __builtin_amdgcn_readfirstlane(tid / H);
+  const unsigned long long p = u0 + wg_block<ORD>() * H + r;
+  const unsigned long long i = insert0(insert0(p, lo), hi) + ((u & 1u) ? o0 : 0ull) + ((u & 2u) ? o1 : 0ull);
+  const vd2 v = gld<NTM>(a + i);
+  t[tid] = v;
+  __syncthreads();
+  // row u picked by value (a pointer into the argument would copy it to scratch)
+  auto coef = [&](int c) {
+    return tov(u == 0 ? m.m[c] : (u == 1 ? m.m[4 + c] : (u == 2 ? m.m[8 + c] : m.m[12 + c])));
+  };
+  vd2 acc = cmul(coef(0), t[r]);
+  acc = cfma(coef(1), t[H + r], acc);
+  acc = cfma(coef(2), t[2 * H + r], acc);
+  acc = cfma(coef(3), t[3 * H + r], acc);
+  gst<NTM>(a + i, acc);
+}
+
 // Two-qubit dense gate: quads over the sorted bit pair; member u sits at
 // base + bit0(u) 2^{q0} + bit1(u) 2^{q1} (operator order); out = M v.
 template <int PPT, bool NTM>
@@ -508,6 +538,35 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsig
     for (int c = 1; c < D; ++c) acc = cfma(tov(M[r * D + c]), v[c], acc);
     gst<NTM>(a + idx[r], acc);
   }
+}
+
+// 16 x 16 operator in the split-workgroup layout: a workgroup of 1024 threads
+// takes 64 consecutive groups, wave u of it holding member u (operator order)
+// of each, one coalesced entry per thread.  After one barrier each thread
+// forms row u of M (uniform per wave: scalar loads) times its group, read
+// from the workgroup's copy in LDS.
+template <bool NTM, bool ORD>
+__global__ __launch_bounds__(1024) void k_sv_kq4_x16(double2* __restrict__ a, unsigned long long g0, QSet qs,
+                                                     const double2* __restrict__ M) {
+  __shared__ vd2 t[1024];
+  const unsigned tid = threadIdx.x, r = tid & 63u;
+  const unsigned u = __builtin_amdgcn_readfirstlane(tid >> 6);
+  unsigned long long base = g0 + wg_block<ORD>() * 64 + r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) base = insert0(base, qs.sorted[j]);
+  unsigned long long o = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if ((u >> j) & 1u) o += qs.off[j];
+  const unsigned long long i = base + o;
+  const vd2 v = gld<NTM>(a + i);
+  t[tid] = v;
+  __syncthreads();
+  const double2* row = M + 16 * u;
+  vd2 acc = cmul(tov(row[0]), t[r]);
+#pragma unroll
+  for (int c = 1; c < 16; ++c) acc = cfma(tov(row[c]), t[64 * c + r], acc);
+  gst<NTM>(a + i, acc);
 }
 
 // 16 x 16 operator whose two lower bits s0 < s1 lie inside a 256-entry run
@@ -684,6 +743,20 @@ void launch_swap_x2_cfg(hipStream_t s, double2* a, unsigned long long ngroups, i
   else launch_swap_x2<1024>(s, a, ngroups, qlo, qhi, offA, offB, cfg.nt);
 }
 
+template <int NB>
+void launch_2q_x4(hipStream_t s, double2* a, unsigned long long nquads, int lo, int hi, unsigned long long o0,
+                  unsigned long long o1, const Mat4& m, int flags) {
+  const unsigned long long per = kMaxItems / 4;   // quads per launch (four threads each)
+  for (unsigned long long u0 = 0; u0 < nquads; u0 += per) {
+    const unsigned long long cnt = nquads - u0 < per ? nquads - u0 : per;   // whole workgroups
+    const dim3 grid((unsigned)(cnt / (NB / 4)));
+    with_hint_order(flags & 1, use_order(flags, grid), [&](auto nt, auto ord) {
+      hipLaunchKernelGGL((k_sv_2q_x4<NB, decltype(nt)::value, decltype(ord)::value>), grid, dim3(NB), 0, s, a, u0, lo,
+                         hi, o0, o1, m);
+    });
+  }
+}
+
 template <int X, int E, bool MASKED>
 void launch_perm_lane_e(hipStream_t s, double2* a, unsigned long long len, int xr, int Q, int oa, int ob, int flags) {
   const unsigned long long per = kMaxItems * E;
@@ -828,6 +901,13 @@ void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Ma
     else launch_2q_lane<false>(s, a, nhalf, lo, hi, m, cfg);
     return;
   }
+  // shapes 32 / 64 / 128: split workgroups of 256 / 512 / 1024 threads (256 quads fill the largest)
+  if (cfg.ppt >= 32 && nbits >= 10) {
+    if (cfg.ppt == 32) launch_2q_x4<256>(s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m, cfg.nt);
+    else if (cfg.ppt == 64) launch_2q_x4<512>(s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m, cfg.nt);
+    else launch_2q_x4<1024>(s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m, cfg.nt);
+    return;
+  }
   NWQ_PPT_SWITCH(k_sv_2q, nq, s, a, nq, lo, hi, 1ull << q0, 1ull << q1, m);
 }
 
@@ -898,6 +978,19 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     const dim3 grid((unsigned)(1ull << (nbits - 12)));   // 16 runs of 256 entries per workgroup
     if (cfg.nt & 1) hipLaunchKernelGGL(k_sv_kq4_staged<true>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
     else hipLaunchKernelGGL(k_sv_kq4_staged<false>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    return;
+  }
+  // shape 128: split workgroups of 1024 threads, 64 groups each
+  if (k == 4 && cfg.ppt == 128 && nbits >= 10) {
+    const unsigned long long per = kMaxItems / 16;   // groups per launch (sixteen threads each)
+    for (unsigned long long g0 = 0; g0 < ng; g0 += per) {
+      const unsigned long long cnt = ng - g0 < per ? ng - g0 : per;   // whole workgroups
+      const dim3 grid((unsigned)(cnt / 64));
+      with_hint_order(cfg.nt & 1, use_order(cfg.nt, grid), [&](auto nt, auto ord) {
+        hipLaunchKernelGGL((k_sv_kq4_x16<decltype(nt)::value, decltype(ord)::value>), grid, dim3(1024), 0, s, a, g0,
+                           qs, dev_matrix);
+      });
+    }
     return;
   }
   // one group per thread (16 loads in flight at k = 4); only the hint is tunable

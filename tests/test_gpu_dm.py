@@ -185,6 +185,37 @@ def test_low_qubit_superoperators_every_shape(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n", [5, 6, 7])
+def test_split_workgroup_superoperators(nwq, n):
+    """Noisy 1q gates on every qubit (the 4x4 superoperator on bits q and
+    q + n) under the split-workgroup shapes 32, 64 and 128 of the 1q
+    superoperator class, and noisy 2q gates under shape 128 of the 2q class
+    (16 x 16, 1024 threads), with every flag (hint, XCD-contiguous order; n=7
+    has grids of a multiple of 8 workgroups for every shape, n=6 for shapes
+    32 and 64, n=5 for none, which keeps dispatch order), plus a noisy 2q
+    gate.  Qubits whose bit q is below 3 with q + n at or above 6 keep the
+    lane-exchange kernel."""
+    rho0 = W.random_density_matrix(n, seed=80 + n)
+    st = nwq.DMState(n, reset=False)
+    ops = []
+    for q in range(n):
+        ops += [("u3", (q,), (0.3 + q, 1.2, -0.4)), ("depolarize", (q,), (0.05,)), ("amp_damp", (q,), (0.1,))]
+    for a, b in [(0, n - 1), (2, 1), (n - 1, 3), (n - 2, n - 3)]:
+        ops += [("rzz", (a, b), (0.7,)), ("depolarize2", (a, b), (0.02,))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    for cls, ppt in [(6, 32), (6, 64), (6, 128), (7, 128)]:
+        for nt in (0, 1, 2, 3):
+            nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
+            assert nwq.nwq_get_launch(st.h, cls, 1) == (ppt, nt)
+            st.load(rho0)
+            st.run(ops)
+            assert maxerr(st.numpy(), want) <= TOL, (cls, ppt, nt)
+        nwq.nwq_set_launch(st.h, cls, -1, 1, 1)
+    st.close()
+
+
 @pytest.mark.parametrize("n", [8, 9])
 def test_staged_two_qubit_superoperators(nwq, n):
     """Noisy 2q gates whose superoperator has its two lower bits inside a
