@@ -307,33 +307,38 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * ------------------------------------------------------------------------- */
 
 /* Kernel class ids are the timing classes below (1 sv_1q_dense, 2 sv_diag,
- * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).  A launch
- * shape is the number of pairs / groups per thread (1, 2, 4 or 8; also 16 for
- * classes 1, 2 and 3; class 7 takes 1 and 128 only) and a flags word (the argument
- * named nontemporal): bit 0 puts a non-temporal hint on the loads and stores;
- * bit 1, taken only with shapes 32, 64 and 128, orders the workgroups so
- * that each of the chip's 8 XCDs streams one contiguous eighth of the launch
- * (workgroup i takes block (i mod 8) G/8 + floor(i / 8) of G; launches whose
- * G is not a multiple of 8 keep dispatch order).  Flags other than 0 and 1
- * (0..3 with those shapes) are NWQ_EINVAL.  Class 1 also takes 32, 64 and 128: on targets
- * from 9 up these select a kernel where a workgroup of 256, 512 or 1024
- * threads holds the lower members of its pairs in one half and the upper
- * members in the other, one entry per thread, and exchanges them through LDS
- * (targets 0..8 always use an LDS partner exchange, with the flags only).
- * Class 3 takes them too: X, CX and SWAP then run with one moved member per
- * thread, the two members of a group in the two halves of a workgroup of 256,
- * 512 or 1024 threads, each written to its partner's place after a barrier
- * (gates whose bits are all lane bits keep their lane exchange, one entry per
- * thread).  Classes 4 and 6 (4x4 operators) take them as well: a quarter of
- * the workgroup holds each member of its quads and each thread forms one row
- * of the operator from LDS (operators with one bit below 3 and the other at
- * or above 6 keep their lane exchange).  Class 7 takes 128: a workgroup of
- * 1024 threads holds one member of 64 groups per wave and applies the 16 x 16
- * operator the same way (low-qubit operators that fit the LDS-staged kernel
- * keep it).  Each class keeps one shape per bucket of the
- * launch's lowest target bit: bucket 0 for bits 0..2 (partner amplitudes in
- * one 128-byte line), 1 for bits 3..10, 2 for bits 11 and up.
- * nwq_set_launch with bucket -1 sets all three. */
+ * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).
+ *
+ * A launch shape is the number of pairs / groups per thread (1, 2, 4 or 8;
+ * also 16 for classes 1, 2 and 3; class 7 takes 1 and 128 only) and a flags
+ * word (the argument named nontemporal).  Bit 0 of the flags puts a
+ * non-temporal hint on the loads and stores.  Bit 1, taken with shapes 32,
+ * 64 and 128 and with shape 1 of class 2, orders the workgroups so that each
+ * of the chip's 8 XCDs streams one contiguous eighth of the launch: workgroup
+ * i takes block (i mod 8) G/8 + floor(i / 8) of G (launches whose G is not a
+ * multiple of 8 keep dispatch order).  Other flags are NWQ_EINVAL.
+ *
+ * Shapes 32, 64 and 128 select split-workgroup kernels of 256, 512 or 1024
+ * threads, one entry per thread:
+ *  - class 1, targets from 9 up: the lower members of the workgroup's pairs
+ *    in one half, the upper members in the other, exchanged through LDS
+ *    (targets 0..8 always use an LDS partner exchange, with the flags only);
+ *  - class 3: X, CX and SWAP with the two moved members of a group in the two
+ *    halves, each written to its partner's place after a barrier (gates whose
+ *    bits are all lane bits keep their lane exchange, one entry per thread);
+ *  - classes 4 and 6 (4x4 operators): a quarter of the workgroup holds each
+ *    member of its quads and each thread forms one row of the operator from
+ *    LDS (operators with one bit below 3 and the other at or above 6 keep
+ *    their lane exchange);
+ *  - class 7, shape 128 only: each of the 16 waves of a 1024-thread
+ *    workgroup holds one member of 64 groups, and the 16 x 16 operator is
+ *    applied the same way (low-qubit operators that fit the LDS-staged
+ *    kernel keep it).
+ *
+ * Each class keeps one shape per bucket of the launch's lowest target bit:
+ * bucket 0 for bits 0..2 (partner amplitudes in one 128-byte line), 1 for
+ * bits 3..10, 2 for bits 11 and up.  nwq_set_launch with bucket -1 sets all
+ * three. */
 #define NWQ_LAUNCH_BUCKETS 3
 int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal);
 int nwq_get_launch(nwq_handle h, int cls, int bucket, int* ppt, int* nontemporal);

@@ -25,10 +25,10 @@ namespace {
 struct Cand { int ppt, nt; };
 // Without the hint only 1 and 4 groups per thread are offered: on the MI355X
 // the other hint-free shapes never won a target bit at 30 qubits.
-// Shapes 32, 64 and 128 are timed in dispatch order and in XCD-contiguous
-// order (flags 3).
-const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0},
-                       {32, 1}, {64, 1}, {128, 1}, {32, 3}, {64, 3}, {128, 3}};
+// Shapes 32, 64 and 128 (and one entry per thread of the diagonal class) are
+// timed in dispatch order and in XCD-contiguous order (flags 3).
+const Cand kCands[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {1, 0}, {4, 0}, {32, 1},
+                       {64, 1}, {128, 1}, {32, 3}, {64, 3}, {128, 3}, {1, 3}};
 
 // 16 groups per thread is offered to the kernels with at most two streams
 // per group (the 4x4 kernel would run out of registers).
@@ -46,15 +46,16 @@ bool valid_ppt(int cls, int ppt) {
   return (ppt == 32 || ppt == 64 || ppt == 128) && allows_x2(cls);
 }
 // Flags: bit 0 the non-temporal hint; bit 1 the XCD-contiguous workgroup
-// order, which only the split-workgroup shapes take.
-bool valid_flags(int ppt, int flags) {
+// order, which the split-workgroup shapes and one entry per thread of the
+// diagonal class take.
+bool valid_flags(int cls, int ppt, int flags) {
   if (flags == 0 || flags == 1) return true;
-  return (flags == 2 || flags == 3) && ppt >= 32;
+  return (flags == 2 || flags == 3) && (ppt >= 32 || (cls == KC_DIAG && ppt == 1));
 }
 constexpr const char* kShapeMsg =
     "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; 32, 64 or 128 for classes 1, 3, 4 "
     "and 6); class 7 takes 1 or 128";
-constexpr const char* kFlagsMsg = "flags must be 0 or 1 (0 to 3 with shapes 32, 64 and 128)";
+constexpr const char* kFlagsMsg = "flags must be 0 or 1 (0 to 3 with shapes 32, 64 and 128, and with shape 1 of class 2)";
 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
 
@@ -114,7 +115,7 @@ int nwq_set_launch(nwq_handle h, int cls, int bucket, int ppt, int nontemporal) 
   if (cls < 0 || cls >= KC_COUNT) return set_error(NWQ_EINVAL, "kernel class out of range");
   if (bucket < -1 || bucket >= kBuckets) return set_error(NWQ_EINVAL, "bucket must be -1, 0, 1 or 2");
   if (!valid_ppt(cls, ppt)) return set_error(NWQ_EINVAL, kShapeMsg);
-  if (!valid_flags(ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
+  if (!valid_flags(cls, ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
   for (int b = 0; b < kBuckets; ++b) {
     if (bucket >= 0 && b != bucket) continue;
     h->cfg[cls][b].ppt = ppt;
@@ -134,7 +135,7 @@ int nwq_set_launch_target(nwq_handle h, int cls, int bit, int ppt, int nontempor
     return NWQ_OK;
   }
   if (!valid_ppt(cls, ppt)) return set_error(NWQ_EINVAL, kShapeMsg);
-  if (!valid_flags(ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
+  if (!valid_flags(cls, ppt, nontemporal)) return set_error(NWQ_EINVAL, kFlagsMsg);
   h->tcfg[cls][bit].ppt = ppt;
   h->tcfg[cls][bit].nt = nontemporal;
   h->tset[cls][bit] = true;
@@ -191,7 +192,7 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
     const int nq = std::min(j.lo_max + 1, kMaxTargetBits);
     std::vector<LaunchCfg> cands;
     for (const Cand& c : kCands) {
-      if (!valid_ppt(j.cls, c.ppt)) continue;
+      if (!valid_ppt(j.cls, c.ppt) || !valid_flags(j.cls, c.ppt, c.nt)) continue;
       LaunchCfg cfg;
       cfg.ppt = c.ppt;
       cfg.nt = c.nt;

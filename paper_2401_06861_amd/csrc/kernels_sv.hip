@@ -326,10 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_sv_2q_lane(double2* __restrict__ a, 
 
 // Diagonal gate on one or two qubits: a_i <- d[u(i)] a_i, u = bit q0 + 2 bit q1
 // (q1 < 0: one qubit).  Entries are chosen with selects, not an indexed load.
-template <int EPT, bool NTM>
+template <int EPT, bool NTM, bool ORD = false>
 __global__ __launch_bounds__(kBlock) void k_sv_diag(double2* __restrict__ a, unsigned long long u0, unsigned long long len,
                                                     int q0, int q1, Diag4 d) {
-  const unsigned long long start = u0 + (unsigned long long)blockIdx.x * (kBlock * EPT) + threadIdx.x;
+  const unsigned long long start = u0 + wg_block<ORD>() * (kBlock * EPT) + threadIdx.x;
   const vd2 d0 = tov(d.d[0]), d1 = tov(d.d[1]), d2 = tov(d.d[2]), d3 = tov(d.d[3]);
   const bool two = q1 >= 0;
   const int qq = two ? q1 : q0;
@@ -833,6 +833,17 @@ void launch_sv_1q(hipStream_t s, double2* a, int nbits, int q, const Mat2& m, co
 
 void launch_sv_diag(hipStream_t s, double2* a, int nbits, int q0, int q1, const Diag4& d, const LaunchCfg& cfg) {
   const unsigned long long len = 1ull << nbits;
+  if (cfg.ppt == 1 && (cfg.nt & 2)) {   // one entry per thread in XCD-contiguous order
+    for (unsigned long long u0 = 0; u0 < len; u0 += kMaxItems) {
+      const unsigned long long cnt = len - u0 < kMaxItems ? len - u0 : kMaxItems;
+      const dim3 grid(grid_for(cnt, kBlock));
+      with_hint_order(cfg.nt & 1, use_order(cfg.nt, grid), [&](auto nt, auto ord) {
+        hipLaunchKernelGGL((k_sv_diag<1, decltype(nt)::value, decltype(ord)::value>), grid, dim3(kBlock), 0, s, a, u0,
+                           len, q0, q1, d);
+      });
+    }
+    return;
+  }
   NWQ_PPT_SWITCH16(k_sv_diag, len, s, a, len, q0, q1, d);
 }
 

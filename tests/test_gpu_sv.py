@@ -213,7 +213,7 @@ def test_every_launch_shape_matches_oracle(nwq, n):
     for cls in (1, 2, 3, 4):
         for ppt in {1: (1, 2, 4, 8, 16, 32, 64, 128), 3: (1, 2, 4, 8, 16, 32, 64, 128),
                     4: (1, 2, 4, 8, 32, 64, 128)}.get(cls, (1, 2, 4, 8, 16)):
-            for nt in ((0, 1, 2, 3) if ppt >= 32 else (0, 1)):
+            for nt in ((0, 1, 2, 3) if ppt >= 32 or (cls == 2 and ppt == 1) else (0, 1)):
                 nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
                 st.load(psi0)
                 if cls == 4:
@@ -335,7 +335,8 @@ def test_per_target_launch_shapes(nwq):
     nwq.nwq_set_launch_target(st.h, 1, 12, 0, 0)       # cleared: the bucket's shape again
     assert nwq.nwq_get_launch_target(st.h, 1, 12) == (4, 1)
     for bad in ((1, 64, 4, 0), (1, -1, 4, 0), (1, 3, 3, 0), (4, 3, 16, 0), (7, 3, 2, 1), (2, 3, 32, 1),
-                (1, 3, 4, 2), (3, 3, 16, 3), (1, 3, 64, 4), (3, 3, 32, -1), (7, 3, 32, 1), (4, 3, 8, 3)):
+                (1, 3, 4, 2), (3, 3, 16, 3), (1, 3, 64, 4), (3, 3, 32, -1), (7, 3, 32, 1), (4, 3, 8, 3),
+                (2, 3, 2, 3), (4, 3, 1, 3), (1, 3, 1, 2)):
         with pytest.raises(nwq.NwqError) as e:
             nwq.nwq_set_launch_target(st.h, *bad)
         assert e.value.code == nwq.NWQ_EINVAL
