@@ -679,12 +679,12 @@ struct PassPlan {
   std::vector<int> terms;
 };
 
-static std::vector<PassPlan> plan_pauli_passes(int n, int T, const uint64_t* xm) {
+static std::vector<PassPlan> plan_pauli_passes(int n, const std::vector<int>& ids, const uint64_t* xm) {
   std::vector<PassPlan> passes;
   const int c = n <= 11 ? n : 6;
   const int mmax = n <= 11 ? 0 : std::min(5, n - c);   // tile <= 2^11 amplitudes (32 KiB LDS)
   const uint64_t lowmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
-  for (int t = 0; t < T; ++t) {
+  for (int t : ids) {
     const uint64_t hx = xm[t] & ~lowmask;
     std::vector<int> bits;
     for (int b = 0; b < n; ++b)
@@ -793,12 +793,35 @@ static int run_pauli(nwq_state* h, int T, const uint64_t* xm, const uint64_t* zm
     *rows_out = 2 * T;
     return last_launch("reduce_rows");
   }
-  std::vector<PassPlan> passes = plan_pauli_passes(n, T, xm);
+  // terms with no flipped bits (Z strings) run in streaming passes of their
+  // own, up to 16 consecutive rows each; the others are planned into tiles
+  std::vector<int> flip_ids;
+  for (int t = 0; t < T; ++t)
+    if (xm[t] != 0) flip_ids.push_back(t);
+  std::vector<PassPlan> passes = plan_pauli_passes(n, flip_ids, xm);
   const int G = pauli_tile_grid(n, TileShape{n <= 11 ? n : 6, n <= 11 ? 0 : 5, {}});
   int rc = ensure_partials(h, (size_t)T * G);
   if (rc) return rc;
   rc = ensure_results(h, (size_t)T + 1);
   if (rc) return rc;
+  for (int t = 0; t < T;) {
+    if (xm[t] != 0) {
+      ++t;
+      continue;
+    }
+    ZMasks zs{};
+    int cnt = 0;
+    while (t + cnt < T && cnt < 16 && xm[t + cnt] == 0) {
+      zs.z[cnt] = zm[t + cnt];
+      ++cnt;
+    }
+    timing_begin(h, KC_REDUCE);
+    launch_pauli_diag(h->stream, h->data, n, zs, cnt, h->partials, t, G);
+    timing_end(h);
+    rc = last_launch("pauli_diag");
+    if (rc) return rc;
+    t += cnt;
+  }
   // rows follow the caller's term order
   for (auto& pp : passes) {
     if (pp.shape.m < 0) {

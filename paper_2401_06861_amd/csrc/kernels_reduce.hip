@@ -127,6 +127,77 @@ __global__ __launch_bounds__(kRedBlock) void k_pauli_tile(const double2* __restr
   }
 }
 
+// Terms with no flipped bits: <Z^z> = sum_j (-1)^{|j & z|} |a_j|^2.  A
+// workgroup visits chunks of 256 EPT consecutive entries (grid-stride);
+// thread tid reads entries B + 256 e + tid (e < EPT), one coalesced load each.
+// The sign of entry j splits as the parities of (j & z) over three disjoint
+// bit fields: tid (fixed per thread), e (bits 8.., fixed per e) and the chunk
+// base B (uniform per chunk, scalar work).  Per chunk each term's EPT signs
+// are one bit mask, so a term costs a bit extract and an add per entry (|a|^2
+// is never negative, so the sign bit is set by an OR).
+template <int TPL, int EPT>
+__global__ __launch_bounds__(kRedBlock) void k_pauli_diag(const double2* __restrict__ a, unsigned long long len,
+                                                          ZMasks zs, int count, double* __restrict__ partials,
+                                                          int first_row) {
+  static_assert(kRedBlock == 256 && EPT <= 32, "entry e sits at bit 8 + log2 e");
+  __shared__ double s_acc[TPL][kRedWaves];
+  constexpr unsigned long long kChunk = (unsigned long long)kRedBlock * EPT;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const unsigned tid = threadIdx.x;
+  // per-thread part of each term's sign masks: bit e = parity((tid + 256 e) & z)
+  unsigned fixed[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    fixed[t] = 0u;
+    if (t < count) {
+      const unsigned long long z = zs.z[t];
+      const unsigned tp = (unsigned)__popc(tid & (unsigned)(z & 0xFFull)) & 1u;
+      unsigned m = 0u;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) m |= (((unsigned)__popc((unsigned)e & (unsigned)(z >> 8)) & 1u) ^ tp) << e;
+      fixed[t] = m;
+    }
+  }
+  double acc[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) acc[t] = 0.0;
+  for (unsigned long long B = (unsigned long long)blockIdx.x * kChunk; B < len; B += (unsigned long long)gridDim.x * kChunk) {
+    double p[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const unsigned long long i = B + (unsigned long long)e * kRedBlock + tid;
+      const double2 v = i < len ? a[i] : make_double2(0.0, 0.0);
+      p[e] = fma(v.x, v.x, v.y * v.y);
+    }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+      if (t < count) {
+        // chunk parity: bits of B at and above bit 8 + log2(EPT) (B has none below)
+        const unsigned cb = (unsigned)__popcll(B & zs.z[t]) & 1u;
+        const unsigned sm = fixed[t] ^ (cb ? 0xFFFFFFFFu : 0u);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int hi = __double2hiint(p[e]) | (int)(((sm >> e) & 1u) << 31);
+          acc[t] += __hiloint2double(hi, __double2loint(p[e]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    if (t < count) {
+      const double w = wave_sum(acc[t]);
+      if (lane == 0) s_acc[t][wave] = w;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < count) {
+    double s = 0.0;
+    for (int w = 0; w < kRedWaves; ++w) s += s_acc[threadIdx.x][w];
+    partials[(unsigned long long)(first_row + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
 // One term whose flipped bits do not fit a tile: pairs (j, j^x) over the
 // j with bit h (the lowest bit of x) clear, read straight from global memory.
 __global__ __launch_bounds__(kRedBlock) void k_pauli_pairs(const double2* __restrict__ a, int nbits,
@@ -264,6 +335,12 @@ void launch_pauli_tile(hipStream_t s, const double2* a, int nbits, const TileSha
   const size_t lds = sizeof(double2) << (t.c + t.m);
   hipLaunchKernelGGL(k_pauli_tile<kMaxTermsPerPass>, dim3(grid), dim3(kRedBlock), lds, s, a, nbits, t, terms, count, partials,
                      first_row);
+}
+
+void launch_pauli_diag(hipStream_t s, const double2* a, int nbits, const ZMasks& zs, int count, double* partials,
+                       int first_row, int grid) {
+  hipLaunchKernelGGL((k_pauli_diag<kMaxTermsPerPass, 8>), dim3(grid), dim3(kRedBlock), 0, s, a, 1ull << nbits, zs,
+                     count, partials, first_row);
 }
 
 void launch_pauli_pairs(hipStream_t s, const double2* a, int nbits, unsigned long long x, unsigned long long z,

@@ -82,6 +82,13 @@ struct TileShape {
   int hi[8];                // the high bit positions, ascending
 };
 int pauli_tile_grid(int nbits, const TileShape& t);
+// Terms with no flipped bits (x = 0): up to 16 z masks (global bit
+// positions) by value; partials as above, with the same grid.
+struct ZMasks {
+  unsigned long long z[16];
+};
+void launch_pauli_diag(hipStream_t s, const double2* a, int nbits, const ZMasks& zs, int count, double* partials,
+                       int first_row, int grid);
 void launch_pauli_tile(hipStream_t s, const double2* a, int nbits, const TileShape& t,
                        const TermDev* terms, int count, double* partials, int first_row, int grid);
 // One term with wide x support, pairs read from global memory; partials[block].

@@ -150,6 +150,28 @@ def test_pauli_terms_and_sums(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n", [3, 11, 14])
+def test_diagonal_terms_streaming_pass(nwq, n):
+    """Z strings (no flipped bits) run in streaming passes of up to 16
+    consecutive terms: runs longer than 16, runs cut by terms with flips, and
+    z masks over the thread, entry and chunk bit fields of that pass (bits
+    0-7, 8-10 and 11 up) all match the oracle."""
+    rng = np.random.default_rng(7 + n)
+    psi = W.random_state(n, seed=60 + n)
+    full = (1 << n) - 1
+    terms = [(0, int(rng.integers(1, full + 1)), 1.0) for _ in range(21)]
+    terms += [(1 << (n // 2), 1, 1.0)]
+    terms += [(0, 1 << q, 1.0) for q in range(n)] + [(0, full, 1.0), (0, full & 0x700, 1.0), (0, full & ~0xFF, 1.0)]
+    terms += [(3 & full, 0, 1.0)] + [(0, int(rng.integers(1, full + 1)), 1.0) for _ in range(5)]
+    st = nwq.SVState(n, reset=False)
+    st.load(psi)
+    got = st.expvals(terms)
+    want = np.array([tensor.sv_expval(psi, x, z, n).real for x, z, _ in terms])
+    assert maxerr(got, want) <= TOL
+    assert np.array_equal(st.expvals(terms), got)
+    st.close()
+
+
 def test_tfim_energy_matches_dense(nwq):
     n = 9
     terms = W.tfim_hamiltonian(n, 1.0, 0.8)
