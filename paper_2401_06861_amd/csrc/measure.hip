@@ -40,12 +40,17 @@ __device__ __forceinline__ unsigned long long quantize(double p) {
   return (unsigned long long)(p * kQuantScale);   // exact scaling, truncation = floor
 }
 
+// One streaming pass with non-temporal loads and stores (each entry is read
+// and written once).  xcd_order (grid a multiple of 8): workgroup i takes
+// block (i mod 8) G/8 + floor(i / 8) of each sweep of the grid, so that each
+// of the 8 XCDs, dealt workgroups in turn, streams one contiguous eighth.
 __global__ __launch_bounds__(kBlock) void k_probs_sv(const double2* __restrict__ a, unsigned long long N,
-                                                     double* __restrict__ p) {
-  for (unsigned long long j = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; j < N;
-       j += (unsigned long long)gridDim.x * kBlock) {
-    const vd2m v = *reinterpret_cast<const vd2m*>(a + j);
-    p[j] = v.x * v.x + v.y * v.y;
+                                                     double* __restrict__ p, int xcd_order) {
+  const unsigned long long b =
+      xcd_order ? (unsigned long long)((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3)) : blockIdx.x;
+  for (unsigned long long j = b * kBlock + threadIdx.x; j < N; j += (unsigned long long)gridDim.x * kBlock) {
+    const vd2m v = __builtin_nontemporal_load(reinterpret_cast<const vd2m*>(a + j));
+    __builtin_nontemporal_store(v.x * v.x + v.y * v.y, p + j);
   }
 }
 
@@ -249,10 +254,12 @@ int nwq_probabilities(nwq_handle h, double* probs_dev) {
   int rc = flush_all(h);
   if (rc) return rc;
   const unsigned long long dim = 1ull << h->n;
-  if (h->kind == NWQ_KIND_SV)
-    hipLaunchKernelGGL(k_probs_sv, dim3(grid_n(dim, kBlock, 1u << 20)), dim3(kBlock), 0, h->stream, h->data, dim,
-                       probs_dev);
-  else
+  if (h->kind == NWQ_KIND_SV) {
+    // one entry per thread up to 2^30 entries (the largest grid a dispatch takes)
+    const unsigned grid = grid_n(dim, kBlock, 1u << 22);
+    hipLaunchKernelGGL(k_probs_sv, dim3(grid), dim3(kBlock), 0, h->stream, h->data, dim, probs_dev,
+                       grid % 8u == 0 ? 1 : 0);
+  } else
     hipLaunchKernelGGL(k_probs_dm, dim3(grid_n(dim, kBlock, 1u << 16)), dim3(kBlock), 0, h->stream, h->data, h->n,
                        probs_dev);
   return check_hip(hipGetLastError(), "probabilities");

@@ -36,13 +36,13 @@ def confusions(n, seed, identity_every=3):
 
 
 def test_probabilities_sv_and_dm(nwq, torch):
-    n = 12
-    psi = W.random_state(n, seed=21)
-    st = nwq.SVState(n, reset=False)
-    st.load(psi)
-    p = st.probabilities().cpu().numpy()
-    assert np.max(np.abs(p - M.probabilities_sv(psi))) <= 1e-15
-    st.close()
+    for n in (3, 12, 15):   # one partial workgroup; grids of 16 and 128 (XCD order)
+        psi = W.random_state(n, seed=21 + n)
+        st = nwq.SVState(n, reset=False)
+        st.load(psi)
+        p = st.probabilities().cpu().numpy()
+        assert np.max(np.abs(p - M.probabilities_sv(psi))) <= 1e-15, n
+        st.close()
     n = 5
     rho = W.random_density_matrix(n, seed=22)
     dm = nwq.DMState(n, reset=False)
