@@ -15,7 +15,7 @@ through fused k-qubit LDS blocks, a per-target-qubit U3/CX sweep, the noisy
 density-matrix gate at n=14, and the oracle on the host CPU.
 
     python bench.py [--steps K] [--warmup W] [--n 30] [--depth 40]
-    python bench.py --profile-mode {trace,pmc,fused,vqe}   (short runs for rocprofv3)
+    python bench.py --profile-mode {trace,pmc,fused,vqe,dm}   (short runs for rocprofv3)
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-requests", type=int, default=600)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--profile-mode", choices=["trace", "pmc", "fused", "vqe"], default=None)
+    ap.add_argument("--profile-mode", choices=["trace", "pmc", "fused", "vqe", "dm"], default=None)
     return ap.parse_args()
 
 
@@ -147,6 +147,29 @@ def main():
     arrays = nwq.circuit_arrays(gates)
     zterms = W.single_site_terms(n, "Z")
     stream = torch.cuda.current_stream()
+    if args.profile_mode == "dm":
+        # the noisy TFIM at n=14 (10 Trotter steps, one superoperator pass per
+        # noisy gate, then <Z_i> and purity), twice, after the launch-shape
+        # autotuner; a one-element torch kernel marks where the autotuner ends
+        from paper_2401_06861_amd import autotune
+        nd = 14
+        dm = nwq.DMState(nd)
+        autotune.tune(dm.h, reps=1, cache_path=None)
+        torch.cuda.synchronize()
+        torch.ones(1, dtype=torch.float64, device=dev).add_(1.0)
+        torch.cuda.synchronize()
+        circ = W.noisy_tfim_circuit(nd, 10)
+        zt = W.single_site_terms(nd, "Z")
+        for _ in range(2):
+            dm.reset()
+            dm.run(circ)
+            dm.expvals(zt)
+            dm.purity()
+        torch.cuda.synchronize()
+        dm.close()
+        log("[bench] profile mode dm done")
+        print(json.dumps({"profile_mode": args.profile_mode, "n": nd}))
+        return
     log(f"[bench] allocating n={n} state ({16 * N / 1e9:.2f} GB)")
     psi = torch.empty(N, dtype=torch.complex128, device=dev)
     st = nwq.SVState(n, tensor=psi, stream=stream)
