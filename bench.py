@@ -271,7 +271,7 @@ def main():
                                   "one kernel per gate, then <Z_i> for all i", "n": n, "depth": args.depth,
                       "gates": len(gates), "seed": 0, "parallelism": "single GPU"},
            "pct_peak": round(value / HBM_PEAK_GBS, 4), "roofline": roofline, "kernels": per_class,
-           "launch_shapes": {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
+           "launch_shapes": {k: {b: {"ppt": v[0], "flags": v[1]} for b, v in per.items()}
                              for k, per in tuned.items()}}
 
     if not args.no_extras:
@@ -518,7 +518,7 @@ def dm_leg(nwq, torch):
                           "dpurity": abs(purf - pur)}
     st.set_fusion(0)
     out["tfim_n14_10_steps_fused"] = fused
-    out["launch_shapes"] = {k: {b: {"ppt": v[0], "nontemporal": v[1]} for b, v in per.items()}
+    out["launch_shapes"] = {k: {b: {"ppt": v[0], "flags": v[1]} for b, v in per.items()}
                             for k, per in tuned.items()}
     st.close()
     return out
