@@ -283,12 +283,17 @@ int nwq_readout_noise(int n, double* probs_dev, const double* confusion, void* s
     const double* c = confusion + 4 * q;
     if (!(c[0] == 1.0 && c[3] == 1.0)) qs.push_back(q);
   }
-  for (size_t i0 = 0; i0 < qs.size(); i0 += 4) {
+  // The per-qubit matrices act on different bits and commute, so any grouping
+  // gives the same result up to rounding.  Pass k takes qubits k, k + P,
+  // k + 2P, ... of the list (P passes): the low bits, whose groups would
+  // otherwise be read as short per-thread runs, are spread over the passes.
+  const size_t P = (qs.size() + 3) / 4;
+  for (size_t k = 0; k < P; ++k) {
     ConfGroup cg{};
-    cg.g = (int)std::min<size_t>(4, qs.size() - i0);
-    for (int i = 0; i < cg.g; ++i) {
-      cg.bit[i] = qs[i0 + i];
-      for (int e = 0; e < 4; ++e) cg.cm[i][e] = confusion[4 * qs[i0 + i] + e];
+    for (size_t j = k; j < qs.size() && cg.g < 4; j += P) {
+      cg.bit[cg.g] = qs[j];
+      for (int e = 0; e < 4; ++e) cg.cm[cg.g][e] = confusion[4 * qs[j] + e];
+      ++cg.g;
     }
     const unsigned long long ng = 1ull << (n - cg.g);
     const dim3 grid(grid_n(ng, kBlock, 1u << 20));
