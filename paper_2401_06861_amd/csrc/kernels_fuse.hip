@@ -192,14 +192,21 @@ __device__ __forceinline__ unsigned padl(unsigned l) { return l + (l >> 4); }
 // reads (an in-place update ends every op with a copy of all 16 amplitudes
 // back into the loop-carried registers).  With 3 register bits the second set
 // would push the kernel past 128 VGPRs, so it updates in place.
-template <int NV, int B>
+// R00: M[0][0] is real (U3, RX, RY, H), its imaginary part is not read and
+// the first output of a pair takes two FMAs fewer.
+template <int NV, int B, bool R00 = false>
 __device__ __forceinline__ void rb_dense1(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
   const vd2 m0 = ldv(M), m1 = ldv(M + 1), m2 = ldv(M + 2), m3 = ldv(M + 3);
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     if (j & (1 << B)) continue;
     const vd2 a = x[j], b = x[j | (1 << B)];
-    y[j] = vfma(m0, a, vmul(m1, b));
+    if constexpr (R00) {
+      const vd2 c = vmul(m1, b);
+      y[j] = mkv(fma(m0.x, a.x, c.x), fma(m0.x, a.y, c.y));
+    } else {
+      y[j] = vfma(m0, a, vmul(m1, b));
+    }
     y[j | (1 << B)] = vfma(m2, a, vmul(m3, b));
   }
 }
@@ -263,6 +270,7 @@ template <int R, int B>
 __device__ __forceinline__ void rb_c1(int sel, const vd2 (&x)[1 << R], vd2 (&y)[1 << R], const double2* M) {
   if constexpr (B < R) {
     if (sel == 0) rb_dense1<(1 << R), B>(x, y, M);
+    else if (sel == 3) rb_dense1<(1 << R), B, true>(x, y, M);
     else rb_diag1<(1 << R), B>(x, y, ldv(M), ldv(M + (sel == 1 ? 1 : 3)));
   }
 }
@@ -306,6 +314,7 @@ __device__ __forceinline__ void rb_apply(int code, const double2* __restrict__ M
     NWQ_RB1(0, 0)
     NWQ_RB1(4, 1)
     NWQ_RB1(8, 2)
+    NWQ_RB1(84, 3)
     NWQ_RB2(16, 0)
     NWQ_RB2(32, 1)
     NWQ_RB2(48, 2)
