@@ -134,7 +134,9 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
       return true;
     default:
       op.kind = 0;
-      op.real00 = m[0].imag() == 0.0 ? 1 : 0;
+      op.real00 = (m[0].imag() == 0.0 && m[1].imag() == 0.0 && m[2].imag() == 0.0 && m[3].imag() == 0.0)
+                      ? 2
+                      : (m[0].imag() == 0.0 ? 1 : 0);
       for (int i = 0; i < 4; ++i) mats.push_back(make_double2(m[i].real(), m[i].imag()));
       return true;
   }

@@ -192,15 +192,21 @@ __device__ __forceinline__ unsigned padl(unsigned l) { return l + (l >> 4); }
 // reads (an in-place update ends every op with a copy of all 16 amplitudes
 // back into the loop-carried registers).  With 3 register bits the second set
 // would push the kernel past 128 VGPRs, so it updates in place.
-// R00: M[0][0] is real (U3, RX, RY, H), its imaginary part is not read and
-// the first output of a pair takes two FMAs fewer.
-template <int NV, int B, bool R00 = false>
+// R00: M[0][0] is real (U3, RX), its imaginary part is not read and the
+// first output of a pair takes two FMAs fewer.  REAL: all of M is real (RY,
+// H): four FP64 operations per output instead of eight.
+template <int NV, int B, bool R00 = false, bool REAL = false>
 __device__ __forceinline__ void rb_dense1(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
   const vd2 m0 = ldv(M), m1 = ldv(M + 1), m2 = ldv(M + 2), m3 = ldv(M + 3);
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     if (j & (1 << B)) continue;
     const vd2 a = x[j], b = x[j | (1 << B)];
+    if constexpr (REAL) {
+      y[j] = mkv(fma(m0.x, a.x, m1.x * b.x), fma(m0.x, a.y, m1.x * b.y));
+      y[j | (1 << B)] = mkv(fma(m2.x, a.x, m3.x * b.x), fma(m2.x, a.y, m3.x * b.y));
+      continue;
+    }
     if constexpr (R00) {
       const vd2 c = vmul(m1, b);
       y[j] = mkv(fma(m0.x, a.x, c.x), fma(m0.x, a.y, c.y));
@@ -271,6 +277,7 @@ __device__ __forceinline__ void rb_c1(int sel, const vd2 (&x)[1 << R], vd2 (&y)[
   if constexpr (B < R) {
     if (sel == 0) rb_dense1<(1 << R), B>(x, y, M);
     else if (sel == 3) rb_dense1<(1 << R), B, true>(x, y, M);
+    else if (sel == 4) rb_dense1<(1 << R), B, false, true>(x, y, M);
     else rb_diag1<(1 << R), B>(x, y, ldv(M), ldv(M + (sel == 1 ? 1 : 3)));
   }
 }
@@ -315,6 +322,7 @@ __device__ __forceinline__ void rb_apply(int code, const double2* __restrict__ M
     NWQ_RB1(4, 1)
     NWQ_RB1(8, 2)
     NWQ_RB1(84, 3)
+    NWQ_RB1(88, 4)
     NWQ_RB2(16, 0)
     NWQ_RB2(32, 1)
     NWQ_RB2(48, 2)

@@ -113,17 +113,18 @@ struct FusedOp {            // one gate inside a fused block, tile-local bits
   int o0, o1;               // kind 2: local offsets of q0, q1; kind 3: offsets swapped; kind 4: local bits of q0, q1
   int mat;                  // start of its matrix in the block program's matrix table (double2 units)
   int code;                 // register-blocked kernels: rb_op_code() of the fields above
-  int real00;               // kind 0: M[0][0] is real (U3, RX, RY, H), so its imaginary part is skipped
+  int real00;               // kind 0: 1 when M[0][0] is real (U3, RX), 2 when all of M is (RY, H);
+                            // the imaginary parts known to be zero are skipped
 };
 // One switch index per register-blocked op (kind and register bits): 0 + B
 // dense 2x2, 4 + B diagonal (M[0], M[1]), 8 + B diagonal (M[0], M[3]); with
 // u = 4 o0 + o1: 16 + u dense 4x4, 32 + u CX, 48 + u SWAP, 64 + u 2q diagonal;
-// 84 + B dense 2x2 with a real M[0][0].
+// 84 + B dense 2x2 with a real M[0][0], 88 + B real dense 2x2.
 constexpr int kRbCodeCopy = 80;   // kernel-internal copy that pads an odd gate count
 inline int rb_op_code(const FusedOp& op) {
   const int u = 4 * op.o0 + op.o1;
   switch (op.kind) {
-    case 0: return op.real00 ? 84 + op.lo : op.lo;
+    case 0: return op.real00 == 2 ? 88 + op.lo : (op.real00 == 1 ? 84 + op.lo : op.lo);
     case 1: return 4 + op.lo;
     case 6: return 8 + op.lo;
     case 2: return 16 + u;

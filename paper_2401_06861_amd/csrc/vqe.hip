@@ -1255,7 +1255,8 @@ static int build_fused(nwq_vqe* h) {
           f.kind = 6;   // RZ: diagonal of its 2x2 table entry
         } else if (op.kind == OP_ROT || op.kind == OP_FIX1) {
           f.kind = 0;
-          f.real00 = op.kind == OP_ROT ? 1 : 0;   // RX, RY: M[0][0] = cos(theta / 2) for every theta
+          // RX: M[0][0] = cos(theta / 2) is real for every theta; RY: all of M is
+          f.real00 = op.kind == OP_ROT ? (op.axis == 1 ? 2 : 1) : 0;
         } else if (op.kind == OP_RZZ || op.kind == OP_CZ) {
           f.kind = 4; f.o0 = r0; f.o1 = r1;
         } else if (op.kind == OP_CX) {
