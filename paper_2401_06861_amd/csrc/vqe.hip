@@ -839,6 +839,19 @@ __device__ __forceinline__ void bw_rot(vd2 (&p)[NV], vd2 (&l)[NV], const double2
       p[k] = cmul(m3, p1);
       l[j] = cmul(m0, l0);
       l[k] = cmul(m3, l1);
+    } else if constexpr (AX == 1) {
+      // RY adjoint: a real 2x2 (the zero imaginary parts are not multiplied;
+      // the rounding is that of the complex form)
+      p[j] = mk(fma(m0.x, p0.x, m1.x * p1.x), fma(m0.x, p0.y, m1.x * p1.y));
+      p[k] = mk(fma(m2.x, p0.x, m3.x * p1.x), fma(m2.x, p0.y, m3.x * p1.y));
+      l[j] = mk(fma(m0.x, l0.x, m1.x * l1.x), fma(m0.x, l0.y, m1.x * l1.y));
+      l[k] = mk(fma(m2.x, l0.x, m3.x * l1.x), fma(m2.x, l0.y, m3.x * l1.y));
+    } else if constexpr (AX == 0) {
+      // RX adjoint: real diagonal, imaginary off-diagonal entries
+      p[j] = mk(fma(m0.x, p0.x, -(m1.y * p1.y)), fma(m0.x, p0.y, m1.y * p1.x));
+      p[k] = mk(fma(-m2.y, p0.y, m3.x * p1.x), fma(m2.y, p0.x, m3.x * p1.y));
+      l[j] = mk(fma(m0.x, l0.x, -(m1.y * l1.y)), fma(m0.x, l0.y, m1.y * l1.x));
+      l[k] = mk(fma(-m2.y, l0.y, m3.x * l1.x), fma(m2.y, l0.x, m3.x * l1.y));
     } else {
       p[j] = cfma(m0, p0, cmul(m1, p1));
       p[k] = cfma(m2, p0, cmul(m3, p1));
