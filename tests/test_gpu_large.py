@@ -83,15 +83,24 @@ def test_above_30_qubits_split_launches_sampled(nwq, torch, n):
     st = nwq.SVState(n, tensor=v, reset=False)
     ops = [("u3", (0,), (0.7, 1.9, -2.3)), ("u3", (n - 1,), (2.9, -1.4, 0.6)), ("rz", (n - 1,), (0.8,)),
            ("rzz", (1, n - 2), (1.1,)), ("cx", (n - 1, 0), ()), ("x", (n - 3,), ()), ("swap", (6, n - 1), ())]
-    for ppt, nt in ((1, 0), (2, 1)):
+    m4 = np.linalg.qr(np.random.default_rng(n).normal(size=(4, 4)) + 1j * np.random.default_rng(n + 1).normal(size=(4, 4)))[0]
+    # shapes 32 / 64 / 128 select the split-workgroup kernels (the diagonal
+    # class takes flags with one entry per thread); flags 2 and 3 add the
+    # XCD-contiguous workgroup order
+    for ppt, nt in ((1, 0), (2, 1), (32, 3), (128, 1), (64, 2)):
         for cls in (1, 2, 3, 4):
-            nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
-        for i, (name, qubits, params) in enumerate(ops):
+            nwq.nwq_set_launch(st.h, cls, -1, 1 if (cls == 2 and ppt >= 32) else ppt, nt)
+        for i, (name, qubits, params) in enumerate(ops + [("matrix", (3, n - 2), None)]):
             idx = tensor.group_indices(sample_bases(n, qubits, seed=100 * ppt + i, count=1 << 14), list(qubits))
             pre = gather(torch, v, idx)
-            st.apply(name, qubits, params)
+            if name == "matrix":
+                st.apply_matrix(list(qubits), m4)
+                M = m4
+            else:
+                st.apply(name, qubits, params)
+                M = G.gate_matrix(name, qubits, params)
             torch.cuda.synchronize()
-            want = tensor.groups_apply(pre, G.gate_matrix(name, qubits, params))
+            want = tensor.groups_apply(pre, M)
             assert np.max(np.abs(gather(torch, v, idx) - want)) <= TOL, (n, ppt, nt, name, qubits)
     assert abs(float(torch.linalg.vector_norm(v)) - 1.0) <= 1e-10
     st.reset()
