@@ -157,9 +157,12 @@ def test_n30_reductions_match_sampled_sums(nwq, torch):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("kind,qubits", [("1q", (0,)), ("1q", (13,)), ("2q", (0, 1)), ("2q", (13, 5))])
-def test_dm_n14_noisy_gate_sampled(nwq, torch, kind, qubits):
-    n = 14
+@pytest.mark.parametrize("n,kind,qubits,shape", [
+    (14, "1q", (0,), None), (14, "1q", (13,), None), (14, "2q", (0, 1), None), (14, "2q", (13, 5), None),
+    # 16 qubits (68.7 GB): split-workgroup superoperator kernels over several launches
+    (16, "1q", (5,), (32, 3)), (16, "1q", (15,), (128, 1)), (16, "2q", (4, 11), (128, 3)), (16, "2q", (15, 3), (128, 2)),
+])
+def test_dm_noisy_gate_sampled(nwq, torch, n, kind, qubits, shape):
     nb = 2 * n
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
@@ -179,6 +182,8 @@ def test_dm_n14_noisy_gate_sampled(nwq, torch, kind, qubits):
     idx = tensor.group_indices(sample_bases(nb, vq, seed=3), vq)
     pre = gather(torch, v, idx)
     st = nwq.DMState(n, tensor=v, reset=False)
+    if shape is not None:
+        nwq.nwq_set_launch(st.h, 6 if kind == "1q" else 7, -1, *shape)
     st.run(ops)
     st.flush()
     torch.cuda.synchronize()
