@@ -310,7 +310,7 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  * 3 sv_perm, 4 sv_2q_dense, 6 dm_superop_1q, 7 dm_superop_2q).
  *
  * A launch shape is the number of pairs / groups per thread (1, 2, 4 or 8;
- * also 16 for classes 1, 2 and 3; class 7 takes 1 and 128 only) and a flags
+ * also 16 for classes 1, 2 and 3; class 7 takes 1, 64 and 128 only) and a flags
  * word (the argument named nontemporal).  Bit 0 of the flags puts a
  * non-temporal hint on the loads and stores.  Bit 1, taken with shapes 32,
  * 64 and 128 and with shape 1 of class 2, orders the workgroups so that each
@@ -330,8 +330,9 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms);
  *    member of its quads and each thread forms one row of the operator from
  *    LDS (operators with one bit below 3 and the other at or above 6 keep
  *    their lane exchange);
- *  - class 7, shape 128 only: each of the 16 waves of a 1024-thread
- *    workgroup holds one member of 64 groups, and the 16 x 16 operator is
+ *  - class 7, shapes 128 and 64: each of the 16 waves of a 1024-thread
+ *    workgroup holds one member of 64 groups (128), or each of the 8 waves
+ *    of a 512-thread workgroup holds two (64), and the 16 x 16 operator is
  *    applied the same way (low-qubit operators that fit the LDS-staged
  *    kernel keep it).
  *

@@ -39,8 +39,9 @@ bool allows16(int cls) { return cls == KC_SV1Q || cls == KC_DIAG || cls == KC_PE
 // exchange applies.
 bool allows_x2(int cls) { return cls == KC_SV1Q || cls == KC_PERM || cls == KC_SV2Q || cls == KC_DM1; }
 bool valid_ppt(int cls, int ppt) {
-  // class 7: one group per thread, or the split-workgroup kernel of 1024 threads
-  if (cls == KC_DM2) return ppt == 1 || ppt == 128;
+  // class 7: one group per thread, or the split-workgroup kernels of 1024 or
+  // 512 threads (one or two members per thread)
+  if (cls == KC_DM2) return ppt == 1 || ppt == 64 || ppt == 128;
   if (ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8) return true;
   if (ppt == 16) return allows16(cls);
   return (ppt == 32 || ppt == 64 || ppt == 128) && allows_x2(cls);
@@ -54,7 +55,7 @@ bool valid_flags(int cls, int ppt, int flags) {
 }
 constexpr const char* kShapeMsg =
     "groups per thread must be 1, 2, 4 or 8 (or 16 for classes 1, 2 and 3; 32, 64 or 128 for classes 1, 3, 4 "
-    "and 6); class 7 takes 1 or 128";
+    "and 6); class 7 takes 1, 64 or 128";
 constexpr const char* kFlagsMsg = "flags must be 0 or 1 (0 to 3 with shapes 32, 64 and 128, and with shape 1 of class 2)";
 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);

@@ -540,33 +540,48 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsig
   }
 }
 
-// 16 x 16 operator in the split-workgroup layout: a workgroup of 1024 threads
-// takes 64 consecutive groups, wave u of it holding member u (operator order)
-// of each, one coalesced entry per thread.  After one barrier each thread
-// forms row u of M (uniform per wave: scalar loads) times its group, read
-// from the workgroup's copy in LDS.
-template <bool NTM, bool ORD>
-__global__ __launch_bounds__(1024) void k_sv_kq4_x16(double2* __restrict__ a, unsigned long long g0, QSet qs,
-                                                     const double2* __restrict__ M) {
+// 16 x 16 operator in the split-workgroup layout: a workgroup takes 64
+// consecutive groups; member u (operator order) of each sits in the run of 64
+// entries that wave u mod W loads (W = 16 / MPT waves, MPT members per
+// thread), one coalesced entry per load.  After one barrier each thread forms
+// rows u of M (uniform per wave: scalar loads) times its group, read from the
+// workgroup's copy in LDS; with MPT = 2 each LDS read serves two rows.
+template <int MPT, bool NTM, bool ORD>
+__global__ __launch_bounds__(1024 / MPT) void k_sv_kq4_x16(double2* __restrict__ a, unsigned long long g0, QSet qs,
+                                                           const double2* __restrict__ M) {
+  constexpr unsigned W = 16 / MPT;
   __shared__ vd2 t[1024];
   const unsigned tid = threadIdx.x, r = tid & 63u;
-  const unsigned u = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const unsigned w = __builtin_amdgcn_readfirstlane(tid >> 6);
   unsigned long long base = g0 + wg_block<ORD>() * 64 + r;
 #pragma unroll
   for (int j = 0; j < 4; ++j) base = insert0(base, qs.sorted[j]);
-  unsigned long long o = 0;
+  unsigned long long i[MPT];
+  vd2 acc[MPT];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if ((u >> j) & 1u) o += qs.off[j];
-  const unsigned long long i = base + o;
-  const vd2 v = gld<NTM>(a + i);
-  t[tid] = v;
+  for (int mi = 0; mi < MPT; ++mi) {
+    const unsigned u = w + mi * W;
+    unsigned long long o = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if ((u >> j) & 1u) o += qs.off[j];
+    i[mi] = base + o;
+    acc[mi] = gld<NTM>(a + i[mi]);
+  }
+#pragma unroll
+  for (int mi = 0; mi < MPT; ++mi) t[(w + mi * W) * 64 + r] = acc[mi];
   __syncthreads();
-  const double2* row = M + 16 * u;
-  vd2 acc = cmul(tov(row[0]), t[r]);
+  const vd2 x0 = t[r];
 #pragma unroll
-  for (int c = 1; c < 16; ++c) acc = cfma(tov(row[c]), t[64 * c + r], acc);
-  gst<NTM>(a + i, acc);
+  for (int mi = 0; mi < MPT; ++mi) acc[mi] = cmul(tov(M[16 * (w + mi * W)]), x0);
+#pragma unroll
+  for (int c = 1; c < 16; ++c) {
+    const vd2 x = t[64 * c + r];
+#pragma unroll
+    for (int mi = 0; mi < MPT; ++mi) acc[mi] = cfma(tov(M[16 * (w + mi * W) + c]), x, acc[mi]);
+  }
+#pragma unroll
+  for (int mi = 0; mi < MPT; ++mi) gst<NTM>(a + i[mi], acc[mi]);
 }
 
 // 16 x 16 operator whose two lower bits s0 < s1 lie inside a 256-entry run
@@ -991,15 +1006,20 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     else hipLaunchKernelGGL(k_sv_kq4_staged<false>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
     return;
   }
-  // shape 128: split workgroups of 1024 threads, 64 groups each
-  if (k == 4 && cfg.ppt == 128 && nbits >= 10) {
-    const unsigned long long per = kMaxItems / 16;   // groups per launch (sixteen threads each)
+  // shapes 128 / 64: split workgroups of 1024 threads (one member each) or 512
+  // threads (two members each), 64 groups per workgroup
+  if (k == 4 && (cfg.ppt == 128 || cfg.ppt == 64) && nbits >= 10) {
+    const unsigned long long per = kMaxItems / 16;   // groups per launch (at most sixteen threads each)
     for (unsigned long long g0 = 0; g0 < ng; g0 += per) {
       const unsigned long long cnt = ng - g0 < per ? ng - g0 : per;   // whole workgroups
       const dim3 grid((unsigned)(cnt / 64));
       with_hint_order(cfg.nt & 1, use_order(cfg.nt, grid), [&](auto nt, auto ord) {
-        hipLaunchKernelGGL((k_sv_kq4_x16<decltype(nt)::value, decltype(ord)::value>), grid, dim3(1024), 0, s, a, g0,
-                           qs, dev_matrix);
+        if (cfg.ppt == 128)
+          hipLaunchKernelGGL((k_sv_kq4_x16<1, decltype(nt)::value, decltype(ord)::value>), grid, dim3(1024), 0, s, a,
+                             g0, qs, dev_matrix);
+        else
+          hipLaunchKernelGGL((k_sv_kq4_x16<2, decltype(nt)::value, decltype(ord)::value>), grid, dim3(512), 0, s, a,
+                             g0, qs, dev_matrix);
       });
     }
     return;

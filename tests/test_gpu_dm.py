@@ -189,8 +189,8 @@ def test_low_qubit_superoperators_every_shape(nwq, n):
 def test_split_workgroup_superoperators(nwq, n):
     """Noisy 1q gates on every qubit (the 4x4 superoperator on bits q and
     q + n) under the split-workgroup shapes 32, 64 and 128 of the 1q
-    superoperator class, and noisy 2q gates under shape 128 of the 2q class
-    (16 x 16, 1024 threads), with every flag (hint, XCD-contiguous order; n=7
+    superoperator class, and noisy 2q gates under shapes 64 and 128 of the 2q
+    class (16 x 16; 512 threads with two members each, or 1024 with one), with every flag (hint, XCD-contiguous order; n=7
     has grids of a multiple of 8 workgroups for every shape, n=6 for shapes
     32 and 64, n=5 for none, which keeps dispatch order), plus a noisy 2q
     gate.  Qubits whose bit q is below 3 with q + n at or above 6 keep the
@@ -205,7 +205,7 @@ def test_split_workgroup_superoperators(nwq, n):
     want = rho0
     for op in ops:
         want = tensor.dm_apply(want, op, n)
-    for cls, ppt in [(6, 32), (6, 64), (6, 128), (7, 128)]:
+    for cls, ppt in [(6, 32), (6, 64), (6, 128), (7, 64), (7, 128)]:
         for nt in (0, 1, 2, 3):
             nwq.nwq_set_launch(st.h, cls, -1, ppt, nt)
             assert nwq.nwq_get_launch(st.h, cls, 1) == (ppt, nt)

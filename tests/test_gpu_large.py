@@ -160,7 +160,7 @@ def test_n30_reductions_match_sampled_sums(nwq, torch):
 @pytest.mark.parametrize("n,kind,qubits,shape", [
     (14, "1q", (0,), None), (14, "1q", (13,), None), (14, "2q", (0, 1), None), (14, "2q", (13, 5), None),
     # 16 qubits (68.7 GB): split-workgroup superoperator kernels over several launches
-    (16, "1q", (5,), (32, 3)), (16, "1q", (15,), (128, 1)), (16, "2q", (4, 11), (128, 3)), (16, "2q", (15, 3), (128, 2)),
+    (16, "1q", (5,), (32, 3)), (16, "1q", (15,), (128, 1)), (16, "2q", (4, 11), (128, 3)), (16, "2q", (15, 3), (64, 2)),
 ])
 def test_dm_noisy_gate_sampled(nwq, torch, n, kind, qubits, shape):
     nb = 2 * n
