@@ -135,10 +135,15 @@ __global__ __launch_bounds__(kRedBlock) void k_pauli_tile(const double2* __restr
 // base B (uniform per chunk, scalar work).  Per chunk each term's EPT signs
 // are one bit mask, so a term costs a bit extract and an add per entry (|a|^2
 // is never negative, so the sign bit is set by an OR).
+// Loads are non-temporal, and with xcd_order (grid a multiple of 8)
+// workgroup i starts at chunk (i mod 8) G/8 + floor(i / 8), so each of the 8
+// XCDs (dealt workgroups in turn) reads contiguous chunks on every sweep.  The
+// chunks each block visits, and so the rounding of the sums, are fixed by the
+// grid size alone.
 template <int TPL, int EPT>
 __global__ __launch_bounds__(kRedBlock) void k_pauli_diag(const double2* __restrict__ a, unsigned long long len,
                                                           ZMasks zs, int count, double* __restrict__ partials,
-                                                          int first_row) {
+                                                          int first_row, int xcd_order) {
   static_assert(kRedBlock == 256 && EPT <= 32, "entry e sits at bit 8 + log2 e");
   __shared__ double s_acc[TPL][kRedWaves];
   constexpr unsigned long long kChunk = (unsigned long long)kRedBlock * EPT;
@@ -161,12 +166,15 @@ __global__ __launch_bounds__(kRedBlock) void k_pauli_diag(const double2* __restr
   double acc[TPL];
 #pragma unroll
   for (int t = 0; t < TPL; ++t) acc[t] = 0.0;
-  for (unsigned long long B = (unsigned long long)blockIdx.x * kChunk; B < len; B += (unsigned long long)gridDim.x * kChunk) {
+  const unsigned long long first =
+      xcd_order ? (unsigned long long)((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3)) : blockIdx.x;
+  for (unsigned long long B = first * kChunk; B < len; B += (unsigned long long)gridDim.x * kChunk) {
     double p[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const unsigned long long i = B + (unsigned long long)e * kRedBlock + tid;
-      const double2 v = i < len ? a[i] : make_double2(0.0, 0.0);
+      typedef double vd2r __attribute__((ext_vector_type(2)));
+      const vd2r v = i < len ? __builtin_nontemporal_load(reinterpret_cast<const vd2r*>(a + i)) : vd2r{0.0, 0.0};
       p[e] = fma(v.x, v.x, v.y * v.y);
     }
 #pragma unroll
@@ -340,7 +348,7 @@ void launch_pauli_tile(hipStream_t s, const double2* a, int nbits, const TileSha
 void launch_pauli_diag(hipStream_t s, const double2* a, int nbits, const ZMasks& zs, int count, double* partials,
                        int first_row, int grid) {
   hipLaunchKernelGGL((k_pauli_diag<kMaxTermsPerPass, 8>), dim3(grid), dim3(kRedBlock), 0, s, a, 1ull << nbits, zs,
-                     count, partials, first_row);
+                     count, partials, first_row, grid % 8 == 0 ? 1 : 0);
 }
 
 void launch_pauli_pairs(hipStream_t s, const double2* a, int nbits, unsigned long long x, unsigned long long z,
