@@ -132,7 +132,7 @@ def cpu_baseline(seconds: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+        print(json.dumps({"error": "the benchmark runs on one GPU; sharding over several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
