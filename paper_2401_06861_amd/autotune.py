@@ -32,7 +32,8 @@ def _load(path: str) -> dict:
 
 
 def tune(h: int, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, force: bool = False) -> dict:
-    """Launch shapes for handle h: {class name: {bucket: [ppt, nontemporal, ms or None]}}
+    """Launch shapes for handle h: {class name: {bucket: [ppt, flags, ms or None]}}
+    (flags: bit 0 the non-temporal hint, bit 1 the XCD-contiguous workgroup order)
     (buckets "low", "mid" and "high" of the lowest target bit: 0-2, 3-10, 11 and up).
     The per-target shapes the tuner picks are cached too (under "targets") and
     applied on a cache hit."""
