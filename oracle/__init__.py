@@ -20,6 +20,9 @@ definitions behind them:
 * ``tensor``  -- tier 1: the same maths as a contraction over the qubit's
                  tensor axis (no dense 2^n operator), for larger n, plus the
                  per-group form used for sampled checks at full size.
+* ``loops``   -- tier 1 again, as plain C index loops (``loops.c``, gcc +
+                 OpenMP) for the full-size workloads: a 14-qubit density
+                 matrix, a 20-qubit VQE, a 30-qubit state vector.
 * ``tfim``    -- exact diagonalisation of the Ising chain and the
                  free-fermion ground energy (the exact reference of Fig. 3).
 * ``vqe``     -- VQE energy, parameter-shift and finite-difference

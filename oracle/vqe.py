@@ -9,8 +9,9 @@ independent ways:
   applied per gate occurrence so shared parameters are summed;
 * central finite differences with step h.
 
-The circuit is simulated with tier 0 (dense) for n <= 6 and tier 1 (tensor
-contractions, pinned to tier 0) above.
+The circuit is simulated with tier 0 (dense) for n <= 6, tier 1 as tensor
+contractions (pinned to tier 0) up to n = 12, and tier 1 as C loops (pinned to
+tiers 0 and 1) above.
 """
 from __future__ import annotations
 
@@ -19,22 +20,27 @@ from typing import Sequence
 
 import numpy as np
 
-from . import dense, tensor
+from . import dense, loops, tensor
 
 
-DENSE_MAX_N = 6   # tier 0 up to here, tier 1 (pinned to tier 0) above
+DENSE_MAX_N = 6    # tier 0 up to here
+TENSOR_MAX_N = 12  # then tier 1 as tensor contractions, then as C loops
 
 
 def _run(gates, n):
     if n <= DENSE_MAX_N:
         return dense.sv_run(gates, n)
-    return tensor.sv_run(gates, n)
+    if n <= TENSOR_MAX_N:
+        return tensor.sv_run(gates, n)
+    return loops.sv_run(gates, n)
 
 
 def _pauli_sum(psi, terms, n):
     if n <= DENSE_MAX_N:
         return dense.sv_pauli_sum(psi, terms, n)
-    return tensor.sv_pauli_sum(psi, terms, n)
+    if n <= TENSOR_MAX_N:
+        return tensor.sv_pauli_sum(psi, terms, n)
+    return loops.sv_pauli_sum(psi, terms, n)
 
 
 def bind(prog, theta, shift_gate: int = -1, shift: float = 0.0):
