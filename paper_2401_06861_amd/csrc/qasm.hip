@@ -229,8 +229,10 @@ class Parser {
     else if (id == "ln") f = std::log;
     else if (id == "sqrt") f = std::sqrt;
     if (!f || !expect('(')) return false;
+    if (++depth_ > 64) return false;     // nested calls count like parentheses
     double a;
     if (!expr(a) || !expect(')')) return false;
+    --depth_;
     v = f(a);
     return true;
   }

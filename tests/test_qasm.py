@@ -86,6 +86,8 @@ def test_library_parser_matches_oracle_reader(nwq, split):
     ("OPENQASM 2.0;\nqreg q[2];\nif (c==1) x q[0];\n", 3),
     ("OPENQASM 2.0;\nqreg q[2];\nrz(" + "(" * 500 + "1" + ")" * 500 + ") q[0];\n", 3),
     ("OPENQASM 2.0;\nqreg q[2];\nrz(" + "-" * 500 + "1) q[0];\n", 3),
+    ("OPENQASM 2.0;\nqreg q[2];\nrz(" + "sin(" * 100000 + "1" + ")" * 100000 + ") q[0];\n", 3),
+    ("OPENQASM 2.0;\nqreg q[2];\nrz(" + "2^" * 500 + "1) q[0];\n", 3),
 ])
 def test_library_parser_errors(nwq, text, line):
     with pytest.raises(nwq.NwqError) as e:
