@@ -412,6 +412,20 @@ size_t nwq_sample_workspace_bytes(int n);
 int nwq_sample(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
                void* work_dev, size_t work_bytes, void* stream);
 
+/* Allocation-free variant of nwq_sample, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as nwq_sample, bit for
+ * bit, without the workspace: the CDF, tile totals and tile offsets live in a
+ * device array inside the library (8 MiB per GPU, held until the process
+ * ends), so n must be at most 20 (NWQ_ERANGE otherwise, before any launch).
+ * The call allocates nothing (its first call on a device looks up that
+ * device's array once).  Every call on one GPU shares that GPU's array and
+ * overwrites it: calls that overlap on one GPU (different streams or
+ * threads) race, and must be ordered by the caller.  The stream must belong
+ * to the current device.  Asynchronous on `stream`. */
+int nwq_sample_noalloc(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
+                       void* stream);
+
 /* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */

@@ -20,6 +20,7 @@
 //     Integer sums are exact and associative, so the CDF is the same in any
 //     order, monotone, and never selects a zero-probability outcome.
 #include <cmath>
+#include <mutex>
 
 #include "engine.h"
 
@@ -236,6 +237,36 @@ __global__ __launch_bounds__(kBlock) void k_sample(const unsigned long long* __r
   out[s] = (long long)lo_i;
 }
 
+// Device scratch of the allocation-free sampler: the CDF of up to
+// 2^kNoAllocMaxN outcomes, then the tile totals and tile offsets.  Each GPU
+// the library runs on holds its own copy (8 MiB) until the process ends.
+constexpr int kNoAllocMaxN = 20;
+constexpr unsigned long long kNoAllocTiles = ((1ull << kNoAllocMaxN) + kScanTile - 1) / kScanTile;
+constexpr unsigned long long kNoAllocEntries = (1ull << kNoAllocMaxN) + 2 * kNoAllocTiles;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocEntries];
+
+// The device address of `scratch` on each device, looked up once per device
+// with that device current (the host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(unsigned long long** out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(NWQ_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return NWQ_OK;
+}
+
 inline unsigned grid_n(unsigned long long units, unsigned long long per, unsigned cap) {
   const unsigned long long g = (units + per - 1) / per;
   return (unsigned)(g < cap ? g : cap);
@@ -316,19 +347,19 @@ size_t nwq_sample_workspace_bytes(int n) {
   return (size_t)(N + 2 * nt) * sizeof(unsigned long long);
 }
 
-int nwq_sample(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
-               void* work_dev, size_t work_bytes, void* stream) {
-  if (n < 1 || n > 34) return set_error(NWQ_ERANGE, "n outside [1, 34]");
-  if (shots < 0 || shots >= (1ll << 31)) return set_error(NWQ_EINVAL, "shot count outside [0, 2^31)");
-  if (!probs_dev || !work_dev || (shots > 0 && (!u_dev || !out_dev))) return set_error(NWQ_EINVAL, "NULL argument");
-  if (work_bytes < nwq_sample_workspace_bytes(n)) return set_error(NWQ_EINVAL, "workspace smaller than nwq_sample_workspace_bytes(n)");
+}  // extern "C"
+
+namespace {
+
+// The scan and the search, with the workspace (CDF of 2^n entries, then the
+// tile totals and the tile offsets) at `work`; arguments already checked.
+int sample_launch(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
+                  unsigned long long* work, hipStream_t s) {
   const unsigned long long N = 1ull << n;
   const unsigned long long ntiles = (N + kScanTile - 1) / kScanTile;
-  if (ntiles > (1ull << 31)) return set_error(NWQ_ERANGE, "too many scan tiles");
-  unsigned long long* cdf = static_cast<unsigned long long*>(work_dev);
+  unsigned long long* cdf = work;
   unsigned long long* totals = cdf + N;
   unsigned long long* offsets = totals + ntiles;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, probs_dev, N, totals);
   hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, totals, (int)ntiles, offsets);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, probs_dev, N, offsets, cdf);
@@ -336,6 +367,40 @@ int nwq_sample(int n, const double* probs_dev, const double* u_dev, long long sh
     hipLaunchKernelGGL(k_sample, dim3((unsigned)((shots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cdf, N, u_dev,
                        shots, out_dev);
   return check_hip(hipGetLastError(), "sample");
+}
+
+int sample_args(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev) {
+  if (n < 1 || n > 34) return set_error(NWQ_ERANGE, "n outside [1, 34]");
+  if (shots < 0 || shots >= (1ll << 31)) return set_error(NWQ_EINVAL, "shot count outside [0, 2^31)");
+  if (!probs_dev || (shots > 0 && (!u_dev || !out_dev))) return set_error(NWQ_EINVAL, "NULL argument");
+  return NWQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nwq_sample(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
+               void* work_dev, size_t work_bytes, void* stream) {
+  int rc = sample_args(n, probs_dev, u_dev, shots, out_dev);
+  if (rc) return rc;
+  if (!work_dev) return set_error(NWQ_EINVAL, "NULL argument");
+  if (work_bytes < nwq_sample_workspace_bytes(n)) return set_error(NWQ_EINVAL, "workspace smaller than nwq_sample_workspace_bytes(n)");
+  return sample_launch(n, probs_dev, u_dev, shots, out_dev, static_cast<unsigned long long*>(work_dev),
+                       static_cast<hipStream_t>(stream));
+}
+
+int nwq_sample_noalloc(int n, const double* probs_dev, const double* u_dev, long long shots, long long* out_dev,
+                       void* stream) {
+  if (n > kNoAllocMaxN)
+    return set_error(NWQ_ERANGE, "nwq_sample_noalloc takes n <= " + std::to_string(kNoAllocMaxN) +
+                                     " (its device scratch holds 2^" + std::to_string(kNoAllocMaxN) + " CDF entries)");
+  int rc = sample_args(n, probs_dev, u_dev, shots, out_dev);
+  if (rc) return rc;
+  unsigned long long* work = nullptr;
+  rc = scratch_address(&work);
+  if (rc) return rc;
+  return sample_launch(n, probs_dev, u_dev, shots, out_dev, work, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -90,6 +90,7 @@ _SIG = {
     "nwq_readout_noise": [C.c_int, C.c_void_p, _dp, C.c_void_p],
     "nwq_sample_workspace_bytes": [C.c_int],
     "nwq_sample": [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
+    "nwq_sample_noalloc": [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p],
     "nwq_timing_read": [_h, C.POINTER(C.c_longlong), _dp, C.c_int],
 }
 for _name, _args in _SIG.items():
@@ -408,6 +409,14 @@ def nwq_sample(n: int, probs, u, out, work, stream=None) -> None:
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(lib.nwq_sample(n, probs.data_ptr(), u.data_ptr(), u.numel(), out.data_ptr(), work.data_ptr(),
                           work.numel() * work.element_size(), s.cuda_stream))
+
+
+def nwq_sample_noalloc(n: int, probs, u, out, stream=None) -> None:
+    """As nwq_sample, with the library's own device scratch instead of a
+    workspace (n <= 20; calls on one GPU must not overlap)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.nwq_sample_noalloc(n, probs.data_ptr(), u.data_ptr(), u.numel(), out.data_ptr(), s.cuda_stream))
 
 
 def nwq_timing_enable(h: int, enable: bool = True) -> None:

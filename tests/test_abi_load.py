@@ -44,6 +44,8 @@ def test_validation_errors_without_device():
     with pytest.raises(nwq.NwqError) as e:
         nwq.nwq_sv_create_from(None, 4)
     assert e.value.code == nwq.NWQ_EINVAL
+    # the allocation-free sampler rejects sizes beyond its scratch before any launch
+    assert nwq.lib.nwq_sample_noalloc(21, None, None, 0, None, None) == nwq.NWQ_ERANGE
 
 
 def test_gate_table_matches_header():
