@@ -174,6 +174,12 @@ int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates);
  * than 2^8 are padded to 2^8 on registers of at least 8 qubits.  Other values:
  * NWQ_EINVAL. */
 int nwq_set_fusion_kernel(nwq_handle h, int kernel);
+/* Flags of the register-blocked fused kernels (1 and 2): bit 0 = load and
+ * store the tiles with non-temporal accesses (each entry is read and written
+ * once per block).  Default 1 (on the MI355X the depth-40 brickwork at 30
+ * qubits runs about 3% faster with it).  Results do not depend on the
+ * flags.  Other values: NWQ_EINVAL. */
+int nwq_set_fusion_flags(nwq_handle h, int flags);
 
 /* Number of register phases (LDS exchanges) of the last fused
  * nwq_apply_circuit (0 when no register-blocked block ran). */
@@ -237,6 +243,21 @@ int nwq_expval_pauli_sum(nwq_handle h, int n_terms, const uint64_t* xmask,
 /* out[t] = Re <P_t> for each term (no coefficients).  Synchronises. */
 int nwq_expval_pauli_terms(nwq_handle h, int n_terms, const uint64_t* xmask,
                            const uint64_t* zmask, double* out);
+/* As nwq_expval_pauli_terms with imaginary parts: out_real[t] = Re <P_t>,
+ * out_imag[t] = Im <P_t> (out_imag may be NULL).  DM: both parts of
+ * Tr(rho P_t) as summed by the kernel, so |Im| measures how far the state
+ * has drifted from Hermitian.  SV: P_t is Hermitian, so the contributions of
+ * the index pairs (j, j ^ x) are complex conjugates; the kernels sum each
+ * pair once (twice its real part), and Im <P_t> is 0 by construction and
+ * returned as 0.  Synchronises. */
+int nwq_expval_pauli_terms_complex(nwq_handle h, int n_terms, const uint64_t* xmask,
+                                   const uint64_t* zmask, double* out_real, double* out_imag);
+
+/* Device bytes the handle holds now: the state if the library allocated it
+ * (nwq_*_create, not *_create_from), the 4 MiB upload ring once used,
+ * reduction scratch and the fused-block program buffer.  Host-side
+ * bookkeeping only: no device call. */
+int nwq_memory(nwq_handle h, size_t* bytes);
 
 /* DM only: out = Re Tr(rho) (imaginary part in *imag_out if non-NULL). */
 int nwq_trace(nwq_handle h, double* out, double* imag_out);
@@ -267,6 +288,17 @@ int nwq_vqe_create(int n, int n_ops, const int* types, const int* qubits, const 
 int nwq_vqe_destroy(nwq_vqe_handle h);
 int nwq_vqe_info(nwq_vqe_handle h, int* n_params, int* n_ops, int* n_slots);
 
+/* Device memory of a context, for callers that budget HBM (the serving
+ * loop): *held = bytes the context holds now (program tables, the fused-block
+ * program once built, and the per-vector buffers of the batched path at its
+ * current capacity); *at_B = bytes it will hold after evaluating B vectors
+ * with its current configuration (the per-vector buffers grow to the largest
+ * B evaluated and are kept until nwq_vqe_destroy; the LDS-resident path
+ * needs none; the fused-block program, tens of KiB, is not counted before
+ * it is built).  Either pointer may be NULL.  Host-side bookkeeping only:
+ * no device call. */
+int nwq_vqe_memory(nwq_vqe_handle h, int B, size_t* held, size_t* at_B);
+
 /* Batched path: B parameter vectors theta_dev[B][n_params] (device, FP64)
  * -> energy_dev[B] and, if grad_dev is non-NULL, grad_dev[B][n_params]
  * (device).  n <= 12 runs one persistent LDS-resident kernel (one workgroup
@@ -296,6 +328,31 @@ int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energ
  * two); blocks_per_state: workgroups per state of modes 2 and 3 (0 = default). */
 int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_state);
 int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_per_state);
+/* Flags of the fused schedule's tile kernels (forward and backward): bit 0 =
+ * non-temporal loads and stores of the tiles.  Default 1.  Results do not
+ * depend on the flags.  Other values: NWQ_EINVAL. */
+int nwq_vqe_set_flags(nwq_vqe_handle h, int flags);
+
+/* Batched VQE for the Ising model of Sec. III (Fig. 4) in one call, without
+ * a context: the n-qubit hardware-efficient ansatz of L layers (each layer
+ * RY(theta) on qubits 0..n-1, RZ(theta) on 0..n-1, then CX(0,1), CX(1,2), ...,
+ * CX(n-2,n-1); P = 2 n L parameters, layer-major, RY block then RZ block)
+ * from |0...0>, and the open-chain transverse-field Ising Hamiltonian
+ * H = -J sum_{i<n-1} Z_i Z_{i+1} - h sum_i X_i with J = J_h[0], h = J_h[1]
+ * (host array of two finite doubles, shared by the batch).
+ * theta_dev[B][P] (device, FP64) -> E_dev[B] and, if grad_dev is non-NULL,
+ * grad_dev[B][P] (device), exactly as nwq_vqe_eval on a context built with
+ * nwq_vqe_create from the same program and terms.  The library keeps one
+ * context per (device, n, L), up to 8 (least recently used freed first), so
+ * only the first call for a shape allocates; a new (J, h) rewrites the
+ * context's term table after its earlier work has finished (the call waits
+ * for it).  Ordered on `stream` like nwq_vqe_eval.  1 <= n <= 30, L >= 1,
+ * 1 <= B <= 65535; errors before any launch leave the outputs untouched.
+ * Calls are serialised by a library lock. */
+int nwq_vqe_batch(int n, int L, const double* J_h, int B, const double* theta_dev, double* E_dev, double* grad_dev,
+                  void* stream);
+/* Frees every context nwq_vqe_batch keeps (waits for their work). */
+int nwq_vqe_batch_release(void);
 
 /* Autotuner: times every valid (mode, threads, blocks_per_state) candidate on
  * B zero parameter vectors with HIP events, keeps the fastest and returns
@@ -354,8 +411,9 @@ int nwq_get_launch_target(nwq_handle h, int cls, int bit, int* ppt, int* nontemp
 
 /* Autotuner: for each class that applies to the handle (SV: 1, 2, 3, 4;
  * DM: 6, 7) and each lowest target bit, time every launch shape with HIP
- * events on the handle's stream and state (self-inverse operations applied in
- * pairs, so the state is unchanged up to the rounding of H H).  Each target
+ * events on the handle's stream and state (self-inverse operations whose
+ * entries are 0 or +-1, applied in pairs: every product and sum is exact, so
+ * the state's values are unchanged).  Each target
  * bit keeps its fastest shape; each bucket keeps the shape with the least
  * total time over its bits.  The mean over a bucket's bits of their best time
  * per launch (ms) goes to best_ms[class * NWQ_LAUNCH_BUCKETS + bucket]
@@ -432,6 +490,15 @@ int nwq_sample_noalloc(int n, const double* probs_dev, const double* u_dev, long
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* nwq_last_error(void);
+
+/* Streaming ceilings (yardsticks for the gate kernels' bandwidth): an
+ * in-place scale a_j <- s a_j of n_entries complex128 entries (read and
+ * write at the same address, the access pattern of a gate pass), and a copy
+ * dst_j <- src_j (buffers must not overlap).  One entry per thread with
+ * non-temporal loads and stores, workgroups in XCD-contiguous order.
+ * Asynchronous on `stream` (hipStream_t); NWQ_EINVAL on a NULL buffer. */
+int nwq_stream_scale(void* buf_dev, size_t n_entries, double s, void* stream);
+int nwq_stream_copy(void* dst_dev, const void* src_dev, size_t n_entries, void* stream);
 
 /* Per-kernel timing with HIP events on the handle's stream: when enabled,
  * every launch is bracketed by events and nwq_timing_read returns, per

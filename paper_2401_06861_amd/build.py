@@ -67,5 +67,53 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# Host-side checking build: every source with AddressSanitizer and
+# UndefinedBehaviorSanitizer on its host code only (the device code is built
+# as usual, without them), linked against the shared sanitizer runtime.  The
+# library then serves the device-free entry points (argument validation, the
+# OpenQASM reader, the fusion planner) in a CPU process that preloads that
+# runtime; it is not used on a GPU.
+SAN_DIR = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libnwq_san.so")
+SAN_FLAGS = [f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"),
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Wno-unused-command-line-argument"]
+
+
+def sanitizer_runtime() -> str:
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
+def build_sanitized(verbose: bool = True) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    def one(src):
+        obj = os.path.join(SAN_DIR, os.path.basename(src) + ".o")
+        r = subprocess.run([HIPCC, *SAN_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc (host, sanitizers) failed on {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, srcs))
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan",
+                        "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                        "-o", SAN_LIB, *objs], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (sanitizers) failed:\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {SAN_LIB} (ASan and UBSan on host code)", file=sys.stderr)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build()
+    if sys.argv[1:] == ["sanitized"]:
+        build_sanitized()
+    else:
+        build()

@@ -5,12 +5,14 @@
 // and 16 for the 1q, diagonal and permutation kernels, x non-temporal hint
 // off/on) with HIP events on the handle's own stream and
 // state, and keeps the fastest.  Candidates apply self-inverse operations in
-// pairs on up to three target bits of the bucket (H H for the dense 1-qubit
-// kernel, Z Z for the diagonal kernel, CX CX for the permutation kernel, CZ
-// as a dense 4x4 twice for the 2-qubit kernel, and on a density matrix
-// Z (x) conj(Z) twice for the 1-qubit superoperator kernel and the diagonal
-// superoperator of Z (x) Z twice for the 16 x 16 kernel), so the state is
-// unchanged except for the rounding of H H.
+// pairs on up to three target bits of the bucket (X as a dense 2x2 twice for
+// the dense 1-qubit kernel, Z Z for the diagonal kernel, CX CX for the
+// permutation kernel, CZ as a dense 4x4 twice for the 2-qubit kernel, and on
+// a density matrix Z (x) conj(Z) twice for the 1-qubit superoperator kernel
+// and the diagonal superoperator of Z (x) Z twice for the 16 x 16 kernel).
+// Every operator entry is 0 or +-1, so each product and sum is exact in
+// FP64 and the pairs leave the state's values unchanged (a zero may change
+// the sign of its zero).  The kernels' timing does not depend on the values.
 //
 // The fusion autotuner times a caller's circuit under every fusion width and
 // fused-kernel choice and keeps the fastest.
@@ -61,9 +63,8 @@ constexpr const char* kFlagsMsg = "flags must be 0 or 1 (0 to 3 with shapes 32, 
 using Runner = void (*)(nwq_state*, const LaunchCfg&, int);
 
 void run_1q(nwq_state* h, const LaunchCfg& c, int q) {
-  const double r = 1.0 / std::sqrt(2.0);
-  Mat2 m;
-  m.m[0] = make_double2(r, 0); m.m[1] = make_double2(r, 0); m.m[2] = make_double2(r, 0); m.m[3] = make_double2(-r, 0);
+  Mat2 m;   // X through the dense kernel
+  m.m[0] = make_double2(0, 0); m.m[1] = make_double2(1, 0); m.m[2] = make_double2(1, 0); m.m[3] = make_double2(0, 0);
   launch_sv_1q(h->stream, h->data, h->nbits, q, m, c);
   launch_sv_1q(h->stream, h->data, h->nbits, q, m, c);
 }

@@ -310,7 +310,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
   const double2* dmats = reinterpret_cast<const double2*>(static_cast<char*>(dev) + mats_off);
   for (const Launch& L : launches) {
     timing_begin(h, KC_FUSED);
-    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats, L.rbits);
+    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats, L.rbits, 1, 0, 0, h->fuse_flags);
     else launch_fused_block(h->stream, h->data, h->nbits, L.d, dops, dmats, h->fuse_k);
     timing_end(h);
     const int rc = check_hip(hipGetLastError(), "fused_block");
@@ -389,6 +389,13 @@ int nwq_set_fusion_kernel(nwq_handle h, int kernel) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
   if (kernel < 0 || kernel > 2) return set_error(NWQ_EINVAL, "fusion kernel must be 0, 1 or 2");
   h->fuse_rb = kernel;
+  return NWQ_OK;
+}
+
+int nwq_set_fusion_flags(nwq_handle h, int flags) {
+  if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
+  if (flags < 0 || flags > 1) return set_error(NWQ_EINVAL, "fusion flags must be 0 or 1");
+  h->fuse_flags = flags;
   return NWQ_OK;
 }
 

@@ -894,6 +894,37 @@ int nwq_expval_pauli_terms(nwq_handle h, int T, const uint64_t* xm, const uint64
   return NWQ_OK;
 }
 
+int nwq_memory(nwq_handle h, size_t* bytes) {
+  if (!h) return set_error(NWQ_EINVAL, "NULL handle");
+  if (!bytes) return set_error(NWQ_EINVAL, "NULL output pointer");
+  size_t b = h->owns ? (size_t)h->len * sizeof(double2) : 0;
+  if (h->arena_dev) b += kArenaBytes;
+  b += h->partials_cap * sizeof(double) + h->results_cap * sizeof(double) + h->fuse_cap;
+  *bytes = b;
+  return NWQ_OK;
+}
+
+int nwq_expval_pauli_terms_complex(nwq_handle h, int T, const uint64_t* xm, const uint64_t* zm, double* out_re,
+                                   double* out_im) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (T < 0 || (T > 0 && (!xm || !zm || !out_re))) return set_error(NWQ_EINVAL, "bad term arrays");
+  if (T == 0) return NWQ_OK;
+  rc = flush_all(h);
+  if (rc) return rc;
+  int rows = 0;
+  rc = run_pauli(h, T, xm, zm, nullptr, &rows);
+  if (rc) return rc;
+  rc = fetch_results(h, rows);
+  if (rc) return rc;
+  const bool dm = h->kind == NWQ_KIND_DM;
+  for (int t = 0; t < T; ++t) {
+    out_re[t] = dm ? h->results_host[2 * t] : h->results_host[t];
+    if (out_im) out_im[t] = dm ? h->results_host[2 * t + 1] : 0.0;
+  }
+  return NWQ_OK;
+}
+
 int nwq_expval_pauli_sum(nwq_handle h, int T, const uint64_t* xm, const uint64_t* zm, const double* coeffs,
                          double* out) {
   int rc = check_handle(h);

@@ -343,7 +343,20 @@ __device__ __forceinline__ void rb_store_phase(double2* __restrict__ tl, const F
   for (int j = 0; j < (1 << R); ++j) stv(tl + ph.st_off[j], v[j]);
 }
 
-template <int R>
+// Global loads and stores of tile entries; NT: non-temporal (each entry is
+// read and written once per block, so nothing is worth keeping in cache).
+template <bool NT>
+__device__ __forceinline__ vd2 gld(const double2* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const vd2*>(p));
+  else return ldv(p);
+}
+template <bool NT>
+__device__ __forceinline__ void gst(double2* p, vd2 v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vd2*>(p));
+  else stv(p, v);
+}
+
+template <int R, bool NT>
 __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __restrict__ a0, int nbits,
                                                                   FusedBlockDev blk,
                                                                   const FusedPhase* __restrict__ phases,
@@ -380,7 +393,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   if (blockIdx.x < ntiles) {
     double2* __restrict__ a0p = tile_ptr(blockIdx.x);
 #pragma unroll
-    for (int j = 0; j < NV; ++j) pf[j] = ldv(a0p + blk.joff[j]);
+    for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(a0p + blk.joff[j]);
   }
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     double2* __restrict__ at = tile_ptr(tile);
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
       if (nx < ntiles) {
         double2* __restrict__ an = tile_ptr(nx);
 #pragma unroll
-        for (int j = 0; j < NV; ++j) pf[j] = ldv(an + blk.joff[j]);
+        for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(an + blk.joff[j]);
       }
     }
     for (int pi = 0; pi < blk.op_count; ++pi) {
@@ -432,7 +445,7 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
 #pragma unroll
       for (int j = 0; j < NV; ++j) r[j] = ldv(t + padl(tid + j * nt));
 #pragma unroll
-      for (int j = 0; j < NV; ++j) stv(at + blk.joff[j], r[j]);
+      for (int j = 0; j < NV; ++j) gst<NT>(at + blk.joff[j], r[j]);
     }
   }
 }
@@ -442,7 +455,8 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
 size_t fused_rb_lds_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << k) / 16); }
 
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
-                     const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid) {
+                     const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid,
+                     int flags) {
   const int k = blk.c + blk.m;
   const unsigned long long ntiles = 1ull << (nbits - k);
   // about four tiles per workgroup (so that the next tile's loads overlap
@@ -452,14 +466,18 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
   const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
   const size_t lds = fused_rb_lds_bytes(k);
   const unsigned long long stride = batch > 1 ? (1ull << nbits) : 0ull;
+  auto go = [&](auto kern, int rb) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(grid, batch), dim3(1u << (k - rb)), lds, s, a, nbits, blk, phases, ops, mats,
+                       stride, mat_stride);
+  };
+  const bool nt = (flags & kFusedNonTemporal) != 0;
   if (rbits == 3) {
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused_rb<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_fused_rb<3>, dim3(grid, batch), dim3(1u << (k - 3)), lds, s, a, nbits, blk, phases, ops, mats,
-                       stride, mat_stride);
+    if (nt) go(k_fused_rb<3, true>, 3);
+    else go(k_fused_rb<3, false>, 3);
   } else {
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused_rb<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_fused_rb<4>, dim3(grid, batch), dim3(1u << (k - 4)), lds, s, a, nbits, blk, phases, ops, mats,
-                       stride, mat_stride);
+    if (nt) go(k_fused_rb<4, true>, 4);
+    else go(k_fused_rb<4, false>, 4);
   }
 }
 

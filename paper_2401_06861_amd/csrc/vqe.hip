@@ -23,6 +23,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "engine.h"
 
@@ -67,6 +68,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
+}
+
+// Sum over a full wave (all 64 lanes active) with DPP lane moves only, no LDS
+// traffic: pairs within quads, quads (half mirror), half rows (mirror), then
+// rows 0 -> 1 and 2 -> 3 (broadcast of lane 15) and rows 0..1 -> 3
+// (broadcast of lane 31); lane 63 ends with the total, which every lane
+// reads.  Lanes a move does not write add 0.  The order is fixed.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_full(double v) {
+  v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);        // row_half_mirror
+  v += dpp_move<0x140>(v);        // row_mirror
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // 2x2 matrices.  Rotations exp(-i t P/2) are built branch-free (the axis
@@ -945,7 +969,20 @@ __device__ __forceinline__ void bw_apply(int code, vd2 (&p)[1 << R], vd2 (&l)[1 
 #undef NWQ_BW2
 }
 
-template <int R>
+// Global loads and stores of tile entries; NT: non-temporal (each entry of
+// phi and lambda is read and written once per block).
+template <bool NT>
+__device__ __forceinline__ vd2 bgld(const double2* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const vd2*>(p));
+  else return ld(p);
+}
+template <bool NT>
+__device__ __forceinline__ void bgst(double2* p, vd2 v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vd2*>(p));
+  else st(p, v);
+}
+
+template <int R, bool NT>
 __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* __restrict__ phi0,
                                                                       double2* __restrict__ lam0, int n,
                                                                       FusedBlockDev blk,
@@ -976,7 +1013,7 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
   const int nops = last.op_begin + last.op_count - op0;
   for (int i = tid; i < nops * kBwdRbMaxWaves; i += nt) acc[i / kBwdRbMaxWaves][i % kBwdRbMaxWaves] = 0.0;
   const unsigned long long glane = bwd_index(0ull, tid, cmask, c, m, blk);
-  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  auto tile_off = [&](unsigned long long tile) {
     unsigned long long base = tile << c;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -985,20 +1022,39 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
         base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
       }
     }
-    double2* __restrict__ ap = phi + (base + glane);
-    double2* __restrict__ al = lam + (base + glane);
+    return base + glane;
+  };
+  // The tile's entries of phi and lambda are loaded one tile ahead: the
+  // loads of the next tile are in flight while this one runs its phases
+  // (tiles are disjoint, so the early read is safe).
+  vd2 fp[NV], fl[NV];
+  if (blockIdx.x < ntiles) {
+    const unsigned long long o = tile_off(blockIdx.x);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      fp[j] = bgld<NT>(phi + o + blk.joff[j]);
+      fl[j] = bgld<NT>(lam + o + blk.joff[j]);
+    }
+  }
+  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const unsigned long long toff = tile_off(tile);
+    double2* __restrict__ ap = phi + toff;
+    double2* __restrict__ al = lam + toff;
     __syncthreads();
     {
-      vd2 rp[NV], rl[NV];
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        rp[j] = ld(ap + blk.joff[j]);
-        rl[j] = ld(al + blk.joff[j]);
+        st(tp + padl_b(tid + j * nt), fp[j]);
+        st(tl + padl_b(tid + j * nt), fl[j]);
       }
+      const unsigned long long nx = tile + gridDim.x;
+      if (nx < ntiles) {
+        const unsigned long long o = tile_off(nx);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        st(tp + padl_b(tid + j * nt), rp[j]);
-        st(tl + padl_b(tid + j * nt), rl[j]);
+        for (int j = 0; j < NV; ++j) {
+          fp[j] = bgld<NT>(phi + o + blk.joff[j]);
+          fl[j] = bgld<NT>(lam + o + blk.joff[j]);
+        }
       }
     }
     for (int pi = 0; pi < blk.op_count; ++pi) {
@@ -1020,7 +1076,7 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
         double g = 0.0;
         bw_apply<R>(op.code, vp, vl, table + op.mat, g);
         if (op.slot >= 0) {
-          const double w = wave_sum(g);
+          const double w = wave_sum_full(g);   // tiles of >= 2^9 entries: whole waves
           if (lane == 0) acc[ph.op_begin + oi - op0][wave] += w;
         }
       }
@@ -1040,8 +1096,8 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
       }
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        st(ap + blk.joff[j], rp[j]);
-        st(al + blk.joff[j], rl[j]);
+        bgst<NT>(ap + blk.joff[j], rp[j]);
+        bgst<NT>(al + blk.joff[j], rl[j]);
       }
     }
   }
@@ -1102,6 +1158,9 @@ struct nwq_vqe {
   size_t fused_ops_off = 0, fused_bwd_off = 0;
   nwq::VqeConfig cfg;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (B, want_grad) -> exec
+  int fused_flags = 1;         // fused schedule: bit 0 non-temporal tile loads and stores
+  size_t program_bytes = 0;    // device bytes of d_ops, d_fixed, d_terms, d_slot_param
+  size_t fused_bytes = 0;      // device bytes of d_fused once built
 };
 
 namespace nwq {
@@ -1150,6 +1209,16 @@ static int launch_lds(nwq_vqe* h, int B, const double* theta, const double* coef
   }
 #undef NWQ_VQE_LDS
   return check_hip(hipGetLastError(), "k_vqe_lds");
+}
+
+// Device bytes of the global-path buffers per parameter vector (what
+// ensure_global allocates for each unit of its capacity).
+static size_t global_bytes_per_vector(const nwq_vqe* h) {
+  const size_t N = 1ull << h->n;
+  const size_t G = (size_t)blocks_per_state(h);
+  const size_t P = std::max(1, h->P), S = std::max(1, h->nslots), T = std::max(1, h->nterms), O = std::max(1, h->nops);
+  return 2 * N * sizeof(double2) + G * sizeof(double) + S * G * sizeof(double) + 2 * P * sizeof(double) +
+         sizeof(double) + T * sizeof(double) + O * 8 * sizeof(double2) + S * sizeof(double);
 }
 
 static int ensure_global(nwq_vqe* h, int B) {
@@ -1411,12 +1480,16 @@ static int build_fused(nwq_vqe* h) {
   int rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)max_bwd_lds), "hipFuncSetAttribute");
   if (!rc && h->bwd_rb)
-    rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)max_rb_lds), "hipFuncSetAttribute");
+  if (!rc && h->bwd_rb)
+    rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_rb_lds), "hipFuncSetAttribute");
   if (!rc) rc = check_hip(hipMalloc(&h->d_fused, total), "hipMalloc(vqe fused program)");
   if (!rc) rc = check_hip(hipMemcpy(h->d_fused, prog.data(), total, hipMemcpyHostToDevice), "hipMemcpy(vqe fused program)");
   if (rc) return rc;
   h->fused_built = true;
+  h->fused_bytes = total;
   return NWQ_OK;
 }
 
@@ -1442,7 +1515,7 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
   hipLaunchKernelGGL(k_vqe_mats, dim3((h->nops + 255) / 256, B), dim3(256), 0, s, h->d_ops, h->nops, h->d_fixed,
                      theta, h->P, h->d_table);
   for (const FusedBlockDev& d : h->fwd_blocks)
-    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, h->fused_rbits, B, stride, G);
+    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, h->fused_rbits, B, stride, G, h->fused_flags);
   hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
                      coeffs, h->d_epart, grad != nullptr ? 1 : 0);
   if (grad != nullptr) {
@@ -1450,8 +1523,12 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
     for (const FusedBlockDev& d : h->bwd_blocks) {
       const int kb = d.c + d.m;
       if (h->bwd_rb) {
-        hipLaunchKernelGGL(k_vqe_bwd_rb<3>, grid, dim3(1u << (kb - 3)), 2 * bwd_rb_tile_bytes(kb), s, h->d_phi,
-                           h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart);
+        if (h->fused_flags & kFusedNonTemporal)
+          hipLaunchKernelGGL((k_vqe_bwd_rb<3, true>), grid, dim3(1u << (kb - 3)), 2 * bwd_rb_tile_bytes(kb), s,
+                             h->d_phi, h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart);
+        else
+          hipLaunchKernelGGL((k_vqe_bwd_rb<3, false>), grid, dim3(1u << (kb - 3)), 2 * bwd_rb_tile_bytes(kb), s,
+                             h->d_phi, h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart);
       } else {
         const size_t lds = 2 * sizeof(double2) << kb;
         hipLaunchKernelGGL(k_vqe_bwd_tile, grid, dim3(kBwdBlock), lds, s, h->d_phi, h->d_lam, h->n, d, dbo,
@@ -1576,6 +1653,7 @@ int nwq_vqe_create(int n, int n_ops, const int* types, const int* qubits, const 
     const size_t b = std::max<size_t>(bytes, 16);
     int r = check_hip(hipMalloc(dst, b), "hipMalloc(vqe program)");
     if (r) return r;
+    h->program_bytes += b;
     if (bytes) r = check_hip(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(vqe program)");
     return r;
   };
@@ -1604,6 +1682,22 @@ int nwq_vqe_destroy(nwq_vqe_handle h) {
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
   if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
+  return NWQ_OK;
+}
+
+int nwq_vqe_memory(nwq_vqe_handle h, int B, size_t* held, size_t* at_B) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (B < 0 || B > 65535) return vqe_fail(NWQ_EINVAL, "batch size must be in [0, 65535]");
+  const size_t per = global_bytes_per_vector(h);
+  const size_t base = h->program_bytes + h->fused_bytes;
+  if (held) *held = base + (size_t)h->Bcap * per;
+  if (at_B) {
+    // the LDS-resident path keeps no per-vector buffers; every other path
+    // grows the capacity to B (never shrinks it)
+    const bool lds = h->cfg.mode == 1 || (h->cfg.mode == 0 && lds_fits(h, h->cfg.threads, true));
+    const size_t cap = lds ? (size_t)h->Bcap : std::max<size_t>(h->Bcap, (size_t)B);
+    *at_B = base + cap * per;
+  }
   return NWQ_OK;
 }
 
@@ -1637,6 +1731,18 @@ int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_s
   }
   h->cfg.mode = mode;
   h->cfg.threads = threads;
+  return NWQ_OK;
+}
+
+int nwq_vqe_set_flags(nwq_vqe_handle h, int flags) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (flags < 0 || flags > 1) return vqe_fail(NWQ_EINVAL, "flags must be 0 or 1");
+  if (flags != h->fused_flags) {   // the captured schedules hold the kernels
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->fused_flags = flags;
+  }
   return NWQ_OK;
 }
 
@@ -1757,6 +1863,137 @@ int nwq_vqe_autotune(nwq_vqe_handle h, int B, int with_grad, double* best_ms) {
   for (void* p : {(void*)theta, (void*)E, (void*)grad})
     if (p) (void)hipFree(p);
   if (!rc && best_ms) *best_ms = best;
+  return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One-call batched VQE for the Ising model (Sec. III, Fig. 4): the
+// hardware-efficient ansatz and the open-chain transverse-field Ising
+// Hamiltonian are built here, and the evaluation runs through a context kept
+// per (device, n, L).  When (J, h) change, the context's term table is
+// rewritten in place on the context's stream (the captured graphs read it at
+// run time), so a new field costs no re-capture.
+namespace {
+
+struct BatchEntry {
+  int device = -1, n = 0, L = 0;
+  double J = 0.0, hx = 0.0;
+  nwq_vqe_handle ctx = nullptr;
+  std::vector<nwq::VqeTerm> terms;   // host copy of the table last uploaded (source of the async copy)
+  unsigned long long used = 0;
+};
+constexpr size_t kBatchCacheMax = 8;
+std::mutex g_batch_mu;
+std::vector<BatchEntry> g_batch;
+unsigned long long g_batch_clock = 0;
+
+void tfim_terms(int n, double J, double hx, std::vector<nwq::VqeTerm>& out) {
+  out.clear();
+  for (int i = 0; i + 1 < n; ++i)
+    out.push_back(nwq::VqeTerm{0ull, (1ull << i) | (1ull << (i + 1)), -J, 0, 0});
+  for (int i = 0; i < n; ++i) out.push_back(nwq::VqeTerm{1ull << i, 0ull, -hx, 0, 0});
+}
+
+int batch_context(int device, int n, int L, double J, double hx, void* stream, BatchEntry** out) {
+  for (auto& e : g_batch)
+    if (e.device == device && e.n == n && e.L == L) {
+      *out = &e;
+      return NWQ_OK;
+    }
+  // ansatz: per layer RY on 0..n-1, RZ on 0..n-1, CX(0,1) .. CX(n-2,n-1)
+  std::vector<int> types, qubits, params;
+  for (int l = 0; l < L; ++l) {
+    for (int axis = 0; axis < 2; ++axis)
+      for (int q = 0; q < n; ++q) {
+        types.push_back(axis == 0 ? NWQ_GATE_RY : NWQ_GATE_RZ);
+        qubits.push_back(q);
+        qubits.push_back(-1);
+        params.push_back(l * 2 * n + axis * n + q);
+      }
+    for (int q = 0; q + 1 < n; ++q) {
+      types.push_back(NWQ_GATE_CX);
+      qubits.push_back(q);
+      qubits.push_back(q + 1);
+      params.push_back(-1);
+    }
+  }
+  std::vector<nwq::VqeTerm> t;
+  tfim_terms(n, J, hx, t);
+  std::vector<uint64_t> xm, zm;
+  std::vector<double> co;
+  for (const auto& v : t) {
+    xm.push_back(v.x);
+    zm.push_back(v.z);
+    co.push_back(v.c);
+  }
+  if (g_batch.size() >= kBatchCacheMax) {   // evict the least recently used context
+    auto lru = std::min_element(g_batch.begin(), g_batch.end(),
+                                [](const BatchEntry& a, const BatchEntry& b) { return a.used < b.used; });
+    (void)nwq_vqe_destroy(lru->ctx);
+    g_batch.erase(lru);
+  }
+  BatchEntry e;
+  e.device = device;
+  e.n = n;
+  e.L = L;
+  e.J = J;
+  e.hx = hx;
+  e.terms = t;
+  int rc = nwq_vqe_create(n, (int)types.size(), types.data(), qubits.data(), params.data(), 2 * n * L, (int)t.size(),
+                          xm.data(), zm.data(), co.data(), stream, &e.ctx);
+  if (rc) return rc;
+  g_batch.push_back(std::move(e));
+  *out = &g_batch.back();
+  return NWQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nwq_vqe_batch(int n, int L, const double* J_h, int B, const double* theta_dev, double* E_dev, double* grad_dev,
+                  void* stream) {
+  if (n < 1 || n > 30) return vqe_fail(NWQ_ERANGE, "nwq_vqe_batch needs 1..30 qubits");
+  if (L < 1 || 2LL * n * L > (1LL << 24)) return vqe_fail(NWQ_EINVAL, "layer count out of range");
+  if (!J_h || !std::isfinite(J_h[0]) || !std::isfinite(J_h[1])) return vqe_fail(NWQ_EINVAL, "J_h must hold finite J and h");
+  if (B < 1 || B > 65535) return vqe_fail(NWQ_EINVAL, "batch size must be in [1, 65535]");
+  if (!theta_dev || !E_dev) return vqe_fail(NWQ_EINVAL, "NULL theta or energy pointer");
+  int device = 0;
+  int rc = check_hip(hipGetDevice(&device), "hipGetDevice");
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  BatchEntry* e = nullptr;
+  rc = batch_context(device, n, L, J_h[0], J_h[1], stream, &e);
+  if (rc) return rc;
+  e->used = ++g_batch_clock;
+  nwq_vqe_handle h = e->ctx;
+  h->user_stream = static_cast<hipStream_t>(stream);
+  if (e->J != J_h[0] || e->hx != J_h[1]) {
+    // rewrite the term table on the context's stream, after its earlier
+    // evaluations; the host copy is reused, so the previous upload from it
+    // must have finished
+    rc = check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize(vqe batch)");
+    e->J = J_h[0];
+    e->hx = J_h[1];
+    tfim_terms(n, e->J, e->hx, e->terms);
+    if (!rc)
+      rc = check_hip(hipMemcpyAsync(h->d_terms, e->terms.data(), e->terms.size() * sizeof(nwq::VqeTerm),
+                                    hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync(vqe terms)");
+    if (rc) return rc;
+  }
+  return eval_common(h, B, theta_dev, nullptr, E_dev, grad_dev, false);
+}
+
+int nwq_vqe_batch_release(void) {
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  int rc = NWQ_OK;
+  for (auto& e : g_batch) {
+    const int r = nwq_vqe_destroy(e.ctx);
+    if (r && !rc) rc = r;
+  }
+  g_batch.clear();
   return rc;
 }
 

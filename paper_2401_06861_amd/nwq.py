@@ -22,7 +22,9 @@ import numpy as np
 # of pulling a second copy into the process.
 import torch  # noqa: F401
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnwq.so")
+# NWQ_LIB may name another build of the same ABI (the host-only sanitizer
+# build used by the CPU tests); by default the in-tree libnwq.so.
+_LIB_PATH = os.environ.get("NWQ_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnwq.so")
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"HIP engine not built ({_LIB_PATH} missing); run `python -m paper_2401_06861_amd.build`")
 lib = C.CDLL(_LIB_PATH)
@@ -65,6 +67,7 @@ _SIG = {
     "nwq_set_fusion": [_h, C.c_int, _ip],
     "nwq_fusion_stats": [_h, _ip, _ip],
     "nwq_set_fusion_kernel": [_h, C.c_int],
+    "nwq_set_fusion_flags": [_h, C.c_int],
     "nwq_fusion_phases": [_h, _ip],
     "nwq_fusion_plan": [C.c_int, C.c_int, C.c_int, _ip, _ip, _ip, _ip, _ip],
     "nwq_apply_channel": [_h, _ip, C.c_int, _dp, C.c_int],
@@ -75,7 +78,9 @@ _SIG = {
     "nwq_phase_damp": [_h, C.c_int, C.c_double],
     "nwq_expval_pauli_sum": [_h, C.c_int, _up, _up, _dp, _dp],
     "nwq_expval_pauli_terms": [_h, C.c_int, _up, _up, _dp],
+    "nwq_expval_pauli_terms_complex": [_h, C.c_int, _up, _up, _dp, _dp],
     "nwq_trace": [_h, _dp, _dp],
+    "nwq_memory": [_h, C.POINTER(C.c_size_t)],
     "nwq_purity": [_h, _dp],
     "nwq_timing_enable": [_h, C.c_int],
     "nwq_set_launch": [_h, C.c_int, C.c_int, C.c_int, C.c_int],
@@ -92,6 +97,8 @@ _SIG = {
     "nwq_sample": [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
     "nwq_sample_noalloc": [C.c_int, C.c_void_p, C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p],
     "nwq_timing_read": [_h, C.POINTER(C.c_longlong), _dp, C.c_int],
+    "nwq_stream_scale": [C.c_void_p, C.c_size_t, C.c_double, C.c_void_p],
+    "nwq_stream_copy": [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
 }
 for _name, _args in _SIG.items():
     _f = getattr(lib, _name)
@@ -227,6 +234,10 @@ def nwq_set_fusion_kernel(h: int, kernel: int) -> None:
     _check(lib.nwq_set_fusion_kernel(h, int(kernel)))
 
 
+def nwq_set_fusion_flags(h: int, flags: int) -> None:
+    _check(lib.nwq_set_fusion_flags(h, flags))
+
+
 def nwq_fusion_phases(h: int) -> int:
     p = C.c_int()
     _check(lib.nwq_fusion_phases(h, C.byref(p)))
@@ -289,6 +300,25 @@ def nwq_expval_pauli_terms(h: int, terms) -> np.ndarray:
     _check(lib.nwq_expval_pauli_terms(h, len(terms), _u64([t[0] for t in terms]), _u64([t[1] for t in terms]),
                                       out.ctypes.data_as(_dp)))
     return out[:len(terms)]
+
+
+def nwq_expval_pauli_terms_complex(h: int, terms) -> np.ndarray:
+    """Complex <P_t> per term (DM: the kernel's imaginary parts of Tr(rho P_t);
+    SV: imaginary parts are 0 by construction)."""
+    terms = list(terms)
+    re = np.zeros(max(len(terms), 1))
+    im = np.zeros(max(len(terms), 1))
+    _check(lib.nwq_expval_pauli_terms_complex(h, len(terms), _u64([t[0] for t in terms]),
+                                              _u64([t[1] for t in terms]), re.ctypes.data_as(_dp),
+                                              im.ctypes.data_as(_dp)))
+    return (re + 1j * im)[:len(terms)]
+
+
+def nwq_memory(h: int) -> int:
+    """Device bytes the handle holds."""
+    b = C.c_size_t()
+    _check(lib.nwq_memory(h, C.byref(b)))
+    return b.value
 
 
 def nwq_trace(h: int) -> Tuple[float, float]:
@@ -419,6 +449,21 @@ def nwq_sample_noalloc(n: int, probs, u, out, stream=None) -> None:
     _check(lib.nwq_sample_noalloc(n, probs.data_ptr(), u.data_ptr(), u.numel(), out.data_ptr(), s.cuda_stream))
 
 
+def nwq_stream_scale(buf, s: float, stream=None) -> None:
+    """In-place a <- s a over a complex128 cuda tensor (streaming yardstick)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.nwq_stream_scale(buf.data_ptr(), buf.numel(), float(s), st.cuda_stream))
+
+
+def nwq_stream_copy(dst, src, stream=None) -> None:
+    """dst <- src for complex128 cuda tensors of equal size (streaming yardstick)."""
+    import torch
+    assert dst.numel() == src.numel()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.nwq_stream_copy(dst.data_ptr(), src.data_ptr(), src.numel(), st.cuda_stream))
+
+
 def nwq_timing_enable(h: int, enable: bool = True) -> None:
     _check(lib.nwq_timing_enable(h, int(bool(enable))))
 
@@ -434,18 +479,28 @@ def nwq_timing_read(h: int, reset: bool = True) -> dict:
 class _State:
     kind = KIND_SV
 
-    def __init__(self, n: int, tensor=None, stream=None, reset: bool = True):
+    def __init__(self, n: int, tensor=None, stream=None, reset: bool = True, owned: bool = False):
+        """The state lives in `tensor` (a torch complex128 buffer, allocated
+        here if None) or, with owned=True, in memory the library allocates
+        and frees itself (nwq_sv_create / nwq_dm_create)."""
         import torch
         self.n = n
         size = (1 << n) if self.kind == KIND_SV else (1 << (2 * n))
-        if tensor is None:
-            tensor = torch.empty(size, dtype=torch.complex128, device="cuda")
-        assert tensor.dtype == torch.complex128 and tensor.is_cuda and tensor.is_contiguous()
-        assert tensor.numel() == size
-        self.tensor = tensor
+        self.size = size
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        create = nwq_sv_create_from if self.kind == KIND_SV else nwq_dm_create_from
-        self.h = create(tensor.data_ptr(), n, self.stream.cuda_stream)
+        if owned:
+            assert tensor is None
+            self.tensor = None
+            create = nwq_sv_create if self.kind == KIND_SV else nwq_dm_create
+            self.h = create(n, self.stream.cuda_stream)
+        else:
+            if tensor is None:
+                tensor = torch.empty(size, dtype=torch.complex128, device="cuda")
+            assert tensor.dtype == torch.complex128 and tensor.is_cuda and tensor.is_contiguous()
+            assert tensor.numel() == size
+            self.tensor = tensor
+            create = nwq_sv_create_from if self.kind == KIND_SV else nwq_dm_create_from
+            self.h = create(tensor.data_ptr(), n, self.stream.cuda_stream)
         if reset:
             nwq_reset(self.h)
 
@@ -500,6 +555,9 @@ class _State:
     def expvals(self, terms) -> np.ndarray:
         return nwq_expval_pauli_terms(self.h, terms)
 
+    def expvals_complex(self, terms) -> np.ndarray:
+        return nwq_expval_pauli_terms_complex(self.h, terms)
+
     def pauli_sum(self, terms) -> float:
         return nwq_expval_pauli_sum(self.h, terms)
 
@@ -509,12 +567,12 @@ class _State:
     def probabilities(self):
         """Outcome probabilities as a float64 cuda tensor of 2^n entries."""
         import torch
-        p = torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device)
+        p = torch.empty(1 << self.n, dtype=torch.float64, device="cuda")
         nwq_probabilities(self.h, p)
         return p
 
     def numpy(self) -> np.ndarray:
-        out = np.empty(self.tensor.numel(), dtype=np.complex128)
+        out = np.empty(self.size, dtype=np.complex128)
         nwq_get_state(self.h, out)
         return out
 

@@ -27,6 +27,10 @@ for _name, _args in {
     "nwq_vqe_set_config": [_vh, C.c_int, C.c_int, C.c_int],
     "nwq_vqe_get_config": [_vh, _ip, _ip, _ip],
     "nwq_vqe_autotune": [_vh, C.c_int, C.c_int, _dp],
+    "nwq_vqe_batch": [C.c_int, C.c_int, _dp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "nwq_vqe_batch_release": [],
+    "nwq_vqe_memory": [_vh, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
+    "nwq_vqe_set_flags": [_vh, C.c_int],
 }.items():
     _f = getattr(lib, _name)
     _f.argtypes = _args
@@ -34,7 +38,8 @@ for _name, _args in {
 
 EXPORTED = ("nwq_vqe_create", "nwq_vqe_destroy", "nwq_vqe_info", "nwq_vqe_eval", "nwq_vqe_eval_coeffs",
             "nwq_vqe_eval_single",
-            "nwq_vqe_set_config", "nwq_vqe_get_config", "nwq_vqe_autotune")
+            "nwq_vqe_set_config", "nwq_vqe_get_config", "nwq_vqe_autotune", "nwq_vqe_batch",
+            "nwq_vqe_batch_release", "nwq_vqe_memory", "nwq_vqe_set_flags")
 
 
 def program_arrays(prog) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
@@ -120,15 +125,46 @@ class VQE:
     def set_config(self, mode: int = 0, threads: int = 256, blocks_per_state: int = 0):
         _check(lib.nwq_vqe_set_config(self.h, mode, threads, blocks_per_state))
 
+    def set_flags(self, flags: int) -> None:
+        _check(lib.nwq_vqe_set_flags(self.h, flags))
+
     def get_config(self) -> Tuple[int, int, int]:
         m, t, b = C.c_int(), C.c_int(), C.c_int()
         _check(lib.nwq_vqe_get_config(self.h, C.byref(m), C.byref(t), C.byref(b)))
         return m.value, t.value, b.value
 
+    def memory(self, B: int = 0) -> Tuple[int, int]:
+        """(bytes held now, bytes held after evaluating B vectors)."""
+        held, at = C.c_size_t(), C.c_size_t()
+        _check(lib.nwq_vqe_memory(self.h, B, C.byref(held), C.byref(at)))
+        return held.value, at.value
+
     def autotune(self, B: int, with_grad: bool = True) -> float:
         ms = C.c_double()
         _check(lib.nwq_vqe_autotune(self.h, B, int(with_grad), C.byref(ms)))
         return ms.value
+
+
+def vqe_batch(n: int, L: int, J: float, h: float, theta: torch.Tensor, grad: bool = True, stream=None):
+    """nwq_vqe_batch: energies (and gradients) of the hardware-efficient
+    ansatz with L layers under the open-chain Ising Hamiltonian
+    -J sum Z_i Z_{i+1} - h sum X_i, for theta [B, 2 n L] on the GPU."""
+    t = theta.detach()
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    assert t.is_cuda and t.shape[-1] == 2 * n * L
+    t = t.to(torch.float64).contiguous()
+    B = t.shape[0]
+    s = stream if stream is not None else torch.cuda.current_stream()
+    E = torch.empty(B, dtype=torch.float64, device=t.device)
+    G = torch.empty(B, 2 * n * L, dtype=torch.float64, device=t.device) if grad else None
+    jh = (C.c_double * 2)(float(J), float(h))
+    _check(lib.nwq_vqe_batch(n, L, jh, B, t.data_ptr(), E.data_ptr(), G.data_ptr() if grad else None, s.cuda_stream))
+    return E, G
+
+
+def vqe_batch_release() -> None:
+    _check(lib.nwq_vqe_batch_release())
 
 
 class AdjointEnergy(torch.autograd.Function):

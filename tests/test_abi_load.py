@@ -44,6 +44,17 @@ def test_validation_errors_without_device():
     with pytest.raises(nwq.NwqError) as e:
         nwq.nwq_sv_create_from(None, 4)
     assert e.value.code == nwq.NWQ_EINVAL
+    # the one-call VQE rejects bad shapes before touching the device
+    from paper_2401_06861_amd import vqe
+    jh = (C.c_double * 2)(1.0, 1.0)
+    assert nwq.lib.nwq_vqe_batch(0, 1, jh, 1, None, None, None, None) == nwq.NWQ_ERANGE
+    assert nwq.lib.nwq_vqe_batch(4, 0, jh, 1, None, None, None, None) == nwq.NWQ_EINVAL
+    assert nwq.lib.nwq_vqe_batch(4, 1, None, 1, None, None, None, None) == nwq.NWQ_EINVAL
+    assert nwq.lib.nwq_vqe_batch(4, 1, jh, 0, None, None, None, None) == nwq.NWQ_EINVAL
+    assert nwq.lib.nwq_vqe_batch(4, 1, jh, 1, None, None, None, None) == nwq.NWQ_EINVAL
+    nan = (C.c_double * 2)(1.0, float("nan"))
+    assert nwq.lib.nwq_vqe_batch(4, 1, nan, 1, None, None, None, None) == nwq.NWQ_EINVAL
+    assert vqe.lib.nwq_vqe_batch_release() == nwq.NWQ_OK
     # the allocation-free sampler rejects sizes beyond its scratch before any launch
     assert nwq.lib.nwq_sample_noalloc(21, None, None, 0, None, None) == nwq.NWQ_ERANGE
 

@@ -107,8 +107,9 @@ def test_noisy_tfim_n14_tuned_shapes(torch, dm14, fuse_k):
         nwq.nwq_set_fusion_kernel(st.h, 1)
     st.reset()
     st.run(W.noisy_tfim_circuit(n, g["steps"]))
-    z = st.expvals(W.single_site_terms(n, "Z"))
-    assert float(np.max(np.abs(z - np.array(g["Z"])))) <= 1e-12
+    zc = st.expvals_complex(W.single_site_terms(n, "Z"))
+    assert float(np.max(np.abs(zc.real - np.array(g["Z"])))) <= 1e-12
+    assert float(np.max(np.abs(zc.imag))) <= 1e-13
     assert abs(st.purity() - g["purity"]) <= 1e-12
     tr = st.trace()
     assert abs(tr[0] - g["trace"][0]) <= 1e-12 and abs(tr[1]) <= 1e-13

@@ -109,6 +109,12 @@ def test_noisy_tfim_n8(nwq):
     tr, tri = st.trace()
     assert abs(tr - 1) <= TOL and abs(tri) <= 1e-13
     assert abs(st.purity() - gold["purity"]) <= TOL
+    # one-body terms with their imaginary parts: Hermitian rho gives |Im| <= 1e-13
+    terms = W.single_site_terms(n, "Z") + W.single_site_terms(n, "X") + W.single_site_terms(n, "Y")
+    zc = st.expvals_complex(terms)
+    wantc = np.array([tensor.dm_expval(want, x, z, n) for x, z, _ in terms])
+    assert maxerr(zc.real, wantc.real) <= TOL
+    assert float(np.max(np.abs(zc.imag))) <= 1e-13
     st.close()
 
 
@@ -122,6 +128,14 @@ def test_dm_pauli_terms(nwq):
     want = np.array([tensor.dm_expval(rho, x, z, n).real for x, z, _ in terms])
     assert maxerr(got, want) <= TOL
     assert abs(st.pauli_sum(terms) - sum(c * w for (_, _, c), w in zip(terms, want))) <= TOL
+    # complex values on a matrix that is not Hermitian: the imaginary parts are summed, not assumed
+    g = np.random.default_rng(23)
+    m = (g.standard_normal((1 << n, 1 << n)) + 1j * g.standard_normal((1 << n, 1 << n))) / (1 << n)
+    st.load(m)
+    gotc = st.expvals_complex(terms)
+    wantc = np.array([tensor.dm_expval(m, x, z, n) for x, z, _ in terms])
+    assert maxerr(gotc, wantc) <= TOL
+    assert float(np.max(np.abs(wantc.imag))) > 1e-3
     st.close()
 
 

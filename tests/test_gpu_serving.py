@@ -2,7 +2,10 @@
 the per-gate graph paths, noisy DM TFIM) is served with continuous batching;
 every request's outputs equal, bit for bit, those of the same request served
 alone, and sampled outputs match the oracle (energies <= 1e-10, gradients
-<= 1e-10 vs parameter shift, DM magnetisations <= 1e-12)."""
+<= 1e-10 vs parameter shift, DM magnetisations <= 1e-12).  A second stream
+at the serving workload's sizes (SV n 10-24, L 4-8; DM n 6-12) runs under
+a budget that forces admission to wait and idle contexts to be freed, while
+the device memory in use (hipMemGetInfo) is sampled against the budget."""
 import numpy as np
 import pytest
 
@@ -69,3 +72,62 @@ def test_outputs_match_oracle(served):
         out = by[q.rid].outputs[0]
         assert np.max(np.abs(out["Z"] - np.array(want))) <= 1e-12
         assert abs(out["purity"] - tensor.dm_purity(rho)) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def served_large():
+    import torch
+    from paper_2401_06861_amd.serving import GpuExecutor, Server, summarize
+    reqs = W.serving_trace(num=40, rate=400.0, seed=12, sv_n=(10, 24), dm_n=(6, 12), L_range=(4, 8),
+                           opt_steps=(1, 3), dm_steps=10)
+    budget = 6 << 30
+    ex = GpuExecutor()
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    samples = []
+
+    def tick(srv):
+        if len(srv.batches) % 4 == 0:
+            f, _ = torch.cuda.mem_get_info()
+            samples.append((free0 - f, srv.in_use))
+
+    srv = Server(ex, budget_bytes=budget, on_tick=tick)
+    res = srv.run(reqs)
+    torch.cuda.synchronize()
+    yield reqs, res, ex, srv, samples, budget
+    ex.close()
+
+
+def test_large_mix_within_measured_budget(served_large):
+    reqs, res, ex, srv, samples, budget = served_large
+    from paper_2401_06861_amd.serving import dm_footprint
+    assert all(r.error is None for r in res), [r.error for r in res if r.error]
+    assert max(q.n for q in reqs if q.kind == "sv_vqe") >= 22
+    assert srv.max_in_use <= budget
+    assert samples
+    # device memory the run added, as the HIP runtime reports it; torch's
+    # caching allocator may keep the small per-batch tensors (256 MiB slack)
+    assert max(used for used, _ in samples) <= budget + (256 << 20)
+    for q, r in zip(sorted(reqs, key=lambda x: (x.arrival, x.rid)), res):
+        if q.kind == "dm_tfim":
+            assert r.outputs[0]["device_bytes"] <= dm_footprint(q.n)
+            assert abs(r.outputs[0]["trace"] - 1.0) <= 1e-12
+
+
+def test_large_mix_equals_alone(served_large):
+    from paper_2401_06861_amd.serving import Server
+    reqs, res, ex, _, _, budget = served_large
+    by = {r.rid: r for r in res}
+    sv = [q for q in reqs if q.kind == "sv_vqe"]
+    pick = sv[:3] + [q for q in reqs if q.kind == "dm_tfim"][:2]
+    for q in pick:
+        q1 = W.Request(q.rid, 0.0, q.kind, q.n, L=q.L, want_grad=q.want_grad, steps=q.steps, seed=q.seed, h=q.h)
+        alone = Server(ex, budget_bytes=budget).run([q1])[0]
+        mix = by[q.rid]
+        for a, m in zip(alone.outputs, mix.outputs):
+            if q.kind == "sv_vqe":
+                assert a[0] == m[0] and (a[1] is None) == (not q.want_grad)
+                if q.want_grad:
+                    assert np.array_equal(a[1], m[1])
+            else:
+                assert np.array_equal(a["Z"], m["Z"]) and a["purity"] == m["purity"]

@@ -147,6 +147,11 @@ def test_pauli_terms_and_sums(nwq, n):
     assert abs(st.purity() - 1.0) <= TOL
     # deterministic: same value bit for bit on a repeat
     assert np.array_equal(st.expvals(terms), got)
+    # complex form: the same real parts, imaginary parts 0 (Hermitian P; the oracle's within 1e-13)
+    gotc = st.expvals_complex(terms)
+    assert np.array_equal(gotc.real, got) and not gotc.imag.any()
+    wanti = np.array([tensor.sv_expval(psi, x, z, n).imag for x, z, _ in terms])
+    assert float(np.max(np.abs(wanti))) <= 1e-13
     st.close()
 
 
@@ -376,7 +381,7 @@ def test_autotune_keeps_state_and_parity(nwq):
     chosen = autotune.tune(st.h, reps=2, cache_path=cache)
     assert set(chosen) == {"sv_1q_dense", "sv_diag", "sv_perm", "sv_2q_dense"}
     assert all(set(v) == {"low", "mid", "high"} for v in chosen.values())
-    assert maxerr(st.numpy(), psi0) <= 1e-13          # H H rounding only
+    assert np.array_equal(st.numpy(), psi0)           # the tuner's operator pairs are exact
     again = autotune.tune(st.h, reps=2, cache_path=cache)   # from the cache
     shapes = lambda e: {(k, b): tuple(v[:2]) for k, per in e.items() for b, v in per.items()}
     assert shapes(again) == shapes(chosen)
@@ -411,16 +416,21 @@ def test_register_blocked_fused_kernel(nwq, n, k):
     gates = W.random_gate_list(n, 300, seed=7 * n + k) + W.brickwork_circuit(n, 6, seed=n)
     psi0 = W.random_state(n, seed=n)
     want = tensor.sv_run(gates, n, psi0)
-    for rb in (2, 1, 0):
+    outs = {}
+    for rb, flags in ((2, 0), (1, 0), (0, 0), (2, 1), (1, 1)):
         st = nwq.SVState(n, reset=False)
         st.load(psi0)
         st.set_fusion(k)
         nwq.nwq_set_fusion_kernel(st.h, rb)
+        nwq.nwq_set_fusion_flags(st.h, flags)
         st.run_circuit(gates)
-        assert maxerr(st.numpy(), want) <= TOL, (n, k, rb)
+        outs[(rb, flags)] = st.numpy()
+        assert maxerr(outs[(rb, flags)], want) <= TOL, (n, k, rb, flags)
         if rb:
             assert nwq.nwq_fusion_phases(st.h) > 0
         st.close()
+    # the non-temporal tile accesses change nothing but the cache hints
+    assert np.array_equal(outs[(1, 0)], outs[(1, 1)]) and np.array_equal(outs[(2, 0)], outs[(2, 1)])
 
 
 def test_fusion_autotuner(nwq):
@@ -480,3 +490,18 @@ def test_apply_qasm_program(nwq, fuse):
         nwq.nwq_apply_qasm(st.h, "OPENQASM 2.0;\nqreg q[3];\nh q[0];\n")
     assert e.value.code == nwq.NWQ_ERANGE
     st.close()
+
+
+@pytest.mark.parametrize("size", [1, 1000, 4096 + 3, 1 << 16])
+def test_streaming_ceiling_kernels(nwq, size):
+    """The yardstick kernels: in-place scale and copy, exact, on sizes that
+    do and do not fill whole workgroups (grids with and without XCD order)."""
+    import torch
+    g = torch.Generator().manual_seed(size)
+    x = torch.complex(torch.randn(size, generator=g, dtype=torch.float64),
+                      torch.randn(size, generator=g, dtype=torch.float64)).cuda()
+    y = torch.empty_like(x)
+    nwq.nwq_stream_copy(y, x)
+    nwq.nwq_stream_scale(x, 2.0)
+    torch.cuda.synchronize()
+    assert torch.equal(y * 2.0, x)

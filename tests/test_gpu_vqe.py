@@ -202,6 +202,10 @@ def test_fused_path_matches_oracle(V, torch, n, L, bps):
     ctx.set_config(3, 256, bps)
     t = torch.from_numpy(theta).cuda()
     E, G = ctx.eval(t)
+    ctx.set_flags(1)                           # non-temporal tile accesses: the same bits
+    E1, G1 = ctx.eval(t)
+    assert torch.equal(E, E1) and torch.equal(G, G1)
+    ctx.set_flags(0)
     E2, G2 = ctx.eval_single(t[1])
     E = E.cpu().numpy()
     G = G.cpu().numpy()
@@ -264,3 +268,38 @@ def test_graph_replays_with_eager_work_between(V, torch, n, mode):
         E, G = ctx.eval(t[4 * r: 4 * r + 4])
         assert torch.equal(E, first[r][0]) and torch.equal(G, first[r][1])
     ctx.close()
+
+
+def test_vqe_batch_one_call(V, torch):
+    """nwq_vqe_batch builds the ansatz and the Ising Hamiltonian in the
+    library: energies and gradients against the oracle, bit-identical to a
+    context built from the same program, and a new (J, h) on the same shape
+    (term table rewritten in place) matches the oracle again."""
+    n, L, B = 9, 2, 4
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=B)
+    t = torch.from_numpy(theta).cuda()
+    for J, hx in ((1.0, h), (0.7, 1.3), (1.0, h)):
+        E, G = V.vqe_batch(n, L, J, hx, t)
+        terms = W.tfim_hamiltonian(n, J, hx)
+        for b in range(B):
+            assert abs(E[b].item() - OV.energy(prog, theta[b], terms, n)) <= 1e-10
+        g_ps = OV.grad_parameter_shift(prog, theta[0], terms, n)
+        assert np.max(np.abs(G[0].cpu().numpy() - g_ps)) <= 1e-10
+        ctx = V.VQE(n, prog, terms)
+        E2, G2 = ctx.eval(t)
+        assert torch.equal(E, E2) and torch.equal(G, G2)
+        ctx.close()
+    E3, G3 = V.vqe_batch(n, L, 1.0, h, t, grad=False)
+    assert G3 is None and torch.equal(E3, E)
+    for nn, LL in ((14, 1), (5, 3)):               # more shapes in the cache, one above the LDS size
+        th, hh = W.vqe_batch(nn, LL, B=2)
+        E, G = V.vqe_batch(nn, LL, 1.0, hh, torch.from_numpy(th).cuda())
+        pr = W.hea_ansatz(nn, LL)
+        te = W.tfim_hamiltonian(nn, 1.0, hh)
+        assert abs(E[1].item() - OV.energy(pr, th[1], te, nn)) <= 1e-10
+    V.vqe_batch_release()
+    from paper_2401_06861_amd import nwq
+    with pytest.raises(nwq.NwqError) as e:
+        V.vqe_batch(31, 1, 1.0, 1.0, torch.zeros(1, 62, dtype=torch.float64, device="cuda"))
+    assert e.value.code == nwq.NWQ_ERANGE

@@ -94,3 +94,21 @@ def test_library_parser_errors(nwq, text, line):
         nwq.nwq_qasm_parse(text)
     assert e.value.code == nwq.NWQ_EINVAL
     assert f"line {line}:" in str(e.value)
+
+
+def test_library_parser_survives_random_token_soup(nwq):
+    """Random sequences of OpenQASM tokens and stray bytes: the reader either
+    parses them or returns NWQ_EINVAL, never anything else (run under the
+    host sanitizers too)."""
+    rng = np.random.default_rng(5)
+    toks = ["OPENQASM 2.0;", "include \"qelib1.inc\";", "qreg", "creg", "q", "c", "[", "]", "(", ")", ",", ";",
+            "->", "u3", "cx", "rz", "sin", "cos", "pi", "^", "-", "+", "*", "/", "1", "0.5", "2e3", "1e400",
+            "measure", "barrier", "gate", "if", "==", "{", "}", "\n", " ", "//", "\x00", "\xff", "ＱＡ"]
+    for i in range(300):
+        parts = ["OPENQASM 2.0;\nqreg q[3];\n"] if i % 2 else []
+        parts += [toks[j] for j in rng.integers(0, len(toks), size=int(rng.integers(1, 60)))]
+        text = " ".join(parts)
+        try:
+            nwq.nwq_qasm_parse(text)
+        except nwq.NwqError as e:
+            assert e.code == nwq.NWQ_EINVAL, (text, e)
