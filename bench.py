@@ -47,14 +47,14 @@ def parse():
                     help="fusion width for the fused leg (default: picked by the fusion autotuner)")
     ap.add_argument("--fuse-kernel", type=int, default=1, choices=[0, 1, 2],
                     help="fused kernel with --fuse-k: 0 per-gate LDS, 1 / 2 register-blocked with 4 / 3 bits")
-    ap.add_argument("--tune-depth", type=int, default=10, help="brickwork depth the fusion autotuner times")
+    ap.add_argument("--tune-depth", type=int, default=6, help="brickwork depth the fusion autotuner times")
     ap.add_argument("--no-n32", action="store_true", help="skip the n=32 sweep")
     ap.add_argument("--no-extras", action="store_true", help="only the timed step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-vqe", action="store_true", help="skip the batched VQE leg")
-    ap.add_argument("--vqe-sizes", default="8:4,12:8,16:8,20:8", help="n:L pairs for the VQE leg")
+    ap.add_argument("--vqe-sizes", default="8:4,8:8,12:4,12:8,16:4,16:8,20:4,20:8", help="n:L pairs for the VQE leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serving-requests", type=int, default=600)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-mode", choices=["trace", "pmc", "fused", "vqe", "dm"], default=None)
     return ap.parse_args()
@@ -99,33 +99,66 @@ def load_traffic(name):
 
 
 # ---------------------------------------------------------------- CPU leg
-def cpu_baseline(seconds: float):
-    """The tier-1 oracle (numpy tensor contractions, as written) applying the
-    brickwork circuit's gates in order on n=26 from |0...0>, stopped after
-    `seconds`; GB/s with the same per-gate algorithmic bytes."""
-    import workloads as W
-    from oracle import tensor
+def host_info():
+    """Core count, CPU model and RAM of the host the benchmark runs on."""
+    info = {"nproc": os.cpu_count()}
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
-    n = 26
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_GB"] = round(int(line.split()[1]) * 1024 / 1e9, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(seconds: float, n: int = 30):
+    """The oracle's C-loop tier (plain OpenMP loops, as written) applying the
+    same depth-40 brickwork gates (seed 0) in order on the same n-qubit
+    register from |0...0>: first with every thread OpenMP is given, then the
+    following gates on one thread; each run stops after its share of
+    `seconds` (at least one gate).  GB/s uses the GPU line's per-gate
+    algorithmic bytes (32N per U3, 16N per CX)."""
+    import workloads as W
+    from oracle import loops
     gates = W.brickwork_circuit(n, 40, seed=0)
-    psi = np.zeros(1 << n, dtype=np.complex128)
-    psi[0] = 1.0
-    done, byt = 0, 0
+    threads = loops.get_threads()
     t0 = time.perf_counter()
-    for g in gates:
-        psi = tensor.sv_apply(psi, g, n)
-        done += 1
-        byt += (16 if g[0] in ("cx", "swap") else 32) << n
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": round(byt / dt / 1e9, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"tier-1 numpy oracle, first {done} gates of the depth-40 brickwork at n={n} "
-                      f"(2^{n} complex128 amplitudes, {dt:.1f} s)"}
+    psi = loops.sv_zero(n)
+    t_alloc = time.perf_counter() - t0
+
+    def run(first, budget):
+        done, byt = 0, 0
+        t = time.perf_counter()
+        for g in gates[first:]:
+            loops.sv_apply(psi, g, n)
+            done += 1
+            byt += (16 if g[0] in ("cx", "swap") else 32) << n
+            if time.perf_counter() - t > budget:
+                break
+        return done, byt, time.perf_counter() - t
+
+    d_all, b_all, t_all = run(0, 0.6 * seconds)
+    loops.set_threads(1)
+    try:
+        d_one, b_one, t_one = run(d_all, 0.4 * seconds)
+    finally:
+        loops.set_threads(threads)
+    del psi
+    return {"value": round(b_all / t_all / 1e9, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle C-loop tier (OpenMP, {threads} threads), the first {d_all} gates of the same depth-40 "
+                      f"brickwork (seed 0) on the same n={n} register (2^{n} complex128 amplitudes) from |0...0>, "
+                      f"{t_all:.1f} s; then gates {d_all}-{d_all + d_one - 1} on 1 thread",
+            "one_thread_GBs": round(b_one / t_one / 1e9, 3), "one_thread_gates": d_one,
+            "gates_per_s": round(d_all / t_all, 3), "reset_s": round(t_alloc, 2), "host": host_info()}
 
 
 # ---------------------------------------------------------------- GPU legs
@@ -187,13 +220,16 @@ def main():
         print(json.dumps({"profile_mode": args.profile_mode, "n": n}))
         return
     if args.profile_mode == "vqe":
-        # fused-graph VQE energy + gradient: n=20, B=256 and n=24, B=1 (L=8), three evaluations each
+        # fused-graph VQE energy + gradient: n=20, B=256 (64 workgroups per state, the
+        # configuration the VQE autotuner picks there) and n=24, B=1 (L=8), three evaluations each
         from paper_2401_06861_amd import vqe as V
         del st, psi
         torch.cuda.empty_cache()
         for nv, B in ((20, 256), (24, 1)):
             theta, h = W.vqe_batch(nv, 8, B=B)
             ctx = V.VQE(nv, W.hea_ansatz(nv, 8), W.tfim_hamiltonian(nv, 1.0, h))
+            if B == 256:
+                ctx.set_config(3, 256, 64)
             t = torch.from_numpy(theta).cuda()
             for _ in range(3):
                 ctx.eval(t)
@@ -205,7 +241,8 @@ def main():
     if args.profile_mode is not None:
         # short, fixed work for rocprofv3: a plain copy of known size (counter
         # calibration), the launch-shape autotuner, then U3 and CX launches at
-        # n in the tuned shapes (the last 3 x 3 U3 and 3 CX dispatches)
+        # n in the tuned shapes (the last 3 x 3 U3 and 3 x 4 CX dispatches:
+        # CX(3,4), then the low pairs (0,1), (1,2), (2,3))
         src = torch.empty(1 << 27, dtype=torch.complex128, device=dev)   # 2 GiB
         src.fill_(0.5)
         dst = torch.empty_like(src)
@@ -222,6 +259,8 @@ def main():
             for q in (0, 7, n - 1):
                 st.apply("u3", (q,), (0.3, 0.2, 0.1))
             st.apply("cx", (3, 4), ())
+            for qs in ((0, 1), (1, 2), (2, 3)):
+                st.apply("cx", qs, ())
         torch.cuda.synchronize()
         log("[bench] profile mode done")
         print(json.dumps({"profile_mode": args.profile_mode, "n": n}))
@@ -264,6 +303,11 @@ def main():
                 "traffic": traffic, "avg_launch_ms": round(u3_avg_ms, 4), "launches": cnt}
     per_class = {k: {"launches": c, "avg_ms": round(m / c, 4)} for k, (c, m) in tim.items() if c}
 
+    ceiling = copy_ceiling(torch, 16 * N) if not args.no_extras else None
+    if ceiling:
+        roofline["measured_ceiling_GBs"] = ceiling["best_GBs"]
+        roofline["frac_of_measured_ceiling"] = round(achieved / ceiling["best_GBs"], 4)
+
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -274,8 +318,11 @@ def main():
            "launch_shapes": {k: {b: {"ppt": v[0], "flags": v[1]} for b, v in per.items()}
                              for k, per in tuned.items()}}
 
+    if ceiling:
+        out["copy_ceiling"] = ceiling
     if not args.no_extras:
         out["fused"] = fused_leg(nwq, st, arrays, n, args, ms_per_step)
+        out["seeds"] = seeds_leg(nwq, st, n, args, out["fused"])
         out["sweep"] = sweep_leg(nwq, st, n)
         out["measure"] = measure_leg(nwq, st, n)
         del st, psi
@@ -283,6 +330,7 @@ def main():
         if n == 30 and not args.no_n32:
             out["sweep_n32"] = sweep_n32_leg(nwq, torch, tuned)
         out["dm_noisy_gate_n14"] = dm_leg(nwq, torch)
+        out["dm_noisy_gate_n15"] = dm15_leg(nwq, torch)
     if not args.no_extras and not args.no_vqe:
         out["vqe"] = vqe_leg(torch)
     if not args.no_extras and not args.no_serving:
@@ -291,6 +339,77 @@ def main():
         log("[bench] cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))
+
+
+def copy_ceiling(torch, nbytes, reps=5):
+    """Measured streaming ceilings at the state's footprint (GB/s counts the
+    read and the write): the library's in-place scale and copy kernels (one
+    entry per thread, non-temporal, XCD-contiguous order: the gate kernels'
+    layout with no arithmetic), a device-to-device hipMemcpy, and torch's
+    elementwise in-place scale."""
+    from paper_2401_06861_amd import nwq
+    log(f"[bench] copy ceiling at {nbytes / 1e9:.2f} GB")
+    src = torch.empty(nbytes // 16, dtype=torch.complex128, device="cuda")
+    src.fill_(0.5)
+    dst = torch.empty_like(src)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms = {"stream_scale": timed(lambda: nwq.nwq_stream_scale(src, 1.0)),
+          "stream_copy": timed(lambda: nwq.nwq_stream_copy(dst, src)),
+          "hipmemcpy_d2d": timed(lambda: dst.copy_(src)),
+          "torch_inplace_scale": timed(lambda: src.mul_(1.0))}
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = {k: 2 * nbytes / (v * 1e-3) / 1e9 for k, v in ms.items()}
+    best = max(gbs["stream_scale"], gbs["stream_copy"])
+    return {"footprint_GB": round(nbytes / 1e9, 2), "ms": {k: round(v, 3) for k, v in ms.items()},
+            "GBs": {k: round(v, 1) for k, v in gbs.items()}, "best_GBs": round(best, 1),
+            "best_frac_of_spec": round(best / HBM_PEAK_GBS, 4)}
+
+
+def seeds_leg(nwq, st, n, args, fused):
+    """The brickwork with seeds 1 and 2 (seed 0 is the timed step): one kernel
+    per gate and through fused blocks at the width and kernel the fusion
+    autotuner picked, one timed run each after a warm-up."""
+    import torch
+    import workloads as W
+    res = {}
+    zterms = W.single_site_terms(n, "Z")
+    for seed in (1, 2):
+        log(f"[bench] brickwork seed {seed}")
+        arr = nwq.circuit_arrays(W.brickwork_circuit(n, args.depth, seed=seed))
+        row = {}
+        for label, k in (("unfused", 0), ("fused", fused["k"])):
+            nwq.nwq_set_fusion(st.h, k)
+            if k:
+                nwq.nwq_set_fusion_kernel(st.h, fused["kernel_id"])
+            st.reset()
+            nwq.nwq_apply_circuit(st.h, *arr)
+            st.flush()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.reset()
+            nwq.nwq_apply_circuit(st.h, *arr)
+            z = st.expvals(zterms)
+            dt = time.perf_counter() - t0
+            row[label + "_ms"] = round(dt * 1e3, 2)
+            row[label + "_z"] = z
+        nwq.nwq_set_fusion(st.h, 0)
+        row["max_abs_dz_fused_vs_unfused"] = float(np.max(np.abs(row.pop("fused_z") - row.pop("unfused_z"))))
+        row["unfused_GBs"] = round(step_bytes(n, W.brickwork_circuit(n, args.depth, seed=seed)) /
+                                   (row["unfused_ms"] * 1e-3) / 1e9, 1)
+        res[f"seed{seed}"] = row
+    return res
 
 
 def fused_leg(nwq, st, arrays, n, args, unfused_ms):
@@ -333,7 +452,7 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
     avg = ms / max(c, 1)
     kname = ["one LDS pass per gate", "register-blocked (4 register bits per phase)",
              "register-blocked (3 register bits per phase)"][rb]
-    res = {"k": k, "kernel": kname,
+    res = {"k": k, "kernel": kname, "kernel_id": rb,
            "blocks": blocks, "phases": phases, "gates": fg, "mean_gates_per_block": round(fg / max(blocks, 1), 2),
            "circuit_ms": round(dt * 1e3, 2), "speedup_vs_one_kernel_per_gate": round(unfused_ms / (dt * 1e3), 2),
            "avg_block_ms": round(avg, 3), "block_hbm_GBs": round(32 * N / (avg * 1e-3) / 1e9, 1)}
@@ -524,6 +643,39 @@ def dm_leg(nwq, torch):
     return out
 
 
+def dm15_leg(nwq, torch):
+    """Noisy-gate sweep on a 15-qubit density matrix (17.18 GB, the footprint
+    of the 30-qubit state vector) after the launch-shape autotuner."""
+    log("[bench] DM n=15 noisy gate sweep")
+    from paper_2401_06861_amd import autotune
+    n = 15
+    st = nwq.DMState(n)
+    autotune.tune(st.h, reps=1, cache_path=None)
+    nbytes = 32 * (1 << (2 * n))
+    sweep = {}
+    for label, qs_list, cls in (("1q", [(0,), (3,), (7,), (n - 1,)], "dm_superop_1q"),
+                                ("2q", [(0, 1), (2, 3), (6, 7), (n - 2, n - 1)], "dm_superop_2q")):
+        for qs in qs_list:
+            ops = ([("u3", qs, (0.3, 0.2, 0.1)), ("depolarize", qs, (1e-3,)), ("amp_damp", qs, (1e-3,)),
+                    ("phase_damp", qs, (2e-3,))] if label == "1q"
+                   else [("rzz", qs, (0.2,)), ("depolarize2", qs, (1e-2,))])
+            st.run(ops)
+            st.flush()
+            torch.cuda.synchronize()
+            nwq.nwq_timing_read(st.h, reset=True)
+            nwq.nwq_timing_enable(st.h, True)
+            for _ in range(3):
+                st.run(ops)
+                st.flush()
+            nwq.nwq_timing_enable(st.h, False)
+            c, ms = nwq.nwq_timing_read(st.h, reset=True)[cls]
+            avg = ms / max(c, 1)
+            sweep[f"{label}{list(qs)}"] = {"ms": round(avg, 3), "GBs": round(nbytes / (avg * 1e-3) / 1e9, 1)}
+    st.close()
+    torch.cuda.empty_cache()
+    return {"n": n, "state_GB": round(16 * (1 << (2 * n)) / 1e9, 2), "sweep": sweep}
+
+
 def vqe_leg(torch, sizes=None, B=256):
     """Energy + full adjoint gradient for B parameter vectors on the batched
     path (autotuned) against the plain per-circuit path (one vector at a time,
@@ -583,41 +735,47 @@ def vqe_leg(torch, sizes=None, B=256):
     return res
 
 
-def serving_leg(torch, num):
+def serving_leg(torch, num, num_side=600):
     """Continuous-batching server on a Poisson stream: 70% SV VQE (n 10..24,
     L 4..8, half with gradient, 1..20 optimiser steps with the state resident
     between them), 30% noisy DM TFIM (n 6..12, 10 Trotter steps).  First all
-    requests arrive at once (saturation throughput), then Poisson arrivals at
-    0.5, 0.8 and 0.95 x that rate (latency)."""
+    `num` requests arrive at once (saturation throughput), then Poisson
+    arrivals at 0.8 x that rate (`num` requests, the reported latency) and at
+    0.5 and 0.95 x (`num_side` requests each).  Admission is by the device
+    memory the library reports for each class's context; the budget is 64 GiB."""
     import workloads as W
-    from paper_2401_06861_amd.serving import GpuExecutor, Server, summarize
-    log(f"[bench] serving leg, {num} requests per run")
-    kw = dict(num=num, seed=7, sv_n=(10, 24), dm_n=(6, 12), L_range=(4, 8), opt_steps=(1, 20), dm_steps=10)
+    from paper_2401_06861_amd.serving import GpuExecutor, Server, batch_stats, summarize
+    log(f"[bench] serving leg, {num} requests (saturation and 0.8 load), {num_side} at 0.5 and 0.95")
+    kw = dict(seed=7, sv_n=(10, 24), dm_n=(6, 12), L_range=(4, 8), opt_steps=(1, 20), dm_steps=10)
     ex = GpuExecutor()
     budget = 64 << 30
     warm = W.serving_trace(rate=1e9, **{**kw, "num": 60, "seed": 8})
     Server(ex, budget).run(warm)                       # contexts, graphs, allocator warm
     t0 = time.perf_counter()
-    sat = summarize(Server(ex, budget).run(W.serving_trace(rate=1e9, **kw)))
+    srv = Server(ex, budget)
+    sat = summarize(srv.run(W.serving_trace(rate=1e9, num=num, **kw)))
+    sat_batches = batch_stats(srv.batches)
     log(f"[bench] saturation {sat['throughput_req_per_s']:.1f} req/s in {time.perf_counter() - t0:.1f}s")
     loads = {}
     main = None
-    for frac in (0.5, 0.8, 0.95):
+    for frac in (0.8, 0.5, 0.95):
         rate = frac * sat["throughput_req_per_s"]
+        cnt = num if frac == 0.8 else num_side
         srv = Server(ex, budget)
-        lat = summarize(srv.run(W.serving_trace(rate=rate, **kw)))
-        log(f"[bench] load {frac}: p50 {lat['p50_ms']:.1f} ms p99 {lat['p99_ms']:.1f} ms")
-        loads[str(frac)] = {"offered_req_per_s": round(rate, 2), "throughput_req_per_s": round(lat["throughput_req_per_s"], 2),
+        lat = summarize(srv.run(W.serving_trace(rate=rate, num=cnt, **kw)))
+        log(f"[bench] load {frac} ({cnt} requests): p50 {lat['p50_ms']:.1f} ms p99 {lat['p99_ms']:.1f} ms")
+        loads[str(frac)] = {"requests": cnt, "offered_req_per_s": round(rate, 2),
+                            "throughput_req_per_s": round(lat["throughput_req_per_s"], 2),
                             "p50_ms": round(lat["p50_ms"], 2), "p99_ms": round(lat["p99_ms"], 2),
-                            "batches": len(srv.batches),
-                            "mean_batch": round(sum(b for _, b in srv.batches) / max(len(srv.batches), 1), 2),
-                            "errors": lat["errors"]}
+                            "batches": batch_stats(srv.batches), "max_charged_GB": round(srv.max_in_use / 1e9, 2),
+                            "contexts_released": srv.released, "errors": lat["errors"]}
         if frac == 0.8:
             main = loads[str(frac)]
     ex.close()
     torch.cuda.empty_cache()
     return {"requests": num, "mix": "70% SV VQE n10-24 L4-8 (half +grad, 1-20 steps), 30% DM TFIM n6-12",
             "budget_GB": budget / 1e9, "saturation_req_per_s": round(sat["throughput_req_per_s"], 2),
+            "saturation_batches": sat_batches,
             "offered_req_per_s": main["offered_req_per_s"], "throughput_req_per_s": main["throughput_req_per_s"],
             "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "errors": main["errors"], "by_load": loads}
 
