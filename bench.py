@@ -393,13 +393,11 @@ def seeds_leg(nwq, st, n, args, fused):
             nwq.nwq_set_fusion(st.h, k)
             if k:
                 nwq.nwq_set_fusion_kernel(st.h, fused["kernel_id"])
-            st.reset()
-            nwq.nwq_apply_circuit(st.h, *arr)
+            nwq.nwq_run_circuit(st.h, *arr)
             st.flush()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st.reset()
-            nwq.nwq_apply_circuit(st.h, *arr)
+            nwq.nwq_run_circuit(st.h, *arr)
             z = st.expvals(zterms)
             dt = time.perf_counter() - t0
             row[label + "_ms"] = round(dt * 1e3, 2)
@@ -413,9 +411,11 @@ def seeds_leg(nwq, st, n, args, fused):
 
 
 def fused_leg(nwq, st, arrays, n, args, unfused_ms):
-    """The same circuit through fused k-qubit blocks.  The fusion width and
-    kernel are picked by the library's fusion autotuner timing the first
-    --tune-depth layers under every candidate (or fixed by --fuse-k)."""
+    """The same circuit through fused k-qubit blocks (nwq_run_circuit: reset,
+    then the circuit; the first block runs only the tile holding index 0).
+    The fusion width and kernel are picked by the library's fusion autotuner
+    timing the first --tune-depth layers under every candidate (or fixed by
+    --fuse-k)."""
     import torch
     import workloads as W
     table = None
@@ -429,8 +429,7 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
         nwq.nwq_set_fusion(st.h, k)
         nwq.nwq_set_fusion_kernel(st.h, rb)
     log(f"[bench] fused leg k={k} rb={rb}")
-    st.reset()
-    nwq.nwq_apply_circuit(st.h, *arrays)          # warm-up (and plan)
+    nwq.nwq_run_circuit(st.h, *arrays)            # warm-up (and plan): reset, then the circuit
     st.flush()
     torch.cuda.synchronize()
     reps = 2
@@ -438,8 +437,7 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
     nwq.nwq_timing_enable(st.h, True)
     t0 = time.perf_counter()
     for _ in range(reps):
-        st.reset()
-        nwq.nwq_apply_circuit(st.h, *arrays)
+        nwq.nwq_run_circuit(st.h, *arrays)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     nwq.nwq_timing_enable(st.h, False)

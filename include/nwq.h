@@ -131,6 +131,13 @@ int nwq_apply_matrix(nwq_handle h, const int* qubits, int k, const double* m);
  * blocks, each applied in one pass through LDS. */
 int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types,
                       const int* qubits, const double* params);
+/* Reset to |0...0> and apply the circuit (arguments as nwq_apply_circuit,
+ * all validated before the reset).  With fusion on an SV handle, the first
+ * block runs only on the tile that holds index 0: every other tile is zero
+ * and a block maps each tile to itself, so they stay zero (the result equals
+ * nwq_reset + nwq_apply_circuit, up to the sign of zero entries). */
+int nwq_run_circuit(nwq_handle h, int n_gates, const int* types,
+                    const int* qubits, const double* params);
 
 /* OpenQASM 2.0 front-end (host only).  Accepts the header, include lines,
  * qreg / creg (quantum registers laid out in declaration order), the qelib1

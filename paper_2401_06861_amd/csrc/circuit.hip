@@ -198,7 +198,8 @@ void fill_entry_offsets(FusedBlockDev& d, int rbits) {
 // Runs a gate list through fused blocks over `nbits` bits of the vector (the
 // qubit count for a state vector; 2n for the vectorised density matrix, whose
 // queued 1q superoperators arrive as kGateMat4 gates with matrices in `side`).
-int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side) {
+int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side,
+                bool from_zero) {
   const std::vector<Block> blocks = plan_blocks(gates, nbits, h->fuse_k);
   if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
   // Program: [phase table][op table][matrix table] in one upload.
@@ -308,9 +309,14 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
   const FusedPhase* dph = static_cast<const FusedPhase*>(dev);
   const FusedOp* dops = reinterpret_cast<const FusedOp*>(static_cast<char*>(dev) + ops_off);
   const double2* dmats = reinterpret_cast<const double2*>(static_cast<char*>(dev) + mats_off);
-  for (const Launch& L : launches) {
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const Launch& L = launches[li];
+    // from |0...0>, the first block runs only tile 0 (it holds index 0; every
+    // other tile is zero and a block maps each tile to itself)
+    const unsigned long long max_tiles = from_zero && li == 0 ? 1ull : 0ull;
     timing_begin(h, KC_FUSED);
-    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats, L.rbits, 1, 0, 0, h->fuse_flags);
+    if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats, L.rbits, 1, 0, 0, h->fuse_flags,
+                              max_tiles);
     else launch_fused_block(h->stream, h->data, h->nbits, L.d, dops, dmats, h->fuse_k);
     timing_end(h);
     const int rc = check_hip(hipGetLastError(), "fused_block");
@@ -361,16 +367,21 @@ static int parse_circuit(int n, int n_gates, const int* types, const int* qubits
   return NWQ_OK;
 }
 
-int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params) {
+static int apply_circuit_common(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params,
+                                bool from_zero) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
   std::vector<PGate> gates;
   // validate everything before launching anything
   int rc0 = parse_circuit(h->n, n_gates, types, qubits, params, true, gates);
   if (rc0) return rc0;
+  if (from_zero) {
+    rc0 = nwq_reset(h);
+    if (rc0) return rc0;
+  }
   h->last_blocks = 0;
   h->last_fused_gates = 0;
   h->last_phases = 0;
-  if (h->kind == NWQ_KIND_SV && h->fuse_k > 0 && n_gates > 0) return apply_fused(h, gates, h->n, nullptr);
+  if (h->kind == NWQ_KIND_SV && h->fuse_k > 0 && n_gates > 0) return apply_fused(h, gates, h->n, nullptr, from_zero);
   for (const PGate& g : gates) {
     int rc;
     if (h->kind == NWQ_KIND_SV) {
@@ -383,6 +394,14 @@ int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qu
     if (rc) return rc;
   }
   return NWQ_OK;
+}
+
+int nwq_apply_circuit(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params) {
+  return apply_circuit_common(h, n_gates, types, qubits, params, false);
+}
+
+int nwq_run_circuit(nwq_handle h, int n_gates, const int* types, const int* qubits, const double* params) {
+  return apply_circuit_common(h, n_gates, types, qubits, params, true);
 }
 
 int nwq_set_fusion_kernel(nwq_handle h, int kernel) {

@@ -93,7 +93,9 @@ struct Phase {
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
 // internal gate type: dense 4x4 whose matrix is entry p[0] of a side table
 constexpr int kGateMat4 = 1000;
-int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side);
+// from_zero: the state is |0...0> (the first block then runs tile 0 only)
+int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side,
+                bool from_zero = false);
 // Fold the permutation gates that can open or close a register phase into its
 // LDS offsets instead of moving registers.  A permutation moves past a
 // following (preceding) non-permutation gate on other register bits, since the

@@ -362,7 +362,8 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
                                                                   const FusedPhase* __restrict__ phases,
                                                                   const FusedOp* __restrict__ ops,
                                                                   const double2* __restrict__ mats0,
-                                                                  unsigned long long state_stride, int mat_stride) {
+                                                                  unsigned long long state_stride, int mat_stride,
+                                                                  unsigned long long ntiles) {
   constexpr int NV = 1 << R;
   extern __shared__ double2 t[];
   // batch element blockIdx.y: its own state and its own matrix table
@@ -371,7 +372,6 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   const int c = blk.c, m = blk.m, k = c + m;
   const unsigned len = 1u << k;
   const unsigned nt = len >> R;
-  const unsigned long long ntiles = 1ull << (nbits - k);
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
   const unsigned long long glane = tile_index(0ull, tid, cmask, c, m, blk);   // thread part of entry indices
@@ -456,9 +456,10 @@ size_t fused_rb_lds_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << 
 
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid,
-                     int flags) {
+                     int flags, unsigned long long max_tiles) {
   const int k = blk.c + blk.m;
-  const unsigned long long ntiles = 1ull << (nbits - k);
+  unsigned long long ntiles = 1ull << (nbits - k);
+  if (max_tiles > 0 && max_tiles < ntiles) ntiles = max_tiles;
   // about four tiles per workgroup (so that the next tile's loads overlap
   // this one's phases), at least 2048 workgroups
   const unsigned long long cap = max_grid > 0 ? (unsigned long long)max_grid
@@ -469,7 +470,7 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
   auto go = [&](auto kern, int rb) {
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, dim3(grid, batch), dim3(1u << (k - rb)), lds, s, a, nbits, blk, phases, ops, mats,
-                       stride, mat_stride);
+                       stride, mat_stride, ntiles);
   };
   const bool nt = (flags & kFusedNonTemporal) != 0;
   if (rbits == 3) {

@@ -176,10 +176,13 @@ size_t fused_rb_lds_bytes(int k);
 // batch > 1: blockIdx.y = batch element b works on a + b * 2^nbits with the
 // matrix table mats + b * mat_stride; max_grid caps the tiles' grid (0 = 2^20).
 // flags: kFusedNonTemporal = non-temporal global loads and stores of the tiles.
+// max_tiles > 0 runs only the first max_tiles tiles of each state (the block
+// leaves the others alone: used when they are known to hold zeros, which a
+// block maps to zeros).
 constexpr int kFusedNonTemporal = 1;
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch = 1, int mat_stride = 0,
-                     int max_grid = 0, int flags = 0);
+                     int max_grid = 0, int flags = 0, unsigned long long max_tiles = 0);
 
 // ---- error handling (engine.hip) ------------------------------------------
 int set_error(int code, const std::string& msg);

@@ -476,6 +476,187 @@ __global__ __launch_bounds__(kVqeBlock) void k_vqe_hphi(const double2* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// lambda = H phi over tiles staged in LDS (fused schedule).  A pass takes a
+// tile shape (low c bits plus m high bits) and the terms whose flipped bits
+// x lie inside it; the first pass also takes every diagonal term (x = 0) and
+// writes lambda, later passes add to it.  For entry j of a tile (local index
+// l) a term contributes c_t i^y (-1)^{|(j ^ x) & z|} phi[j ^ x], with the
+// partner read from the tile; the sign splits into the tile-local bits
+// (|(l ^ xl) & zl|) and a per-tile constant (|base & zo| + |x & z|, on the
+// bits outside the tile).  The last pass also sums Re<phi|lambda> into the
+// energy partial of its workgroup.  Terms whose flipped bits fit no tile
+// take a gather pass of their own (k_vqe_hphi_wide).
+// ---------------------------------------------------------------------------
+constexpr int kHBlock = 1024;     // threads per tile workgroup
+constexpr int kHTileBits = 13;    // tiles of at most 2^13 entries (128 KiB of LDS)
+constexpr int kHPer = (1 << kHTileBits) / kHBlock;
+constexpr int kHMaxTerms = 128;   // terms per launch
+
+struct HTerm {
+  unsigned xl, zl;            // x and the z bits inside the tile, tile-local
+  unsigned long long zo;      // z bits outside the tile (global)
+  int y;                      // popcount(x & z) mod 4 (the i^y factor)
+  int sx;                     // popcount(x & z) mod 2 (the sign of (j ^ x) vs j)
+  int t;                      // index of the term (its coefficient)
+  int pad;
+};
+struct HPass {
+  int c, m;
+  int hi[8];
+  int first, last;
+  int t_begin, n_diag, n_flip;   // diagonal terms first, then flipped ones
+  int pad;
+};
+
+__host__ __device__ inline unsigned hpad(unsigned l) { return l + (l >> 4); }
+
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(kHBlock) void k_vqe_hphi_tile(const double2* __restrict__ phi0, double2* __restrict__ lam0,
+                                                           int n, HPass ps, const HTerm* __restrict__ hterms,
+                                                           const VqeTerm* __restrict__ terms, int nterms,
+                                                           const double* __restrict__ coeffs,
+                                                           double* __restrict__ epart) {
+  extern __shared__ double2 tl[];
+  __shared__ double s_c[kHMaxTerms];
+  __shared__ double red[kHBlock / kWave];
+  const unsigned long long N = 1ull << n;
+  const double2* __restrict__ phi = phi0 + (size_t)blockIdx.y * N;
+  double2* __restrict__ lam = lam0 + (size_t)blockIdx.y * N;
+  const int k = ps.c + ps.m;
+  const unsigned len = 1u << k;
+  const unsigned long long ntiles = 1ull << (n - k);
+  const unsigned tid = threadIdx.x;
+  const int nt = ps.n_diag + ps.n_flip;
+  for (int i = tid; i < nt; i += kHBlock) {
+    const int t = hterms[ps.t_begin + i].t;
+    s_c[i] = coeffs ? coeffs[(size_t)blockIdx.y * nterms + t] : terms[t].c;
+  }
+  const unsigned cmask = (1u << ps.c) - 1u;
+  double e = 0.0;
+  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    unsigned long long base = tile << ps.c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i < ps.m) {
+        const int q = ps.hi[i];
+        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
+      }
+    }
+    vd2 v[kHPer];
+    unsigned long long g[kHPer];
+    __syncthreads();   // the previous tile's readers are done (and s_c is written)
+#pragma unroll
+    for (int r = 0; r < kHPer; ++r) {
+      const unsigned l = tid + r * kHBlock;
+      if (l < len) {
+        unsigned long long gi = base | (l & cmask);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < ps.m && ((l >> (ps.c + i)) & 1u)) gi |= 1ull << ps.hi[i];
+        g[r] = gi;
+        v[r] = __builtin_nontemporal_load(reinterpret_cast<const vd2*>(phi + gi));
+        st(tl + hpad(l), v[r]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kHPer; ++r) {
+      const unsigned l = tid + r * kHBlock;
+      if (l >= len) continue;
+      vd2 acc = FIRST ? mk(0.0, 0.0) : __builtin_nontemporal_load(reinterpret_cast<const vd2*>(lam + g[r]));
+      if (ps.n_diag > 0) {
+        double d = 0.0;   // diagonal terms: one real coefficient per entry
+        for (int i = 0; i < ps.n_diag; ++i) {
+          const HTerm T = hterms[ps.t_begin + i];
+          const unsigned s = (unsigned)(__popc(l & T.zl) + __popcll(base & T.zo)) & 1u;
+          d += s ? -s_c[i] : s_c[i];
+        }
+        acc.x = fma(d, v[r].x, acc.x);
+        acc.y = fma(d, v[r].y, acc.y);
+      }
+      for (int i = ps.n_diag; i < nt; ++i) {
+        const HTerm T = hterms[ps.t_begin + i];
+        vd2 p = ld(tl + hpad(l ^ T.xl));
+        switch (T.y & 3) {
+          case 1: p = mk(-p.y, p.x); break;
+          case 2: p = mk(-p.x, -p.y); break;
+          case 3: p = mk(p.y, -p.x); break;
+          default: break;
+        }
+        const unsigned s = (unsigned)(__popc(l & T.zl) + __popcll(base & T.zo) + T.sx) & 1u;
+        const double cf = s ? -s_c[i] : s_c[i];
+        acc.x = fma(cf, p.x, acc.x);
+        acc.y = fma(cf, p.y, acc.y);
+      }
+      __builtin_nontemporal_store(acc, reinterpret_cast<vd2*>(lam + g[r]));
+      if (LAST) e += v[r].x * acc.x + v[r].y * acc.y;
+    }
+  }
+  if (LAST) {
+    e = wave_sum_full(e);
+    if ((tid & (kWave - 1)) == 0) red[tid / kWave] = e;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kHBlock / kWave; ++w) s += red[w];
+      epart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// Terms whose flipped bits span more high bits than a tile holds: partners
+// gathered from global memory (as k_vqe_hphi), added to lambda (written on
+// the first pass); the last pass also sums the energy partials.
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(kVqeBlock) void k_vqe_hphi_wide(const double2* __restrict__ phi0, double2* __restrict__ lam0,
+                                                             int n, const VqeTerm* __restrict__ terms,
+                                                             const int* __restrict__ tidx, int cnt, int nterms,
+                                                             const double* __restrict__ coeffs,
+                                                             double* __restrict__ epart) {
+  __shared__ double red[kVqeBlock / kWave];
+  const unsigned long long N = 1ull << n;
+  const double2* __restrict__ p = phi0 + (size_t)blockIdx.y * N;
+  double2* __restrict__ l = lam0 + (size_t)blockIdx.y * N;
+  const double* cb = coeffs ? coeffs + (size_t)blockIdx.y * nterms : nullptr;
+  double e = 0.0;
+  for (unsigned long long j = (unsigned long long)blockIdx.x * kVqeBlock + threadIdx.x; j < N;
+       j += (unsigned long long)gridDim.x * kVqeBlock) {
+    vd2 acc = FIRST ? mk(0.0, 0.0) : ld(l + j);
+    for (int i = 0; i < cnt; ++i) {
+      const int t = tidx[i];
+      const VqeTerm T = terms[t];
+      const double tc = cb ? cb[t] : T.c;
+      const unsigned long long k = j ^ T.x;
+      vd2 v = ld(p + k);
+      switch (T.y & 3) {
+        case 1: v = mk(-v.y, v.x); break;
+        case 2: v = mk(-v.x, -v.y); break;
+        case 3: v = mk(v.y, -v.x); break;
+        default: break;
+      }
+      const double c = (__popcll(k & T.z) & 1) ? -tc : tc;
+      acc.x = fma(c, v.x, acc.x);
+      acc.y = fma(c, v.y, acc.y);
+    }
+    st(l + j, acc);
+    if (LAST) {
+      const vd2 v = ld(p + j);
+      e += v.x * acc.x + v.y * acc.y;
+    }
+  }
+  if (LAST) {
+    e = wave_sum(e);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kVqeBlock / kWave; ++w) s += red[w];
+      epart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
 // Backward step over all states; gradient partials gpart[(b * nslots + slot) * G + block]
 __global__ __launch_bounds__(kVqeBlock) void k_vqe_adjoint(double2* __restrict__ phi, double2* __restrict__ lam,
                                                            int n, VqeOp op, const double2* __restrict__ fixed,
@@ -675,7 +856,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_vqe_bwd_tile(double2* __restrict_
                                                             int n, FusedBlockDev blk,
                                                             const VqeBwdOp* __restrict__ ops,
                                                             const double2* __restrict__ table0, int mat_stride,
-                                                            int nslots, double* __restrict__ gpart) {
+                                                            int nslots, double* __restrict__ gpart,
+                                                            unsigned long long ntiles) {
   extern __shared__ double2 sh[];
   __shared__ double acc[kBwdMaxOps][kBwdBlock / kWave];
   constexpr int NW = kBwdBlock / kWave;
@@ -687,7 +869,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_vqe_bwd_tile(double2* __restrict_
   double2* __restrict__ phi = phi0 + (size_t)blockIdx.y * N;
   double2* __restrict__ lam = lam0 + (size_t)blockIdx.y * N;
   const double2* __restrict__ table = table0 + (size_t)blockIdx.y * mat_stride;
-  const unsigned long long ntiles = 1ull << (n - k);
+  
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
@@ -990,7 +1172,8 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
                                                                       const VqeBwdRop* __restrict__ ops,
                                                                       const double2* __restrict__ table0,
                                                                       int mat_stride, int nslots,
-                                                                      double* __restrict__ gpart) {
+                                                                      double* __restrict__ gpart,
+                                                                      unsigned long long ntiles) {
   constexpr int NV = 1 << R;
   extern __shared__ double2 sh[];
   __shared__ double acc[kBwdMaxOps][kBwdRbMaxWaves];
@@ -1003,7 +1186,7 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
   double2* __restrict__ phi = phi0 + (size_t)blockIdx.y * N;
   double2* __restrict__ lam = lam0 + (size_t)blockIdx.y * N;
   const double2* __restrict__ table = table0 + (size_t)blockIdx.y * mat_stride;
-  const unsigned long long ntiles = 1ull << (n - k);
+  
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
@@ -1134,6 +1317,7 @@ struct nwq_vqe {
   nwq::VqeOp* d_ops = nullptr;
   double2* d_fixed = nullptr;
   nwq::VqeTerm* d_terms = nullptr;
+  std::vector<nwq::VqeTerm> terms;   // host copy of the term table
   int* d_slot_param = nullptr;
   // global path buffers
   int Bcap = 0;
@@ -1154,6 +1338,19 @@ struct nwq_vqe {
   bool bwd_rb = false;         // backward sweep register-blocked (3 bits) when every tile has >= 2^9 entries
   size_t fused_rop_off = 0;    // offset of the register-blocked backward ops in d_fused
   std::vector<nwq::FusedBlockDev> fwd_blocks, bwd_blocks;
+  // backward dispatches of the first planned block (the last of the sweep):
+  // phi is non-zero in tile 0 only there (it equals that block applied to
+  // |0...0>), and lambda is not read after the sweep, so they run tile 0 only
+  std::vector<char> bwd_tile0;
+  // lambda = H phi of the fused schedule: tiled passes (and a gather pass for
+  // terms that fit no tile), in launch order
+  struct HLaunch {
+    int wide;            // 1: k_vqe_hphi_wide over the term indices at widx[w_begin .. w_begin + w_count)
+    nwq::HPass p;        // tiled pass (p.t_begin indexes the HTerm table)
+    int w_begin, w_count;
+  };
+  std::vector<HLaunch> hlaunch;
+  size_t fused_hterm_off = 0, fused_widx_off = 0;
   void* d_fused = nullptr;     // [forward phases][forward ops][backward ops]
   size_t fused_ops_off = 0, fused_bwd_off = 0;
   nwq::VqeConfig cfg;
@@ -1301,6 +1498,7 @@ static int build_fused(nwq_vqe* h) {
   std::vector<VqeBwdOp> bops;
   h->fwd_blocks.clear();
   h->bwd_blocks.clear();
+  h->bwd_tile0.clear();
   std::vector<Block> padded(blocks);
   for (Block& b : padded) pad_block(b, n, std::max(k, 8));
   size_t max_bwd_lds = 0;
@@ -1432,6 +1630,7 @@ static int build_fused(nwq_vqe* h) {
       d.op_count = (int)phases.size() - d.op_begin;
       fill_entry_offsets(d, kBwdBits);
       h->bwd_blocks.push_back(d);
+      h->bwd_tile0.push_back(bit + 1 == bpadded.rend() ? 1 : 0);
     }
   }
   for (auto bit = bpadded.rbegin(); !h->bwd_rb && bit != bpadded.rend(); ++bit) {
@@ -1462,23 +1661,114 @@ static int build_fused(nwq_vqe* h) {
       for (size_t i = s0; i < e; ++i) bops.push_back(rev[i]);
       d.op_count = (int)(e - s0);
       h->bwd_blocks.push_back(d);
+      h->bwd_tile0.push_back(bit + 1 == bpadded.rend() ? 1 : 0);
+    }
+  }
+  // lambda = H phi: the first pass takes tiles of the low kt bits with every
+  // diagonal term and the terms whose flipped bits lie there; further passes
+  // take tiles of the 6 low bits plus up to kt - 6 high bits, greedily, for
+  // the remaining terms; terms needing more high bits than that go to a
+  // gather pass.  Tiles are widened to 2^kt entries with unused high bits.
+  std::vector<HTerm> hterms;
+  std::vector<int> widx;
+  h->hlaunch.clear();
+  {
+    const int kt = std::min(n, kHTileBits);
+    std::vector<int> diag, rest, wide;
+    for (int t = 0; t < h->nterms; ++t) {
+      const unsigned long long x = h->terms[t].x;
+      if (x == 0) diag.push_back(t);
+      else if ((x >> kt) == 0) rest.push_back(t);   // in the first pass
+      else if (__builtin_popcountll(x >> 6) > kt - 6) wide.push_back(t);
+      else rest.push_back(t);
+    }
+    auto add_pass = [&](int c, std::vector<int> hi, const std::vector<int>& dg, const std::vector<int>& fl) {
+      for (int q = c; q < n && (int)hi.size() < kt - c; ++q)
+        if (std::find(hi.begin(), hi.end(), q) == hi.end()) hi.push_back(q);
+      std::sort(hi.begin(), hi.end());
+      auto local = [&](unsigned long long mask) {
+        unsigned l = (unsigned)(mask & ((1ull << c) - 1ull));
+        for (size_t i = 0; i < hi.size(); ++i)
+          if ((mask >> hi[i]) & 1ull) l |= 1u << (c + i);
+        return l;
+      };
+      unsigned long long inside = (1ull << c) - 1ull;
+      for (int q : hi) inside |= 1ull << q;
+      std::vector<int> all(dg);
+      all.insert(all.end(), fl.begin(), fl.end());
+      for (size_t s0 = 0; s0 < all.size(); s0 += kHMaxTerms) {
+        nwq_vqe::HLaunch L{};
+        L.p.c = c;
+        L.p.m = (int)hi.size();
+        for (size_t i = 0; i < hi.size(); ++i) L.p.hi[i] = hi[i];
+        L.p.t_begin = (int)hterms.size();
+        for (size_t i = s0; i < std::min(all.size(), s0 + kHMaxTerms); ++i) {
+          const VqeTerm& T = h->terms[all[i]];
+          const int pc = __builtin_popcountll(T.x & T.z);
+          hterms.push_back(HTerm{local(T.x), local(T.z & inside), T.z & ~inside, pc & 3, pc & 1, all[i], 0});
+          if (T.x == 0) ++L.p.n_diag;
+          else ++L.p.n_flip;
+        }
+        h->hlaunch.push_back(L);
+      }
+    };
+    std::vector<int> first_flips, later;
+    for (int t : rest) ((h->terms[t].x >> kt) == 0 ? first_flips : later).push_back(t);
+    add_pass(kt, {}, diag, first_flips);
+    const int c = std::min(6, kt);
+    while (!later.empty()) {
+      std::vector<int> hi, take, keep;
+      for (int t : later) {
+        std::vector<int> need;
+        for (int q = c; q < n; ++q)
+          if (((h->terms[t].x >> q) & 1ull) && std::find(hi.begin(), hi.end(), q) == hi.end()) need.push_back(q);
+        if ((int)(hi.size() + need.size()) <= kt - c) {
+          hi.insert(hi.end(), need.begin(), need.end());
+          take.push_back(t);
+        } else {
+          keep.push_back(t);
+        }
+      }
+      add_pass(c, hi, {}, take);
+      later.swap(keep);
+    }
+    if (!wide.empty()) {
+      nwq_vqe::HLaunch L{};
+      L.wide = 1;
+      L.w_begin = 0;
+      L.w_count = (int)wide.size();
+      widx = wide;
+      h->hlaunch.push_back(L);
+    }
+    for (size_t i = 0; i < h->hlaunch.size(); ++i) {
+      h->hlaunch[i].p.first = i == 0;
+      h->hlaunch[i].p.last = i + 1 == h->hlaunch.size();
     }
   }
   const size_t ph_bytes = phases.size() * sizeof(FusedPhase);
   h->fused_ops_off = (ph_bytes + 255) & ~size_t(255);
   h->fused_bwd_off = (h->fused_ops_off + fops.size() * sizeof(FusedOp) + 255) & ~size_t(255);
   h->fused_rop_off = (h->fused_bwd_off + bops.size() * sizeof(VqeBwdOp) + 255) & ~size_t(255);
-  const size_t total = h->fused_rop_off + rops.size() * sizeof(VqeBwdRop) + 16;
+  h->fused_hterm_off = (h->fused_rop_off + rops.size() * sizeof(VqeBwdRop) + 255) & ~size_t(255);
+  h->fused_widx_off = (h->fused_hterm_off + hterms.size() * sizeof(HTerm) + 255) & ~size_t(255);
+  const size_t total = h->fused_widx_off + widx.size() * sizeof(int) + 16;
   std::vector<char> prog(total, 0);
   if (!phases.empty()) std::memcpy(prog.data(), phases.data(), ph_bytes);
   if (!fops.empty()) std::memcpy(prog.data() + h->fused_ops_off, fops.data(), fops.size() * sizeof(FusedOp));
   if (!bops.empty()) std::memcpy(prog.data() + h->fused_bwd_off, bops.data(), bops.size() * sizeof(VqeBwdOp));
   if (!rops.empty()) std::memcpy(prog.data() + h->fused_rop_off, rops.data(), rops.size() * sizeof(VqeBwdRop));
+  if (!hterms.empty()) std::memcpy(prog.data() + h->fused_hterm_off, hterms.data(), hterms.size() * sizeof(HTerm));
+  if (!widx.empty()) std::memcpy(prog.data() + h->fused_widx_off, widx.data(), widx.size() * sizeof(int));
   // dynamic LDS above 64 KiB is enabled here, outside any graph capture
   const int kbt = std::min(std::min(h->fused_k, kBwdMaxTileBits), n);
   const size_t max_rb_lds = 2 * bwd_rb_tile_bytes(kbt < 8 ? 8 : kbt);
   int rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)max_bwd_lds), "hipFuncSetAttribute");
+  for (const void* f : {(const void*)k_vqe_hphi_tile<false, false>, (const void*)k_vqe_hphi_tile<true, false>,
+                        (const void*)k_vqe_hphi_tile<false, true>, (const void*)k_vqe_hphi_tile<true, true>})
+    if (!rc)
+      rc = check_hip(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(sizeof(double2) * hpad(1u << kHTileBits))), "hipFuncSetAttribute");
   if (!rc && h->bwd_rb)
     rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_rb_lds), "hipFuncSetAttribute");
@@ -1514,25 +1804,45 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
   hipLaunchKernelGGL(k_vqe_init, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n);
   hipLaunchKernelGGL(k_vqe_mats, dim3((h->nops + 255) / 256, B), dim3(256), 0, s, h->d_ops, h->nops, h->d_fixed,
                      theta, h->P, h->d_table);
-  for (const FusedBlockDev& d : h->fwd_blocks)
-    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, h->fused_rbits, B, stride, G, h->fused_flags);
-  hipLaunchKernelGGL(k_vqe_hphi, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, h->nterms,
-                     coeffs, h->d_epart, grad != nullptr ? 1 : 0);
+  // the first block acts on |0...0>: only the tile holding index 0 (tile 0)
+  // is non-zero, and a block maps each tile to itself, so the others stay 0
+  for (size_t bi = 0; bi < h->fwd_blocks.size(); ++bi)
+    launch_fused_rb(s, h->d_phi, h->n, h->fwd_blocks[bi], dph, dfo, h->d_table, h->fused_rbits, B, stride, G,
+                    h->fused_flags, bi == 0 ? 1ull : 0ull);
+  const HTerm* dht = reinterpret_cast<const HTerm*>(static_cast<char*>(h->d_fused) + h->fused_hterm_off);
+  const int* dwi = reinterpret_cast<const int*>(static_cast<char*>(h->d_fused) + h->fused_widx_off);
+  for (const auto& L : h->hlaunch) {
+    const int sel = (L.p.first ? 1 : 0) | (L.p.last ? 2 : 0);
+    if (L.wide) {
+      auto kw = sel == 0 ? k_vqe_hphi_wide<false, false> : sel == 1 ? k_vqe_hphi_wide<true, false>
+              : sel == 2 ? k_vqe_hphi_wide<false, true> : k_vqe_hphi_wide<true, true>;
+      hipLaunchKernelGGL(kw, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->d_lam, h->n, h->d_terms, dwi + L.w_begin,
+                         L.w_count, h->nterms, coeffs, h->d_epart);
+    } else {
+      auto kt = sel == 0 ? k_vqe_hphi_tile<false, false> : sel == 1 ? k_vqe_hphi_tile<true, false>
+              : sel == 2 ? k_vqe_hphi_tile<false, true> : k_vqe_hphi_tile<true, true>;
+      const size_t lds = sizeof(double2) * hpad(1u << (L.p.c + L.p.m));
+      hipLaunchKernelGGL(kt, grid, dim3(kHBlock), lds, s, h->d_phi, h->d_lam, h->n, L.p, dht, h->d_terms, h->nterms,
+                         coeffs, h->d_epart);
+    }
+  }
   if (grad != nullptr) {
     const VqeBwdRop* dro = reinterpret_cast<const VqeBwdRop*>(static_cast<char*>(h->d_fused) + h->fused_rop_off);
-    for (const FusedBlockDev& d : h->bwd_blocks) {
+    for (size_t bi = 0; bi < h->bwd_blocks.size(); ++bi) {
+      const FusedBlockDev& d = h->bwd_blocks[bi];
       const int kb = d.c + d.m;
+      const unsigned long long nt = h->bwd_tile0[bi] ? 1ull : 1ull << (h->n - kb);
       if (h->bwd_rb) {
         if (h->fused_flags & kFusedNonTemporal)
           hipLaunchKernelGGL((k_vqe_bwd_rb<3, true>), grid, dim3(1u << (kb - 3)), 2 * bwd_rb_tile_bytes(kb), s,
-                             h->d_phi, h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart);
+                             h->d_phi, h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart, nt);
         else
           hipLaunchKernelGGL((k_vqe_bwd_rb<3, false>), grid, dim3(1u << (kb - 3)), 2 * bwd_rb_tile_bytes(kb), s,
-                             h->d_phi, h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart);
+                             h->d_phi, h->d_lam, h->n, d, dph, dro, h->d_table, stride, h->nslots, h->d_gpart, nt);
       } else {
         const size_t lds = 2 * sizeof(double2) << kb;
         hipLaunchKernelGGL(k_vqe_bwd_tile, grid, dim3(kBwdBlock), lds, s, h->d_phi, h->d_lam, h->n, d, dbo,
-                           h->d_table, stride, h->nslots, h->d_gpart);
+                           h->d_table, stride, h->nslots, h->d_gpart, nt);
       }
     }
   }
@@ -1646,6 +1956,7 @@ int nwq_vqe_create(int n, int n_ops, const int* types, const int* qubits, const 
     terms[t] = VqeTerm{xmask[t], zmask[t], coeffs[t], __builtin_popcountll(xmask[t] & zmask[t]) & 3, 0};
   }
   h->nterms = n_terms;
+  h->terms = terms;
   int rc = check_hip(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "hipStreamCreate");
   if (!rc) rc = check_hip(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming), "hipEventCreate");
   if (!rc) rc = check_hip(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming), "hipEventCreate");
@@ -1978,6 +2289,7 @@ int nwq_vqe_batch(int n, int L, const double* J_h, int B, const double* theta_de
     e->J = J_h[0];
     e->hx = J_h[1];
     tfim_terms(n, e->J, e->hx, e->terms);
+    h->terms = e->terms;
     if (!rc)
       rc = check_hip(hipMemcpyAsync(h->d_terms, e->terms.data(), e->terms.size() * sizeof(nwq::VqeTerm),
                                     hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync(vqe terms)");

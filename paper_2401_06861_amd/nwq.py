@@ -64,6 +64,7 @@ _SIG = {
     "nwq_apply_gate": [_h, C.c_int, _ip, C.c_int, _dp, C.c_int],
     "nwq_apply_matrix": [_h, _ip, C.c_int, _dp],
     "nwq_apply_circuit": [_h, C.c_int, _ip, _ip, _dp],
+    "nwq_run_circuit": [_h, C.c_int, _ip, _ip, _dp],
     "nwq_set_fusion": [_h, C.c_int, _ip],
     "nwq_fusion_stats": [_h, _ip, _ip],
     "nwq_set_fusion_kernel": [_h, C.c_int],
@@ -215,6 +216,15 @@ def nwq_apply_circuit(h: int, types: np.ndarray, qubits: np.ndarray, params: np.
     params = np.ascontiguousarray(params, dtype=np.float64)
     _check(lib.nwq_apply_circuit(h, len(types), types.ctypes.data_as(_ip), qubits.ctypes.data_as(_ip),
                                  params.ctypes.data_as(_dp)))
+
+
+def nwq_run_circuit(h: int, types: np.ndarray, qubits: np.ndarray, params: np.ndarray) -> None:
+    """Reset to |0...0> and apply the circuit (arrays of circuit_arrays)."""
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    qubits = np.ascontiguousarray(qubits, dtype=np.int32)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    _check(lib.nwq_run_circuit(h, len(types), types.ctypes.data_as(_ip), qubits.ctypes.data_as(_ip),
+                               params.ctypes.data_as(_dp)))
 
 
 def nwq_set_fusion(h: int, k: int) -> int:

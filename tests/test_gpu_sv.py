@@ -505,3 +505,29 @@ def test_streaming_ceiling_kernels(nwq, size):
     nwq.nwq_stream_scale(x, 2.0)
     torch.cuda.synchronize()
     assert torch.equal(y * 2.0, x)
+
+
+@pytest.mark.parametrize("n,k", [(9, 8), (14, 10), (20, 12)])
+def test_run_circuit_from_zero(nwq, n, k):
+    """nwq_run_circuit (reset, then the circuit; the first fused block runs
+    only the tile holding index 0) equals reset + nwq_apply_circuit and the
+    oracle, for every fused kernel and unfused, on a state that held other
+    values before."""
+    gates = W.brickwork_circuit(n, 6, seed=n) + W.random_gate_list(n, 40, seed=n)
+    want = tensor.sv_run(gates, n)
+    arrays = nwq.circuit_arrays(gates)
+    for rb in (1, 2, 0, None):
+        st = nwq.SVState(n, reset=False)
+        st.load(W.random_state(n, seed=3))
+        if rb is None:
+            st.set_fusion(0)
+        else:
+            st.set_fusion(k)
+            nwq.nwq_set_fusion_kernel(st.h, rb)
+        nwq.nwq_run_circuit(st.h, *arrays)
+        got = st.numpy()
+        assert maxerr(got, want) <= TOL, (n, k, rb)
+        st.reset()
+        nwq.nwq_apply_circuit(st.h, *arrays)
+        assert np.array_equal(st.numpy(), got), (n, k, rb)
+        st.close()

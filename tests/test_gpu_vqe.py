@@ -221,9 +221,12 @@ def test_fused_path_matches_oracle(V, torch, n, L, bps):
 
 def test_fused_generic_program(V, torch):
     """Fused path with fixed gates, CZ, SWAP and RZZ on a 10-qubit register
-    (one tile) and with several tiles at 13 qubits."""
+    (one tile) and with several tiles at 13 and 17 qubits; at 17 qubits the
+    random Pauli sum needs every kind of lambda = H phi pass (the low-bit
+    tile with the diagonal terms, tiles over high bits, and gathered terms
+    whose flipped bits fit no tile)."""
     A = W.AnsatzGate
-    for n in (10, 13):
+    for n in (10, 13, 17):
         prog = []
         for l in range(2):
             prog += [A("h", (q,), -1) for q in range(0, n, 3)]
@@ -232,6 +235,9 @@ def test_fused_generic_program(V, torch):
             prog += [A("cz", (n - 1, 0), -1), A("swap", (1, n - 2), -1), A("s", (3,), -1), A("cx", (n - 1, 2), -1)]
             prog += [A("ry", (q,), 10 + l) for q in range(1, n, 2)]
         terms = W.random_pauli_sum(n, 10, seed=n)
+        if n == 17:   # flips only on high bits, flips over many high bits, Z strings, one-body X
+            terms += [(0b11 << 14, 1 << 15, 0.3), (0b1111111101 << 7, 0, -0.4), (0, 0b101 << 12, 0.2),
+                      (1 << 16, 0, 0.5), (1 << 13, 1 << 2, -0.7)]
         theta = np.random.default_rng(n).uniform(-math.pi, math.pi, (2, 12))
         ctx = V.VQE(n, prog, terms, n_params=12)
         ctx.set_config(3, 256, 0)
