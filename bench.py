@@ -209,12 +209,12 @@ def main():
 
     if args.profile_mode == "fused":
         # the brickwork (depth 8) through fused blocks at k=12, 4 register bits, twice
+        # (nwq_run_circuit: reset, then the circuit, as the fused leg runs it)
         nwq.nwq_set_fusion(st.h, 12)
         nwq.nwq_set_fusion_kernel(st.h, 1)
         short = nwq.circuit_arrays(W.brickwork_circuit(n, 8, seed=0))
         for _ in range(2):
-            st.reset()
-            nwq.nwq_apply_circuit(st.h, *short)
+            nwq.nwq_run_circuit(st.h, *short)
         torch.cuda.synchronize()
         log(f"[bench] profile mode done: {nwq.nwq_fusion_stats(st.h)} blocks/gates per run")
         print(json.dumps({"profile_mode": args.profile_mode, "n": n}))
