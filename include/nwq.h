@@ -429,7 +429,8 @@ int nwq_get_launch_target(nwq_handle h, int cls, int bit, int* ppt, int* nontemp
 int nwq_autotune(nwq_handle h, int reps, double* best_ms);
 
 /* Fusion autotuner (SV handles): runs the given circuit (arrays as for
- * nwq_apply_circuit) from |0...0> once untimed and reps times timed under
+ * nwq_apply_circuit) from |0...0> as nwq_run_circuit does (the reset
+ * included) once untimed and reps times timed under
  * each candidate: unfused, and every fusion width from 6 to min(13, n) with
  * each fused kernel (the register-blocked ones only on 8 or more qubits).
  * Keeps the fastest on the handle and returns it in *best_k (0 = unfused)

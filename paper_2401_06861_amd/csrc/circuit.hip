@@ -463,9 +463,8 @@ int nwq_autotune_fusion(nwq_handle h, int n_gates, const int* types, const int* 
     h->fuse_rb = c.rb;
     double total = 0.0;
     for (int r = 0; r <= reps && !rc; ++r) {   // r == 0 is the untimed run
-      rc = nwq_reset(h);
-      if (!rc) rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
-      if (!rc) rc = nwq_apply_circuit(h, n_gates, types, qubits, params);
+      rc = check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+      if (!rc) rc = apply_circuit_common(h, n_gates, types, qubits, params, true);   // from |0...0>
       if (!rc) rc = flush_all(h);
       if (!rc) rc = check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
       if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");

@@ -532,7 +532,19 @@ __global__ __launch_bounds__(kHBlock) void k_vqe_hphi_tile(const double2* __rest
     const int t = hterms[ps.t_begin + i].t;
     s_c[i] = coeffs ? coeffs[(size_t)blockIdx.y * nterms + t] : terms[t].c;
   }
+  // Entry r of this thread is tile entry l = tid + r kHBlock; its global
+  // index is the tile base plus a tile-independent part, computed once.
   const unsigned cmask = (1u << ps.c) - 1u;
+  unsigned long long sc[kHPer];
+#pragma unroll
+  for (int r = 0; r < kHPer; ++r) {
+    const unsigned l = tid + r * kHBlock;
+    unsigned long long gi = l & cmask;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < ps.m && ((l >> (ps.c + i)) & 1u)) gi |= 1ull << ps.hi[i];
+    sc[r] = gi;
+  }
   double e = 0.0;
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     unsigned long long base = tile << ps.c;
@@ -543,54 +555,66 @@ __global__ __launch_bounds__(kHBlock) void k_vqe_hphi_tile(const double2* __rest
         base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
       }
     }
-    vd2 v[kHPer];
-    unsigned long long g[kHPer];
+    vd2 v[kHPer], acc[kHPer];
     __syncthreads();   // the previous tile's readers are done (and s_c is written)
 #pragma unroll
     for (int r = 0; r < kHPer; ++r) {
       const unsigned l = tid + r * kHBlock;
       if (l < len) {
-        unsigned long long gi = base | (l & cmask);
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (i < ps.m && ((l >> (ps.c + i)) & 1u)) gi |= 1ull << ps.hi[i];
-        g[r] = gi;
-        v[r] = __builtin_nontemporal_load(reinterpret_cast<const vd2*>(phi + gi));
+        v[r] = __builtin_nontemporal_load(reinterpret_cast<const vd2*>(phi + (base | sc[r])));
+        acc[r] = FIRST ? mk(0.0, 0.0) : __builtin_nontemporal_load(reinterpret_cast<const vd2*>(lam + (base | sc[r])));
         st(tl + hpad(l), v[r]);
       }
     }
     __syncthreads();
+    // The sign of a term at entry l: the parity of (l & zl) splits into the
+    // thread's bits (tid & zl) and the entry slot's (r kHBlock & zl); the bits
+    // outside the tile (base & zo) and x & z are per tile and term.
+    if (ps.n_diag > 0) {
+      double d[kHPer];
+#pragma unroll
+      for (int r = 0; r < kHPer; ++r) d[r] = 0.0;
+      for (int i = 0; i < ps.n_diag; ++i) {
+        const HTerm T = hterms[ps.t_begin + i];
+        const double c = s_c[i];
+        const unsigned pb = (unsigned)(__popcll(base & T.zo) + __popc(tid & T.zl)) & 1u;
+#pragma unroll
+        for (int r = 0; r < kHPer; ++r) {
+          const unsigned sg = pb ^ ((unsigned)__popc((unsigned)(r * kHBlock) & T.zl) & 1u);
+          d[r] += sg ? -c : c;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kHPer; ++r) {
+        acc[r].x = fma(d[r], v[r].x, acc[r].x);
+        acc[r].y = fma(d[r], v[r].y, acc[r].y);
+      }
+    }
+    for (int i = ps.n_diag; i < nt; ++i) {
+      const HTerm T = hterms[ps.t_begin + i];
+      const double c = s_c[i];
+      const unsigned pb = (unsigned)(__popcll(base & T.zo) + __popc(tid & T.zl) + T.sx) & 1u;
+      const int y = T.y & 3;
+#pragma unroll
+      for (int r = 0; r < kHPer; ++r) {
+        const unsigned l = tid + r * kHBlock;
+        if (l >= len) continue;
+        vd2 p = ld(tl + hpad(l ^ T.xl));
+        if (y == 1) p = mk(-p.y, p.x);
+        else if (y == 2) p = mk(-p.x, -p.y);
+        else if (y == 3) p = mk(p.y, -p.x);
+        const unsigned sg = pb ^ ((unsigned)__popc((unsigned)(r * kHBlock) & T.zl) & 1u);
+        const double cf = sg ? -c : c;
+        acc[r].x = fma(cf, p.x, acc[r].x);
+        acc[r].y = fma(cf, p.y, acc[r].y);
+      }
+    }
 #pragma unroll
     for (int r = 0; r < kHPer; ++r) {
       const unsigned l = tid + r * kHBlock;
       if (l >= len) continue;
-      vd2 acc = FIRST ? mk(0.0, 0.0) : __builtin_nontemporal_load(reinterpret_cast<const vd2*>(lam + g[r]));
-      if (ps.n_diag > 0) {
-        double d = 0.0;   // diagonal terms: one real coefficient per entry
-        for (int i = 0; i < ps.n_diag; ++i) {
-          const HTerm T = hterms[ps.t_begin + i];
-          const unsigned s = (unsigned)(__popc(l & T.zl) + __popcll(base & T.zo)) & 1u;
-          d += s ? -s_c[i] : s_c[i];
-        }
-        acc.x = fma(d, v[r].x, acc.x);
-        acc.y = fma(d, v[r].y, acc.y);
-      }
-      for (int i = ps.n_diag; i < nt; ++i) {
-        const HTerm T = hterms[ps.t_begin + i];
-        vd2 p = ld(tl + hpad(l ^ T.xl));
-        switch (T.y & 3) {
-          case 1: p = mk(-p.y, p.x); break;
-          case 2: p = mk(-p.x, -p.y); break;
-          case 3: p = mk(p.y, -p.x); break;
-          default: break;
-        }
-        const unsigned s = (unsigned)(__popc(l & T.zl) + __popcll(base & T.zo) + T.sx) & 1u;
-        const double cf = s ? -s_c[i] : s_c[i];
-        acc.x = fma(cf, p.x, acc.x);
-        acc.y = fma(cf, p.y, acc.y);
-      }
-      __builtin_nontemporal_store(acc, reinterpret_cast<vd2*>(lam + g[r]));
-      if (LAST) e += v[r].x * acc.x + v[r].y * acc.y;
+      __builtin_nontemporal_store(acc[r], reinterpret_cast<vd2*>(lam + (base | sc[r])));
+      if (LAST) e += v[r].x * acc[r].x + v[r].y * acc[r].y;
     }
   }
   if (LAST) {
