@@ -985,7 +985,10 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     }
   for (int j = 0; j < k; ++j) qs.sorted[j] = sorted[j];
   const unsigned long long ng = 1ull << (nbits - k);
-  if (k == 4 && sorted[0] < 3 && sorted[1] < 8 && sorted[2] >= 8 && nbits >= 12) {
+  // two lower bits in a 256-entry run (the lowest below 3): the LDS-staged
+  // kernel, unless the shape picks a split-workgroup kernel (64, 128), which
+  // the tuner compares with it bit by bit
+  if (k == 4 && sorted[0] < 3 && sorted[1] < 8 && sorted[2] >= 8 && nbits >= 12 && cfg.ppt != 64 && cfg.ppt != 128) {
     KqStaged ks{};
     ks.h0 = sorted[2] - 8;
     ks.h1 = sorted[3] - 8;

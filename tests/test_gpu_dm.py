@@ -244,11 +244,13 @@ def test_staged_two_qubit_superoperators(nwq, n):
     want = rho0
     for op in ops:
         want = tensor.dm_apply(want, op, n)
-    for nt in (0, 1):
-        nwq.nwq_set_launch(st.h, 7, -1, 1, nt)
+    # the staged kernel (shape 1) and, on the same pairs, the split-workgroup
+    # kernels the tuner compares with it (shapes 64, 128, both workgroup orders)
+    for ppt, flags in ((1, 0), (1, 1), (64, 1), (128, 1), (64, 3), (128, 3)):
+        nwq.nwq_set_launch(st.h, 7, -1, ppt, flags)
         st.load(rho0)
         st.run(ops)
-        assert maxerr(st.numpy(), want) <= TOL, nt
+        assert maxerr(st.numpy(), want) <= TOL, (ppt, flags)
     st.close()
 
 
