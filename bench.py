@@ -769,9 +769,25 @@ def serving_leg(torch, num, num_side=600):
                             "contexts_released": srv.released, "errors": lat["errors"]}
         if frac == 0.8:
             main = loads[str(frac)]
+    # one shape class: the same loop on a stream of n=20, L=8 VQE requests (half with gradient,
+    # 1-20 optimiser steps), where arrivals do overlap in flight
+    kw1 = dict(seed=9, sv_frac=1.0, sv_n=(20, 20), L_range=(8, 8), opt_steps=(1, 20))
+    srv = Server(ex, budget)
+    sat1 = summarize(srv.run(W.serving_trace(rate=1e9, num=400, **kw1)))
+    rate1 = 0.8 * sat1["throughput_req_per_s"]
+    srv = Server(ex, budget)
+    lat1 = summarize(srv.run(W.serving_trace(rate=rate1, num=400, **kw1)))
+    log(f"[bench] single class n=20 L=8: saturation {sat1['throughput_req_per_s']:.1f} req/s, "
+        f"0.8 load p50 {lat1['p50_ms']:.1f} ms p99 {lat1['p99_ms']:.1f} ms")
+    single = {"requests": 400, "mix": "SV VQE n=20 L=8 only (half +grad, 1-20 steps)",
+              "saturation_req_per_s": round(sat1["throughput_req_per_s"], 2), "offered_req_per_s": round(rate1, 2),
+              "throughput_req_per_s": round(lat1["throughput_req_per_s"], 2), "p50_ms": round(lat1["p50_ms"], 2),
+              "p99_ms": round(lat1["p99_ms"], 2), "batches": batch_stats(srv.batches, top=1),
+              "errors": lat1["errors"]}
     ex.close()
     torch.cuda.empty_cache()
     return {"requests": num, "mix": "70% SV VQE n10-24 L4-8 (half +grad, 1-20 steps), 30% DM TFIM n6-12",
+            "single_class_0.8": single,
             "budget_GB": budget / 1e9, "saturation_req_per_s": round(sat["throughput_req_per_s"], 2),
             "saturation_batches": sat_batches,
             "offered_req_per_s": main["offered_req_per_s"], "throughput_req_per_s": main["throughput_req_per_s"],
