@@ -183,9 +183,11 @@ int nwq_fusion_stats(nwq_handle h, int* blocks, int* gates);
 int nwq_set_fusion_kernel(nwq_handle h, int kernel);
 /* Flags of the register-blocked fused kernels (1 and 2): bit 0 = load and
  * store the tiles with non-temporal accesses (each entry is read and written
- * once per block).  Default 1 (on the MI355X the depth-40 brickwork at 30
- * qubits runs about 3% faster with it).  Results do not depend on the
- * flags.  Other values: NWQ_EINVAL. */
+ * once per block; on the MI355X the depth-40 brickwork at 30 qubits runs
+ * about 3% faster with it); bit 1 = when a block's first (last) register
+ * phase holds only tile bits above its low contiguous bits, load (store) that
+ * phase's registers straight from (to) HBM instead of through LDS.  Default
+ * 3.  Results do not depend on the flags.  Other values: NWQ_EINVAL. */
 int nwq_set_fusion_flags(nwq_handle h, int flags);
 
 /* Number of register phases (LDS exchanges) of the last fused
@@ -336,8 +338,10 @@ int nwq_vqe_eval_single(nwq_vqe_handle h, const double* theta_dev, double* energ
 int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_state);
 int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_per_state);
 /* Flags of the fused schedule's tile kernels (forward and backward): bit 0 =
- * non-temporal loads and stores of the tiles.  Default 1.  Results do not
- * depend on the flags.  Other values: NWQ_EINVAL. */
+ * non-temporal loads and stores of the tiles; bit 1 = direct HBM loads and
+ * stores of a forward block's first and last register phase where the block
+ * allows it (as in nwq_set_fusion_flags).  Default 3.  Results do not depend
+ * on the flags.  Other values: NWQ_EINVAL. */
 int nwq_vqe_set_flags(nwq_vqe_handle h, int flags);
 
 /* Batched VQE for the Ising model of Sec. III (Fig. 4) in one call, without

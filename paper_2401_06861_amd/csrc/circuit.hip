@@ -144,9 +144,12 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
 
 // Split a block's gates (tile-local bits) into register phases: greedily
 // take, in order, every gate whose bits fit the phase's rbits register bits
-// and that no earlier left-out gate shares a bit with; pad the set to rbits.
+// and that no earlier left-out gate shares a bit with; pad the set to rbits,
+// from tile bit c up first (a set above the low c bits keeps each wave's
+// lanes on contiguous amplitudes, so the phase can move between registers and
+// HBM directly when it is the block's first or last).
 std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
-                                      const std::vector<int>& nq, int k, int rbits) {
+                               const std::vector<int>& nq, int k, int c, int rbits) {
   std::vector<Phase> out;
   std::vector<int> rem = order;
   while (!rem.empty()) {
@@ -169,6 +172,7 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
         keep.push_back(gi);
       }
     }
+    for (int b = c; b < k && __builtin_popcount(S) < rbits; ++b) S |= 1u << b;
     for (int b = 0; b < k && __builtin_popcount(S) < rbits; ++b) S |= 1u << b;
     int r = 0;
     for (int b = 0; b < k; ++b)
@@ -182,16 +186,39 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
 
 // Global offsets of the tile entries j * 2^(k - rbits), j < 2^rbits: the low
 // c bits stay in place, tile bit c + i lands on qubit hi[i].
+static unsigned long long tile_entry_offset(const FusedBlockDev& d, unsigned l) {
+  unsigned long long g = l & ((1u << d.c) - 1u);
+  for (int i = 0; i < d.m; ++i)
+    if ((l >> (d.c + i)) & 1u) g |= 1ull << d.hi[i];
+  return g;
+}
+
 void fill_entry_offsets(FusedBlockDev& d, int rbits) {
   const int k = d.c + d.m;
+  d.direct = 0;
   for (int j = 0; j < 16; ++j) {
-    d.joff[j] = 0;
-    if (j >= (1 << rbits)) continue;
-    const unsigned l = (unsigned)j << (k - rbits);
-    unsigned long long g = l & ((1u << d.c) - 1u);
-    for (int i = 0; i < d.m; ++i)
-      if ((l >> (d.c + i)) & 1u) g |= 1ull << d.hi[i];
-    d.joff[j] = g;
+    d.joff[j] = d.jdir[j] = d.sdir[j] = 0;
+    if (j < (1 << rbits)) d.joff[j] = tile_entry_offset(d, (unsigned)j << (k - rbits));
+  }
+}
+
+// A phase's LDS offsets are padded by one entry per 16 (o + o / 16); the
+// entry offset is recovered from them.
+void set_direct_io(FusedBlockDev& d, const FusedPhase& first, const FusedPhase& last, int rbits) {
+  auto above_c = [&](const FusedPhase& ph) {
+    for (int r = 0; r < rbits; ++r)
+      if (ph.reg[r] < d.c) return false;
+    return true;
+  };
+  auto unpad = [](unsigned p) { return 16u * (p / 17u) + p % 17u; };
+  d.direct = 0;
+  if (above_c(first)) {
+    d.direct |= 1;
+    for (int j = 0; j < (1 << rbits); ++j) d.jdir[j] = tile_entry_offset(d, unpad(first.ld_off[j]));
+  }
+  if (above_c(last)) {
+    d.direct |= 2;
+    for (int j = 0; j < (1 << rbits); ++j) d.sdir[j] = tile_entry_offset(d, unpad(last.st_off[j]));
   }
 }
 
@@ -240,7 +267,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
     }
     if (order.empty()) continue;
     d.op_begin = (int)phases.size();
-    for (const Phase& ph : plan_phases(order, lb, nq, k, rbits)) {
+    for (const Phase& ph : plan_phases(order, lb, nq, k, b.c, rbits)) {
       FusedPhase fp{};
       for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i] < 0 ? 0 : ph.reg[i];
       fp.op_begin = (int)ops.size();
@@ -272,6 +299,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
     }
     d.op_count = (int)phases.size() - d.op_begin;
     fill_entry_offsets(d, rbits);
+    set_direct_io(d, phases[d.op_begin], phases.back(), rbits);
     launches.push_back({d, true, rbits});
   }
   const size_t ph_bytes = phases.size() * sizeof(FusedPhase);
@@ -413,7 +441,7 @@ int nwq_set_fusion_kernel(nwq_handle h, int kernel) {
 
 int nwq_set_fusion_flags(nwq_handle h, int flags) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
-  if (flags < 0 || flags > 1) return set_error(NWQ_EINVAL, "fusion flags must be 0 or 1");
+  if (flags < 0 || flags > 3) return set_error(NWQ_EINVAL, "fusion flags must be in [0, 3]");
   h->fuse_flags = flags;
   return NWQ_OK;
 }

@@ -55,7 +55,8 @@ struct nwq_state {
   int fuse_k = 0;                  // 0 = off
   int last_blocks = 0, last_fused_gates = 0, last_phases = 0;
   int fuse_rb = 1;                 // fused kernel: 0 one LDS pass per gate, 1 / 2 register-blocked with 4 / 3 register bits
-  int fuse_flags = 1;              // register-blocked kernels: bit 0 non-temporal tile loads and stores
+  int fuse_flags = 3;              // register-blocked kernels: bit 0 non-temporal tile loads and stores, bit 1
+                                   // first / last phase straight between HBM and registers
   void* fuse_dev = nullptr;        // device copy of the compiled block program
   // DM with fusion on: 1q superoperators (4x4 on bits q, q + n) wait here and
   // run as fused blocks when a 2q superoperator or a read needs the state
@@ -150,8 +151,13 @@ inline int reg_swap(int a, int b, int j) {
 int local_bit(const Block& b, int q);
 void pad_block(Block& b, int n, int k_target);
 void fill_entry_offsets(FusedBlockDev& d, int rbits);
+// Marks the block's first / last phase for direct HBM loads / stores when its
+// register bits all lie above the low c tile bits (FusedBlockDev::direct).
+void set_direct_io(FusedBlockDev& d, const FusedPhase& first, const FusedPhase& last, int rbits);
+// c: the block's low tile bits; a phase with fewer gate bits than rbits is
+// padded with tile bits from c up first.
 std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
-                               const std::vector<int>& nq, int k, int rbits);
+                               const std::vector<int>& nq, int k, int c, int rbits);
 
 void gate_matrix(int type, const double* p, cd* m);
 int arena_put(nwq_state* h, const void* src, size_t bytes, void** dev_out);

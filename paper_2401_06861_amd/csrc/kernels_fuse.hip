@@ -23,8 +23,9 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
 
 // Global index of tile entry l: low c bits in place, bit c + i of l on
 // qubit hi[i].
+template <class Blk>
 __device__ __forceinline__ unsigned long long tile_index(unsigned long long base, unsigned l, unsigned cmask, int c,
-                                                         int m, const FusedBlockDev& blk) {
+                                                         int m, const Blk& blk) {
   unsigned long long g = base | (l & cmask);
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -356,9 +357,22 @@ __device__ __forceinline__ void gst(double2* p, vd2 v) {
   else stv(p, v);
 }
 
+// Kernel-side view of a register-blocked block: tile shape, phase range and
+// the global offsets of the registers a tile is loaded into (lo) and stored
+// from (so): the first / last phase's register layout when that phase moves
+// straight between HBM and registers (direct bits 0 / 1), else tile entry
+// j * 2^(k - R).
+struct RbBlockArgs {
+  int c, m;
+  int hi[8];
+  int op_begin, op_count;
+  int direct;
+  unsigned long long lo[16], so[16];
+};
+
 template <int R, bool NT>
 __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __restrict__ a0, int nbits,
-                                                                  FusedBlockDev blk,
+                                                                  RbBlockArgs blk,
                                                                   const FusedPhase* __restrict__ phases,
                                                                   const FusedOp* __restrict__ ops,
                                                                   const double2* __restrict__ mats0,
@@ -374,8 +388,20 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   const unsigned nt = len >> R;
   const unsigned cmask = (1u << c) - 1u;
   const unsigned tid = threadIdx.x;
-  const unsigned long long glane = tile_index(0ull, tid, cmask, c, m, blk);   // thread part of entry indices
-  auto tile_ptr = [&](unsigned long long tile) {
+  const int P = blk.op_count;
+  const bool ldd = (blk.direct & 1) != 0, sdd = (blk.direct & 2) != 0;
+  // thread bits -> the tile bits outside a phase's register bits: insert a
+  // zero at each (ascending) register position
+  auto spread = [&](const FusedPhase& ph) {
+    unsigned dep = tid;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dep = ((dep >> ph.reg[r]) << (ph.reg[r] + 1)) | (dep & ((1u << ph.reg[r]) - 1u));
+    return dep;
+  };
+  // thread part of the entry indices of the load and store layouts
+  const unsigned long long gl_ld = tile_index(0ull, ldd ? spread(phases[blk.op_begin]) : tid, cmask, c, m, blk);
+  const unsigned long long gl_st = tile_index(0ull, sdd ? spread(phases[blk.op_begin + P - 1]) : tid, cmask, c, m, blk);
+  auto tile_base = [&](unsigned long long tile) {
     unsigned long long base = tile << c;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -384,43 +410,52 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
         base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
       }
     }
-    return a + (base + glane);
+    return base;
   };
-  // The tile has exactly NV entries per thread.  They are loaded one tile
-  // ahead: the loads of the next tile are in flight while this one runs its
-  // phases (tiles are disjoint, so the early read is safe).
-  vd2 pf[NV];
+  // A tile's NV entries per thread are loaded one tile ahead: the loads of
+  // the next tile are in flight while this one runs its phases (tiles are
+  // disjoint, so the early read is safe).  A tile's results wait in v and go
+  // to HBM at the top of the next trip, ahead of the next loads: the vector
+  // memory counter retires in issue order, so a store issued after those
+  // loads would make the next trip's wait for them cover the store's
+  // completion too.  With direct I/O the first phase runs on the loaded
+  // registers and the last phase's registers are the results, so a block of
+  // one such phase never touches LDS.
+  vd2 pf[NV], v[NV];
+  double2* __restrict__ prev = nullptr;
   if (blockIdx.x < ntiles) {
-    double2* __restrict__ a0p = tile_ptr(blockIdx.x);
+    const double2* __restrict__ p = a + tile_base(blockIdx.x) + gl_ld;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(a0p + blk.joff[j]);
+    for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(p + blk.lo[j]);
   }
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    double2* __restrict__ at = tile_ptr(tile);
-    __syncthreads();
-    {
+    if (prev) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) gst<NT>(prev + blk.so[j], v[j]);
+    }
+    if (ldd) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) v[j] = pf[j];
+    } else {
+      __syncthreads();
 #pragma unroll
       for (int j = 0; j < NV; ++j) stv(t + padl(tid + j * nt), pf[j]);
-      const unsigned long long nx = tile + gridDim.x;
-      if (nx < ntiles) {
-        double2* __restrict__ an = tile_ptr(nx);
-#pragma unroll
-        for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(an + blk.joff[j]);
-      }
     }
-    for (int pi = 0; pi < blk.op_count; ++pi) {
+    const unsigned long long nx = tile + gridDim.x;
+    if (nx < ntiles) {
+      const double2* __restrict__ p = a + tile_base(nx) + gl_ld;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(p + blk.lo[j]);
+    }
+    for (int pi = 0; pi < P; ++pi) {
       const FusedPhase ph = phases[blk.op_begin + pi];
-      // thread bits -> the tile bits outside the phase's register bits: insert
-      // a zero at each (ascending) register position
-      unsigned dep = tid;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dep = ((dep >> ph.reg[r]) << (ph.reg[r] + 1)) | (dep & ((1u << ph.reg[r]) - 1u));
       // padl(dep | off) = padl(dep) + padl(off) for disjoint bit sets
-      double2* __restrict__ tl = t + padl(dep);
-      __syncthreads();
-      vd2 v[NV];
+      double2* __restrict__ tl = t + padl(spread(ph));
+      if (pi > 0 || !ldd) {
+        __syncthreads();
 #pragma unroll
-      for (int j = 0; j < NV; ++j) v[j] = ldv(tl + ph.ld_off[j]);
+        for (int j = 0; j < NV; ++j) v[j] = ldv(tl + ph.ld_off[j]);
+      }
       const FusedOp* __restrict__ po = ops + ph.op_begin;
       if constexpr (R == 4) {
         // two gates per trip, v -> w -> v; an odd count ends with a copy
@@ -437,16 +472,23 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
       } else {
         for (int oi = 0; oi < ph.op_count; ++oi) rb_apply<R>(po[oi].code, mats + po[oi].mat, v, v);
       }
-      rb_store_phase<R>(tl, ph, v);
+      if (pi < P - 1 || !sdd) {   // else the results stay in v
+        // the tile's first LDS write when the first phase came from HBM:
+        // every wave must be done reading the previous tile
+        if (pi == 0 && ldd) __syncthreads();
+        rb_store_phase<R>(tl, ph, v);
+      }
     }
-    __syncthreads();
-    {
-      vd2 r[NV];
+    if (!sdd) {
+      __syncthreads();
 #pragma unroll
-      for (int j = 0; j < NV; ++j) r[j] = ldv(t + padl(tid + j * nt));
-#pragma unroll
-      for (int j = 0; j < NV; ++j) gst<NT>(at + blk.joff[j], r[j]);
+      for (int j = 0; j < NV; ++j) v[j] = ldv(t + padl(tid + j * nt));
     }
+    prev = a + tile_base(tile) + gl_st;
+  }
+  if (prev) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) gst<NT>(prev + blk.so[j], v[j]);
   }
 }
 
@@ -467,9 +509,20 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
   const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
   const size_t lds = fused_rb_lds_bytes(k);
   const unsigned long long stride = batch > 1 ? (1ull << nbits) : 0ull;
+  RbBlockArgs b{};
+  b.c = blk.c;
+  b.m = blk.m;
+  for (int i = 0; i < 8; ++i) b.hi[i] = blk.hi[i];
+  b.op_begin = blk.op_begin;
+  b.op_count = blk.op_count;
+  b.direct = (flags & kFusedDirect) ? blk.direct : 0;
+  for (int j = 0; j < 16; ++j) {
+    b.lo[j] = (b.direct & 1) ? blk.jdir[j] : blk.joff[j];
+    b.so[j] = (b.direct & 2) ? blk.sdir[j] : blk.joff[j];
+  }
   auto go = [&](auto kern, int rb) {
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(grid, batch), dim3(1u << (k - rb)), lds, s, a, nbits, blk, phases, ops, mats,
+    hipLaunchKernelGGL(kern, dim3(grid, batch), dim3(1u << (k - rb)), lds, s, a, nbits, b, phases, ops, mats,
                        stride, mat_stride, ntiles);
   };
   const bool nt = (flags & kFusedNonTemporal) != 0;

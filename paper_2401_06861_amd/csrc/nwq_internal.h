@@ -140,6 +140,13 @@ struct FusedBlockDev {
   // register-blocked kernels: global offset of tile entry j * 2^(k - rbits)
   // (the per-thread part of an entry's index is added to it)
   unsigned long long joff[16];
+  // Register-blocked SV kernel: bit 0 = the first phase's register bits all
+  // lie above the low c tile bits, so its registers are loaded straight from
+  // HBM (register j from the tile entry at jdir[j] plus the thread's part);
+  // bit 1 = the same for the last phase, stored straight to HBM (sdir).
+  // Such a phase skips its LDS round trip and barrier.
+  int direct;
+  unsigned long long jdir[16], sdir[16];
 };
 void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk,
                         const FusedOp* ops, const double2* mats, int lds_k);
@@ -175,11 +182,14 @@ inline void fill_phase_offsets(FusedPhase& fp, int rbits, const int* ld_perm, co
 size_t fused_rb_lds_bytes(int k);
 // batch > 1: blockIdx.y = batch element b works on a + b * 2^nbits with the
 // matrix table mats + b * mat_stride; max_grid caps the tiles' grid (0 = 2^20).
-// flags: kFusedNonTemporal = non-temporal global loads and stores of the tiles.
+// flags: kFusedNonTemporal = non-temporal global loads and stores of the
+// tiles; kFusedDirect = load the first phase / store the last phase straight
+// between HBM and registers where the block allows it (FusedBlockDev::direct).
 // max_tiles > 0 runs only the first max_tiles tiles of each state (the block
 // leaves the others alone: used when they are known to hold zeros, which a
 // block maps to zeros).
 constexpr int kFusedNonTemporal = 1;
+constexpr int kFusedDirect = 2;
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch = 1, int mat_stride = 0,
                      int max_grid = 0, int flags = 0, unsigned long long max_tiles = 0);

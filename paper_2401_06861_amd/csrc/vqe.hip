@@ -1233,8 +1233,13 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
   };
   // The tile's entries of phi and lambda are loaded one tile ahead: the
   // loads of the next tile are in flight while this one runs its phases
-  // (tiles are disjoint, so the early read is safe).
-  vd2 fp[NV], fl[NV];
+  // (tiles are disjoint, so the early read is safe).  A tile's results leave
+  // LDS at the end of its trip and go to HBM after the next tile is staged,
+  // ahead of the next loads: the vector memory counter retires in issue
+  // order, so stores issued after those loads would make the next trip's
+  // wait for them cover the stores' completion too.
+  vd2 fp[NV], fl[NV], rp[NV], rl[NV];
+  unsigned long long prev = ~0ull;
   if (blockIdx.x < ntiles) {
     const unsigned long long o = tile_off(blockIdx.x);
 #pragma unroll
@@ -1244,15 +1249,19 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
     }
   }
   for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const unsigned long long toff = tile_off(tile);
-    double2* __restrict__ ap = phi + toff;
-    double2* __restrict__ al = lam + toff;
     __syncthreads();
     {
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
         st(tp + padl_b(tid + j * nt), fp[j]);
         st(tl + padl_b(tid + j * nt), fl[j]);
+      }
+      if (prev != ~0ull) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          bgst<NT>(phi + prev + blk.joff[j], rp[j]);
+          bgst<NT>(lam + prev + blk.joff[j], rl[j]);
+        }
       }
       const unsigned long long nx = tile + gridDim.x;
       if (nx < ntiles) {
@@ -1294,18 +1303,18 @@ __global__ __launch_bounds__(kWave * kBwdRbMaxWaves) void k_vqe_bwd_rb(double2* 
       }
     }
     __syncthreads();
-    {
-      vd2 rp[NV], rl[NV];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        rp[j] = ld(tp + padl_b(tid + j * nt));
-        rl[j] = ld(tl + padl_b(tid + j * nt));
-      }
+    for (int j = 0; j < NV; ++j) {
+      rp[j] = ld(tp + padl_b(tid + j * nt));
+      rl[j] = ld(tl + padl_b(tid + j * nt));
+    }
+    prev = tile_off(tile);
+  }
+  if (prev != ~0ull) {
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        bgst<NT>(ap + blk.joff[j], rp[j]);
-        bgst<NT>(al + blk.joff[j], rl[j]);
-      }
+    for (int j = 0; j < NV; ++j) {
+      bgst<NT>(phi + prev + blk.joff[j], rp[j]);
+      bgst<NT>(lam + prev + blk.joff[j], rl[j]);
     }
   }
   __syncthreads();
@@ -1379,7 +1388,8 @@ struct nwq_vqe {
   size_t fused_ops_off = 0, fused_bwd_off = 0;
   nwq::VqeConfig cfg;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (B, want_grad) -> exec
-  int fused_flags = 1;         // fused schedule: bit 0 non-temporal tile loads and stores
+  int fused_flags = 3;         // fused schedule: bit 0 non-temporal tile loads and stores, bit 1 direct
+                               // HBM loads / stores of a forward block's first / last phase
   size_t program_bytes = 0;    // device bytes of d_ops, d_fixed, d_terms, d_slot_param
   size_t fused_bytes = 0;      // device bytes of d_fused once built
 };
@@ -1540,7 +1550,7 @@ static int build_fused(nwq_vqe* h) {
     d.m = b.m;
     for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
     d.op_begin = (int)phases.size();
-    for (const Phase& ph : plan_phases(b.gates, lb, nq, kb, h->fused_rbits)) {
+    for (const Phase& ph : plan_phases(b.gates, lb, nq, kb, b.c, h->fused_rbits)) {
       FusedPhase fp{};
       for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i] < 0 ? 0 : ph.reg[i];
       fp.op_begin = (int)fops.size();
@@ -1577,6 +1587,7 @@ static int build_fused(nwq_vqe* h) {
     }
     d.op_count = (int)phases.size() - d.op_begin;
     fill_entry_offsets(d, h->fused_rbits);
+    set_direct_io(d, phases[d.op_begin], phases.back(), h->fused_rbits);
     h->fwd_blocks.push_back(d);
   }
   // Backward: register-blocked with 3 register bits when every tile gives at
@@ -1615,7 +1626,7 @@ static int build_fused(nwq_vqe* h) {
       d.m = b.m;
       for (int i = 0; i < b.m; ++i) d.hi[i] = b.hi[i];
       d.op_begin = (int)phases.size();
-      for (const Phase& ph : plan_phases(chunk, lb, nq, kb, kBwdBits)) {
+      for (const Phase& ph : plan_phases(chunk, lb, nq, kb, 0, kBwdBits)) {
         FusedPhase fp{};
         for (int i = 0; i < 4; ++i) fp.reg[i] = ph.reg[i] < 0 ? 0 : ph.reg[i];
         fp.op_begin = (int)rops.size();
@@ -2071,7 +2082,7 @@ int nwq_vqe_set_config(nwq_vqe_handle h, int mode, int threads, int blocks_per_s
 
 int nwq_vqe_set_flags(nwq_vqe_handle h, int flags) {
   if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
-  if (flags < 0 || flags > 1) return vqe_fail(NWQ_EINVAL, "flags must be 0 or 1");
+  if (flags < 0 || flags > 3) return vqe_fail(NWQ_EINVAL, "flags must be in [0, 3]");
   if (flags != h->fused_flags) {   // the captured schedules hold the kernels
     (void)hipStreamSynchronize(h->stream);
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);

@@ -417,7 +417,7 @@ def test_register_blocked_fused_kernel(nwq, n, k):
     psi0 = W.random_state(n, seed=n)
     want = tensor.sv_run(gates, n, psi0)
     outs = {}
-    for rb, flags in ((2, 0), (1, 0), (0, 0), (2, 1), (1, 1)):
+    for rb, flags in ((2, 0), (1, 0), (0, 0), (2, 1), (1, 1), (2, 3), (1, 3), (1, 2)):
         st = nwq.SVState(n, reset=False)
         st.load(psi0)
         st.set_fusion(k)
@@ -429,8 +429,41 @@ def test_register_blocked_fused_kernel(nwq, n, k):
         if rb:
             assert nwq.nwq_fusion_phases(st.h) > 0
         st.close()
-    # the non-temporal tile accesses change nothing but the cache hints
-    assert np.array_equal(outs[(1, 0)], outs[(1, 1)]) and np.array_equal(outs[(2, 0)], outs[(2, 1)])
+    # the non-temporal tile accesses change nothing but the cache hints, and
+    # the direct first / last phase nothing but where the registers come from
+    for rb in (1, 2):
+        for flags in (1, 2, 3):
+            if (rb, flags) in outs:
+                assert np.array_equal(outs[(rb, 0)], outs[(rb, flags)]), (rb, flags)
+
+
+@pytest.mark.parametrize("n,k", [(14, 12), (20, 12), (20, 13)])
+def test_fused_direct_phase_blocks(nwq, n, k):
+    """Blocks whose first and last register phases hold only high tile bits
+    (gates on qubits above the low contiguous bits, a single phase moving
+    straight between HBM and registers with no LDS at all, and two-phase
+    blocks) against the oracle, with direct I/O on and off."""
+    rng = np.random.default_rng(n + k)
+    hi = list(range(6, n))
+    gates = []
+    for _ in range(40):
+        a, b = rng.choice(hi, size=2, replace=False)
+        gates.append(("cx", (int(a), int(b)), ()))
+        gates.append(("u3", (int(rng.choice(hi)),), tuple(rng.uniform(-3, 3, size=3))))
+    gates += W.brickwork_circuit(n, 3, seed=n + 1)
+    psi0 = W.random_state(n, seed=n + 3)
+    want = tensor.sv_run(gates, n, psi0)
+    outs = {}
+    for flags in (1, 3):
+        st = nwq.SVState(n, reset=False)
+        st.load(psi0)
+        st.set_fusion(k)
+        nwq.nwq_set_fusion_flags(st.h, flags)
+        st.run_circuit(gates)
+        outs[flags] = st.numpy()
+        assert maxerr(outs[flags], want) <= TOL, (n, k, flags)
+        st.close()
+    assert np.array_equal(outs[1], outs[3])
 
 
 def test_fusion_autotuner(nwq):

@@ -202,7 +202,7 @@ def test_fused_path_matches_oracle(V, torch, n, L, bps):
     ctx.set_config(3, 256, bps)
     t = torch.from_numpy(theta).cuda()
     E, G = ctx.eval(t)
-    ctx.set_flags(1)                           # non-temporal tile accesses: the same bits
+    ctx.set_flags(1)                           # no direct first / last phase: the same bits
     E1, G1 = ctx.eval(t)
     assert torch.equal(E, E1) and torch.equal(G, G1)
     ctx.set_flags(0)
