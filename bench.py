@@ -424,11 +424,26 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
         t0 = time.perf_counter()
         k, rb, table = nwq.nwq_autotune_fusion(st.h, *nwq.circuit_arrays(W.brickwork_circuit(n, args.tune_depth, seed=0)))
         log(f"[bench] fusion autotuner picked k={k} rb={rb} in {time.perf_counter() - t0:.1f}s")
+        # the three fastest candidates on the short prefix, timed once on the whole circuit
+        full = {}
+        for _, kk, r in sorted((v, kk, r) for (kk, r), v in table.items() if kk > 0)[:3]:
+            nwq.nwq_set_fusion(st.h, kk)
+            nwq.nwq_set_fusion_kernel(st.h, r)
+            nwq.nwq_run_circuit(st.h, *arrays)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            nwq.nwq_run_circuit(st.h, *arrays)
+            torch.cuda.synchronize()
+            full[(kk, r)] = (time.perf_counter() - t1) * 1e3
+        k, rb = min(full, key=full.get)
+        log(f"[bench] whole-circuit check of the top three: {full} -> k={k} rb={rb}")
     else:
         k, rb = args.fuse_k, args.fuse_kernel
         nwq.nwq_set_fusion(st.h, k)
         nwq.nwq_set_fusion_kernel(st.h, rb)
     log(f"[bench] fused leg k={k} rb={rb}")
+    nwq.nwq_set_fusion(st.h, k)
+    nwq.nwq_set_fusion_kernel(st.h, rb)
     nwq.nwq_run_circuit(st.h, *arrays)            # warm-up (and plan): reset, then the circuit
     st.flush()
     torch.cuda.synchronize()
@@ -457,7 +472,9 @@ def fused_leg(nwq, st, arrays, n, args, unfused_ms):
     if table is not None:
         res["autotuner"] = {"depth": args.tune_depth,
                             "ms_per_circuit": {("unfused" if kk == 0 else f"k{kk}_{nwq.FUSION_KERNELS[r]}"): round(v, 1)
-                                               for (kk, r), v in sorted(table.items())}}
+                                               for (kk, r), v in sorted(table.items())},
+                            "whole_circuit_ms_of_top3": {f"k{kk}_{nwq.FUSION_KERNELS[r]}": round(v, 1)
+                                                         for (kk, r), v in sorted(full.items())}}
     return res
 
 

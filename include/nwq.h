@@ -186,8 +186,13 @@ int nwq_set_fusion_kernel(nwq_handle h, int kernel);
  * once per block; on the MI355X the depth-40 brickwork at 30 qubits runs
  * about 3% faster with it); bit 1 = when a block's first (last) register
  * phase holds only tile bits above its low contiguous bits, load (store) that
- * phase's registers straight from (to) HBM instead of through LDS.  Default
- * 3.  Results do not depend on the flags.  Other values: NWQ_EINVAL. */
+ * phase's registers straight from (to) HBM instead of through LDS; bit 2 =
+ * (state vectors) inside each register phase, a two-qubit gate and the
+ * one-qubit gates next to it on its two qubits, or a run of one-qubit gates on
+ * one qubit, become one 4x4 or 2x2 product where that takes fewer FP64
+ * operations (the products round differently: results agree to about 1e-15).
+ * Default 7.  Bits 0 and 1 do not change results.  Other values:
+ * NWQ_EINVAL. */
 int nwq_set_fusion_flags(nwq_handle h, int flags);
 
 /* Number of register phases (LDS exchanges) of the last fused

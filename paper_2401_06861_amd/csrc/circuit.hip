@@ -142,6 +142,203 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gate fusion inside a register phase.  A two-qubit gate takes the one-qubit
+// gates next to it on its two bits (back to the previous and on to the next
+// two-qubit gate on each bit: each of them commutes with everything it is
+// moved past) and the product becomes one operator, when that costs less FP64
+// work than the gates one by one.  Runs of one-qubit gates on one bit that are
+// left become one 2x2 the same way.  Costs are FP64 instructions per amplitude
+// in the register-blocked kernel plus one per op for its dispatch.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PhaseItem {
+  int gate = -1;              // an original gate (index into the gate list), or -1: a product
+  int nb = 0, r[2] = {0, 0};  // product: register bits; r[0] is bit 0 of the operator index
+  cd m[16];                   // product: 2x2 (nb = 1) or 4x4 (nb = 2), row-major
+};
+
+bool is_diag(const cd* m, int dim) {
+  for (int u = 0; u < dim; ++u)
+    for (int v = 0; v < dim; ++v)
+      if (u != v && m[u * dim + v] != 0.0) return false;
+  return true;
+}
+
+int matrix_cost(const cd* m, int nb) {
+  if (nb == 2) return is_diag(m, 4) ? 4 : 16;
+  if (is_diag(m, 2)) return 4;
+  bool real = true;
+  for (int i = 0; i < 4; ++i) real = real && m[i].imag() == 0.0;
+  return real ? 4 : (m[0].imag() == 0.0 ? 7 : 8);
+}
+
+int gate_cost(const PGate& g) {
+  switch (g.type) {
+    case NWQ_GATE_I: return 0;
+    case NWQ_GATE_CX: case NWQ_GATE_SWAP: return 0;   // register permutations
+    case NWQ_GATE_CZ: case NWQ_GATE_RZZ: return 4;
+    case kGateMat4: return 16;
+    default: {
+      cd m[16];
+      gate_matrix(g.type, g.p, m);
+      return matrix_cost(m, 1);
+    }
+  }
+}
+
+// M <- G M, G acting on bit `pos` (0 or 1) of the 4x4 operator index
+void lmul_1q(cd* M, const cd* G, int pos) {
+  cd R[16];
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      cd acc = 0.0;
+      for (int w = 0; w < 4; ++w)
+        if ((u & ~(1 << pos)) == (w & ~(1 << pos))) acc += G[((u >> pos) & 1) * 2 + ((w >> pos) & 1)] * M[w * 4 + v];
+      R[u * 4 + v] = acc;
+    }
+  std::memcpy(M, R, sizeof R);
+}
+
+// M <- G M, G a 4x4 in its own (q0, q1) index order; swapped: q0 is bit 1 here
+void lmul_2q(cd* M, const cd* G, bool swapped) {
+  auto sw = [&](int u) { return swapped ? ((u & 1) << 1) | (u >> 1) : u; };
+  cd R[16];
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      cd acc = 0.0;
+      for (int w = 0; w < 4; ++w) acc += G[sw(u) * 4 + sw(w)] * M[w * 4 + v];
+      R[u * 4 + v] = acc;
+    }
+  std::memcpy(M, R, sizeof R);
+}
+
+// seq: the phase's gates in order; r0 / r1: their register bits (r1 < 0 for
+// one-qubit gates).  Returns the ops in application order.
+std::vector<PhaseItem> fuse_phase(const std::vector<int>& seq, const std::vector<PGate>& gates,
+                                  const std::vector<int>& r0, const std::vector<int>& r1) {
+  const int n = (int)seq.size();
+  auto touches = [&](int i, int bit) { return r0[i] == bit || r1[i] == bit; };
+  auto two = [&](int i) { return r1[i] >= 0; };
+  std::vector<int> owner(n, -1), unit_at(n, -1);
+  std::vector<PhaseItem> units;
+  for (int p = 0; p < n; ++p) {
+    if (!two(p)) continue;
+    std::vector<int> take;
+    for (int bit : {r0[p], r1[p]}) {
+      for (int t = p - 1; t >= 0; --t) {
+        if (!touches(t, bit)) continue;
+        if (two(t) || owner[t] != -1) break;
+        take.push_back(t);
+      }
+      for (int t = p + 1; t < n; ++t) {
+        if (!touches(t, bit)) continue;
+        if (two(t)) break;
+        take.push_back(t);
+      }
+    }
+    if (take.empty()) continue;
+    take.push_back(p);
+    std::sort(take.begin(), take.end());
+    PhaseItem u;
+    u.nb = 2;
+    u.r[0] = r0[p];
+    u.r[1] = r1[p];
+    for (int i = 0; i < 16; ++i) u.m[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    int unfused = 0;
+    for (int i : take) {
+      const PGate& g = gates[seq[i]];
+      unfused += gate_cost(g) + 1;
+      cd G[16];
+      gate_matrix(g.type, g.p, G);
+      if (two(i)) lmul_2q(u.m, G, r0[i] != u.r[0]);
+      else lmul_1q(u.m, G, r0[i] == u.r[0] ? 0 : 1);
+    }
+    if (matrix_cost(u.m, 2) + 1 >= unfused) continue;
+    for (int i : take) owner[i] = (int)units.size();
+    unit_at[p] = (int)units.size();
+    units.push_back(u);
+  }
+  std::vector<PhaseItem> out;
+  for (int i = 0; i < n; ++i) {
+    if (unit_at[i] >= 0) {
+      out.push_back(units[unit_at[i]]);
+      continue;
+    }
+    if (owner[i] != -1) continue;
+    if (two(i)) {
+      out.push_back(PhaseItem{});
+      out.back().gate = seq[i];
+      continue;
+    }
+    std::vector<int> run{i};
+    for (int t = i + 1; t < n; ++t) {
+      if (!touches(t, r0[i])) continue;
+      if (two(t) || owner[t] != -1) break;
+      run.push_back(t);
+    }
+    PhaseItem u;
+    u.nb = 1;
+    u.r[0] = r0[i];
+    u.m[0] = u.m[3] = 1.0;
+    int unfused = 0;
+    for (int t : run) {
+      const PGate& g = gates[seq[t]];
+      unfused += gate_cost(g) + 1;
+      cd G[16];
+      gate_matrix(g.type, g.p, G);
+      const cd a = G[0] * u.m[0] + G[1] * u.m[2], b = G[0] * u.m[1] + G[1] * u.m[3];
+      const cd c = G[2] * u.m[0] + G[3] * u.m[2], d = G[2] * u.m[1] + G[3] * u.m[3];
+      u.m[0] = a; u.m[1] = b; u.m[2] = c; u.m[3] = d;
+    }
+    if (run.size() > 1 && matrix_cost(u.m, 1) + 1 < unfused) {
+      for (int t : run) owner[t] = -2;
+      out.push_back(u);
+    } else {
+      out.push_back(PhaseItem{});
+      out.back().gate = seq[i];
+    }
+  }
+  return out;
+}
+
+// The op of a product (register-bit indices).
+FusedOp encode_product(const PhaseItem& u, std::vector<double2>& mats) {
+  FusedOp op{};
+  op.mat = (int)mats.size();
+  if (u.nb == 2) {
+    op.lo = std::min(u.r[0], u.r[1]);
+    op.hi = std::max(u.r[0], u.r[1]);
+    op.o0 = u.r[0];
+    op.o1 = u.r[1];
+    if (is_diag(u.m, 4)) {
+      op.kind = 4;
+      for (int v = 0; v < 4; ++v) mats.push_back(make_double2(u.m[5 * v].real(), u.m[5 * v].imag()));
+    } else {
+      op.kind = 2;
+      for (int i = 0; i < 16; ++i) mats.push_back(make_double2(u.m[i].real(), u.m[i].imag()));
+    }
+  } else {
+    op.lo = u.r[0];
+    if (is_diag(u.m, 2)) {
+      op.kind = 1;
+      mats.push_back(make_double2(u.m[0].real(), u.m[0].imag()));
+      mats.push_back(make_double2(u.m[3].real(), u.m[3].imag()));
+    } else {
+      op.kind = 0;
+      bool real = true;
+      for (int i = 0; i < 4; ++i) real = real && u.m[i].imag() == 0.0;
+      op.real00 = real ? 2 : (u.m[0].imag() == 0.0 ? 1 : 0);
+      for (int i = 0; i < 4; ++i) mats.push_back(make_double2(u.m[i].real(), u.m[i].imag()));
+    }
+  }
+  op.code = rb_op_code(op);
+  return op;
+}
+
+}  // namespace
+
 // Split a block's gates (tile-local bits) into register phases: greedily
 // take, in order, every gate whose bits fit the phase's rbits register bits
 // and that no earlier left-out gate shares a bit with; pad the set to rbits,
@@ -277,11 +474,31 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
         return -1;
       };
       std::vector<FusedOp> pops;
-      for (int gi : ph.gates) {
-        FusedOp op;
-        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
-          op.code = rb_op_code(op);
-          pops.push_back(op);
+      if ((h->fuse_flags & kFusedGateFusion) && side == nullptr) {
+        std::vector<int> r0, r1;
+        for (int gi : ph.gates) {
+          r0.push_back(ridx(lb[gi][0]));
+          r1.push_back(nq[gi] == 2 ? ridx(lb[gi][1]) : -1);
+        }
+        for (const PhaseItem& it : fuse_phase(ph.gates, gates, r0, r1)) {
+          if (it.gate < 0) {
+            pops.push_back(encode_product(it, mats));
+            continue;
+          }
+          FusedOp op;
+          const int gi = it.gate;
+          if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
+            op.code = rb_op_code(op);
+            pops.push_back(op);
+          }
+        }
+      } else {
+        for (int gi : ph.gates) {
+          FusedOp op;
+          if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
+            op.code = rb_op_code(op);
+            pops.push_back(op);
+          }
         }
       }
       int ld_perm[16], st_perm[16];
@@ -441,7 +658,7 @@ int nwq_set_fusion_kernel(nwq_handle h, int kernel) {
 
 int nwq_set_fusion_flags(nwq_handle h, int flags) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
-  if (flags < 0 || flags > 3) return set_error(NWQ_EINVAL, "fusion flags must be in [0, 3]");
+  if (flags < 0 || flags > 7) return set_error(NWQ_EINVAL, "fusion flags must be in [0, 7]");
   h->fuse_flags = flags;
   return NWQ_OK;
 }

@@ -55,8 +55,9 @@ struct nwq_state {
   int fuse_k = 0;                  // 0 = off
   int last_blocks = 0, last_fused_gates = 0, last_phases = 0;
   int fuse_rb = 1;                 // fused kernel: 0 one LDS pass per gate, 1 / 2 register-blocked with 4 / 3 register bits
-  int fuse_flags = 3;              // register-blocked kernels: bit 0 non-temporal tile loads and stores, bit 1
-                                   // first / last phase straight between HBM and registers
+  int fuse_flags = 7;              // register-blocked kernels: bit 0 non-temporal tile loads and stores, bit 1
+                                   // first / last phase straight between HBM and registers, bit 2 gate
+                                   // products inside a phase (SV circuits)
   void* fuse_dev = nullptr;        // device copy of the compiled block program
   // DM with fusion on: 1q superoperators (4x4 on bits q, q + n) wait here and
   // run as fused blocks when a 2q superoperator or a read needs the state

@@ -190,6 +190,9 @@ size_t fused_rb_lds_bytes(int k);
 // block maps to zeros).
 constexpr int kFusedNonTemporal = 1;
 constexpr int kFusedDirect = 2;
+// SV circuits (host side): fuse each register phase's gates into 2x2 / 4x4
+// products where that saves FP64 work (circuit.hip, fuse_phase).
+constexpr int kFusedGateFusion = 4;
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch = 1, int mat_stride = 0,
                      int max_grid = 0, int flags = 0, unsigned long long max_tiles = 0);
