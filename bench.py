@@ -208,13 +208,13 @@ def main():
     st = nwq.SVState(n, tensor=psi, stream=stream)
 
     if args.profile_mode == "fused":
-        # the brickwork (depth 8) through fused blocks at k=12, 4 register bits, twice
-        # (nwq_run_circuit: reset, then the circuit, as the fused leg runs it)
-        nwq.nwq_set_fusion(st.h, 12)
+        # the whole brickwork through fused blocks at k = --fuse-k (default 13), 4 register
+        # bits, twice (nwq_run_circuit: reset, then the circuit, as the fused leg runs it)
+        nwq.nwq_set_fusion(st.h, args.fuse_k or 13)
         nwq.nwq_set_fusion_kernel(st.h, 1)
-        short = nwq.circuit_arrays(W.brickwork_circuit(n, 8, seed=0))
+        full = nwq.circuit_arrays(W.brickwork_circuit(n, args.depth, seed=0))
         for _ in range(2):
-            nwq.nwq_run_circuit(st.h, *short)
+            nwq.nwq_run_circuit(st.h, *full)
         torch.cuda.synchronize()
         log(f"[bench] profile mode done: {nwq.nwq_fusion_stats(st.h)} blocks/gates per run")
         print(json.dumps({"profile_mode": args.profile_mode, "n": n}))
