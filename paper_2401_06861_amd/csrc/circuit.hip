@@ -143,7 +143,7 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
 }
 
 // ---------------------------------------------------------------------------
-// Gate fusion inside a register phase.  A two-qubit gate takes the one-qubit
+// Gate products inside a fused block.  A two-qubit gate takes the one-qubit
 // gates next to it on its two bits (back to the previous and on to the next
 // two-qubit gate on each bit: each of them commutes with everything it is
 // moved past) and the product becomes one operator, when that costs less FP64
@@ -155,7 +155,8 @@ namespace {
 
 struct PhaseItem {
   int gate = -1;              // an original gate (index into the gate list), or -1: a product
-  int nb = 0, r[2] = {0, 0};  // product: register bits; r[0] is bit 0 of the operator index
+  int nb = 0, r[2] = {0, 0};  // product: its bits (tile bits, then register indices); r[0] is bit 0
+                              // of the operator index
   cd m[16];                   // product: 2x2 (nb = 1) or 4x4 (nb = 2), row-major
 };
 
@@ -214,9 +215,11 @@ void lmul_2q(cd* M, const cd* G, bool swapped) {
   std::memcpy(M, R, sizeof R);
 }
 
-// seq: the phase's gates in order; r0 / r1: their register bits (r1 < 0 for
-// one-qubit gates).  Returns the ops in application order.
-std::vector<PhaseItem> fuse_phase(const std::vector<int>& seq, const std::vector<PGate>& gates,
+// seq: the block's gates in order; r0 / r1: their tile bits (r1 < 0 for
+// one-qubit gates).  Returns the ops in application order.  Products act on
+// at most two bits, so the register phases are planned over them as over
+// gates, and no phase boundary cuts a product.
+std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector<PGate>& gates,
                                   const std::vector<int>& r0, const std::vector<int>& r1) {
   const int n = (int)seq.size();
   auto touches = [&](int i, int bit) { return r0[i] == bit || r1[i] == bit; };
@@ -303,7 +306,7 @@ std::vector<PhaseItem> fuse_phase(const std::vector<int>& seq, const std::vector
   return out;
 }
 
-// The op of a product (register-bit indices).
+// The op of a product whose bits are register indices.
 FusedOp encode_product(const PhaseItem& u, std::vector<double2>& mats) {
   FusedOp op{};
   op.mat = (int)mats.size();
@@ -463,6 +466,27 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
       order.push_back(gi);
     }
     if (order.empty()) continue;
+    // gate products over the block (tile-local bits); a product becomes one
+    // more entry of lb / nq at index gates.size() + its position in prods
+    std::vector<PhaseItem> prods;
+    if ((h->fuse_flags & kFusedGateFusion) && side == nullptr) {
+      std::vector<int> r0, r1, order2;
+      for (int gi : order) {
+        r0.push_back(lb[gi][0]);
+        r1.push_back(nq[gi] == 2 ? lb[gi][1] : -1);
+      }
+      for (const PhaseItem& it : fuse_block(order, gates, r0, r1)) {
+        if (it.gate >= 0) {
+          order2.push_back(it.gate);
+          continue;
+        }
+        order2.push_back((int)(gates.size() + prods.size()));
+        lb.push_back({it.r[0], it.nb == 2 ? it.r[1] : 0});
+        nq.push_back(it.nb);
+        prods.push_back(it);
+      }
+      order.swap(order2);
+    }
     d.op_begin = (int)phases.size();
     for (const Phase& ph : plan_phases(order, lb, nq, k, b.c, rbits)) {
       FusedPhase fp{};
@@ -474,31 +498,18 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
         return -1;
       };
       std::vector<FusedOp> pops;
-      if ((h->fuse_flags & kFusedGateFusion) && side == nullptr) {
-        std::vector<int> r0, r1;
-        for (int gi : ph.gates) {
-          r0.push_back(ridx(lb[gi][0]));
-          r1.push_back(nq[gi] == 2 ? ridx(lb[gi][1]) : -1);
+      for (int gi : ph.gates) {
+        if (gi >= (int)gates.size()) {   // a product: its bits in register indices
+          PhaseItem u = prods[gi - gates.size()];
+          u.r[0] = ridx(u.r[0]);
+          if (u.nb == 2) u.r[1] = ridx(u.r[1]);
+          pops.push_back(encode_product(u, mats));
+          continue;
         }
-        for (const PhaseItem& it : fuse_phase(ph.gates, gates, r0, r1)) {
-          if (it.gate < 0) {
-            pops.push_back(encode_product(it, mats));
-            continue;
-          }
-          FusedOp op;
-          const int gi = it.gate;
-          if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
-            op.code = rb_op_code(op);
-            pops.push_back(op);
-          }
-        }
-      } else {
-        for (int gi : ph.gates) {
-          FusedOp op;
-          if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
-            op.code = rb_op_code(op);
-            pops.push_back(op);
-          }
+        FusedOp op;
+        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
+          op.code = rb_op_code(op);
+          pops.push_back(op);
         }
       }
       int ld_perm[16], st_perm[16];

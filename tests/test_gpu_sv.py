@@ -441,6 +441,48 @@ def test_register_blocked_fused_kernel(nwq, n, k):
             assert np.array_equal(same[0], out), key
 
 
+def _product_circuits(n, seed):
+    """Gate runs that the block products rewrite: U3 pairs around CX on both
+    operator orders, diagonal-only runs (RZ, T, S, CZ, RZZ: a diagonal
+    product), runs of one-qubit gates on one qubit, and SWAP between dense
+    gates."""
+    rng = np.random.default_rng(seed)
+    ang = lambda k: tuple(float(x) for x in rng.uniform(-3, 3, size=k))
+    out = []
+    for _ in range(12):
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        out += [("u3", (a,), ang(3)), ("u3", (b,), ang(3)), ("cx", (a, b), ()), ("u3", (a,), ang(3)),
+                ("u3", (b,), ang(3)), ("cx", (b, a), ()), ("ry", (a,), ang(1))]
+        c, d = (int(x) for x in rng.choice(n, size=2, replace=False))
+        out += [("rz", (c,), ang(1)), ("t", (d,), ()), ("cz", (c, d), ()), ("s", (c,), ()),
+                ("rzz", (d, c), ang(1)), ("rz", (d,), ang(1))]
+        e = int(rng.integers(n))
+        out += [("h", (e,), ()), ("rx", (e,), ang(1)), ("u3", (e,), ang(3)), ("x", (e,), ())]
+        f, g = (int(x) for x in rng.choice(n, size=2, replace=False))
+        out += [("u3", (f,), ang(3)), ("swap", (f, g), ()), ("u3", (g,), ang(3)), ("ry", (f,), ang(1))]
+    return out
+
+
+@pytest.mark.parametrize("n,k", [(10, 8), (14, 12), (20, 13)])
+def test_gate_products_in_blocks(nwq, n, k):
+    """Fused blocks with gate products (fusion flags bit 2) against the
+    oracle, for both register-blocked kernels, on circuits built to exercise
+    every product form (dense 4x4, diagonal 4x4, dense and diagonal 2x2)."""
+    gates = _product_circuits(n, seed=n + k) + W.brickwork_circuit(n, 4, seed=n + 2)
+    psi0 = W.random_state(n, seed=n + 5)
+    want = tensor.sv_run(gates, n, psi0)
+    for rb in (1, 2):
+        for flags in (3, 7):
+            st = nwq.SVState(n, reset=False)
+            st.load(psi0)
+            st.set_fusion(k)
+            nwq.nwq_set_fusion_kernel(st.h, rb)
+            nwq.nwq_set_fusion_flags(st.h, flags)
+            st.run_circuit(gates)
+            assert maxerr(st.numpy(), want) <= TOL, (n, k, rb, flags)
+            st.close()
+
+
 @pytest.mark.parametrize("n,k", [(14, 12), (20, 12), (20, 13)])
 def test_fused_direct_phase_blocks(nwq, n, k):
     """Blocks whose first and last register phases hold only high tile bits
