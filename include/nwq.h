@@ -187,10 +187,11 @@ int nwq_set_fusion_kernel(nwq_handle h, int kernel);
  * about 3% faster with it); bit 1 = when a block's first (last) register
  * phase holds only tile bits above its low contiguous bits, load (store) that
  * phase's registers straight from (to) HBM instead of through LDS; bit 2 =
- * (state vectors) inside each register phase, a two-qubit gate and the
- * one-qubit gates next to it on its two qubits, or a run of one-qubit gates on
- * one qubit, become one 4x4 or 2x2 product where that takes fewer FP64
- * operations (the products round differently: results agree to about 1e-15).
+ * (state vectors, register-blocked kernels) before the blocks are planned, a
+ * two-qubit gate and the one-qubit gates next to it on its two qubits, or a
+ * run of one-qubit gates on one qubit, become one 4x4 or 2x2 product where
+ * that takes fewer FP64 operations (the products round differently: results
+ * agree to about 1e-15).
  * Default 7.  Bits 0 and 1 do not change results.  Other values:
  * NWQ_EINVAL. */
 int nwq_set_fusion_flags(nwq_handle h, int flags);
@@ -200,7 +201,9 @@ int nwq_set_fusion_flags(nwq_handle h, int flags);
 int nwq_fusion_phases(nwq_handle h, int* phases);
 
 /* Host-only: the block plan nwq_apply_circuit would use for a circuit on n
- * qubits at fusion width k (parameters are not needed).  Writes the number
+ * qubits at fusion width k with gate products off (nwq_set_fusion_flags bit
+ * 2 clear; products depend on the gates' parameters, which are not needed
+ * here).  Writes the number
  * of blocks to *n_blocks, the block index of each gate to block_of_gate[]
  * (n_gates entries), and, if block_qubits is non-NULL, each block's tile
  * qubit mask as two 32-bit halves (2 * n_gates ints of room).  Touches no

@@ -92,6 +92,34 @@ int local_bit(const Block& b, int q) {
 static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats, FusedOp& op, bool reg,
                       const std::vector<cd>* side) {
   op = FusedOp{};
+  if (g.type == kGateDiag4) {   // diagonal 4x4 from the side table, operator order (q[0], q[1])
+    op.mat = (int)mats.size();
+    op.lo = std::min(b0, b1);
+    op.hi = std::max(b0, b1);
+    op.kind = 4;
+    op.o0 = b0;
+    op.o1 = b1;
+    const cd* M = side->data() + 16 * (size_t)g.p[0];
+    for (int u = 0; u < 4; ++u) mats.push_back(make_double2(M[5 * u].real(), M[5 * u].imag()));
+    return true;
+  }
+  if (g.type == kGateMat2) {   // 2x2 from the side table
+    const cd* M = side->data() + 16 * (size_t)g.p[0];
+    op.mat = (int)mats.size();
+    op.lo = b0;
+    if (M[1] == 0.0 && M[2] == 0.0) {
+      op.kind = 1;
+      mats.push_back(make_double2(M[0].real(), M[0].imag()));
+      mats.push_back(make_double2(M[3].real(), M[3].imag()));
+      return true;
+    }
+    op.kind = 0;
+    bool real = true;
+    for (int i = 0; i < 4; ++i) real = real && M[i].imag() == 0.0;
+    op.real00 = real ? 2 : (M[0].imag() == 0.0 ? 1 : 0);
+    for (int i = 0; i < 4; ++i) mats.push_back(make_double2(M[i].real(), M[i].imag()));
+    return true;
+  }
   if (g.type == kGateMat4) {   // dense 4x4 from the side table, operator order (q[0], q[1])
     op.mat = (int)mats.size();
     op.lo = std::min(b0, b1);
@@ -143,20 +171,21 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
 }
 
 // ---------------------------------------------------------------------------
-// Gate products inside a fused block.  A two-qubit gate takes the one-qubit
-// gates next to it on its two bits (back to the previous and on to the next
-// two-qubit gate on each bit: each of them commutes with everything it is
-// moved past) and the product becomes one operator, when that costs less FP64
-// work than the gates one by one.  Runs of one-qubit gates on one bit that are
-// left become one 2x2 the same way.  Costs are FP64 instructions per amplitude
-// in the register-blocked kernel plus one per op for its dispatch.
+// Gate products.  A two-qubit gate takes the one-qubit gates next to it on
+// its two qubits (back to the previous and on to the next two-qubit gate on
+// each: each of them commutes with everything it is moved past) and the
+// product becomes one gate, when that costs less FP64 work than the gates one
+// by one.  Runs of one-qubit gates on one qubit that are left become one 2x2
+// the same way.  Costs are FP64 instructions per amplitude in the
+// register-blocked kernel plus one per op for its dispatch.  Products act on
+// at most two qubits, so blocks and register phases are planned over them as
+// over gates.
 // ---------------------------------------------------------------------------
 namespace {
 
 struct PhaseItem {
   int gate = -1;              // an original gate (index into the gate list), or -1: a product
-  int nb = 0, r[2] = {0, 0};  // product: its bits (tile bits, then register indices); r[0] is bit 0
-                              // of the operator index
+  int nb = 0, r[2] = {0, 0};  // product: its qubits; r[0] is bit 0 of the operator index
   cd m[16];                   // product: 2x2 (nb = 1) or 4x4 (nb = 2), row-major
 };
 
@@ -181,6 +210,7 @@ int gate_cost(const PGate& g) {
     case NWQ_GATE_CX: case NWQ_GATE_SWAP: return 0;   // register permutations
     case NWQ_GATE_CZ: case NWQ_GATE_RZZ: return 4;
     case kGateMat4: return 16;
+    case kGateDiag4: return 4;
     default: {
       cd m[16];
       gate_matrix(g.type, g.p, m);
@@ -215,28 +245,40 @@ void lmul_2q(cd* M, const cd* G, bool swapped) {
   std::memcpy(M, R, sizeof R);
 }
 
-// seq: the block's gates in order; r0 / r1: their tile bits (r1 < 0 for
-// one-qubit gates).  Returns the ops in application order.  Products act on
-// at most two bits, so the register phases are planned over them as over
-// gates, and no phase boundary cuts a product.
+// seq: the gates in order (indices into gates); r0 / r1: their qubits (r1 <
+// 0 for one-qubit gates).  Returns the ops in application order.
 std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector<PGate>& gates,
                                   const std::vector<int>& r0, const std::vector<int>& r1) {
   const int n = (int)seq.size();
-  auto touches = [&](int i, int bit) { return r0[i] == bit || r1[i] == bit; };
   auto two = [&](int i) { return r1[i] >= 0; };
+  // positions touching each bit, and each position's place in its bits' lists
+  int nbit = 0;
+  for (int i = 0; i < n; ++i) nbit = std::max(nbit, std::max(r0[i], r1[i]) + 1);
+  std::vector<std::vector<int>> on(nbit);
+  std::vector<int> at0(n), at1(n, -1);
+  for (int i = 0; i < n; ++i) {
+    at0[i] = (int)on[r0[i]].size();
+    on[r0[i]].push_back(i);
+    if (two(i)) {
+      at1[i] = (int)on[r1[i]].size();
+      on[r1[i]].push_back(i);
+    }
+  }
   std::vector<int> owner(n, -1), unit_at(n, -1);
   std::vector<PhaseItem> units;
   for (int p = 0; p < n; ++p) {
     if (!two(p)) continue;
     std::vector<int> take;
-    for (int bit : {r0[p], r1[p]}) {
-      for (int t = p - 1; t >= 0; --t) {
-        if (!touches(t, bit)) continue;
+    for (int side = 0; side < 2; ++side) {
+      const std::vector<int>& lst = on[side == 0 ? r0[p] : r1[p]];
+      const int here = side == 0 ? at0[p] : at1[p];
+      for (int j = here - 1; j >= 0; --j) {
+        const int t = lst[j];
         if (two(t) || owner[t] != -1) break;
         take.push_back(t);
       }
-      for (int t = p + 1; t < n; ++t) {
-        if (!touches(t, bit)) continue;
+      for (int j = here + 1; j < (int)lst.size(); ++j) {
+        const int t = lst[j];
         if (two(t)) break;
         take.push_back(t);
       }
@@ -276,8 +318,9 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
       continue;
     }
     std::vector<int> run{i};
-    for (int t = i + 1; t < n; ++t) {
-      if (!touches(t, r0[i])) continue;
+    const std::vector<int>& lst = on[r0[i]];
+    for (int j = at0[i] + 1; j < (int)lst.size(); ++j) {
+      const int t = lst[j];
       if (two(t) || owner[t] != -1) break;
       run.push_back(t);
     }
@@ -304,40 +347,6 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
     }
   }
   return out;
-}
-
-// The op of a product whose bits are register indices.
-FusedOp encode_product(const PhaseItem& u, std::vector<double2>& mats) {
-  FusedOp op{};
-  op.mat = (int)mats.size();
-  if (u.nb == 2) {
-    op.lo = std::min(u.r[0], u.r[1]);
-    op.hi = std::max(u.r[0], u.r[1]);
-    op.o0 = u.r[0];
-    op.o1 = u.r[1];
-    if (is_diag(u.m, 4)) {
-      op.kind = 4;
-      for (int v = 0; v < 4; ++v) mats.push_back(make_double2(u.m[5 * v].real(), u.m[5 * v].imag()));
-    } else {
-      op.kind = 2;
-      for (int i = 0; i < 16; ++i) mats.push_back(make_double2(u.m[i].real(), u.m[i].imag()));
-    }
-  } else {
-    op.lo = u.r[0];
-    if (is_diag(u.m, 2)) {
-      op.kind = 1;
-      mats.push_back(make_double2(u.m[0].real(), u.m[0].imag()));
-      mats.push_back(make_double2(u.m[3].real(), u.m[3].imag()));
-    } else {
-      op.kind = 0;
-      bool real = true;
-      for (int i = 0; i < 4; ++i) real = real && u.m[i].imag() == 0.0;
-      op.real00 = real ? 2 : (u.m[0].imag() == 0.0 ? 1 : 0);
-      for (int i = 0; i < 4; ++i) mats.push_back(make_double2(u.m[i].real(), u.m[i].imag()));
-    }
-  }
-  op.code = rb_op_code(op);
-  return op;
 }
 
 }  // namespace
@@ -425,8 +434,39 @@ void set_direct_io(FusedBlockDev& d, const FusedPhase& first, const FusedPhase& 
 // Runs a gate list through fused blocks over `nbits` bits of the vector (the
 // qubit count for a state vector; 2n for the vectorised density matrix, whose
 // queued 1q superoperators arrive as kGateMat4 gates with matrices in `side`).
-int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side,
+int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, const std::vector<cd>* side_in,
                 bool from_zero) {
+  // Gate products over the whole circuit (state vectors, register-blocked
+  // kernels): they act on at most two qubits, so the blocks and their register
+  // phases are planned over them as over gates, and no boundary cuts one.
+  std::vector<PGate> prod_gates;
+  std::vector<cd> prod_side;
+  const bool products = (h->fuse_flags & kFusedGateFusion) && side_in == nullptr && h->fuse_rb != 0;
+  if (products) {
+    std::vector<int> seq, r0, r1;
+    for (size_t i = 0; i < gates_in.size(); ++i) {
+      if (gates_in[i].type == NWQ_GATE_I) continue;
+      seq.push_back((int)i);
+      r0.push_back(gates_in[i].q[0]);
+      r1.push_back(gates_in[i].nq == 2 ? gates_in[i].q[1] : -1);
+    }
+    for (const PhaseItem& it : fuse_block(seq, gates_in, r0, r1)) {
+      if (it.gate >= 0) {
+        prod_gates.push_back(gates_in[it.gate]);
+        continue;
+      }
+      PGate g{};
+      g.nq = it.nb;
+      g.q[0] = it.r[0];
+      g.q[1] = it.nb == 2 ? it.r[1] : 0;
+      g.type = it.nb == 1 ? kGateMat2 : (is_diag(it.m, 4) ? kGateDiag4 : kGateMat4);
+      g.p[0] = (double)(prod_side.size() / 16);
+      for (int i = 0; i < 16; ++i) prod_side.push_back(it.m[i]);
+      prod_gates.push_back(g);
+    }
+  }
+  const std::vector<PGate>& gates = products ? prod_gates : gates_in;
+  const std::vector<cd>* side = products ? &prod_side : side_in;
   const std::vector<Block> blocks = plan_blocks(gates, nbits, h->fuse_k);
   if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
   // Program: [phase table][op table][matrix table] in one upload.
@@ -466,27 +506,6 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
       order.push_back(gi);
     }
     if (order.empty()) continue;
-    // gate products over the block (tile-local bits); a product becomes one
-    // more entry of lb / nq at index gates.size() + its position in prods
-    std::vector<PhaseItem> prods;
-    if ((h->fuse_flags & kFusedGateFusion) && side == nullptr) {
-      std::vector<int> r0, r1, order2;
-      for (int gi : order) {
-        r0.push_back(lb[gi][0]);
-        r1.push_back(nq[gi] == 2 ? lb[gi][1] : -1);
-      }
-      for (const PhaseItem& it : fuse_block(order, gates, r0, r1)) {
-        if (it.gate >= 0) {
-          order2.push_back(it.gate);
-          continue;
-        }
-        order2.push_back((int)(gates.size() + prods.size()));
-        lb.push_back({it.r[0], it.nb == 2 ? it.r[1] : 0});
-        nq.push_back(it.nb);
-        prods.push_back(it);
-      }
-      order.swap(order2);
-    }
     d.op_begin = (int)phases.size();
     for (const Phase& ph : plan_phases(order, lb, nq, k, b.c, rbits)) {
       FusedPhase fp{};
@@ -499,13 +518,6 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
       };
       std::vector<FusedOp> pops;
       for (int gi : ph.gates) {
-        if (gi >= (int)gates.size()) {   // a product: its bits in register indices
-          PhaseItem u = prods[gi - gates.size()];
-          u.r[0] = ridx(u.r[0]);
-          if (u.nb == 2) u.r[1] = ridx(u.r[1]);
-          pops.push_back(encode_product(u, mats));
-          continue;
-        }
         FusedOp op;
         if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
           op.code = rb_op_code(op);
@@ -580,8 +592,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const 
   }
   h->last_blocks = (int)launches.size();
   h->last_fused_gates = 0;
-  for (const Block& b : blocks)
-    for (int gi : b.gates) h->last_fused_gates += gates[gi].type != NWQ_GATE_I;
+  for (const PGate& g : gates_in) h->last_fused_gates += g.type != NWQ_GATE_I;
   h->last_phases = (int)phases.size();
   return NWQ_OK;
 }

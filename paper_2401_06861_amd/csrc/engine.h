@@ -95,6 +95,10 @@ struct Phase {
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
 // internal gate type: dense 4x4 whose matrix is entry p[0] of a side table
 constexpr int kGateMat4 = 1000;
+// internal gate types of circuit gate products (side table entry p[0], 16 slots
+// each): a diagonal 4x4 (entries 5u), a 2x2 (first 4 slots)
+constexpr int kGateDiag4 = 1001;
+constexpr int kGateMat2 = 1002;
 // from_zero: the state is |0...0> (the first block then runs tile 0 only)
 int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side,
                 bool from_zero = false);
