@@ -183,7 +183,7 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
 // ---------------------------------------------------------------------------
 namespace {
 
-struct PhaseItem {
+struct FuseItem {
   int gate = -1;              // an original gate (index into the gate list), or -1: a product
   int nb = 0, r[2] = {0, 0};  // product: its qubits; r[0] is bit 0 of the operator index
   cd m[16];                   // product: 2x2 (nb = 1) or 4x4 (nb = 2), row-major
@@ -247,7 +247,7 @@ void lmul_2q(cd* M, const cd* G, bool swapped) {
 
 // seq: the gates in order (indices into gates); r0 / r1: their qubits (r1 <
 // 0 for one-qubit gates).  Returns the ops in application order.
-std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector<PGate>& gates,
+std::vector<FuseItem> gate_products(const std::vector<int>& seq, const std::vector<PGate>& gates,
                                   const std::vector<int>& r0, const std::vector<int>& r1) {
   const int n = (int)seq.size();
   auto two = [&](int i) { return r1[i] >= 0; };
@@ -265,7 +265,7 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
     }
   }
   std::vector<int> owner(n, -1), unit_at(n, -1);
-  std::vector<PhaseItem> units;
+  std::vector<FuseItem> units;
   for (int p = 0; p < n; ++p) {
     if (!two(p)) continue;
     std::vector<int> take;
@@ -286,7 +286,7 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
     if (take.empty()) continue;
     take.push_back(p);
     std::sort(take.begin(), take.end());
-    PhaseItem u;
+    FuseItem u;
     u.nb = 2;
     u.r[0] = r0[p];
     u.r[1] = r1[p];
@@ -305,7 +305,7 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
     unit_at[p] = (int)units.size();
     units.push_back(u);
   }
-  std::vector<PhaseItem> out;
+  std::vector<FuseItem> out;
   for (int i = 0; i < n; ++i) {
     if (unit_at[i] >= 0) {
       out.push_back(units[unit_at[i]]);
@@ -313,7 +313,7 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
     }
     if (owner[i] != -1) continue;
     if (two(i)) {
-      out.push_back(PhaseItem{});
+      out.push_back(FuseItem{});
       out.back().gate = seq[i];
       continue;
     }
@@ -324,7 +324,7 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
       if (two(t) || owner[t] != -1) break;
       run.push_back(t);
     }
-    PhaseItem u;
+    FuseItem u;
     u.nb = 1;
     u.r[0] = r0[i];
     u.m[0] = u.m[3] = 1.0;
@@ -342,7 +342,7 @@ std::vector<PhaseItem> fuse_block(const std::vector<int>& seq, const std::vector
       for (int t : run) owner[t] = -2;
       out.push_back(u);
     } else {
-      out.push_back(PhaseItem{});
+      out.push_back(FuseItem{});
       out.back().gate = seq[i];
     }
   }
@@ -450,7 +450,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       r0.push_back(gates_in[i].q[0]);
       r1.push_back(gates_in[i].nq == 2 ? gates_in[i].q[1] : -1);
     }
-    for (const PhaseItem& it : fuse_block(seq, gates_in, r0, r1)) {
+    for (const FuseItem& it : gate_products(seq, gates_in, r0, r1)) {
       if (it.gate >= 0) {
         prod_gates.push_back(gates_in[it.gate]);
         continue;
@@ -467,6 +467,10 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
   }
   const std::vector<PGate>& gates = products ? prod_gates : gates_in;
   const std::vector<cd>* side = products ? &prod_side : side_in;
+  if (gates.empty()) {   // identities only
+    h->last_blocks = h->last_fused_gates = h->last_phases = 0;
+    return NWQ_OK;
+  }
   const std::vector<Block> blocks = plan_blocks(gates, nbits, h->fuse_k);
   if (blocks.empty()) return set_error(NWQ_EINVAL, "fusion planner made no progress");
   // Program: [phase table][op table][matrix table] in one upload.

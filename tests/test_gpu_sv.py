@@ -483,6 +483,23 @@ def test_gate_products_in_blocks(nwq, n, k):
             st.close()
 
 
+def test_fused_identity_only_circuit(nwq):
+    """A circuit of identities through the fused path (gate products drop
+    them): no error, the state unchanged, no block launched."""
+    n = 10
+    psi0 = W.random_state(n, seed=3)
+    st = nwq.SVState(n, reset=False)
+    st.load(psi0)
+    st.set_fusion(8)
+    st.run_circuit([("id", (q,), ()) for q in range(n)])
+    assert np.array_equal(st.numpy(), psi0)
+    assert nwq.nwq_fusion_stats(st.h)[0] == 0
+    nwq.nwq_run_circuit(st.h, *nwq.circuit_arrays([("id", (0,), ())]))
+    out = st.numpy()
+    assert out[0] == 1 and np.count_nonzero(out) == 1
+    st.close()
+
+
 @pytest.mark.parametrize("n,k", [(14, 12), (20, 12), (20, 13)])
 def test_fused_direct_phase_blocks(nwq, n, k):
     """Blocks whose first and last register phases hold only high tile bits
