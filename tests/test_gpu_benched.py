@@ -122,9 +122,9 @@ def test_noisy_tfim_n14_tuned_shapes(torch, dm14, fuse_k):
 def test_brickwork_n30_unfused_and_fused(torch):
     """The benchmark's step workload at full size: the n=30 depth-40
     brickwork (seed 0), one kernel per gate in the launch shapes the
-    autotuner picks, then through fused k=12 blocks (nwq_run_circuit):
-    <Z_i>, the norm and 1024 sampled amplitudes against the stored oracle
-    values (1e-12)."""
+    autotuner picks, then through fused k=12 and k=13 blocks with gate
+    products (nwq_run_circuit; the bench picks k=13): <Z_i>, the norm and
+    1024 sampled amplitudes against the stored oracle values (1e-12)."""
     from paper_2401_06861_amd import autotune, nwq
     g = golden("brickwork_n30_seed0.json")
     n = g["n"]
@@ -133,13 +133,13 @@ def test_brickwork_n30_unfused_and_fused(torch):
     want = np.array([complex(s[1], s[2]) for s in g["samples"]])
     st = nwq.SVState(n)
     autotune.tune(st.h, reps=1, cache_path=None)
-    for label in ("unfused", "fused"):
+    for label in ("unfused", "fused12", "fused13"):
         if label == "unfused":
             st.set_fusion(0)
             st.reset()
             nwq.nwq_apply_circuit(st.h, *arrays)
         else:
-            st.set_fusion(12)
+            st.set_fusion(int(label[5:]))
             nwq.nwq_set_fusion_kernel(st.h, 1)
             nwq.nwq_run_circuit(st.h, *arrays)
         z = st.expvals(W.single_site_terms(n, "Z"))
