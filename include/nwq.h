@@ -163,10 +163,13 @@ int nwq_apply_qasm(nwq_handle h, const char* text);
  * a block may touch (6..13).  SV handles: nwq_apply_circuit runs its gates
  * through fused blocks.  DM handles: each 1q gate with the channels composed
  * after it (a 4x4 superoperator on bits q and q + n of vec(rho)) is queued,
- * and the queue runs as fused blocks over the 2n bits when a 2q
- * superoperator, a read or nwq_flush needs the state (a reset or
- * nwq_set_state drops it); changing the width on a DM handle flushes first.
- * Returns the value in effect through *k_out when non-NULL. */
+ * and so is each 2q gate with its channels (a 16x16 on bits q0, q1, q0 + n,
+ * q1 + n) when the fused kernel is 1 (4 register bits) and n >= 4; the queue
+ * runs as fused blocks over the 2n bits when a read or nwq_flush needs the
+ * state, or a 2q superoperator that cannot be queued comes (a reset or
+ * nwq_set_state drops it); changing the width or the fused kernel on a DM
+ * handle flushes first.  Returns the value in effect through *k_out when
+ * non-NULL. */
 int nwq_set_fusion(nwq_handle h, int k, int* k_out);
 
 /* Statistics of the last nwq_apply_circuit: number of fused blocks and

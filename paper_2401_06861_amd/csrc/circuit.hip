@@ -99,12 +99,12 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
     op.kind = 4;
     op.o0 = b0;
     op.o1 = b1;
-    const cd* M = side->data() + 16 * (size_t)g.p[0];
+    const cd* M = side->data() + (size_t)g.p[0];
     for (int u = 0; u < 4; ++u) mats.push_back(make_double2(M[5 * u].real(), M[5 * u].imag()));
     return true;
   }
   if (g.type == kGateMat2) {   // 2x2 from the side table
-    const cd* M = side->data() + 16 * (size_t)g.p[0];
+    const cd* M = side->data() + (size_t)g.p[0];
     op.mat = (int)mats.size();
     op.lo = b0;
     if (M[1] == 0.0 && M[2] == 0.0) {
@@ -127,7 +127,7 @@ static bool encode_op(const PGate& g, int b0, int b1, std::vector<double2>& mats
     op.kind = 2;
     op.o0 = reg ? b0 : (1 << b0);
     op.o1 = reg ? b1 : (1 << b1);
-    const cd* M = side->data() + 16 * (size_t)g.p[0];
+    const cd* M = side->data() + (size_t)g.p[0];
     for (int i = 0; i < 16; ++i) mats.push_back(make_double2(M[i].real(), M[i].imag()));
     return true;
   }
@@ -357,7 +357,7 @@ std::vector<FuseItem> gate_products(const std::vector<int>& seq, const std::vect
 // from tile bit c up first (a set above the low c bits keeps each wave's
 // lanes on contiguous amplitudes, so the phase can move between registers and
 // HBM directly when it is the block's first or last).
-std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
+std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 4>>& lb,
                                const std::vector<int>& nq, int k, int c, int rbits) {
   std::vector<Phase> out;
   std::vector<int> rem = order;
@@ -366,8 +366,8 @@ std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<
     Phase ph;
     std::vector<int> keep;
     for (int gi : rem) {
-      unsigned B = 1u << lb[gi][0];
-      if (nq[gi] == 2) B |= 1u << lb[gi][1];
+      unsigned B = 0;
+      for (int t = 0; t < nq[gi]; ++t) B |= 1u << lb[gi][t];
       if (B & blocked) {
         blocked |= B;
         keep.push_back(gi);
@@ -460,7 +460,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       g.q[0] = it.r[0];
       g.q[1] = it.nb == 2 ? it.r[1] : 0;
       g.type = it.nb == 1 ? kGateMat2 : (is_diag(it.m, 4) ? kGateDiag4 : kGateMat4);
-      g.p[0] = (double)(prod_side.size() / 16);
+      g.p[0] = (double)prod_side.size();
       for (int i = 0; i < 16; ++i) prod_side.push_back(it.m[i]);
       prod_gates.push_back(g);
     }
@@ -492,6 +492,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       d.op_begin = (int)ops.size();
       for (int gi : b.gates) {
         const PGate& g = gates[gi];
+        if (g.nq > 2) return set_error(NWQ_EINVAL, "a four-bit operator needs the register-blocked kernel");
         FusedOp op;
         if (encode_op(g, local_bit(b, g.q[0]), g.nq == 2 ? local_bit(b, g.q[1]) : 0, mats, op, false, side))
           ops.push_back(op);
@@ -500,12 +501,13 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       if (d.op_count > 0) launches.push_back({d, false, 0});
       continue;
     }
-    std::vector<std::array<int, 2>> lb(gates.size());
+    std::vector<std::array<int, 4>> lb(gates.size());
     std::vector<int> nq(gates.size(), 1);
     std::vector<int> order;
     for (int gi : b.gates) {
       if (gates[gi].type == NWQ_GATE_I) continue;
-      lb[gi] = {local_bit(b, gates[gi].q[0]), gates[gi].nq == 2 ? local_bit(b, gates[gi].q[1]) : 0};
+      if (gates[gi].nq > rbits) return set_error(NWQ_EINVAL, "an operator wider than the phase's register bits");
+      for (int t = 0; t < gates[gi].nq; ++t) lb[gi][t] = local_bit(b, gates[gi].q[t]);
       nq[gi] = gates[gi].nq;
       order.push_back(gi);
     }
@@ -522,6 +524,29 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       };
       std::vector<FusedOp> pops;
       for (int gi : ph.gates) {
+        if (gates[gi].type == kGateMat16) {   // all four register bits: the matrix in register order
+          FusedOp op{};
+          op.kind = 7;
+          op.mat = (int)mats.size();
+          int rt[4];
+          for (int t = 0; t < 4; ++t) rt[t] = ridx(lb[gi][t]);
+          auto reg_index = [&](int u) {   // operator index -> register index
+            int j = 0;
+            for (int t = 0; t < 4; ++t) j |= ((u >> t) & 1) << rt[t];
+            return j;
+          };
+          int inv[16];
+          for (int u = 0; u < 16; ++u) inv[reg_index(u)] = u;
+          const cd* M = side->data() + (size_t)gates[gi].p[0];
+          for (int r = 0; r < 16; ++r)
+            for (int c2 = 0; c2 < 16; ++c2) {
+              const cd z = M[inv[r] * 16 + inv[c2]];
+              mats.push_back(make_double2(z.real(), z.imag()));
+            }
+          op.code = rb_op_code(op);
+          pops.push_back(op);
+          continue;
+        }
         FusedOp op;
         if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
           op.code = rb_op_code(op);
@@ -532,6 +557,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       fold_permutations(
           pops, rbits, [](const FusedOp& o) { return o.kind == 3 || o.kind == 5; },
           [](const FusedOp& o) {
+            if (o.kind == 7) return 15u;
             return (o.kind == 0 || o.kind == 1 || o.kind == 6) ? (1u << o.lo) : ((1u << o.o0) | (1u << o.o1));
           },
           [](const FusedOp& o, int j) { return o.kind == 3 ? reg_cx(o.o0, o.o1, j) : reg_swap(o.o0, o.o1, j); },
@@ -678,6 +704,10 @@ int nwq_run_circuit(nwq_handle h, int n_gates, const int* types, const int* qubi
 int nwq_set_fusion_kernel(nwq_handle h, int kernel) {
   if (h == nullptr) return set_error(NWQ_EINVAL, "NULL handle");
   if (kernel < 0 || kernel > 2) return set_error(NWQ_EINVAL, "fusion kernel must be 0, 1 or 2");
+  if (h->kind == NWQ_KIND_DM && kernel != h->fuse_rb) {   // queued work runs on the kernel it was queued for
+    const int rc = flush_all(h);
+    if (rc) return rc;
+  }
   h->fuse_rb = kernel;
   return NWQ_OK;
 }

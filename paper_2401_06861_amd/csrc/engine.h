@@ -59,10 +59,12 @@ struct nwq_state {
                                    // first / last phase straight between HBM and registers, bit 2 gate
                                    // products inside a phase (SV circuits)
   void* fuse_dev = nullptr;        // device copy of the compiled block program
-  // DM with fusion on: 1q superoperators (4x4 on bits q, q + n) wait here and
-  // run as fused blocks when a 2q superoperator or a read needs the state
-  std::vector<int> dmq_q;
-  std::vector<nwq::cd> dmq_S;
+  // DM with fusion on: superoperators (1q: 4x4 on bits q, q + n; 2q with the
+  // 4-register-bit kernel: 16x16 on bits q0, q1, q0 + n, q1 + n) wait here and
+  // run as fused blocks when a read needs the state (a 2q superoperator too
+  // when it cannot be queued)
+  std::vector<std::array<int, 3>> dmq_ops;   // queued superoperators: (k, q0, q1)
+  std::vector<nwq::cd> dmq_S;                // their matrices back to back (16 or 256 entries)
   size_t fuse_cap = 0;
 
   // timing
@@ -77,7 +79,7 @@ namespace nwq {
 // A gate of a circuit (type nwq_gate, qubits, up to 3 parameters).
 struct PGate {
   int type;
-  int q[2];
+  int q[4];   // nq qubits (4 only for the queued DM two-qubit superoperators)
   int nq;
   double p[3];
 };
@@ -94,11 +96,14 @@ struct Phase {
 };
 std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
 // internal gate type: dense 4x4 whose matrix is entry p[0] of a side table
+// Internal gate types whose matrix sits in a side table from entry p[0] on:
+// a dense 4x4 (16 entries), a diagonal 4x4 (16 entries, the diagonal at 5u),
+// a 2x2 (4 entries), and a dense 16x16 on the four bits q[0..3] (256 entries,
+// operator index bit t on q[t]; DM two-qubit superoperators).
 constexpr int kGateMat4 = 1000;
-// internal gate types of circuit gate products (side table entry p[0], 16 slots
-// each): a diagonal 4x4 (entries 5u), a 2x2 (first 4 slots)
 constexpr int kGateDiag4 = 1001;
 constexpr int kGateMat2 = 1002;
+constexpr int kGateMat16 = 1003;
 // from_zero: the state is |0...0> (the first block then runs tile 0 only)
 int apply_fused(nwq_state* h, const std::vector<PGate>& gates, int nbits, const std::vector<cd>* side,
                 bool from_zero = false);
@@ -161,7 +166,7 @@ void fill_entry_offsets(FusedBlockDev& d, int rbits);
 void set_direct_io(FusedBlockDev& d, const FusedPhase& first, const FusedPhase& last, int rbits);
 // c: the block's low tile bits; a phase with fewer gate bits than rbits is
 // padded with tile bits from c up first.
-std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 2>>& lb,
+std::vector<Phase> plan_phases(const std::vector<int>& order, const std::vector<std::array<int, 4>>& lb,
                                const std::vector<int>& nq, int k, int c, int rbits);
 
 void gate_matrix(int type, const double* p, cd* m);

@@ -306,34 +306,64 @@ static void superop(const cd* kraus, int nk, int k, std::vector<cd>& S) {
   }
 }
 
-// Runs the queued 1q superoperators: through fused blocks over the 2n bits
-// of vec(rho) when there are two or more, else as one pass.
+// One pass of a 2q superoperator S (16x16, u = c0 + 2 c1 + 4 r0 + 8 r1) on
+// qubits (q0, q1).
+static int dm_superop2_pass(nwq_state* h, int q0, int q1, const cd* S) {
+  std::vector<double2> buf(256);
+  for (int i = 0; i < 256; ++i) buf[i] = d2(S[i]);
+  void* dev = nullptr;
+  const int rc = arena_put(h, buf.data(), buf.size() * sizeof(double2), &dev);
+  if (rc != NWQ_OK) return rc;
+  const int vq[4] = {q0, q1, q0 + h->n, q1 + h->n};
+  timing_begin(h, KC_DM2);
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev), h->shape(KC_DM2, std::min(q0, q1)));
+  timing_end(h);
+  return last_launch("dm_superop_2q");
+}
+
+// Runs the queued superoperators: through fused blocks over the 2n bits of
+// vec(rho) when there are two or more, else as one pass.
 static int dm_run_queue(nwq_state* h) {
-  const size_t cnt = h->dmq_q.size();
+  const size_t cnt = h->dmq_ops.size();
   if (cnt == 0) return NWQ_OK;
   int rc = NWQ_OK;
-  if (cnt == 1) {
+  if (cnt == 1 && h->dmq_ops[0][0] == 1) {
     Mat4 M;
     for (int i = 0; i < 16; ++i) M.m[i] = d2(h->dmq_S[i]);
-    const int q = h->dmq_q[0];
+    const int q = h->dmq_ops[0][1];
     timing_begin(h, KC_DM1);
     launch_sv_2q(h->stream, h->data, h->nbits, q, q + h->n, M, h->shape(KC_DM1, q));
     timing_end(h);
     rc = last_launch("dm_superop_1q");
+  } else if (cnt == 1) {
+    rc = dm_superop2_pass(h, h->dmq_ops[0][1], h->dmq_ops[0][2], h->dmq_S.data());
   } else {
     std::vector<PGate> gates(cnt);
+    size_t off = 0;
     for (size_t i = 0; i < cnt; ++i) {
       PGate& g = gates[i];
-      g.type = kGateMat4;
-      g.nq = 2;
-      g.q[0] = h->dmq_q[i];              // column bit: u bit 0
-      g.q[1] = h->dmq_q[i] + h->n;       // row bit: u bit 1
-      g.p[0] = (double)i;
+      const int k = h->dmq_ops[i][0], q0 = h->dmq_ops[i][1], q1 = h->dmq_ops[i][2];
+      g.p[0] = (double)off;
       g.p[1] = g.p[2] = 0.0;
+      if (k == 1) {
+        g.type = kGateMat4;
+        g.nq = 2;
+        g.q[0] = q0;              // column bit: u bit 0
+        g.q[1] = q0 + h->n;       // row bit: u bit 1
+        off += 16;
+      } else {
+        g.type = kGateMat16;      // u = c0 + 2 c1 + 4 r0 + 8 r1
+        g.nq = 4;
+        g.q[0] = q0;
+        g.q[1] = q1;
+        g.q[2] = q0 + h->n;
+        g.q[3] = q1 + h->n;
+        off += 256;
+      }
     }
     rc = apply_fused(h, gates, h->nbits, &h->dmq_S);
   }
-  h->dmq_q.clear();
+  h->dmq_ops.clear();
   h->dmq_S.clear();
   return rc;
 }
@@ -341,8 +371,10 @@ static int dm_run_queue(nwq_state* h) {
 int dm_flush(nwq_state* h) {
   if (!h->pend_active) return NWQ_OK;
   const int k = h->pend_k, n = h->n;
-  if (k == 1 && h->fuse_k > 0) {   // queue it for the next fused run
-    h->dmq_q.push_back(h->pend_q[0]);
+  // queue it for the next fused run: 1q always, 2q when the blocks run on the
+  // 4-register-bit kernel (a 16x16 takes all four register bits of a phase)
+  if (h->fuse_k > 0 && (k == 1 || (h->fuse_rb == 1 && h->nbits >= 8))) {
+    h->dmq_ops.push_back({k, h->pend_q[0], k == 2 ? h->pend_q[1] : -1});
     h->dmq_S.insert(h->dmq_S.end(), h->pend_S.begin(), h->pend_S.end());
     h->pend_active = false;
     return NWQ_OK;
@@ -359,18 +391,8 @@ int dm_flush(nwq_state* h) {
     h->pend_active = false;
     return last_launch("dm_superop_1q");
   }
-  std::vector<double2> buf(256);
-  for (int i = 0; i < 256; ++i) buf[i] = d2(h->pend_S[i]);
-  void* dev = nullptr;
-  rc = arena_put(h, buf.data(), buf.size() * sizeof(double2), &dev);
-  if (rc != NWQ_OK) return rc;
-  const int vq[4] = {h->pend_q[0], h->pend_q[1], h->pend_q[0] + n, h->pend_q[1] + n};
-  timing_begin(h, KC_DM2);
-  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev),
-               h->shape(KC_DM2, std::min(h->pend_q[0], h->pend_q[1])));
-  timing_end(h);
   h->pend_active = false;
-  return last_launch("dm_superop_2q");
+  return dm_superop2_pass(h, h->pend_q[0], h->pend_q[1], h->pend_S.data());
 }
 
 // Compose S_new after the pending superoperator (or start a new one).
@@ -496,7 +518,7 @@ int nwq_reset(nwq_handle h) {
   int rc = check_handle(h);
   if (rc) return rc;
   h->pend_active = false;   // pending work on the old state is discarded
-  h->dmq_q.clear();
+  h->dmq_ops.clear();
   h->dmq_S.clear();
   timing_begin(h, KC_RESET);
   launch_fill_basis0(h->stream, h->data, h->len);
@@ -523,7 +545,7 @@ int nwq_set_state(nwq_handle h, const double* host, size_t n_doubles) {
   if (host == nullptr || n_doubles != 2 * h->len)
     return set_error(NWQ_EINVAL, "host buffer must hold " + std::to_string(2 * h->len) + " doubles");
   h->pend_active = false;
-  h->dmq_q.clear();
+  h->dmq_ops.clear();
   h->dmq_S.clear();
   NWQ_TRY_HIP(hipMemcpyAsync(h->data, host, h->len * sizeof(double2), hipMemcpyHostToDevice, h->stream),
               "hipMemcpyAsync(set_state)");

@@ -238,6 +238,21 @@ __device__ __forceinline__ void rb_dense2(const vd2 (&x)[NV], vd2 (&y)[NV], cons
   }
 }
 
+// Dense 16x16 over all four register bits, the matrix in register order:
+// y[r] = sum_c M[16 r + c] x[c] (4-register-bit kernel only).
+template <int NV>
+__device__ __forceinline__ void rb_dense16(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
+  if constexpr (NV == 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      vd2 acc = vmul(ldv(M + 16 * r), x[0]);
+#pragma unroll
+      for (int c = 1; c < 16; ++c) acc = vfma(ldv(M + 16 * r + c), x[c], acc);
+      y[r] = acc;
+    }
+  }
+}
+
 // Exchange of members (base | OA) and (base | OB) of each quad over bits B0, B1.
 template <int NV, int B0, int B1, int OA, int OB>
 __device__ __forceinline__ void rb_swap2(const vd2 (&x)[NV], vd2 (&y)[NV]) {
@@ -328,6 +343,9 @@ __device__ __forceinline__ void rb_apply(int code, const double2* __restrict__ M
     NWQ_RB2(32, 1)
     NWQ_RB2(48, 2)
     NWQ_RB2(64, 3)
+    case kRbCodeDense16:
+      rb_dense16<NV>(x, y, M);
+      break;
     default:   // kRbCodeCopy
 #pragma unroll
       for (int j = 0; j < NV; ++j) y[j] = x[j];

@@ -108,7 +108,8 @@ void launch_reduce_rows(hipStream_t s, const double* partials, int rows, int gri
 // ---- fused LDS blocks (kernels_fuse.hip) ----------------------------------
 struct FusedOp {            // one gate inside a fused block, tile-local bits
   int kind;                 // 0: 1q dense, 1: 1q diag, 2: 2q dense, 3: 2q member swap, 4: 2q diag,
-                            // 6: 1q diag read from a 2x2 entry (M[0], M[3]; register-blocked kernels only)
+                            // 6: 1q diag read from a 2x2 entry (M[0], M[3]; register-blocked kernels only),
+                            // 7: dense 16x16 over all four register bits, in register order (4-bit kernel)
   int lo, hi;               // sorted tile-local bit positions (hi unused for 1q)
   int o0, o1;               // kind 2: local offsets of q0, q1; kind 3: offsets swapped; kind 4: local bits of q0, q1
   int mat;                  // start of its matrix in the block program's matrix table (double2 units)
@@ -119,14 +120,17 @@ struct FusedOp {            // one gate inside a fused block, tile-local bits
 // One switch index per register-blocked op (kind and register bits): 0 + B
 // dense 2x2, 4 + B diagonal (M[0], M[1]), 8 + B diagonal (M[0], M[3]); with
 // u = 4 o0 + o1: 16 + u dense 4x4, 32 + u CX, 48 + u SWAP, 64 + u 2q diagonal;
-// 84 + B dense 2x2 with a real M[0][0], 88 + B real dense 2x2.
+// 84 + B dense 2x2 with a real M[0][0], 88 + B real dense 2x2; 96 dense 16x16
+// over the four register bits (4-register-bit kernel only).
 constexpr int kRbCodeCopy = 80;   // kernel-internal copy that pads an odd gate count
+constexpr int kRbCodeDense16 = 96;
 inline int rb_op_code(const FusedOp& op) {
   const int u = 4 * op.o0 + op.o1;
   switch (op.kind) {
     case 0: return op.real00 == 2 ? 88 + op.lo : (op.real00 == 1 ? 84 + op.lo : op.lo);
     case 1: return 4 + op.lo;
     case 6: return 8 + op.lo;
+    case 7: return kRbCodeDense16;
     case 2: return 16 + u;
     case 3: return 32 + u;
     case 5: return 48 + u;

@@ -1539,7 +1539,7 @@ static int build_fused(nwq_vqe* h) {
   for (const Block& b : padded) {
     const int kb = b.c + b.m;
     if (kb < 8) return set_error(NWQ_EINVAL, "fused VQE path needs tiles of at least 2^8 amplitudes");
-    std::vector<std::array<int, 2>> lb(g.size());
+    std::vector<std::array<int, 4>> lb(g.size());
     std::vector<int> nq(g.size(), 1);
     for (int gi : b.gates) {
       lb[gi] = {local_bit(b, g[gi].q[0]), g[gi].nq == 2 ? local_bit(b, g[gi].q[1]) : 0};
@@ -1612,7 +1612,7 @@ static int build_fused(nwq_vqe* h) {
   for (auto bit = bpadded.rbegin(); h->bwd_rb && bit != bpadded.rend(); ++bit) {
     const Block& b = *bit;
     const int kb = b.c + b.m;
-    std::vector<std::array<int, 2>> lb(g.size());
+    std::vector<std::array<int, 4>> lb(g.size());
     std::vector<int> nq(g.size(), 1);
     std::vector<int> rev(b.gates.rbegin(), b.gates.rend());
     for (int gi : rev) {

@@ -300,6 +300,46 @@ def test_fused_superoperator_queue(nwq, n, k, kernel):
     st.close()
 
 
+@pytest.mark.parametrize("n,k", [(4, 8), (6, 10), (7, 12), (9, 12)])
+def test_fused_queue_two_qubit_superoperators(nwq, n, k):
+    """With the 4-register-bit kernel, 2q superoperators (16x16 on bits q0,
+    q1, q0 + n, q1 + n) queue with the 1q ones and run inside the fused
+    blocks: random pairs in both operator orders, dense and diagonal gates
+    with one- and two-qubit channels, against the oracle; switching the
+    fused kernel with 2q work queued runs it first."""
+    rng = np.random.default_rng(700 + 10 * n + k)
+    rho0 = W.random_density_matrix(n, seed=30 + n)
+    ops = []
+    for _ in range(4 * n):
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        kind = int(rng.integers(4))
+        if kind == 0:
+            ops += [("rzz", (a, b), (float(rng.uniform(-3, 3)),)), ("depolarize2", (a, b), (0.02,))]
+        elif kind == 1:
+            ops += [("cx", (a, b), ()), ("depolarize2", (b, a), (0.01,))]
+        elif kind == 2:
+            ops += [("u3", (a,), tuple(float(x) for x in rng.uniform(-3, 3, 3))), ("amp_damp", (a,), (0.04,))]
+        else:
+            ops += [("swap", (a, b), ()), ("phase_damp", (b,), (0.05,))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    st = nwq.DMState(n, reset=False)
+    st.set_fusion(k)
+    nwq.nwq_set_fusion_kernel(st.h, 1)
+    st.load(rho0)
+    st.run(ops)
+    assert maxerr(st.numpy(), want) <= TOL
+    assert nwq.nwq_fusion_stats(st.h)[0] >= 1
+    st.load(rho0)
+    half = len(ops) // 2
+    st.run(ops[:half])
+    nwq.nwq_set_fusion_kernel(st.h, 2)               # queued 16x16 work runs first, on the 4-bit kernel
+    st.run(ops[half:])
+    assert maxerr(st.numpy(), want) <= TOL
+    st.close()
+
+
 def test_depolarizing_conventions(nwq):
     """Both depolarising conventions on one and two qubits against the
     oracle's Kraus sets, alone and fused after a gate."""
