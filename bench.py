@@ -199,6 +199,18 @@ def main():
             dm.expvals(zt)
             dm.purity()
         torch.cuda.synchronize()
+        # then the same with the superoperators queued and run as fused blocks (k=12,
+        # 4 register bits), twice, after a second marker
+        torch.ones(2, dtype=torch.float64, device=dev).add_(1.0)
+        torch.cuda.synchronize()
+        dm.set_fusion(12)
+        nwq.nwq_set_fusion_kernel(dm.h, 1)
+        for _ in range(2):
+            dm.reset()
+            dm.run(circ)
+            dm.expvals(zt)
+            dm.purity()
+        torch.cuda.synchronize()
         dm.close()
         log("[bench] profile mode dm done")
         print(json.dumps({"profile_mode": args.profile_mode, "n": nd}))
@@ -637,7 +649,7 @@ def dm_leg(nwq, torch):
     out["tfim_n14_10_steps"] = {"ms": round(dt * 1e3, 2), "noisy_gate_passes": gates,
                                 "GBs": round(gates * nbytes / dt / 1e9, 1), "purity": pur,
                                 "trace_re": tr[0], "z0": float(z[0])}
-    # the same with the 1q superoperators queued and run as fused blocks over the 28 bits
+    # the same with the superoperators (1q 4x4 and 2q 16x16) queued and run as fused blocks over the 28 bits
     fused = {}
     for k in (10, 12):
         st.set_fusion(k)

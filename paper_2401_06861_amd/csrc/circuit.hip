@@ -538,11 +538,25 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
           int inv[16];
           for (int u = 0; u < 16; ++u) inv[reg_index(u)] = u;
           const cd* M = side->data() + (size_t)gates[gi].p[0];
+          cd P[256];
           for (int r = 0; r < 16; ++r)
-            for (int c2 = 0; c2 < 16; ++c2) {
-              const cd z = M[inv[r] * 16 + inv[c2]];
-              mats.push_back(make_double2(z.real(), z.imag()));
-            }
+            for (int c2 = 0; c2 < 16; ++c2) P[r * 16 + c2] = M[inv[r] * 16 + inv[c2]];
+          // a Pauli channel after a diagonal gate (RZZ, CZ, ...) leaves the
+          // entries of rho off the 4x4 diagonal scaled and mixes only the
+          // diagonal ones (registers 0, 5, 10, 15 in either qubit order)
+          auto blk = [](int u) { return u % 5 == 0; };
+          bool pauli = true;
+          for (int r = 0; r < 16 && pauli; ++r)
+            for (int c2 = 0; c2 < 16 && pauli; ++c2)
+              if (r != c2 && !(blk(r) && blk(c2)) && P[r * 16 + c2] != 0.0) pauli = false;
+          if (pauli) {
+            op.kind = 8;
+            for (int u = 0; u < 16; ++u) mats.push_back(make_double2(P[u * 17].real(), P[u * 17].imag()));
+            for (int i = 0; i < 4; ++i)
+              for (int j = 0; j < 4; ++j) mats.push_back(make_double2(P[5 * i * 16 + 5 * j].real(), P[5 * i * 16 + 5 * j].imag()));
+          } else {
+            for (int i = 0; i < 256; ++i) mats.push_back(make_double2(P[i].real(), P[i].imag()));
+          }
           op.code = rb_op_code(op);
           pops.push_back(op);
           continue;
@@ -557,7 +571,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       fold_permutations(
           pops, rbits, [](const FusedOp& o) { return o.kind == 3 || o.kind == 5; },
           [](const FusedOp& o) {
-            if (o.kind == 7) return 15u;
+            if (o.kind == 7 || o.kind == 8) return 15u;
             return (o.kind == 0 || o.kind == 1 || o.kind == 6) ? (1u << o.lo) : ((1u << o.o0) | (1u << o.o1));
           },
           [](const FusedOp& o, int j) { return o.kind == 3 ? reg_cx(o.o0, o.o1, j) : reg_swap(o.o0, o.o1, j); },

@@ -11,6 +11,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
+#include <set>
 
 #include "nwq_internal.h"
 #include "engine.h"
@@ -28,6 +30,26 @@ int check_hip(hipError_t e, const char* what) {
   if (e == hipSuccess) return NWQ_OK;
   if (e == hipErrorOutOfMemory) return set_error(NWQ_ENOMEM, std::string(what) + ": out of device memory");
   return set_error(NWQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int enable_dynamic_lds(const void* kernel) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({kernel, dev})) return NWQ_OK;
+  hipFuncAttributes attr{};
+  rc = check_hip(hipFuncGetAttributes(&attr, kernel), "hipFuncGetAttributes");
+  if (rc) return rc;
+  // the static LDS a kernel declares comes out of the same 160 KiB
+  rc = check_hip(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     kMaxDynamicLds - (int)attr.sharedSizeBytes),
+                 "hipFuncSetAttribute");
+  if (rc) return rc;
+  done.insert({kernel, dev});
+  return NWQ_OK;
 }
 
 #define NWQ_TRY_HIP(expr, what)                   \

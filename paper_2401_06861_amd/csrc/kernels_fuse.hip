@@ -158,7 +158,7 @@ void launch_fused_block(hipStream_t s, double2* a, int nbits, const FusedBlockDe
   const unsigned long long cap = 1ull << 20;
   const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
   const size_t lds = sizeof(double2) << k;
-  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536) (void)enable_dynamic_lds((const void*)k_fused);
   hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kFuseBlock), lds, s, a, nbits, blk, ops, mats);
 }
 
@@ -249,6 +249,25 @@ __device__ __forceinline__ void rb_dense16(const vd2 (&x)[NV], vd2 (&y)[NV], con
 #pragma unroll
       for (int c = 1; c < 16; ++c) acc = vfma(ldv(M + 16 * r + c), x[c], acc);
       y[r] = acc;
+    }
+  }
+}
+
+// A 16x16 with the pattern of a Pauli channel after a diagonal gate, in
+// register order: M[u] is the diagonal entry of register u, M[16 + 4 i + j]
+// the 4x4 among registers 5i and 5j (4-register-bit kernel only).
+template <int NV>
+__device__ __forceinline__ void rb_pauli16(const vd2 (&x)[NV], vd2 (&y)[NV], const double2* __restrict__ M) {
+  if constexpr (NV == 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (u % 5 != 0) y[u] = vmul(ldv(M + u), x[u]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      vd2 acc = vmul(ldv(M + 16 + 4 * i), x[0]);
+#pragma unroll
+      for (int j = 1; j < 4; ++j) acc = vfma(ldv(M + 16 + 4 * i + j), x[5 * j], acc);
+      y[5 * i] = acc;
     }
   }
 }
@@ -345,6 +364,9 @@ __device__ __forceinline__ void rb_apply(int code, const double2* __restrict__ M
     NWQ_RB2(64, 3)
     case kRbCodeDense16:
       rb_dense16<NV>(x, y, M);
+      break;
+    case kRbCodePauli16:
+      rb_pauli16<NV>(x, y, M);
       break;
     default:   // kRbCodeCopy
 #pragma unroll
@@ -514,6 +536,14 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
 
 size_t fused_rb_lds_bytes(int k) { return sizeof(double2) * ((1u << k) + (1u << k) / 16); }
 
+int fused_rb_enable_lds() {
+  int rc = NWQ_OK;
+  for (const void* f : {(const void*)k_fused_rb<3, false>, (const void*)k_fused_rb<3, true>,
+                        (const void*)k_fused_rb<4, false>, (const void*)k_fused_rb<4, true>})
+    if (!rc) rc = enable_dynamic_lds(f);
+  return rc;
+}
+
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid,
                      int flags, unsigned long long max_tiles) {
@@ -539,7 +569,7 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
     b.so[j] = (b.direct & 2) ? blk.sdir[j] : blk.joff[j];
   }
   auto go = [&](auto kern, int rb) {
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds > 65536) (void)enable_dynamic_lds((const void*)kern);
     hipLaunchKernelGGL(kern, dim3(grid, batch), dim3(1u << (k - rb)), lds, s, a, nbits, b, phases, ops, mats,
                        stride, mat_stride, ntiles);
   };

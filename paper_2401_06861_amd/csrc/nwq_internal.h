@@ -109,7 +109,9 @@ void launch_reduce_rows(hipStream_t s, const double* partials, int rows, int gri
 struct FusedOp {            // one gate inside a fused block, tile-local bits
   int kind;                 // 0: 1q dense, 1: 1q diag, 2: 2q dense, 3: 2q member swap, 4: 2q diag,
                             // 6: 1q diag read from a 2x2 entry (M[0], M[3]; register-blocked kernels only),
-                            // 7: dense 16x16 over all four register bits, in register order (4-bit kernel)
+                            // 7: dense 16x16 over all four register bits, in register order (4-bit kernel),
+                            // 8: the same with the pattern of a Pauli channel after a diagonal gate: diagonal
+                            //    except for a dense 4x4 among register indices 0, 5, 10, 15 (4-bit kernel)
   int lo, hi;               // sorted tile-local bit positions (hi unused for 1q)
   int o0, o1;               // kind 2: local offsets of q0, q1; kind 3: offsets swapped; kind 4: local bits of q0, q1
   int mat;                  // start of its matrix in the block program's matrix table (double2 units)
@@ -121,9 +123,12 @@ struct FusedOp {            // one gate inside a fused block, tile-local bits
 // dense 2x2, 4 + B diagonal (M[0], M[1]), 8 + B diagonal (M[0], M[3]); with
 // u = 4 o0 + o1: 16 + u dense 4x4, 32 + u CX, 48 + u SWAP, 64 + u 2q diagonal;
 // 84 + B dense 2x2 with a real M[0][0], 88 + B real dense 2x2; 96 dense 16x16
-// over the four register bits (4-register-bit kernel only).
+// over the four register bits, 97 its Pauli-channel pattern (the 16 diagonal
+// entries, then the 4x4 among registers 0, 5, 10, 15; 4-register-bit kernel
+// only).
 constexpr int kRbCodeCopy = 80;   // kernel-internal copy that pads an odd gate count
 constexpr int kRbCodeDense16 = 96;
+constexpr int kRbCodePauli16 = 97;
 inline int rb_op_code(const FusedOp& op) {
   const int u = 4 * op.o0 + op.o1;
   switch (op.kind) {
@@ -131,6 +136,7 @@ inline int rb_op_code(const FusedOp& op) {
     case 1: return 4 + op.lo;
     case 6: return 8 + op.lo;
     case 7: return kRbCodeDense16;
+    case 8: return kRbCodePauli16;
     case 2: return 16 + u;
     case 3: return 32 + u;
     case 5: return 48 + u;
@@ -184,6 +190,8 @@ inline void fill_phase_offsets(FusedPhase& fp, int rbits, const int* ld_perm, co
   }
 }
 size_t fused_rb_lds_bytes(int k);
+// enable_dynamic_lds for every register-blocked instance (outside graph capture)
+int fused_rb_enable_lds();
 // batch > 1: blockIdx.y = batch element b works on a + b * 2^nbits with the
 // matrix table mats + b * mat_stride; max_grid caps the tiles' grid (0 = 2^20).
 // flags: kFusedNonTemporal = non-temporal global loads and stores of the
@@ -204,5 +212,15 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
 // ---- error handling (engine.hip) ------------------------------------------
 int set_error(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
+
+// Dynamic LDS above 64 KiB: up to the CU's whole 160 KiB less the kernel's
+// static LDS (the LDS-resident VQE kernel takes up to that; the fused tiles at
+// most 2^13 amplitudes plus one padding entry per 16).  enable_dynamic_lds
+// raises a kernel's limit to it once per kernel and device, under a lock: the
+// limit is process-wide state of the kernel, so setting it per launch from
+// several host threads raced with launches of the same kernel elsewhere, and a
+// smaller value set for one launch could undercut another's.
+constexpr int kMaxDynamicLds = 160 * 1024;
+int enable_dynamic_lds(const void* kernel);
 
 }  // namespace nwq

@@ -1427,7 +1427,7 @@ static int launch_lds(nwq_vqe* h, int B, const double* theta, const double* coef
   const int grid = std::min(B, 4096);
 #define NWQ_VQE_LDS(NTV)                                                                                     \
   do {                                                                                                       \
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_vqe_lds<NTV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    if (lds > 65536) (void)enable_dynamic_lds((const void*)k_vqe_lds<NTV>);                                  \
     hipLaunchKernelGGL(k_vqe_lds<NTV>, dim3(grid), dim3(NTV), lds, s, h->n, h->d_ops, h->nops, h->d_fixed,   \
                        h->d_terms, h->nterms, h->nslots, h->d_slot_param, theta, h->P, B, coeffs, E, grad);  \
   } while (0)
@@ -1797,19 +1797,15 @@ static int build_fused(nwq_vqe* h) {
   // dynamic LDS above 64 KiB is enabled here, outside any graph capture
   const int kbt = std::min(std::min(h->fused_k, kBwdMaxTileBits), n);
   const size_t max_rb_lds = 2 * bwd_rb_tile_bytes(kbt < 8 ? 8 : kbt);
-  int rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)max_bwd_lds), "hipFuncSetAttribute");
+  if (max_bwd_lds > (size_t)kMaxDynamicLds || max_rb_lds > (size_t)kMaxDynamicLds ||
+      sizeof(double2) * hpad(1u << kHTileBits) > (size_t)kMaxDynamicLds)
+    return set_error(NWQ_EINVAL, "VQE tile larger than the dynamic LDS limit");
+  int rc = enable_dynamic_lds((const void*)k_vqe_bwd_tile);
   for (const void* f : {(const void*)k_vqe_hphi_tile<false, false>, (const void*)k_vqe_hphi_tile<true, false>,
-                        (const void*)k_vqe_hphi_tile<false, true>, (const void*)k_vqe_hphi_tile<true, true>})
-    if (!rc)
-      rc = check_hip(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(sizeof(double2) * hpad(1u << kHTileBits))), "hipFuncSetAttribute");
-  if (!rc && h->bwd_rb)
-    rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)max_rb_lds), "hipFuncSetAttribute");
-  if (!rc && h->bwd_rb)
-    rc = check_hip(hipFuncSetAttribute((const void*)k_vqe_bwd_rb<3, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)max_rb_lds), "hipFuncSetAttribute");
+                        (const void*)k_vqe_hphi_tile<false, true>, (const void*)k_vqe_hphi_tile<true, true>,
+                        (const void*)k_vqe_bwd_rb<3, false>, (const void*)k_vqe_bwd_rb<3, true>})
+    if (!rc) rc = enable_dynamic_lds(f);
+  if (!rc) rc = fused_rb_enable_lds();
   if (!rc) rc = check_hip(hipMalloc(&h->d_fused, total), "hipMalloc(vqe fused program)");
   if (!rc) rc = check_hip(hipMemcpy(h->d_fused, prog.data(), total, hipMemcpyHostToDevice), "hipMemcpy(vqe fused program)");
   if (rc) return rc;
