@@ -328,6 +328,8 @@ static void superop(const cd* kraus, int nk, int k, std::vector<cd>& S) {
   }
 }
 
+static constexpr size_t kDmQueueEntries = (1u << 20) / sizeof(cd);
+
 // One pass of a 2q superoperator S (16x16, u = c0 + 2 c1 + 4 r0 + 8 r1) on
 // qubits (q0, q1).
 static int dm_superop2_pass(nwq_state* h, int q0, int q1, const cd* S) {
@@ -399,6 +401,9 @@ int dm_flush(nwq_state* h) {
     h->dmq_ops.push_back({k, h->pend_q[0], k == 2 ? h->pend_q[1] : -1});
     h->dmq_S.insert(h->dmq_S.end(), h->pend_S.begin(), h->pend_S.end());
     h->pend_active = false;
+    // a long circuit with no read in between runs in pieces of at most 1 MiB
+    // of matrices (host memory stays bounded, the block program small)
+    if (h->dmq_S.size() >= kDmQueueEntries) return dm_run_queue(h);
     return NWQ_OK;
   }
   int rc = dm_run_queue(h);   // queued work comes first

@@ -340,6 +340,30 @@ def test_fused_queue_two_qubit_superoperators(nwq, n, k):
     st.close()
 
 
+def test_fused_queue_long_circuit_runs_in_pieces(nwq):
+    """A noisy circuit with more queued superoperators than one queue run
+    holds (1 MiB of matrices: 256 two-qubit ones) and no read in between runs
+    in pieces and still matches the oracle."""
+    n = 5
+    rng = np.random.default_rng(811)
+    rho0 = W.random_density_matrix(n, seed=812)
+    ops = []
+    for _ in range(330):
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        ops += [("rzz", (a, b), (float(rng.uniform(-3, 3)),)), ("depolarize2", (a, b), (0.002,)),
+                ("ry", (a,), (float(rng.uniform(-3, 3)),))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    st = nwq.DMState(n, reset=False)
+    st.set_fusion(8)
+    nwq.nwq_set_fusion_kernel(st.h, 1)
+    st.load(rho0)
+    st.run(ops)
+    assert maxerr(st.numpy(), want) <= TOL
+    st.close()
+
+
 def test_depolarizing_conventions(nwq):
     """Both depolarising conventions on one and two qubits against the
     oracle's Kraus sets, alone and fused after a gate."""
