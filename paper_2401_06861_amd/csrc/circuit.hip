@@ -32,7 +32,12 @@ std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k) {
     std::fill(blocked.begin(), blocked.end(), 0);
     int nblocked = 0;
     std::vector<int> H;
-    for (int idx : rem) {
+    for (size_t r = 0; r < rem.size(); ++r) {
+      if (nblocked == n) {   // every qubit is held by a left-out gate: the rest waits
+        keep.insert(keep.end(), rem.begin() + r, rem.end());
+        break;
+      }
+      const int idx = rem[r];
       const PGate& gg = g[idx];
       bool hit = false;
       for (int j = 0; j < gg.nq; ++j) hit |= blocked[gg.q[j]] != 0;
@@ -501,15 +506,19 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
       if (d.op_count > 0) launches.push_back({d, false, 0});
       continue;
     }
-    std::vector<std::array<int, 4>> lb(gates.size());
-    std::vector<int> nq(gates.size(), 1);
-    std::vector<int> order;
+    // the block's gates by block-local index (gid: the gate each one is), so
+    // that planning costs time in the block's size, not the circuit's
+    std::vector<int> gid, nq, order;
+    std::vector<std::array<int, 4>> lb;
     for (int gi : b.gates) {
       if (gates[gi].type == NWQ_GATE_I) continue;
       if (gates[gi].nq > rbits) return set_error(NWQ_EINVAL, "an operator wider than the phase's register bits");
-      for (int t = 0; t < gates[gi].nq; ++t) lb[gi][t] = local_bit(b, gates[gi].q[t]);
-      nq[gi] = gates[gi].nq;
-      order.push_back(gi);
+      std::array<int, 4> bits{};
+      for (int t = 0; t < gates[gi].nq; ++t) bits[t] = local_bit(b, gates[gi].q[t]);
+      order.push_back((int)gid.size());
+      gid.push_back(gi);
+      lb.push_back(bits);
+      nq.push_back(gates[gi].nq);
     }
     if (order.empty()) continue;
     d.op_begin = (int)phases.size();
@@ -523,13 +532,14 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
         return -1;
       };
       std::vector<FusedOp> pops;
-      for (int gi : ph.gates) {
-        if (gates[gi].type == kGateMat16) {   // all four register bits: the matrix in register order
+      for (int li : ph.gates) {
+        const PGate& gate = gates[gid[li]];
+        if (gate.type == kGateMat16) {   // all four register bits: the matrix in register order
           FusedOp op{};
           op.kind = 7;
           op.mat = (int)mats.size();
           int rt[4];
-          for (int t = 0; t < 4; ++t) rt[t] = ridx(lb[gi][t]);
+          for (int t = 0; t < 4; ++t) rt[t] = ridx(lb[li][t]);
           auto reg_index = [&](int u) {   // operator index -> register index
             int j = 0;
             for (int t = 0; t < 4; ++t) j |= ((u >> t) & 1) << rt[t];
@@ -537,7 +547,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
           };
           int inv[16];
           for (int u = 0; u < 16; ++u) inv[reg_index(u)] = u;
-          const cd* M = side->data() + (size_t)gates[gi].p[0];
+          const cd* M = side->data() + (size_t)gate.p[0];
           cd P[256];
           for (int r = 0; r < 16; ++r)
             for (int c2 = 0; c2 < 16; ++c2) P[r * 16 + c2] = M[inv[r] * 16 + inv[c2]];
@@ -562,7 +572,7 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
           continue;
         }
         FusedOp op;
-        if (encode_op(gates[gi], ridx(lb[gi][0]), nq[gi] == 2 ? ridx(lb[gi][1]) : 0, mats, op, true, side)) {
+        if (encode_op(gate, ridx(lb[li][0]), nq[li] == 2 ? ridx(lb[li][1]) : 0, mats, op, true, side)) {
           op.code = rb_op_code(op);
           pops.push_back(op);
         }
