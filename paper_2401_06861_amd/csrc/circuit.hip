@@ -631,14 +631,29 @@ int apply_fused(nwq_state* h, const std::vector<PGate>& gates_in, int nbits, con
   const FusedPhase* dph = static_cast<const FusedPhase*>(dev);
   const FusedOp* dops = reinterpret_cast<const FusedOp*>(static_cast<char*>(dev) + ops_off);
   const double2* dmats = reinterpret_cast<const double2*>(static_cast<char*>(dev) + mats_off);
+  // From |0...0>, amplitudes can be nonzero only where every bit outside the
+  // qubits touched so far (`support`) is zero; a block maps each tile to
+  // itself and zero tiles to zero, so it runs only the tiles whose index is
+  // zero on its non-tile qubits outside the support (the first block: tile 0).
+  unsigned long long support = 0;
   for (size_t li = 0; li < launches.size(); ++li) {
     const Launch& L = launches[li];
-    // from |0...0>, the first block runs only tile 0 (it holds index 0; every
-    // other tile is zero and a block maps each tile to itself)
-    const unsigned long long max_tiles = from_zero && li == 0 ? 1ull : 0ull;
+    unsigned long long tile_mask = ~0ull, tiles_of = 0;
+    for (int q = 0; q < L.d.c; ++q) tiles_of |= 1ull << q;
+    for (int i = 0; i < L.d.m; ++i) tiles_of |= 1ull << L.d.hi[i];
+    if (from_zero) {
+      tile_mask = 0;
+      int j = 0;   // tile index bit j = the j-th qubit (ascending) outside the tile
+      for (int q = 0; q < h->nbits; ++q) {
+        if ((tiles_of >> q) & 1ull) continue;
+        if ((support >> q) & 1ull) tile_mask |= 1ull << j;
+        ++j;
+      }
+      support |= tiles_of;
+    }
     timing_begin(h, KC_FUSED);
     if (L.rb) launch_fused_rb(h->stream, h->data, h->nbits, L.d, dph, dops, dmats, L.rbits, 1, 0, 0, h->fuse_flags,
-                              max_tiles);
+                              0, tile_mask);
     else launch_fused_block(h->stream, h->data, h->nbits, L.d, dops, dmats, h->fuse_k);
     timing_end(h);
     const int rc = check_hip(hipGetLastError(), "fused_block");

@@ -407,8 +407,18 @@ struct RbBlockArgs {
   int hi[8];
   int op_begin, op_count;
   int direct;
+  int sparse;                  // tiles t = 0, 1, ... are tile indices pdep(t, tmask)
+  unsigned long long tmask;
   unsigned long long lo[16], so[16];
 };
+
+// The bits of v deposited, lowest first, at the set bits of mask.
+__device__ __forceinline__ unsigned long long pdep64(unsigned long long v, unsigned long long mask) {
+  unsigned long long r = 0;
+  for (; mask; mask &= mask - 1, v >>= 1)
+    if (v & 1ull) r |= mask & (~mask + 1ull);
+  return r;
+}
 
 template <int R, bool NT>
 __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __restrict__ a0, int nbits,
@@ -441,8 +451,8 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   // thread part of the entry indices of the load and store layouts
   const unsigned long long gl_ld = tile_index(0ull, ldd ? spread(phases[blk.op_begin]) : tid, cmask, c, m, blk);
   const unsigned long long gl_st = tile_index(0ull, sdd ? spread(phases[blk.op_begin + P - 1]) : tid, cmask, c, m, blk);
-  auto tile_base = [&](unsigned long long tile) {
-    unsigned long long base = tile << c;
+  auto tile_base = [&](unsigned long long t) {
+    unsigned long long base = (blk.sparse ? pdep64(t, blk.tmask) : t) << c;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (i < m) {
@@ -546,10 +556,12 @@ int fused_rb_enable_lds() {
 
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch, int mat_stride, int max_grid,
-                     int flags, unsigned long long max_tiles) {
+                     int flags, unsigned long long max_tiles, unsigned long long tile_mask) {
   const int k = blk.c + blk.m;
   unsigned long long ntiles = 1ull << (nbits - k);
   if (max_tiles > 0 && max_tiles < ntiles) ntiles = max_tiles;
+  const bool sparse = tile_mask != ~0ull && __builtin_popcountll(tile_mask) < nbits - k;
+  if (sparse) ntiles = 1ull << __builtin_popcountll(tile_mask);
   // about four tiles per workgroup (so that the next tile's loads overlap
   // this one's phases), at least 2048 workgroups
   const unsigned long long cap = max_grid > 0 ? (unsigned long long)max_grid
@@ -564,6 +576,8 @@ void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& 
   b.op_begin = blk.op_begin;
   b.op_count = blk.op_count;
   b.direct = (flags & kFusedDirect) ? blk.direct : 0;
+  b.sparse = sparse ? 1 : 0;
+  b.tmask = sparse ? tile_mask : 0ull;
   for (int j = 0; j < 16; ++j) {
     b.lo[j] = (b.direct & 1) ? blk.jdir[j] : blk.joff[j];
     b.so[j] = (b.direct & 2) ? blk.sdir[j] : blk.joff[j];

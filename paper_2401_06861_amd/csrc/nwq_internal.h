@@ -197,17 +197,19 @@ int fused_rb_enable_lds();
 // flags: kFusedNonTemporal = non-temporal global loads and stores of the
 // tiles; kFusedDirect = load the first phase / store the last phase straight
 // between HBM and registers where the block allows it (FusedBlockDev::direct).
-// max_tiles > 0 runs only the first max_tiles tiles of each state (the block
-// leaves the others alone: used when they are known to hold zeros, which a
-// block maps to zeros).
+// max_tiles > 0 runs only the first max_tiles tiles of each state, and
+// tile_mask != ~0 only the tiles whose index is zero outside tile_mask (the
+// block leaves the others alone: used when they are known to hold zeros,
+// which a block maps to zeros).
 constexpr int kFusedNonTemporal = 1;
 constexpr int kFusedDirect = 2;
-// SV circuits (host side): fuse each register phase's gates into 2x2 / 4x4
-// products where that saves FP64 work (circuit.hip, fuse_phase).
+// SV circuits (host side): gate products before the blocks are planned, where
+// they save FP64 work (circuit.hip, gate_products).
 constexpr int kFusedGateFusion = 4;
 void launch_fused_rb(hipStream_t s, double2* a, int nbits, const FusedBlockDev& blk, const FusedPhase* phases,
                      const FusedOp* ops, const double2* mats, int rbits, int batch = 1, int mat_stride = 0,
-                     int max_grid = 0, int flags = 0, unsigned long long max_tiles = 0);
+                     int max_grid = 0, int flags = 0, unsigned long long max_tiles = 0,
+                     unsigned long long tile_mask = ~0ull);
 
 // ---- error handling (engine.hip) ------------------------------------------
 int set_error(int code, const std::string& msg);

@@ -603,13 +603,19 @@ def test_streaming_ceiling_kernels(nwq, size):
     assert torch.equal(y * 2.0, x)
 
 
-@pytest.mark.parametrize("n,k", [(9, 8), (14, 10), (20, 12)])
-def test_run_circuit_from_zero(nwq, n, k):
-    """nwq_run_circuit (reset, then the circuit; the first fused block runs
-    only the tile holding index 0) equals reset + nwq_apply_circuit and the
+@pytest.mark.parametrize("n,k,lead", [(9, 8, 0), (14, 10, 0), (20, 12, 0), (20, 12, 1), (22, 13, 1)])
+def test_run_circuit_from_zero(nwq, n, k, lead):
+    """nwq_run_circuit (reset, then the circuit; each fused block runs only
+    the tiles that can hold nonzero amplitudes: zero on the qubits no earlier
+    block touched) equals reset + nwq_apply_circuit bit for bit and the
     oracle, for every fused kernel and unfused, on a state that held other
-    values before."""
-    gates = W.brickwork_circuit(n, 6, seed=n) + W.random_gate_list(n, 40, seed=n)
+    values before.  lead = 1 starts with gates on a few high qubits, so the
+    next blocks' supports are partial."""
+    gates = []
+    if lead:
+        hi = list(range(n - 5, n))
+        gates += [("h", (q,), ()) for q in hi] + [("cx", (hi[0], hi[3]), ()), ("rx", (hi[1],), (0.7,))]
+    gates += W.brickwork_circuit(n, 6, seed=n) + W.random_gate_list(n, 40, seed=n)
     want = tensor.sv_run(gates, n)
     arrays = nwq.circuit_arrays(gates)
     for rb in (1, 2, 0, None):
