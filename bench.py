@@ -60,8 +60,11 @@ def parse():
     return ap.parse_args()
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - _T0:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
 def step_bytes(n, gates):

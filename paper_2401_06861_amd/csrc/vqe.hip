@@ -1835,11 +1835,25 @@ static int launch_fused(nwq_vqe* h, int B, const double* theta, const double* co
   hipLaunchKernelGGL(k_vqe_init, grid, dim3(kVqeBlock), 0, s, h->d_phi, h->n);
   hipLaunchKernelGGL(k_vqe_mats, dim3((h->nops + 255) / 256, B), dim3(256), 0, s, h->d_ops, h->nops, h->d_fixed,
                      theta, h->P, h->d_table);
-  // the first block acts on |0...0>: only the tile holding index 0 (tile 0)
-  // is non-zero, and a block maps each tile to itself, so the others stay 0
-  for (size_t bi = 0; bi < h->fwd_blocks.size(); ++bi)
-    launch_fused_rb(s, h->d_phi, h->n, h->fwd_blocks[bi], dph, dfo, h->d_table, h->fused_rbits, B, stride, G,
-                    h->fused_flags, bi == 0 ? 1ull : 0ull);
+  // phi starts at |0...0>: amplitudes can be nonzero only where every qubit no
+  // earlier block touched is zero, and a block maps each tile to itself and
+  // zero tiles to zero, so each block runs only the tiles whose index is zero
+  // on its non-tile qubits outside that support (the first block: tile 0)
+  unsigned long long support = 0;
+  for (size_t bi = 0; bi < h->fwd_blocks.size(); ++bi) {
+    const FusedBlockDev& d = h->fwd_blocks[bi];
+    unsigned long long tiles_of = 0, tile_mask = 0;
+    for (int q = 0; q < d.c; ++q) tiles_of |= 1ull << q;
+    for (int i = 0; i < d.m; ++i) tiles_of |= 1ull << d.hi[i];
+    for (int q = 0, j = 0; q < h->n; ++q) {
+      if ((tiles_of >> q) & 1ull) continue;
+      if ((support >> q) & 1ull) tile_mask |= 1ull << j;
+      ++j;
+    }
+    support |= tiles_of;
+    launch_fused_rb(s, h->d_phi, h->n, d, dph, dfo, h->d_table, h->fused_rbits, B, stride, G, h->fused_flags, 0,
+                    tile_mask);
+  }
   const HTerm* dht = reinterpret_cast<const HTerm*>(static_cast<char*>(h->d_fused) + h->fused_hterm_off);
   const int* dwi = reinterpret_cast<const int*>(static_cast<char*>(h->d_fused) + h->fused_widx_off);
   for (const auto& L : h->hlaunch) {
