@@ -585,6 +585,18 @@ def sweep_n32_leg(nwq, torch, tuned):
     return res
 
 
+def noisy_gate_ops(label, qs):
+    """One noisy gate of the DM sweeps: 1q: U3 + depolarising + amplitude and
+    phase damping (one 4x4 superoperator); 2q: RZZ + two-qubit depolarising (a
+    Pauli-pattern 16x16: coherences scaled, populations mixed); 2q_cx: CX +
+    two-qubit depolarising (a dense 16x16)."""
+    if label == "1q":
+        return [("u3", qs, (0.3, 0.2, 0.1)), ("depolarize", qs, (1e-3,)), ("amp_damp", qs, (1e-3,)),
+                ("phase_damp", qs, (2e-3,))]
+    gate = ("rzz", qs, (0.2,)) if label == "2q" else ("cx", qs, ())
+    return [gate, ("depolarize2", qs, (1e-2,))]
+
+
 def dm_leg(nwq, torch):
     log("[bench] DM n=14 noisy gate leg")
     from paper_2401_06861_amd import autotune
@@ -612,11 +624,10 @@ def dm_leg(nwq, torch):
     # per-qubit sweep: each noisy gate on low, middle and high qubits (row and column bits q, q+n)
     sweep = {}
     for label, qs_list, cls in (("1q", [(0,), (1,), (2,), (7,), (n - 1,)], "dm_superop_1q"),
-                                ("2q", [(0, 1), (2, 3), (6, 7), (n - 2, n - 1)], "dm_superop_2q")):
+                                ("2q", [(0, 1), (2, 3), (6, 7), (n - 2, n - 1)], "dm_superop_2q"),
+                                ("2q_cx", [(0, 1), (2, 3), (6, 7)], "dm_superop_2q")):
         for qs in qs_list:
-            ops = ([("u3", qs, (0.3, 0.2, 0.1)), ("depolarize", qs, (1e-3,)), ("amp_damp", qs, (1e-3,)),
-                    ("phase_damp", qs, (2e-3,))] if label == "1q"
-                   else [("rzz", qs, (0.2,)), ("depolarize2", qs, (1e-2,))])
+            ops = noisy_gate_ops(label, qs)
             st.run(ops)
             st.flush()
             torch.cuda.synchronize()
@@ -684,11 +695,10 @@ def dm15_leg(nwq, torch):
     nbytes = 32 * (1 << (2 * n))
     sweep = {}
     for label, qs_list, cls in (("1q", [(0,), (3,), (7,), (n - 1,)], "dm_superop_1q"),
-                                ("2q", [(0, 1), (2, 3), (6, 7), (n - 2, n - 1)], "dm_superop_2q")):
+                                ("2q", [(0, 1), (2, 3), (6, 7), (n - 2, n - 1)], "dm_superop_2q"),
+                                ("2q_cx", [(0, 1), (2, 3), (6, 7)], "dm_superop_2q")):
         for qs in qs_list:
-            ops = ([("u3", qs, (0.3, 0.2, 0.1)), ("depolarize", qs, (1e-3,)), ("amp_damp", qs, (1e-3,)),
-                    ("phase_damp", qs, (2e-3,))] if label == "1q"
-                   else [("rzz", qs, (0.2,)), ("depolarize2", qs, (1e-2,))])
+            ops = noisy_gate_ops(label, qs)
             st.run(ops)
             st.flush()
             torch.cuda.synchronize()

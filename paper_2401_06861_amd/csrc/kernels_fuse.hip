@@ -464,25 +464,21 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
   };
   // A tile's NV entries per thread are loaded one tile ahead: the loads of
   // the next tile are in flight while this one runs its phases (tiles are
-  // disjoint, so the early read is safe).  A tile's results wait in v and go
-  // to HBM at the top of the next trip, ahead of the next loads: the vector
-  // memory counter retires in issue order, so a store issued after those
-  // loads would make the next trip's wait for them cover the store's
-  // completion too.  With direct I/O the first phase runs on the loaded
-  // registers and the last phase's registers are the results, so a block of
-  // one such phase never touches LDS.
+  // disjoint, so the early read is safe).  A tile's results go to HBM after
+  // its last phase and before the next tile's loaded registers are used; the
+  // vector memory counter retires in issue order, so the wait for those loads
+  // (issued before the stores) leaves the stores in flight.  The loaded
+  // registers are taken up at the bottom of the loop, behind the stores on
+  // every path into it: at the loop head the paths from the first tile and
+  // from the back edge differ, and the compiler's wait counts, merged there,
+  // would wait for the stores too.  With direct I/O the first phase runs on
+  // the loaded registers and the last phase's registers are the results, so
+  // a block of one such phase never touches LDS.
+  if (blockIdx.x >= ntiles) return;
   vd2 pf[NV], v[NV];
-  double2* __restrict__ prev = nullptr;
-  if (blockIdx.x < ntiles) {
-    const double2* __restrict__ p = a + tile_base(blockIdx.x) + gl_ld;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(p + blk.lo[j]);
-  }
-  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    if (prev) {
-#pragma unroll
-      for (int j = 0; j < NV; ++j) gst<NT>(prev + blk.so[j], v[j]);
-    }
+  // first phase input: the registers themselves, or the tile in LDS (every
+  // wave must be done reading the previous tile before it is overwritten)
+  auto take_loaded = [&]() {
     if (ldd) {
 #pragma unroll
       for (int j = 0; j < NV; ++j) v[j] = pf[j];
@@ -491,12 +487,17 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
 #pragma unroll
       for (int j = 0; j < NV; ++j) stv(t + padl(tid + j * nt), pf[j]);
     }
-    const unsigned long long nx = tile + gridDim.x;
-    if (nx < ntiles) {
-      const double2* __restrict__ p = a + tile_base(nx) + gl_ld;
+  };
+  auto load_tile = [&](unsigned long long tl) {
+    const double2* __restrict__ p = a + tile_base(tl) + gl_ld;
 #pragma unroll
-      for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(p + blk.lo[j]);
-    }
+    for (int j = 0; j < NV; ++j) pf[j] = gld<NT>(p + blk.lo[j]);
+  };
+  unsigned long long tile = blockIdx.x;
+  load_tile(tile);
+  take_loaded();
+  if (tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
+  for (;;) {
     for (int pi = 0; pi < P; ++pi) {
       const FusedPhase ph = phases[blk.op_begin + pi];
       // padl(dep | off) = padl(dep) + padl(off) for disjoint bit sets
@@ -534,11 +535,13 @@ __global__ __launch_bounds__(R == 4 ? 512 : 1024) void k_fused_rb(double2* __res
 #pragma unroll
       for (int j = 0; j < NV; ++j) v[j] = ldv(t + padl(tid + j * nt));
     }
-    prev = a + tile_base(tile) + gl_st;
-  }
-  if (prev) {
+    double2* __restrict__ out = a + tile_base(tile) + gl_st;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) gst<NT>(prev + blk.so[j], v[j]);
+    for (int j = 0; j < NV; ++j) gst<NT>(out + blk.so[j], v[j]);
+    tile += gridDim.x;
+    if (tile >= ntiles) break;
+    take_loaded();
+    if (tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
   }
 }
 

@@ -508,10 +508,26 @@ __global__ __launch_bounds__(kBlock) void k_sv_2q(double2* __restrict__ a, unsig
   }
 }
 
+// Row r of a 16 x 16 with the pattern of a Pauli channel after a diagonal
+// two-qubit gate, on the DM entries (q0, q1, q0 + n, q1 + n) of one group
+// (operator index u = c0 + 2 c1 + 4 r0 + 8 r1): an entry whose row and column
+// bits differ on either qubit (a coherence) is only scaled, by M[u]; the four
+// populations u = 0, 5, 10, 15 mix through the 4 x 4 M[16 + 4 i + j] (rows
+// and columns 5i, 5j).  x is the group (a register array or an LDS view).
+template <typename X>
+__device__ __forceinline__ vd2 kq_pauli_row(const double2* __restrict__ M, int r, const X& x) {
+  if (r % 5 != 0) return cmul(tov(M[r]), x[r]);
+  const int i = r / 5;
+  vd2 acc = cmul(tov(M[16 + 4 * i]), x[0]);
+#pragma unroll
+  for (int j = 1; j < 4; ++j) acc = cfma(tov(M[16 + 4 * i + j]), x[5 * j], acc);
+  return acc;
+}
+
 // k-qubit dense operator (k = 3 or 4; the 16 x 16 case is the fused
 // two-qubit gate + channel superoperator of the density matrix).  The
 // matrix lives in device memory and is read with wave-uniform addresses.
-template <int K, bool NTM>
+template <int K, bool NTM, bool PAULI = false>
 __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsigned long long ngroups,
                                                   QSet qs, const double2* __restrict__ M) {
   constexpr int D = 1 << K;
@@ -531,6 +547,11 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsig
     idx[u] = base + o;
     v[u] = gld<NTM>(a + idx[u]);
   }
+  if constexpr (PAULI) {
+#pragma unroll
+    for (int r = 0; r < D; ++r) gst<NTM>(a + idx[r], kq_pauli_row(M, r, v));
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < D; ++r) {
     vd2 acc = cmul(tov(M[r * D]), v[0]);
@@ -546,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq(double2* __restrict__ a, unsig
 // thread), one coalesced entry per load.  After one barrier each thread forms
 // rows u of M (uniform per wave: scalar loads) times its group, read from the
 // workgroup's copy in LDS; with MPT = 2 each LDS read serves two rows.
-template <int MPT, bool NTM, bool ORD>
+template <int MPT, bool NTM, bool ORD, bool PAULI = false>
 __global__ __launch_bounds__(1024 / MPT) void k_sv_kq4_x16(double2* __restrict__ a, unsigned long long g0, QSet qs,
                                                            const double2* __restrict__ M) {
   constexpr unsigned W = 16 / MPT;
@@ -571,6 +592,23 @@ __global__ __launch_bounds__(1024 / MPT) void k_sv_kq4_x16(double2* __restrict__
 #pragma unroll
   for (int mi = 0; mi < MPT; ++mi) t[(w + mi * W) * 64 + r] = acc[mi];
   __syncthreads();
+  if constexpr (PAULI) {
+    // a coherence row needs only its own entry; a population row reads the
+    // other three populations of its group from LDS
+    struct View {
+      const vd2* t;
+      unsigned r;
+      __device__ vd2 operator[](int u) const { return t[64 * u + r]; }
+    } view{t, r};
+#pragma unroll
+    for (int mi = 0; mi < MPT; ++mi) {
+      const unsigned u = w + mi * W;
+      acc[mi] = u % 5u != 0u ? cmul(tov(M[u]), acc[mi]) : kq_pauli_row(M, (int)u, view);
+    }
+#pragma unroll
+    for (int mi = 0; mi < MPT; ++mi) gst<NTM>(a + i[mi], acc[mi]);
+    return;
+  }
   const vd2 x0 = t[r];
 #pragma unroll
   for (int mi = 0; mi < MPT; ++mi) acc[mi] = cmul(tov(M[16 * (w + mi * W)]), x0);
@@ -604,7 +642,7 @@ struct KqStaged {
 __device__ __forceinline__ unsigned kq_swz(unsigned e, int a, int b) {
   return e ^ (((e >> a) ^ (b ? (e >> b) : 0u)) & 7u);
 }
-template <bool NTM>
+template <bool NTM, bool PAULI = false>
 __global__ __launch_bounds__(kBlock) void k_sv_kq4_staged(double2* __restrict__ a, KqStaged ks,
                                                           const double2* __restrict__ M) {
   __shared__ vd2 t[16 * 256];
@@ -631,9 +669,14 @@ __global__ __launch_bounds__(kBlock) void k_sv_kq4_staged(double2* __restrict__ 
     for (int u = 0; u < 16; ++u) v[u] = t[kq_swz(base + (unsigned)ks.idx_off[u], ks.swa, ks.swb)];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      vd2 acc = cmul(tov(M[r * 16]), v[0]);
+      vd2 acc;
+      if constexpr (PAULI) {
+        acc = kq_pauli_row(M, r, v);
+      } else {
+        acc = cmul(tov(M[r * 16]), v[0]);
 #pragma unroll
-      for (int c = 1; c < 16; ++c) acc = cfma(tov(M[r * 16 + c]), v[c], acc);
+        for (int c = 1; c < 16; ++c) acc = cfma(tov(M[r * 16 + c]), v[c], acc);
+      }
       t[kq_swz(base + (unsigned)ks.idx_off[r], ks.swa, ks.swb)] = acc;
     }
   }
@@ -970,7 +1013,8 @@ void kq_pick_swizzle(KqStaged& ks) {
 }  // namespace
 
 void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits, const double2* dev_matrix,
-                  const LaunchCfg& cfg) {
+                  const LaunchCfg& cfg, bool pauli) {
+  pauli = pauli && k == 4;
   QSet qs{};
   int sorted[4];
   for (int j = 0; j < k; ++j) {
@@ -1005,8 +1049,13 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
     }
     kq_pick_swizzle(ks);
     const dim3 grid((unsigned)(1ull << (nbits - 12)));   // 16 runs of 256 entries per workgroup
-    if (cfg.nt & 1) hipLaunchKernelGGL(k_sv_kq4_staged<true>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
-    else hipLaunchKernelGGL(k_sv_kq4_staged<false>, grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    if (pauli) {
+      if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq4_staged<true, true>), grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+      else hipLaunchKernelGGL((k_sv_kq4_staged<false, true>), grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    } else {
+      if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq4_staged<true, false>), grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+      else hipLaunchKernelGGL((k_sv_kq4_staged<false, false>), grid, dim3(kBlock), 0, s, a, ks, dev_matrix);
+    }
     return;
   }
   // shapes 128 / 64: split workgroups of 1024 threads (one member each) or 512
@@ -1017,12 +1066,14 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
       const unsigned long long cnt = ng - g0 < per ? ng - g0 : per;   // whole workgroups
       const dim3 grid((unsigned)(cnt / 64));
       with_hint_order(cfg.nt & 1, use_order(cfg.nt, grid), [&](auto nt, auto ord) {
-        if (cfg.ppt == 128)
-          hipLaunchKernelGGL((k_sv_kq4_x16<1, decltype(nt)::value, decltype(ord)::value>), grid, dim3(1024), 0, s, a,
-                             g0, qs, dev_matrix);
-        else
-          hipLaunchKernelGGL((k_sv_kq4_x16<2, decltype(nt)::value, decltype(ord)::value>), grid, dim3(512), 0, s, a,
-                             g0, qs, dev_matrix);
+        constexpr bool NT = decltype(nt)::value, ORD = decltype(ord)::value;
+        if (cfg.ppt == 128) {
+          if (pauli) hipLaunchKernelGGL((k_sv_kq4_x16<1, NT, ORD, true>), grid, dim3(1024), 0, s, a, g0, qs, dev_matrix);
+          else hipLaunchKernelGGL((k_sv_kq4_x16<1, NT, ORD, false>), grid, dim3(1024), 0, s, a, g0, qs, dev_matrix);
+        } else {
+          if (pauli) hipLaunchKernelGGL((k_sv_kq4_x16<2, NT, ORD, true>), grid, dim3(512), 0, s, a, g0, qs, dev_matrix);
+          else hipLaunchKernelGGL((k_sv_kq4_x16<2, NT, ORD, false>), grid, dim3(512), 0, s, a, g0, qs, dev_matrix);
+        }
       });
     }
     return;
@@ -1032,6 +1083,9 @@ void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits
   if (k == 3) {
     if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq<3, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
     else hipLaunchKernelGGL((k_sv_kq<3, false>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+  } else if (pauli) {
+    if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq<4, true, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
+    else hipLaunchKernelGGL((k_sv_kq<4, false, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
   } else {
     if (cfg.nt & 1) hipLaunchKernelGGL((k_sv_kq<4, true>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);
     else hipLaunchKernelGGL((k_sv_kq<4, false>), grid, dim3(kBlock), 0, s, a, ng, qs, dev_matrix);

@@ -62,8 +62,12 @@ void launch_sv_swap1(hipStream_t s, double2* a, int nbits, int q, const LaunchCf
 void launch_sv_swap2(hipStream_t s, double2* a, int nbits, int qa, int qb,
                      unsigned long long offA, unsigned long long offB, const LaunchCfg& cfg);
 void launch_sv_2q(hipStream_t s, double2* a, int nbits, int q0, int q1, const Mat4& m, const LaunchCfg& cfg);
+// k-qubit operator on the given qubits (operator index bit j = qubits[j]);
+// dev_matrix is the dense 2^k x 2^k, or with pauli (k = 4 only) the 32-entry
+// compact form of a Pauli-pattern 16 x 16: the 16 diagonal entries, then the
+// 4 x 4 among operator indices 0, 5, 10, 15.
 void launch_sv_kq(hipStream_t s, double2* a, int nbits, int k, const int* qubits, const double2* dev_matrix,
-                  const LaunchCfg& cfg);
+                  const LaunchCfg& cfg, bool pauli = false);
 
 // ---- reductions (kernels_reduce.hip) --------------------------------------
 // One pass of the tiled Pauli-term kernel.  `terms` is a device table of

@@ -254,6 +254,34 @@ def test_staged_two_qubit_superoperators(nwq, n):
     st.close()
 
 
+@pytest.mark.parametrize("n", [6, 7])
+def test_pauli_pattern_two_qubit_superoperators(nwq, n):
+    """Noisy 2q gates whose superoperator only scales the coherences and mixes
+    the four populations (RZZ or CZ, then depolarising noise in either
+    convention: the compact Pauli-pattern pass), interleaved with ones that do
+    not (CX or SWAP before the noise: the dense 16 x 16), on pairs that take
+    the LDS-staged kernel, the one-group-per-thread kernel and, under shapes
+    64 and 128, the split-workgroup kernels, in both operator orders."""
+    rho0 = W.random_density_matrix(n, seed=90 + n)
+    st = nwq.DMState(n, reset=False)
+    pairs = [(0, 1), (1, 0), (2, 5), (5, 2), (4, 5), (0, 3), (3, n - 1), (n - 1, 1)]
+    ops = []
+    for i, (a, b) in enumerate(pairs):
+        noise = ("depolarize2", (a, b), (0.02 + 0.01 * i,)) if i % 3 else ("depolarize2_nc", (a, b), (0.05,))
+        ops += [("rzz", (a, b), (0.7 + 0.1 * i,)) if i % 2 else ("cz", (a, b), ()), noise]   # Pauli pattern
+        ops += [("cx", (a, b), ()) if i % 2 else ("swap", (a, b), ()), noise]                   # dense
+    ops += [("depolarize2", (2, 3), (0.04,))]   # the channel alone
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    for ppt, flags in ((1, 0), (1, 1), (64, 1), (128, 1), (64, 3), (128, 3)):
+        nwq.nwq_set_launch(st.h, 7, -1, ppt, flags)
+        st.load(rho0)
+        st.run(ops)
+        assert maxerr(st.numpy(), want) <= TOL, (ppt, flags)
+    st.close()
+
+
 @pytest.mark.parametrize("n,k,kernel", [(4, 8, 1), (5, 8, 2), (6, 10, 1), (7, 12, 1), (7, 8, 0), (8, 12, 2)])
 def test_fused_superoperator_queue(nwq, n, k, kernel):
     """With fusion on, the 1q superoperators (gate + channels, 4x4 on bits
