@@ -691,7 +691,7 @@ def dm15_leg(nwq, torch):
     from paper_2401_06861_amd import autotune
     n = 15
     st = nwq.DMState(n)
-    autotune.tune(st.h, reps=1, cache_path=None)
+    autotune.tune(st.h, reps=2, cache_path=None)
     nbytes = 32 * (1 << (2 * n))
     sweep = {}
     for label, qs_list, cls in (("1q", [(0,), (3,), (7,), (n - 1,)], "dm_superop_1q"),

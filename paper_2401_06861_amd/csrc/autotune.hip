@@ -87,15 +87,26 @@ void run_2q(nwq_state* h, const LaunchCfg& c, int q) {
   launch_sv_2q(h->stream, h->data, h->nbits, q, t, m, c);
 }
 void run_dm2(nwq_state* h, const LaunchCfg& c, int q) {
-  // (Z (x) Z) (x) conj(Z (x) Z) on (a, b, a + n, b + n): diagonal +-1, self-inverse
+  // (Z (x) Z) (x) conj(Z (x) Z) on (a, b, a + n, b + n): diagonal +-1, self-inverse,
+  // twice as a dense 16 x 16 and twice in the compact form of a Pauli-pattern
+  // superoperator (a noisy two-qubit gate takes one or the other, and their
+  // fastest shapes differ): the shape is picked for both
   const int t = q + 1;
   const int vq[4] = {q, t, q + h->n, t + h->n};
-  std::vector<double2> S(256, make_double2(0.0, 0.0));
-  for (int u = 0; u < 16; ++u) S[17 * u] = make_double2(__builtin_popcount(u) % 2 ? -1.0 : 1.0, 0.0);
+  std::vector<double2> S(256 + 32, make_double2(0.0, 0.0));
+  for (int u = 0; u < 16; ++u) {
+    const double d = __builtin_popcount(u) % 2 ? -1.0 : 1.0;
+    S[17 * u] = make_double2(d, 0.0);
+    S[256 + u] = make_double2(d, 0.0);                                 // diagonal entries
+    if (u % 5 == 0) S[256 + 16 + 5 * (u / 5)] = make_double2(d, 0.0);  // 4 x 4 among 0, 5, 10, 15
+  }
   void* dev = nullptr;
   if (arena_put(h, S.data(), S.size() * sizeof(double2), &dev) != NWQ_OK) return;
-  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev), c);
-  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, static_cast<const double2*>(dev), c);
+  const double2* dense = static_cast<const double2*>(dev);
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, dense, c);
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, dense, c);
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, dense + 256, c, true);
+  launch_sv_kq(h->stream, h->data, h->nbits, 4, vq, dense + 256, c, true);
 }
 void run_dm1(nwq_state* h, const LaunchCfg& c, int q) {
   Mat4 m{};   // Z (x) conj(Z) on (column q, row q + n): diag(1, -1, -1, 1)
@@ -170,18 +181,19 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
   if (rc) return rc;
   if (best_ms)
     for (int i = 0; i < KC_COUNT * kBuckets; ++i) best_ms[i] = -1.0;
-  struct Job { int cls; Runner run; int lo_max; };   // lo_max: largest lowest-target bit the runner allows
+  // lo_max: largest lowest-target bit the runner allows; launches: per run
+  struct Job { int cls; Runner run; int lo_max; int launches; };
   std::vector<Job> jobs;
   if (h->kind == NWQ_KIND_SV) {
-    jobs.push_back({KC_SV1Q, run_1q, h->n - 1});
-    jobs.push_back({KC_DIAG, run_diag, h->n - 1});
+    jobs.push_back({KC_SV1Q, run_1q, h->n - 1, 2});
+    jobs.push_back({KC_DIAG, run_diag, h->n - 1, 2});
     if (h->n >= 2) {
-      jobs.push_back({KC_PERM, run_perm, h->n - 2});
-      jobs.push_back({KC_SV2Q, run_2q, h->n - 2});
+      jobs.push_back({KC_PERM, run_perm, h->n - 2, 2});
+      jobs.push_back({KC_SV2Q, run_2q, h->n - 2, 2});
     }
   } else {
-    jobs.push_back({KC_DM1, run_dm1, h->n - 1});
-    if (h->n >= 2) jobs.push_back({KC_DM2, run_dm2, h->n - 2});
+    jobs.push_back({KC_DM1, run_dm1, h->n - 1, 2});
+    if (h->n >= 2) jobs.push_back({KC_DM2, run_dm2, h->n - 2, 4});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
@@ -211,7 +223,7 @@ int nwq_autotune(nwq_handle h, int reps, double* best_ms) {
         if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0.f;
         if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        t[ci * nq + q] = ms / (2.0 * reps);
+        t[ci * nq + q] = ms / ((double)j.launches * reps);
       }
     if (rc) break;
     double bsum[kBuckets] = {0.0, 0.0, 0.0};
