@@ -545,7 +545,7 @@ def measure_leg(nwq, st, n, shots=1 << 20):
     tp = timed(lambda: nwq.nwq_probabilities(st.h, p))
     tr = timed(lambda: nwq.nwq_readout_noise(n, p, conf), reps=1)
     ts = timed(lambda: nwq.nwq_sample(n, p, u, outs, work))
-    passes = (n + 3) // 4
+    passes = (n + 4) // 5   # up to five qubits per pass
     return {"n": n, "shots": shots,
             "probabilities_ms": round(tp * 1e3, 3), "probabilities_GBs": round(24 * N / tp / 1e9, 1),
             "readout_ms": round(tr * 1e3, 3), "readout_passes": passes,

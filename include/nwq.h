@@ -474,7 +474,7 @@ int nwq_probabilities(nwq_handle h, double* probs_dev);
  * C[0][0], C[0][1], C[1][0], C[1][1]; p <- (C_{n-1} (x) ... (x) C_0) p.
  * Entries must lie in [0, 1] and each column sum to 1 (within 1e-12), else
  * NWQ_EINVAL before any launch.  Identity matrices are skipped; the others
- * run four qubits per pass.  Asynchronous on `stream` (hipStream_t). */
+ * run up to five qubits per pass.  Asynchronous on `stream` (hipStream_t). */
 int nwq_readout_noise(int n, double* probs_dev, const double* confusion, void* stream);
 
 /* Workspace of nwq_sample in bytes (0 if n is outside [1, 34]). */

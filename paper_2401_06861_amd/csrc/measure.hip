@@ -10,7 +10,7 @@
 //     matrix), one streaming pass;
 //   * readout noise: per qubit a column-stochastic 2x2 confusion matrix
 //     C[r][t] = P(read r | true t) applied on that qubit's bit of the outcome
-//     index, up to four qubits per pass with the group's entries in
+//     index, up to five qubits per pass with the group's entries in
 //     registers;
 //   * sampling by inverse transform on an integer CDF: q_j = floor(p_j 2^61)
 //     (exact power-of-two scaling), C_j = q_0 + ... + q_j in 64-bit integers
@@ -64,13 +64,14 @@ __global__ __launch_bounds__(kBlock) void k_probs_dm(const double2* __restrict__
     p[j] = rho[(j << n) + j].x;
 }
 
-// Confusion matrices of up to four qubits applied to each group of 2^g
+// Confusion matrices of up to five qubits applied to each group of 2^g
 // outcomes that differ only on those bits.  cm holds 4 entries per qubit:
 // C[0][0], C[0][1], C[1][0], C[1][1] (C[r][t] = P(read r | true t)).
+constexpr int kReadoutMaxGroup = 5;   // qubits per readout pass (2^5 entries per thread; 6 would need 320 VGPRs)
 struct ConfGroup {
-  int g;                 // qubits in the group (1..4)
-  int bit[4];            // outcome bits, ascending
-  double cm[4][4];
+  int g;                              // qubits in the group (1..kReadoutMaxGroup)
+  int bit[kReadoutMaxGroup];          // outcome bits, ascending
+  double cm[kReadoutMaxGroup][4];
 };
 
 __device__ __forceinline__ unsigned long long ins0m(unsigned long long p, int q) {
@@ -81,22 +82,26 @@ template <int G>
 __global__ __launch_bounds__(kBlock) void k_readout(double* __restrict__ p, unsigned long long ngroups,
                                                     ConfGroup cg) {
   constexpr int D = 1 << G;
+  // the group's entry offsets are ORs of these (uniform) bits, formed again
+  // for the stores rather than held in 2^G registers
+  unsigned long long mb[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) mb[i] = 1ull << cg.bit[i];
+  auto off = [&](int u) {
+    unsigned long long o = 0;
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+      if ((u >> i) & 1) o |= mb[i];
+    return o;
+  };
   for (unsigned long long gi = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; gi < ngroups;
        gi += (unsigned long long)gridDim.x * kBlock) {
     unsigned long long base = gi;
 #pragma unroll
     for (int i = 0; i < G; ++i) base = ins0m(base, cg.bit[i]);
-    unsigned long long idx[D];
     double v[D];
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      unsigned long long o = 0;
-#pragma unroll
-      for (int i = 0; i < G; ++i)
-        if ((u >> i) & 1) o |= 1ull << cg.bit[i];
-      idx[u] = base | o;
-      v[u] = p[idx[u]];
-    }
+    for (int u = 0; u < D; ++u) v[u] = p[base | off(u)];
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const double c00 = cg.cm[i][0], c01 = cg.cm[i][1], c10 = cg.cm[i][2], c11 = cg.cm[i][3];
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_readout(double* __restrict__ p, unsi
       }
     }
 #pragma unroll
-    for (int u = 0; u < D; ++u) p[idx[u]] = v[u];
+    for (int u = 0; u < D; ++u) p[base | off(u)] = v[u];
   }
 }
 
@@ -308,7 +313,7 @@ int nwq_readout_noise(int n, double* probs_dev, const double* confusion, void* s
       return set_error(NWQ_EINVAL, "qubit " + std::to_string(q) + ": confusion columns must sum to 1");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // identity matrices are skipped; the rest go four qubits per pass
+  // identity matrices are skipped; the rest go up to five qubits per pass
   std::vector<int> qs;
   for (int q = 0; q < n; ++q) {
     const double* c = confusion + 4 * q;
@@ -318,10 +323,10 @@ int nwq_readout_noise(int n, double* probs_dev, const double* confusion, void* s
   // gives the same result up to rounding.  Pass k takes qubits k, k + P,
   // k + 2P, ... of the list (P passes): the low bits, whose groups would
   // otherwise be read as short per-thread runs, are spread over the passes.
-  const size_t P = (qs.size() + 3) / 4;
+  const size_t P = (qs.size() + kReadoutMaxGroup - 1) / kReadoutMaxGroup;
   for (size_t k = 0; k < P; ++k) {
     ConfGroup cg{};
-    for (size_t j = k; j < qs.size() && cg.g < 4; j += P) {
+    for (size_t j = k; j < qs.size() && cg.g < kReadoutMaxGroup; j += P) {
       cg.bit[cg.g] = qs[j];
       for (int e = 0; e < 4; ++e) cg.cm[cg.g][e] = confusion[4 * qs[j] + e];
       ++cg.g;
@@ -332,7 +337,8 @@ int nwq_readout_noise(int n, double* probs_dev, const double* confusion, void* s
       case 1: hipLaunchKernelGGL(k_readout<1>, grid, dim3(kBlock), 0, s, probs_dev, ng, cg); break;
       case 2: hipLaunchKernelGGL(k_readout<2>, grid, dim3(kBlock), 0, s, probs_dev, ng, cg); break;
       case 3: hipLaunchKernelGGL(k_readout<3>, grid, dim3(kBlock), 0, s, probs_dev, ng, cg); break;
-      default: hipLaunchKernelGGL(k_readout<4>, grid, dim3(kBlock), 0, s, probs_dev, ng, cg); break;
+      case 4: hipLaunchKernelGGL(k_readout<4>, grid, dim3(kBlock), 0, s, probs_dev, ng, cg); break;
+      default: hipLaunchKernelGGL(k_readout<5>, grid, dim3(kBlock), 0, s, probs_dev, ng, cg); break;
     }
     const int rc = check_hip(hipGetLastError(), "readout noise");
     if (rc) return rc;

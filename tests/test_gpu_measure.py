@@ -56,8 +56,11 @@ def test_probabilities_sv_and_dm(nwq, torch):
     dm.close()
 
 
-@pytest.mark.parametrize("n", [1, 3, 10])
+@pytest.mark.parametrize("n", [1, 3, 10, 14, 16])
 def test_readout_noise(nwq, torch, n):
+    """Passes of one to five qubits (every third matrix is the identity and is
+    skipped: n=14 leaves 9 matrices, in passes of five and four; n=16 leaves
+    10, in two passes of five)."""
     rng = np.random.default_rng(n)
     p = rng.dirichlet(np.ones(1 << n))
     cs = confusions(n, seed=n + 1, identity_every=3 if n > 1 else 5)
