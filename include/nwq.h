@@ -164,13 +164,26 @@ int nwq_apply_qasm(nwq_handle h, const char* text);
  * through fused blocks.  DM handles: each 1q gate with the channels composed
  * after it (a 4x4 superoperator on bits q and q + n of vec(rho)) is queued,
  * and so is each 2q gate with its channels (a 16x16 on bits q0, q1, q0 + n,
- * q1 + n) when the fused kernel is 1 (4 register bits) and n >= 4; the queue
+ * q1 + n) when the fused kernel is 1 (4 register bits), n >= 4 and a block
+ * can hold its four bits (2n <= k, or k minus the low tile bits of
+ * nwq_set_fusion_lowbits is at least 4); the queue
  * runs as fused blocks over the 2n bits when a read or nwq_flush needs the
  * state, or a 2q superoperator that cannot be queued comes (a reset or
  * nwq_set_state drops it); changing the width or the fused kernel on a DM
  * handle flushes first.  Returns the value in effect through *k_out when
  * non-NULL. */
 int nwq_set_fusion(nwq_handle h, int k, int* k_out);
+
+/* Low tile bits of fused blocks: every block's tile holds the lowest c bits
+ * of the index (contiguous runs of 2^c entries in HBM) plus up to k - c high
+ * bits its gates touch.  c = 0 (default) picks 6 for state vectors and 4 for
+ * density matrices (on vec(rho) a qubit above the low bits needs two high
+ * bits, q and q + n, so fewer low bits leave room for more qubits per block);
+ * otherwise c in [3, 8], used as max(k - 8, min(c, k - 2)) at width k.  Only
+ * the grouping into blocks changes, and results agree to rounding.  Changing
+ * it on a DM handle runs the queued superoperators first.  Other values:
+ * NWQ_EINVAL. */
+int nwq_set_fusion_lowbits(nwq_handle h, int c);
 
 /* Statistics of the last nwq_apply_circuit: number of fused blocks and
  * gates (both 0 when fusion was off). */

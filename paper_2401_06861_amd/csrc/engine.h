@@ -55,6 +55,7 @@ struct nwq_state {
   int fuse_k = 0;                  // 0 = off
   int last_blocks = 0, last_fused_gates = 0, last_phases = 0;
   int fuse_rb = 1;                 // fused kernel: 0 one LDS pass per gate, 1 / 2 register-blocked with 4 / 3 register bits
+  int fuse_c = 0;                  // low tile bits of a fused block: 0 = the kind's default (fusion_low_bits)
   int fuse_flags = 7;              // register-blocked kernels: bit 0 non-temporal tile loads and stores, bit 1
                                    // first / last phase straight between HBM and registers, bit 2 gate
                                    // products inside a phase (SV circuits)
@@ -94,7 +95,11 @@ struct Phase {
   int reg[4];
   std::vector<int> gates;
 };
-std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k);
+// c: the low bits every block's tile holds (c <= k - 2, k - c <= 8); -1 =
+// min(6, k - 2).  Ignored when the n bits fit one tile.
+std::vector<Block> plan_blocks(const std::vector<PGate>& g, int n, int k, int c = -1);
+// Low tile bits for a handle's fused blocks of width k over nbits bits.
+int fusion_low_bits(const nwq_state* h, int nbits, int k);
 // internal gate type: dense 4x4 whose matrix is entry p[0] of a side table
 // Internal gate types whose matrix sits in a side table from entry p[0] on:
 // a dense 4x4 (16 entries), a diagonal 4x4 (16 entries, the diagonal at 5u),

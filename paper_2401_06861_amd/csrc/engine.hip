@@ -420,7 +420,10 @@ int dm_flush(nwq_state* h) {
   const int k = h->pend_k, n = h->n;
   // queue it for the next fused run: 1q always, 2q when the blocks run on the
   // 4-register-bit kernel (a 16x16 takes all four register bits of a phase)
-  if (h->fuse_k > 0 && (k == 1 || (h->fuse_rb == 1 && h->nbits >= 8))) {
+  // and a block can hold its four bits (the whole state fits one tile, or the
+  // width leaves four bits above the low tile bits)
+  const bool fits4 = h->nbits <= h->fuse_k || h->fuse_k - fusion_low_bits(h, h->nbits, h->fuse_k) >= 4;
+  if (h->fuse_k > 0 && (k == 1 || (h->fuse_rb == 1 && h->nbits >= 8 && fits4))) {
     h->dmq_ops.push_back({k, h->pend_q[0], k == 2 ? h->pend_q[1] : -1});
     h->dmq_S.insert(h->dmq_S.end(), h->pend_S.begin(), h->pend_S.end());
     h->pend_active = false;

@@ -69,6 +69,7 @@ _SIG = {
     "nwq_fusion_stats": [_h, _ip, _ip],
     "nwq_set_fusion_kernel": [_h, C.c_int],
     "nwq_set_fusion_flags": [_h, C.c_int],
+    "nwq_set_fusion_lowbits": [_h, C.c_int],
     "nwq_fusion_phases": [_h, _ip],
     "nwq_fusion_plan": [C.c_int, C.c_int, C.c_int, _ip, _ip, _ip, _ip, _ip],
     "nwq_apply_channel": [_h, _ip, C.c_int, _dp, C.c_int],
@@ -246,6 +247,11 @@ def nwq_set_fusion_kernel(h: int, kernel: int) -> None:
 
 def nwq_set_fusion_flags(h: int, flags: int) -> None:
     _check(lib.nwq_set_fusion_flags(h, flags))
+
+
+def nwq_set_fusion_lowbits(h: int, c: int) -> None:
+    """Low tile bits of fused blocks: 0 = default (6 for SV, 4 for DM), else 3..8."""
+    _check(lib.nwq_set_fusion_lowbits(h, int(c)))
 
 
 def nwq_fusion_phases(h: int) -> int:

@@ -368,6 +368,47 @@ def test_fused_queue_two_qubit_superoperators(nwq, n, k):
     st.close()
 
 
+@pytest.mark.parametrize("n,k,c", [(7, 8, 0), (7, 8, 6), (8, 9, 6), (9, 12, 0), (9, 12, 3), (9, 12, 5),
+                                   (9, 12, 8), (9, 13, 4), (10, 10, 0)])
+def test_fused_queue_low_tile_bits(nwq, n, k, c):
+    """Fused DM blocks under each low-tile-bit setting (0: the default 4 for
+    density matrices; the width clamps it to [k - 8, k - 2]): noisy 1q and 2q
+    gates on every qubit against the oracle.  Where the width leaves fewer
+    than four bits above the low ones (k=8 or 9 with 6 low bits), a 2q
+    superoperator whose four bits all lie above them cannot share a block,
+    so it runs as its own pass after the queue."""
+    rng = np.random.default_rng(900 + 10 * n + k + c)
+    rho0 = W.random_density_matrix(n, seed=60 + n)
+    ops = []
+    for q in range(n):
+        ops += [("u3", (q,), tuple(float(x) for x in rng.uniform(-3, 3, 3))), ("amp_damp", (q,), (0.03,))]
+    for a in range(n - 1):
+        ops += [("rzz", (a, a + 1), (float(rng.uniform(-3, 3)),)), ("depolarize2", (a, a + 1), (0.02,))]
+        ops += [("cx", (a + 1, a), ()), ("phase_damp", (a,), (0.04,))]
+    ops += [("swap", (n - 1, n - 2), ()), ("depolarize2", (n - 2, n - 1), (0.01,))]
+    want = rho0
+    for op in ops:
+        want = tensor.dm_apply(want, op, n)
+    st = nwq.DMState(n, reset=False)
+    st.set_fusion(k)
+    nwq.nwq_set_fusion_kernel(st.h, 1)
+    nwq.nwq_set_fusion_lowbits(st.h, c)
+    st.load(rho0)
+    st.run(ops)
+    assert maxerr(st.numpy(), want) <= TOL
+    assert nwq.nwq_fusion_stats(st.h)[0] >= 1
+    st.load(rho0)                                    # changing the setting runs the queued work first
+    half = len(ops) // 2
+    st.run(ops[:half])
+    nwq.nwq_set_fusion_lowbits(st.h, 6 if c != 6 else 0)
+    st.run(ops[half:])
+    assert maxerr(st.numpy(), want) <= TOL
+    for bad in (-1, 1, 2, 9):
+        with pytest.raises(nwq.NwqError):
+            nwq.nwq_set_fusion_lowbits(st.h, bad)
+    st.close()
+
+
 def test_fused_queue_long_circuit_runs_in_pieces(nwq):
     """A noisy circuit with more queued superoperators than one queue run
     holds (1 MiB of matrices: 256 two-qubit ones) and no read in between runs

@@ -441,6 +441,36 @@ def test_register_blocked_fused_kernel(nwq, n, k):
             assert np.array_equal(same[0], out), key
 
 
+@pytest.mark.parametrize("n,k", [(16, 10), (18, 12), (20, 13)])
+def test_fused_low_tile_bits(nwq, n, k):
+    """Fused SV blocks under every low-tile-bit setting (clamped to [k - 8,
+    k - 2] at width k) and every fused kernel, applied to a random state and
+    run from |0...0> (the sparse start), against the oracle; the setting
+    changes the grouping into blocks (and so the block count), not the
+    result beyond rounding."""
+    gates = W.random_gate_list(n, 200, seed=11 * n + k) + W.brickwork_circuit(n, 8, seed=n + 1)
+    psi0 = W.random_state(n, seed=n + 2)
+    want = tensor.sv_run(gates, n, psi0)
+    zero = np.zeros(1 << n, dtype=np.complex128)
+    zero[0] = 1.0
+    want0 = tensor.sv_run(gates, n, zero)
+    blocks = {}
+    st = nwq.SVState(n, reset=False)
+    st.set_fusion(k)
+    for c in (0, 3, 4, 5, 7, 8):
+        nwq.nwq_set_fusion_lowbits(st.h, c)
+        for rb in (1, 2, 0):
+            nwq.nwq_set_fusion_kernel(st.h, rb)
+            st.load(psi0)
+            st.run_circuit(gates)
+            assert maxerr(st.numpy(), want) <= TOL, (c, rb)
+            blocks[(c, rb)] = nwq.nwq_fusion_stats(st.h)[0]
+            nwq.nwq_run_circuit(st.h, *nwq.circuit_arrays(gates))
+            assert maxerr(st.numpy(), want0) <= TOL, (c, rb, "from zero")
+    assert len({blocks[(c, 1)] for c in (0, 4, 8)}) > 1   # the setting reaches the planner
+    st.close()
+
+
 def _product_circuits(n, seed):
     """Gate runs that the block products rewrite: U3 pairs around CX on both
     operator orders, diagonal-only runs (RZ, T, S, CZ, RZZ: a diagonal
