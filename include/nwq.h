@@ -367,6 +367,13 @@ int nwq_vqe_get_config(nwq_vqe_handle h, int* mode, int* threads, int* blocks_pe
  * allows it (as in nwq_set_fusion_flags).  Default 3.  Results do not depend
  * on the flags.  Other values: NWQ_EINVAL. */
 int nwq_vqe_set_flags(nwq_vqe_handle h, int flags);
+/* Low tile bits of the fused schedule's blocks (mode 3), as
+ * nwq_set_fusion_lowbits for circuits: 0 (default) = 3, else c in [3, 8],
+ * used as max(k - 8, min(c, k - 2)) at tile width k.  Fewer low bits let a
+ * block hold more qubits (n=20, L=8: 26 backward blocks with 6, 18 with 3).
+ * Changing it waits for the context's stream and plans the program again
+ * on next use.  Results agree to rounding.  Other values: NWQ_EINVAL. */
+int nwq_vqe_set_lowbits(nwq_vqe_handle h, int c);
 
 /* Batched VQE for the Ising model of Sec. III (Fig. 4) in one call, without
  * a context: the n-qubit hardware-efficient ansatz of L layers (each layer

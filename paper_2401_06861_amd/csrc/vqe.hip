@@ -1367,6 +1367,7 @@ struct nwq_vqe {
   // fused path program (built on first use)
   bool fused_built = false;
   int fused_k = 12;
+  int low_bits = 0;            // low tile bits of the planned blocks: 0 = kVqeLowBits
   int fused_rbits = 4;         // register bits per phase of the forward kernel
   bool bwd_rb = false;         // backward sweep register-blocked (3 bits) when every tile has >= 2^9 entries
   size_t fused_rop_off = 0;    // offset of the register-blocked backward ops in d_fused
@@ -1515,8 +1516,16 @@ static int launch_global(nwq_vqe* h, int B, const double* theta, const double* c
 // Fused program: blocks over the ops at tile width fused_k, forward phases for
 // the register-blocked kernel, backward ops in reverse per block (chunks of
 // at most kBwdMaxOps).
+// Low tile bits of the fused schedule's blocks (clamped to [k - 8, k - 2] at
+// width k).  A batch of 2^20-amplitude states at n=20 plans the HEA ansatz
+// (L=8) into 26 backward blocks of width 11 with 6 low bits and 18 with 3; the
+// shorter runs cost less than the passes they save (n=20, L=8, B=256: 129 ->
+// 119 ms per batch).
+constexpr int kVqeLowBits = 3;
+
 static int build_fused(nwq_vqe* h) {
   if (h->fused_built) return NWQ_OK;
+  const int low = h->low_bits > 0 ? h->low_bits : kVqeLowBits;
   const int n = h->n;
   std::vector<PGate> g(h->nops);
   for (int i = 0; i < h->nops; ++i) {
@@ -1525,7 +1534,7 @@ static int build_fused(nwq_vqe* h) {
     g[i] = PGate{0, {op.q0, two ? op.q1 : -1}, two ? 2 : 1, {0, 0, 0}};
   }
   const int k = std::min(h->fused_k, n);
-  const std::vector<Block> blocks = plan_blocks(g, n, std::max(k, 6));
+  const std::vector<Block> blocks = plan_blocks(g, n, std::max(k, 6), low);
   if (blocks.empty() && h->nops > 0) return set_error(NWQ_EINVAL, "fusion planner made no progress");
   std::vector<FusedPhase> phases;
   std::vector<FusedOp> fops;
@@ -1601,7 +1610,7 @@ static int build_fused(nwq_vqe* h) {
   if (kbw == k) {
     bpadded = padded;
   } else {
-    bpadded = plan_blocks(g, n, std::max(kbw, 6));
+    bpadded = plan_blocks(g, n, std::max(kbw, 6), low);
     if (bpadded.empty() && h->nops > 0) return set_error(NWQ_EINVAL, "fusion planner made no progress");
     for (Block& b : bpadded) pad_block(b, n, std::max(kbw, 8));
   }
@@ -2098,6 +2107,22 @@ int nwq_vqe_set_flags(nwq_vqe_handle h, int flags) {
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     h->graphs.clear();
     h->fused_flags = flags;
+  }
+  return NWQ_OK;
+}
+
+int nwq_vqe_set_lowbits(nwq_vqe_handle h, int c) {
+  if (!h) return vqe_fail(NWQ_EINVAL, "NULL handle");
+  if (c != 0 && (c < 3 || c > 8)) return vqe_fail(NWQ_EINVAL, "low tile bits must be 0 or in [3, 8]");
+  if (c != h->low_bits) {   // the fused program is planned again on next use
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    if (h->d_fused) (void)hipFree(h->d_fused);
+    h->d_fused = nullptr;
+    h->fused_built = false;
+    h->fused_bytes = 0;
+    h->low_bits = c;
   }
   return NWQ_OK;
 }

@@ -31,6 +31,7 @@ for _name, _args in {
     "nwq_vqe_batch_release": [],
     "nwq_vqe_memory": [_vh, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
     "nwq_vqe_set_flags": [_vh, C.c_int],
+    "nwq_vqe_set_lowbits": [_vh, C.c_int],
 }.items():
     _f = getattr(lib, _name)
     _f.argtypes = _args
@@ -39,7 +40,7 @@ for _name, _args in {
 EXPORTED = ("nwq_vqe_create", "nwq_vqe_destroy", "nwq_vqe_info", "nwq_vqe_eval", "nwq_vqe_eval_coeffs",
             "nwq_vqe_eval_single",
             "nwq_vqe_set_config", "nwq_vqe_get_config", "nwq_vqe_autotune", "nwq_vqe_batch",
-            "nwq_vqe_batch_release", "nwq_vqe_memory", "nwq_vqe_set_flags")
+            "nwq_vqe_batch_release", "nwq_vqe_memory", "nwq_vqe_set_flags", "nwq_vqe_set_lowbits")
 
 
 def program_arrays(prog) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
@@ -127,6 +128,10 @@ class VQE:
 
     def set_flags(self, flags: int) -> None:
         _check(lib.nwq_vqe_set_flags(self.h, flags))
+
+    def set_lowbits(self, c: int) -> None:
+        """Low tile bits of the fused schedule's blocks: 0 = default (3), else 3..8."""
+        _check(lib.nwq_vqe_set_lowbits(self.h, c))
 
     def get_config(self) -> Tuple[int, int, int]:
         m, t, b = C.c_int(), C.c_int(), C.c_int()

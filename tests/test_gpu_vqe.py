@@ -219,6 +219,40 @@ def test_fused_path_matches_oracle(V, torch, n, L, bps):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,L", [(14, 3), (16, 2)])
+def test_fused_low_tile_bits(V, torch, n, L):
+    """The fused schedule planned with each low-tile-bit setting (0: the
+    default 3; clamped to [k - 8, k - 2] at tile width k): energies and
+    parameter-shift gradient components against the oracle, and the same
+    values across settings to rounding."""
+    prog = W.hea_ansatz(n, L)
+    theta, h = W.vqe_batch(n, L, B=2)
+    terms = W.tfim_hamiltonian(n, 1.0, h)
+    ctx = V.VQE(n, prog, terms)
+    ctx.set_config(3, 256, 0)
+    t = torch.from_numpy(theta).cuda()
+    pick = [0, n - 1, n, 2 * n * L - 1]
+    ref = None
+    for c in (0, 3, 4, 5, 6, 8):
+        ctx.set_lowbits(c)
+        E, G = ctx.eval(t)
+        E = E.cpu().numpy()
+        G = G.cpu().numpy()
+        if ref is None:
+            ref = (E, G)
+            for b in range(2):
+                assert abs(E[b] - OV.energy(prog, theta[b], terms, n)) <= 1e-10
+                g_ps = OV.grad_parameter_shift(prog, theta[b], terms, n, params=pick)
+                assert np.max(np.abs(G[b][pick] - g_ps[pick])) <= 1e-10
+        assert np.max(np.abs(E - ref[0])) <= 1e-12, c
+        assert np.max(np.abs(G - ref[1])) <= 1e-12, c
+    from paper_2401_06861_amd import nwq
+    for bad in (-1, 2, 9):
+        with pytest.raises(nwq.NwqError):
+            ctx.set_lowbits(bad)
+    ctx.close()
+
+
 def test_fused_generic_program(V, torch):
     """Fused path with fixed gates, CZ, SWAP and RZZ on a 10-qubit register
     (one tile) and with several tiles at 13 and 17 qubits; at 17 qubits the
