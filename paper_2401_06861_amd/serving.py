@@ -427,7 +427,7 @@ class GpuExecutor:
             with torch.cuda.stream(stream):
                 st = self.nwq.DMState(r.n, stream=stream, owned=True)
                 try:
-                    if r.n >= 8:   # 1q superoperators as fused blocks over the 2n bits
+                    if r.n >= 8:   # the superoperators as fused blocks over the 2n bits
                         st.set_fusion(12)
                     st.run(self.W.noisy_tfim_circuit(r.n, r.steps))
                     Z = st.expvals(self.W.single_site_terms(r.n, "Z"))
